@@ -1,0 +1,148 @@
+"""Benchmark of the Parareal hot path on one MI355X.
+
+One timed step = one pass of the whole hot path over one batch: the
+initial coarse sweep, then one Parareal iteration with the fine solves of
+every slice of every initial condition in one batch (stage-in, 2-D FFT
+steps with the pointwise right-hand side, the spectral divide and, for the
+conservative model, the FP64 mass multiplier) and the sequential
+coarse/correction sweep with its FP64 norm -- i.e. pr_solve with
+max_iter = 1.
+
+value = fine-step grid-point updates per second (B * s * c * N^2 / time)
+roofline = the fine sweep (row + column pass of every step), timed with
+HIP events inside pr_solve on the launch stream, against HBM.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+CONFIGS = {
+    "c1": dict(workload="classic AC 64x64 eps=0.02 FP64, 1 IC x 8 slices x 100 steps dt=1e-4, "
+                        "numerical G (1 step of 0.01)",
+               n=64, eps=0.02, dt=1e-4, steps=100, slices=8, ics=1, conservative=False,
+               seed0=0, g_steps=1),
+    "c2": dict(workload="classic AC 256x256 eps=0.01, 8 ICs x 64 slices x 200 steps dt=2e-5 "
+                        "(512 fine solves per launch), numerical G (1 step of 4e-3)",
+               n=256, eps=0.01, dt=2e-5, steps=200, slices=64, ics=8, conservative=False,
+               seed0=0, g_steps=1),
+    "c3": dict(workload="mass-conservative AC 512x512 eps=0.01, 16 ICs x 128 slices x 100 steps "
+                        "dt=1e-5 (2048 fine solves per launch), numerical G (1 step of 1e-3)",
+               n=512, eps=0.01, dt=1e-5, steps=100, slices=128, ics=16, conservative=True,
+               seed0=0, g_steps=1),
+}
+
+
+def bytes_per_point_step(prec: str) -> int:
+    # each step: one column pass and one row pass, each reading and writing
+    # the field's N*N real numbers once (as N/2 x N complex values)
+    return 32 if prec == "f64" else 16
+
+
+def cpu_baseline(cfg, prec, budget_s=12.0):
+    """The FP64 oracle on host cores: fine steps of the same fields."""
+    from oracle import allen_cahn as ac
+    from paper_2510_07672_amd import synth
+    n = cfg["n"]
+    p = ac.Problem(n=n, length=1.0, eps=cfg["eps"], conservative=cfg["conservative"], stab=2.0,
+                   dt=cfg["dt"], steps=1)
+    u = synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + cfg["ics"]))
+    ac.fine(u, p)  # warm-up (plans, pages)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        u = ac.fine(u, p)
+        steps += 1
+    dt = time.perf_counter() - t0
+    pts = steps * u.shape[0] * n * n
+    return {"value": pts / dt / 1e9, "unit": "Gpts/s", "cores": os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 fine steps of {u.shape[0]} {n}x{n} fields "
+                      f"(scipy.fft, workers={os.cpu_count()}) in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the fine solves would shard by slice with no communication; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_07672_amd import api, synth
+
+    cfg = CONFIGS[args.config]
+    n, s, B, c = cfg["n"], cfg["slices"], cfg["ics"], cfg["steps"]
+    p = api.Problem(n=n, length=1.0, eps=cfg["eps"], conservative=cfg["conservative"], stab=2.0,
+                    dt=cfg["dt"], steps=c, fine_prec=args.prec)
+    g = api.Coarse(dt=cfg["dt"] * c / cfg["g_steps"], steps=cfg["g_steps"], prec="f64")
+    u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
+    U = torch.empty((B, s + 1, n, n), dtype=torch.float64, device="cuda")
+    ws = None
+
+    def one():
+        return api.pr_solve(p, g, u0, s, tol=0.0, max_iter=1, U=U, ws=ws, allow_not_converged=True)
+
+    _, st = one()
+    import ctypes
+    from paper_2510_07672_amd import _lib as L
+    need = L.lib().pr_solve_workspace_bytes(ctypes.byref(p.c()), ctypes.byref(g.c()), B, s)
+    ws = api.workspace(need, "cuda")
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    fine_ms, sweep_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = one()
+        fine_ms.append(st.fine_ms)
+        sweep_ms.append(st.sweep_ms)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    pts = B * s * c * n * n
+    value = pts / (ms_per_step * 1e-3) / 1e9
+
+    fine_ms_avg = float(np.mean(fine_ms))
+    bpp = bytes_per_point_step(args.prec)
+    achieved = pts * bpp / (fine_ms_avg * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "fine step = k_col + k_row<MID> per step, over the whole F sweep",
+            "bytes_per_point_step": bpp,
+            "fine_sweep_ms": round(fine_ms_avg, 3), "sweep_ms": round(float(np.mean(sweep_ms)), 3)}
+    out = {
+        "metric": "Parareal speedup vs serial fine at rel-L2<=1e-6; fine-step Gpts/s; %HBM roofline",
+        "value": round(value, 2), "unit": "Gpts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": cfg["workload"], "n": n, "ics": B, "slices": s, "fine_steps": c,
+                   "fine_solves_per_launch": B * s, "fine_prec": args.prec},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.prec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * pr.h -- C ABI of libpr: the Parareal fine propagator for the classic and
+ * mass-conservative Allen-Cahn equations on one gfx950 GPU.
+ *
+ * Method: arXiv 2510.07672, "Parallel-in-Time Solution of Allen-Cahn
+ * Equations by Integrating Operator Learning into the Parareal Method".
+ *
+ * The problem (Section 2) is the initial-value problem
+ *     u_t = eps^2 Lap u + f(u) [- (1/|Omega|) int f(u)],   f(u) = u - u^3,
+ * periodic on Omega = [0, L]^2 (Section 3.1), u(0) = u0.  The grid is
+ * x_i = i h, i = 0..N-1, h = L/N.  One fine step of size dt is the
+ * stabilised semi-implicit step with the central-difference Laplacian
+ * (Section 3.1 allows finite differences; the stabilised semi-implicit
+ * family is the one the introduction cites):
+ *     ((1 + S dt) I - dt eps^2 Lap_h) u+ = (1 + S dt) u + dt (f(u) - m),
+ * with m = 0 (classic) or the grid mean of f(u) (conservative, the
+ * discrete nonlocal term of Section 3.1).  It is solved exactly by 2-D
+ * real FFTs.  The fine propagator F (eq. fine_operator) is `steps` such
+ * steps; Parareal is Algorithm 2 of Section 3.3.
+ *
+ * Conventions for every entry point:
+ *   - Every array argument is a DEVICE pointer, owned by the caller, C-
+ *     contiguous, with u[b][i][j] = u(x_i, y_j) and N*N elements per field.
+ *     Arrays are expected 256-byte aligned (any torch allocation is).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on that stream except pr_solve and pr_serial_fine,
+ *     which block (pr_solve reads one double per initial condition back
+ *     after each iteration to test convergence).
+ *   - `ws` is a device workspace of at least the size the matching
+ *     *_workspace_bytes() call returns; the library allocates nothing.
+ *   - Arguments are validated before any launch; on a validation error
+ *     nothing is written and pr_last_error() says what was wrong.
+ *   - Thread safety: calls on different streams with different
+ *     workspaces may run concurrently; pr_last_error() is per thread.
+ *   - Results are deterministic: no atomics take part in any floating-
+ *     point sum, and no two fields share a transform, so a field's bits do
+ *     not depend on what else is in the batch.
+ */
+#ifndef PR_H_
+#define PR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PR_ABI_VERSION 1
+
+typedef enum {
+  PR_OK = 0,
+  PR_ERR_INVALID_ARG = 1,  /* null pointer, negative size, bad enum value  */
+  PR_ERR_UNSUPPORTED = 2,  /* N not a power of two in [16, 1024], dim != 2 */
+  PR_ERR_WORKSPACE = 3,    /* ws NULL or smaller than *_workspace_bytes()  */
+  PR_ERR_DEVICE = 4,       /* a HIP call failed (message in last_error)    */
+  PR_ERR_NUMERIC = 5,      /* NaN or Inf reached the convergence norm      */
+  PR_NOT_CONVERGED = 6     /* max_iter < slices stopped Parareal above tol */
+} pr_status;
+
+typedef enum { PR_F64 = 0, PR_F32 = 1, PR_BF16 = 2 } pr_dtype;
+
+/* The fine problem: Section 2 (model), Section 3.1 (grid and scheme). */
+typedef struct {
+  int32_t dim;          /* 2 (3-D is not supported: PR_ERR_UNSUPPORTED)      */
+  int32_t n;            /* N: power of two, 16 <= N <= 1024                  */
+  double length;        /* L > 0, h = L / N                                  */
+  double eps;           /* interfacial parameter epsilon > 0                 */
+  int32_t conservative; /* 0: classic AC, 1: mass-conservative AC            */
+  double stab;          /* stabiliser S >= 0                                 */
+  double dt;            /* fine step dt* > 0                                 */
+  int32_t steps;        /* fine steps per slice c >= 1                       */
+  int32_t fine_prec;    /* PR_F64 or PR_F32: arithmetic of the fine FFTs.
+                           PR_F32 rounds its input state to float once, at
+                           stage-in, and carries a float state in between.  */
+} pr_problem;
+
+typedef enum { PR_G_SCHEME = 0 } pr_coarse_kind;
+
+/* The coarse propagator G of Section 3.3.  PR_G_SCHEME is the numerical
+ * coarse step: `steps` semi-implicit steps of `dt` in precision `prec`. */
+typedef struct {
+  int32_t kind;   /* PR_G_SCHEME                                */
+  double dt;      /* coarse step > 0 (one slice: c * dt*)       */
+  int32_t steps;  /* coarse steps per slice >= 1                */
+  int32_t prec;   /* PR_F64 or PR_F32                           */
+} pr_coarse;
+
+/* Host-side report of pr_solve.  Pointers may be NULL. */
+typedef struct {
+  int32_t iterations;     /* out: iterations run (max over ICs)            */
+  int32_t n_converged;    /* out: ICs whose update norm reached <= tol,
+                             or that ran k = slices iterations (exact)     */
+  int32_t* ic_iterations; /* in: host int32[n_ics] or NULL; out: per IC    */
+  double* history;        /* in: host double[max_iter * n_ics] or NULL;
+                             out: history[(k-1)*n_ics + b] = sup-norm
+                             update of IC b in iteration k (0 once frozen) */
+  double fine_ms;         /* out: wall time spent in the fine sweeps       */
+  double sweep_ms;        /* out: wall time in the coarse/correction sweeps*/
+} pr_stats;
+
+/* ---------------------------------------------------------------- F --- */
+
+/* Bytes of workspace pr_fine_propagate needs for `nfields` fields. */
+size_t pr_fine_workspace_bytes(const pr_problem* p, int64_t nfields);
+
+/* F(t_n, t_{n+1}, U) of eq. fine_operator: p->steps fine steps applied to
+ * each of `nfields` independent fields.
+ *   u_in   device double[nfields][N][N], read only.
+ *   u_out  device [nfields][N][N] of out_dtype (PR_F64 or PR_F32); may not
+ *          alias u_in.
+ * All fields advance in the same launches (Section 3.3 computes the fine
+ * solves of all slices in parallel). */
+pr_status pr_fine_propagate(const pr_problem* p, int64_t nfields,
+                            const double* u_in, void* u_out, pr_dtype out_dtype,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- G --- */
+
+size_t pr_coarse_workspace_bytes(const pr_problem* p, const pr_coarse* g,
+                                 int64_t nfields);
+
+/* G(U) of Section 3.3 on `nfields` fields: u_in, g_out device
+ * double[nfields][N][N] (g_out may not alias u_in).  The model, grid and
+ * stabiliser come from p; the step, count and precision from g. */
+pr_status pr_coarse_apply(const pr_problem* p, const pr_coarse* g,
+                          int64_t nfields, const double* u_in, double* g_out,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------- correction --- */
+
+/* The Parareal correction of Section 3.3 / Algorithm 2, for `nfields`
+ * fields of n*n points, evaluated as  u_new = f + (g_new - g_old):
+ *   f       device [nfields][n][n] of f_dtype (PR_F64 or PR_F32): F(U^{k-1}_j)
+ *   g_new   device double[nfields][n][n]: G(U^k_j)
+ *   g_old   device double[nfields][n][n]: in  G(U^{k-1}_j);
+ *           out G(U^k_j) when update_cache != 0 (the reused coarse value)
+ *   u       device double[nfields][n][n]: in U^{k-1}_{j+1}, out U^k_{j+1}
+ *   upd_max device double[nfields]: running sup norm, updated as
+ *           upd_max[b] = max(upd_max[b], max_points |u_new - u_in|);
+ *           a NaN anywhere makes it NaN.
+ * No two of f, g_new, g_old, u may alias, except that g_new may equal
+ * g_old when update_cache is 0 is meaningless and rejected. */
+pr_status pr_correct(int64_t nfields, int32_t n, const void* f,
+                     pr_dtype f_dtype, const double* g_new, double* g_old,
+                     double* u, double* upd_max, int32_t update_cache,
+                     void* stream);
+
+/* -------------------------------------------------------- Parareal --- */
+
+size_t pr_solve_workspace_bytes(const pr_problem* p, const pr_coarse* g,
+                                int64_t n_ics, int32_t n_slices);
+
+/* Algorithm 2 for n_ics initial conditions at once.
+ *   u0  device double[n_ics][N][N]
+ *   U   device double[n_ics][n_slices+1][N][N]: out, the final iterate
+ *       [U_0, U^1_1, ..., U^k_k, ..., U^k_s] of each IC.
+ * Initial coarse sweep U^0_{j+1} = G(U^0_j); then for k = 1..max_iter the
+ * fine solves of slices k-1..s-1 of every active IC in one batch, and the
+ * sequential sweep U^k_{j+1} = F(U^{k-1}_j) + (G(U^k_j) - G(U^{k-1}_j)).
+ * An IC whose sup-norm update over all slices is <= tol is frozen (so a
+ * batch gives the same bits as its members run alone).  max_iter is
+ * clamped to n_slices; after k iterations slices 0..k equal the serial
+ * fine solve exactly, so k = n_slices always returns PR_OK.
+ * Returns PR_NOT_CONVERGED if max_iter < n_slices stopped an IC above tol
+ * (U still holds the last iterate), PR_ERR_NUMERIC on NaN/Inf. */
+pr_status pr_solve(const pr_problem* p, const pr_coarse* g, int64_t n_ics,
+                   int32_t n_slices, const double* u0, double* U, double tol,
+                   int32_t max_iter, pr_stats* stats, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* The serial fine solve U_{j+1} = F(U_j), j = 0..n_slices-1, for n_ics ICs
+ * batched per slice (the reference Parareal converges to).
+ *   u0 device double[n_ics][N][N]; U device double[n_ics][n_slices+1][N][N].
+ * Workspace: pr_fine_workspace_bytes(p, n_ics) + n_ics*N*N*8 bytes. */
+size_t pr_serial_workspace_bytes(const pr_problem* p, int64_t n_ics);
+pr_status pr_serial_fine(const pr_problem* p, int64_t n_ics, int32_t n_slices,
+                         const double* u0, double* U, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------- helpers --- */
+
+const char* pr_status_string(pr_status s);
+const char* pr_last_error(void);
+int pr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PR_H_ */

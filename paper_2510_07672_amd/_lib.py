@@ -1,0 +1,92 @@
+"""ctypes view of libpr.so (the C ABI declared in include/pr.h).
+
+Loading fails loudly when the library has not been built: there is no
+fallback of any kind.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+from .build import LIB
+
+PR_OK, PR_ERR_INVALID_ARG, PR_ERR_UNSUPPORTED, PR_ERR_WORKSPACE, PR_ERR_DEVICE, \
+    PR_ERR_NUMERIC, PR_NOT_CONVERGED = range(7)
+PR_F64, PR_F32, PR_BF16 = 0, 1, 2
+PR_G_SCHEME = 0
+
+EXPORTED = [
+    "pr_fine_workspace_bytes", "pr_fine_propagate",
+    "pr_coarse_workspace_bytes", "pr_coarse_apply",
+    "pr_correct",
+    "pr_solve_workspace_bytes", "pr_solve",
+    "pr_serial_workspace_bytes", "pr_serial_fine",
+    "pr_status_string", "pr_last_error", "pr_abi_version",
+]
+
+
+class Problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("length", C.c_double),
+                ("eps", C.c_double), ("conservative", C.c_int32), ("stab", C.c_double),
+                ("dt", C.c_double), ("steps", C.c_int32), ("fine_prec", C.c_int32)]
+
+
+class Coarse(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("steps", C.c_int32),
+                ("prec", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("n_converged", C.c_int32),
+                ("ic_iterations", C.POINTER(C.c_int32)), ("history", C.POINTER(C.c_double)),
+                ("fine_ms", C.c_double), ("sweep_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(
+                f"{LIB} is not built; run paper_2510_07672_amd.build.build() "
+                "(hipcc --offload-arch=gfx950) first")
+        L = C.CDLL(LIB)
+        P, G, S = C.POINTER(Problem), C.POINTER(Coarse), C.POINTER(Stats)
+        vp, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
+        sig = {
+            "pr_fine_workspace_bytes": (sz, [P, i64]),
+            "pr_fine_propagate": (C.c_int, [P, i64, vp, vp, C.c_int, vp, sz, vp]),
+            "pr_coarse_workspace_bytes": (sz, [P, G, i64]),
+            "pr_coarse_apply": (C.c_int, [P, G, i64, vp, vp, vp, sz, vp]),
+            "pr_correct": (C.c_int, [i64, i32, vp, C.c_int, vp, vp, vp, vp, i32, vp]),
+            "pr_solve_workspace_bytes": (sz, [P, G, i64, i32]),
+            "pr_solve": (C.c_int, [P, G, i64, i32, vp, vp, C.c_double, i32, S, vp, sz, vp]),
+            "pr_serial_workspace_bytes": (sz, [P, i64]),
+            "pr_serial_fine": (C.c_int, [P, i64, i32, vp, vp, vp, sz, vp]),
+            "pr_status_string": (C.c_char_p, [C.c_int]),
+            "pr_last_error": (C.c_char_p, []),
+            "pr_abi_version": (C.c_int, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class PrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        L = lib()
+        self.status = status
+        msg = L.pr_last_error().decode()
+        super().__init__(f"{where}: {L.pr_status_string(status).decode()}: {msg}")
+
+
+def check(status: int, where: str, allow=(PR_OK,)) -> int:
+    if status not in allow:
+        raise PrError(status, where)
+    return status

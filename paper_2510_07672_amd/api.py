@@ -1,0 +1,173 @@
+"""Python binding of libpr: the entry points of include/pr.h under the same
+names, taking torch CUDA tensors.  Argument marshalling only -- every step
+of the computation runs in the library's HIP kernels.  Workspaces are
+torch allocations sized by the library's *_workspace_bytes() calls, and
+work is queued on torch's current stream.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float64: L.PR_F64, torch.float32: L.PR_F32}
+_PREC = {"f64": L.PR_F64, "f32": L.PR_F32}
+
+
+@dataclass(frozen=True)
+class Problem:
+    """Section 2 model on the Section 3.1 grid; see include/pr.h."""
+    n: int
+    length: float
+    eps: float
+    conservative: bool
+    stab: float
+    dt: float
+    steps: int
+    fine_prec: str = "f64"
+
+    def c(self) -> L.Problem:
+        return L.Problem(2, self.n, self.length, self.eps, int(self.conservative), self.stab,
+                         self.dt, self.steps, _PREC[self.fine_prec])
+
+
+@dataclass(frozen=True)
+class Coarse:
+    """Numerical coarse propagator: `steps` semi-implicit steps of `dt`."""
+    dt: float
+    steps: int = 1
+    prec: str = "f64"
+
+    def c(self) -> L.Coarse:
+        return L.Coarse(L.PR_G_SCHEME, self.dt, self.steps, _PREC[self.prec])
+
+
+@dataclass
+class SolveStats:
+    iterations: int
+    n_converged: int
+    ic_iterations: np.ndarray
+    history: np.ndarray      # [iterations, n_ics] sup-norm updates
+    fine_ms: float
+    sweep_ms: float
+    status: int
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def _fields(u: torch.Tensor, n: int, name: str) -> int:
+    if not u.is_cuda or u.dtype != torch.float64 or not u.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous CUDA float64 tensor")
+    if u.dim() != 3 or u.shape[1] != n or u.shape[2] != n:
+        raise ValueError(f"{name} must have shape [B, {n}, {n}], got {tuple(u.shape)}")
+    return u.shape[0]
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def pr_fine_propagate(p: Problem, u_in: torch.Tensor, out_dtype=torch.float64,
+                      out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """F(U): p.steps fine steps on every field of u_in [B, N, N]."""
+    B = _fields(u_in, p.n, "u_in")
+    pc = p.c()
+    if out is None:
+        out = torch.empty((B, p.n, p.n), dtype=out_dtype, device=u_in.device)
+    need = L.lib().pr_fine_workspace_bytes(C.byref(pc), B)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, u_in.device)
+    L.check(L.lib().pr_fine_propagate(C.byref(pc), B, _ptr(u_in), _ptr(out), _DT[out.dtype],
+                                      _ptr(ws), ws.numel(), _stream(u_in.device)),
+            "pr_fine_propagate")
+    return out
+
+
+def pr_coarse_apply(p: Problem, g: Coarse, u_in: torch.Tensor,
+                    out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """G(U) with the numerical coarse step."""
+    B = _fields(u_in, p.n, "u_in")
+    pc, gc = p.c(), g.c()
+    if out is None:
+        out = torch.empty_like(u_in)
+    need = L.lib().pr_coarse_workspace_bytes(C.byref(pc), C.byref(gc), B)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, u_in.device)
+    L.check(L.lib().pr_coarse_apply(C.byref(pc), C.byref(gc), B, _ptr(u_in), _ptr(out),
+                                    _ptr(ws), ws.numel(), _stream(u_in.device)),
+            "pr_coarse_apply")
+    return out
+
+
+def pr_correct(f: torch.Tensor, g_new: torch.Tensor, g_old: torch.Tensor, u: torch.Tensor,
+               upd_max: torch.Tensor, update_cache: bool = True):
+    """u <- f + (g_new - g_old); upd_max <- max(upd_max, |change|); g_old <- g_new."""
+    B, n = u.shape[0], u.shape[-1]
+    for t, nm in ((g_new, "g_new"), (g_old, "g_old"), (u, "u")):
+        _fields(t, n, nm)
+    if f.shape != u.shape or f.dtype not in _DT or not f.is_contiguous():
+        raise TypeError("f must be a contiguous float64/float32 tensor shaped like u")
+    if upd_max.dtype != torch.float64 or upd_max.numel() != B:
+        raise TypeError("upd_max must be float64[B]")
+    L.check(L.lib().pr_correct(B, n, _ptr(f), _DT[f.dtype], _ptr(g_new), _ptr(g_old), _ptr(u),
+                               _ptr(upd_max), int(update_cache), _stream(u.device)),
+            "pr_correct")
+    return u
+
+
+def pr_solve(p: Problem, g: Coarse, u0: torch.Tensor, n_slices: int, tol: float,
+             max_iter: Optional[int] = None, U: Optional[torch.Tensor] = None,
+             ws: Optional[torch.Tensor] = None, allow_not_converged: bool = False):
+    """Algorithm 2 on every IC of u0 [B, N, N]; returns (U [B, s+1, N, N], stats)."""
+    B = _fields(u0, p.n, "u0")
+    pc, gc = p.c(), g.c()
+    max_iter = n_slices if max_iter is None else int(max_iter)
+    if U is None:
+        U = torch.empty((B, n_slices + 1, p.n, p.n), dtype=torch.float64, device=u0.device)
+    need = L.lib().pr_solve_workspace_bytes(C.byref(pc), C.byref(gc), B, n_slices)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, u0.device)
+    ic_it = np.zeros(B, dtype=np.int32)
+    hist = np.zeros(max(max_iter, 1) * B, dtype=np.float64)
+    st = L.Stats(0, 0, ic_it.ctypes.data_as(C.POINTER(C.c_int32)),
+                 hist.ctypes.data_as(C.POINTER(C.c_double)), 0.0, 0.0)
+    allow = (L.PR_OK, L.PR_NOT_CONVERGED) if allow_not_converged else (L.PR_OK,)
+    status = L.check(L.lib().pr_solve(C.byref(pc), C.byref(gc), B, n_slices, _ptr(u0), _ptr(U),
+                                      float(tol), max_iter, C.byref(st), _ptr(ws), ws.numel(),
+                                      _stream(u0.device)),
+                     "pr_solve", allow)
+    k = st.iterations
+    stats = SolveStats(k, st.n_converged, ic_it.copy(), hist[:k * B].reshape(k, B).copy(),
+                       st.fine_ms, st.sweep_ms, status)
+    return U, stats
+
+
+def pr_serial_fine(p: Problem, u0: torch.Tensor, n_slices: int,
+                   U: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """Serial fine solve [U_0, F(U_0), ...] -> U [B, s+1, N, N] (blocking)."""
+    B = _fields(u0, p.n, "u0")
+    pc = p.c()
+    if U is None:
+        U = torch.empty((B, n_slices + 1, p.n, p.n), dtype=torch.float64, device=u0.device)
+    need = L.lib().pr_serial_workspace_bytes(C.byref(pc), B)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, u0.device)
+    L.check(L.lib().pr_serial_fine(C.byref(pc), B, n_slices, _ptr(u0), _ptr(U), _ptr(ws),
+                                   ws.numel(), _stream(u0.device)), "pr_serial_fine")
+    return U
+
+
+def pr_abi_version() -> int:
+    return L.lib().pr_abi_version()

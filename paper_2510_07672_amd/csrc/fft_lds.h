@@ -1,0 +1,165 @@
+// Device building blocks: complex arithmetic, radix-2/4/8 butterflies, a
+// batched Stockham FFT over lines held in LDS, and block reductions.
+//
+// The 2-D solve of the semi-implicit step (a real 2-D DFT, a division by
+// the symbol of ((1 + S dt) I - dt eps^2 Lap_h), and the inverse DFT) is
+// built from these length-N complex transforms.
+//
+// FFT scheme.  N = 8^a * {1, 2, 4}; stages run radix 8 first and the
+// leftover 2 or 4 last.  Each stage is the self-sorting Stockham step: for
+// butterfly j of a line (j < N/R) the R inputs sit at j + r N/R, are
+// multiplied by w^(r k), k = j mod Ns (Ns = product of earlier radices,
+// w = exp(sign 2 pi i / (Ns R))), transformed by a radix-R DFT, and land at
+// (j / Ns) Ns R + k + r Ns.  Output is in natural order after the last
+// stage.  The transform is in place in LDS: every thread reads its eight
+// elements into registers, the block synchronises, then every thread
+// writes.  So a block of NT threads handles NT * 8 complex elements at a
+// time, and the panel it works on must hold exactly that many.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pr {
+
+template <typename T> struct cpx_sel;
+template <> struct cpx_sel<float> { using type = float2; };
+template <> struct cpx_sel<double> { using type = double2; };
+template <typename T> using cpx = typename cpx_sel<T>::type;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by sign * i
+template <int SIGN, typename C> __device__ __forceinline__ C cmul_i(C a) {
+  if constexpr (SIGN > 0) return C{-a.y, a.x};
+  else return C{a.y, -a.x};
+}
+
+template <int SIGN, typename C>
+__device__ __forceinline__ void dft2(C& a, C& b) {
+  C t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <int SIGN, typename C>
+__device__ __forceinline__ void dft4(C& v0, C& v1, C& v2, C& v3) {
+  C t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3);
+  C t3 = cmul_i<SIGN>(csub(v1, v3));
+  v0 = cadd(t0, t2);
+  v2 = csub(t0, t2);
+  v1 = cadd(t1, t3);
+  v3 = csub(t1, t3);
+}
+
+template <int SIGN, typename C>
+__device__ __forceinline__ void dft8(C* v) {
+  using T = decltype(v[0].x);
+  C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<SIGN>(e0, e1, e2, e3);
+  dft4<SIGN>(o0, o1, o2, o3);
+  const T c = (T)0.70710678118654752440;
+  const T s = (T)SIGN;
+  // o_k *= exp(sign 2 pi i k / 8)
+  o1 = C{c * (o1.x - s * o1.y), c * (o1.y + s * o1.x)};
+  o2 = cmul_i<SIGN>(o2);
+  o3 = C{-c * (o3.x + s * o3.y), c * (s * o3.x - o3.y)};
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+template <int R, int SIGN, typename C>
+__device__ __forceinline__ void dft_r(C* v) {
+  if constexpr (R == 8) dft8<SIGN>(v);
+  else if constexpr (R == 4) dft4<SIGN>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 2) dft2<SIGN>(v[0], v[1]);
+}
+
+// Panel layout: element e of line l lives at l * LS + e.
+template <int LS> struct LinePanel {
+  __device__ __forceinline__ int operator()(int line, int e) const { return line * LS + e; }
+};
+
+// One Stockham stage over LINES lines of length N held in `buf`.
+// tw[t] = exp(-2 pi i t / N) (forward table); SIGN = -1 forward, +1 inverse.
+template <int N, int R, int NS, int SIGN, int NT, typename T, class Lay>
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid) {
+  constexpr int NB = N / R;    // butterflies per line
+  constexpr int BPT = 8 / R;   // butterflies per thread
+  cpx<T> v[8];
+  int line[BPT], jj[BPT];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = tid + q * NT;
+    line[q] = b / NB;
+    jj[q] = b % NB;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q * R + r] = buf[lay(line[q], jj[q] + r * NB)];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int k = jj[q] % NS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cpx<T> w = tw[r * k * (N / (NS * R))];
+        if constexpr (SIGN > 0) w.y = -w.y;
+        v[q * R + r] = cmul(v[q * R + r], w);
+      }
+    }
+    dft_r<R, SIGN>(&v[q * R]);
+    const int base = (jj[q] / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[lay(line[q], base + r * NS)] = v[q * R + r];
+  }
+  __syncthreads();
+}
+
+template <int N, int NS, int SIGN, int NT, typename T, class Lay>
+__device__ __forceinline__ void fft_from(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid) {
+  if constexpr (NS < N) {
+    constexpr int R = (N / NS) >= 8 ? 8 : (N / NS);
+    fft_stage<N, R, NS, SIGN, NT, T>(buf, tw, lay, tid);
+    fft_from<N, NS * R, SIGN, NT, T>(buf, tw, lay, tid);
+  }
+}
+
+// Unnormalised length-N DFT of every line in the panel, in place.
+// Requires NT * 8 == (number of lines) * N, and a __syncthreads() before
+// the call if `buf` was just written.
+template <int N, int SIGN, int NT, typename T, class Lay>
+__device__ __forceinline__ void fft_lines(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid) {
+  fft_from<N, 1, SIGN, NT, T>(buf, tw, lay, tid);
+}
+
+// Deterministic block sum of one double per thread (fixed tree order).
+// `red` is LDS scratch of at least NT/64 + 1 doubles.  Result valid in
+// thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red, int tid) {
+  constexpr int W = NT < 64 ? NT : 64;
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  if constexpr (NT <= 64) {
+    return v;
+  } else {
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (tid == 0) {
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) s += red[w];
+    }
+    __syncthreads();
+    return s;
+  }
+}
+
+}  // namespace pr

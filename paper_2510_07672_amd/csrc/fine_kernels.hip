@@ -1,0 +1,374 @@
+// HIP kernels of the fine propagator (the stabilised semi-implicit step,
+// Section 3.1 / eq. fine_operator), the Parareal correction and its norm
+// (Section 3.3, Algorithm 2).
+//
+// One step maps u to u+ with
+//     ((1 + S dt) I - dt eps^2 Lap_h) u+ = (1 + S dt) u + dt (f(u) - m),
+// f(u) = u - u^3, m = 0 (classic) or the grid mean of f(u) (conservative).
+// In Fourier space the operator is the scalar (1 + S dt) + dt eps^2 mu_k,
+// mu_k = (4/h^2)(sin^2(pi kx/N) + sin^2(pi ky/N)) (5-point stencil).
+//
+// Spectral layout of a field between passes ("row spectra, column-major"):
+// R_r[kx] is the length-N DFT of real row r.  Only kx = 0..N/2 is kept;
+// columns kx = 1..N/2-1 are stored as complex column c = kx, and the two
+// real columns kx = 0 and kx = N/2 share column c = 0 as R_r[0] + i R_r[N/2].
+// So a field is N/2 columns of N complex values, spec[c][r], contiguous per
+// column: exactly N*N real numbers.
+//
+// Row pass   (one block per tile of TR rows of one field): rows 2j and 2j+1
+//   are carried as one complex row z = row_2j + i row_2j+1.  Rebuild Z from
+//   the stored half spectra, inverse FFT, apply the pointwise right-hand
+//   side r = (1 + S dt) v + dt f(v) (and sum f(v) in FP64 for the mass
+//   multiplier), forward FFT, split Z back into R_2j and R_2j+1, store.
+// Column pass (one block per CT columns of one field): forward column FFT,
+//   multiply by 1 / (N^2 ((1 + S dt) + dt eps^2 mu_k)) (the 1/N^2 undoes
+//   both unnormalised inverse transforms), subtract dt * sum f from the DC
+//   bin in the conservative model (dt * N^2 * m), inverse column FFT.
+// The first row pass reads the real state instead of spectra; the last
+// writes the real state and does no forward transform.  Each step is one
+// column pass plus one row pass: two read+write sweeps of the field.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+#include "internal.h"
+
+namespace pr {
+
+// ------------------------------------------------------------------ tables
+
+__global__ void k_tables(int n, double2* tw64, float2* tw32, double* s2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    double s, c;
+    sincospi(2.0 * (double)t / (double)n, &s, &c);
+    tw64[t] = double2{c, -s};
+    tw32[t] = float2{(float)c, (float)-s};
+    const double sn = sinpi((double)t / (double)n);
+    s2[t] = sn * sn;
+  }
+}
+
+// --------------------------------------------------------------- row pass
+
+template <int N, typename T, int MODE>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
+    const double* __restrict__ in_base, const int64_t* __restrict__ in_offs,
+    cpx<T>* __restrict__ spec, double* __restrict__ partials,
+    void* __restrict__ out_base, const int64_t* __restrict__ out_offs,
+    int out_f32, const cpx<T>* __restrict__ tw_g, StepParams sp) {
+  using C = cpx<T>;
+  using Cfg = RowCfg<N, T>;
+  constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
+  constexpr int LS = N;
+  __shared__ C panel[PAIRS * LS];
+  __shared__ C tw[N];
+  __shared__ double red[NT / 64 + 1];
+
+  const int tid = threadIdx.x;
+  const int64_t f = blockIdx.x / TILES;
+  const int tile = blockIdx.x % TILES;
+  const int r0 = tile * TR;
+  for (int t = tid; t < N; t += NT) tw[t] = tw_g[t];
+  C* S = spec + f * (int64_t)(N / 2) * N;
+  const T a = (T)sp.a, dt = (T)sp.dt;
+  double fsum = 0.0;
+
+  if constexpr (MODE == ROW_FIRST) {
+    // stage-in: real rows (FP64) rounded to T, right-hand side
+    const double* u = in_base + (in_offs ? in_offs[f] : f * (int64_t)N * N);
+    for (int e = tid; e < PAIRS * N; e += NT) {
+      const int p = e / N, x = e % N;
+      const T v0 = (T)u[(int64_t)(r0 + 2 * p) * N + x];
+      const T v1 = (T)u[(int64_t)(r0 + 2 * p + 1) * N + x];
+      const T f0 = v0 - v0 * v0 * v0, f1 = v1 - v1 * v1 * v1;
+      fsum += (double)f0 + (double)f1;
+      panel[p * LS + x] = C{a * v0 + dt * f0, a * v1 + dt * f1};
+    }
+    __syncthreads();
+  } else {
+    // rebuild Z_j[kx] = R_2j[kx] + i R_2j+1[kx] for kx = 0..N-1
+    for (int e = tid; e < PAIRS * (N / 2); e += NT) {
+      const int p = e % PAIRS, c = e / PAIRS;
+      const C A = S[(int64_t)c * N + r0 + 2 * p];
+      const C B = S[(int64_t)c * N + r0 + 2 * p + 1];
+      if (c == 0) {
+        panel[p * LS] = C{A.x, B.x};
+        panel[p * LS + N / 2] = C{A.y, B.y};
+      } else {
+        panel[p * LS + c] = C{A.x - B.y, A.y + B.x};
+        panel[p * LS + N - c] = C{A.x + B.y, B.x - A.y};
+      }
+    }
+    __syncthreads();
+    fft_lines<N, +1, NT, T>(panel, tw, LinePanel<LS>{}, tid);
+    if constexpr (MODE == ROW_LAST) {
+      const int64_t ob = out_offs ? out_offs[f] : f * (int64_t)N * N;
+      for (int e = tid; e < PAIRS * N; e += NT) {
+        const int p = e / N, x = e % N;
+        const C z = panel[p * LS + x];
+        const int64_t i0 = ob + (int64_t)(r0 + 2 * p) * N + x;
+        if (out_f32) {
+          float* o = (float*)out_base;
+          o[i0] = (float)z.x;
+          o[i0 + N] = (float)z.y;
+        } else {
+          double* o = (double*)out_base;
+          o[i0] = (double)z.x;
+          o[i0 + N] = (double)z.y;
+        }
+      }
+      return;
+    }
+    for (int e = tid; e < PAIRS * N; e += NT) {
+      const C z = panel[e];
+      const T v0 = z.x, v1 = z.y;
+      const T f0 = v0 - v0 * v0 * v0, f1 = v1 - v1 * v1 * v1;
+      fsum += (double)f0 + (double)f1;
+      panel[e] = C{a * v0 + dt * f0, a * v1 + dt * f1};
+    }
+    __syncthreads();
+  }
+
+  if (sp.conservative) {
+    const double s = block_sum<NT>(fsum, red, tid);
+    if (tid == 0) partials[f * TILES + tile] = s;
+  }
+  fft_lines<N, -1, NT, T>(panel, tw, LinePanel<LS>{}, tid);
+
+  // split Z back into the two rows' half spectra and store column-major
+  for (int e = tid; e < PAIRS * (N / 2); e += NT) {
+    const int p = e % PAIRS, c = e / PAIRS;
+    C A, B;
+    if (c == 0) {
+      const C z0 = panel[p * LS], zn = panel[p * LS + N / 2];
+      A = C{z0.x, zn.x};
+      B = C{z0.y, zn.y};
+    } else {
+      const C z = panel[p * LS + c], w = panel[p * LS + N - c];
+      const T h = (T)0.5;
+      A = C{h * (z.x + w.x), h * (z.y - w.y)};
+      B = C{h * (z.y + w.y), h * (w.x - z.x)};
+    }
+    S[(int64_t)c * N + r0 + 2 * p] = A;
+    S[(int64_t)c * N + r0 + 2 * p + 1] = B;
+  }
+}
+
+// ------------------------------------------------------------ column pass
+
+template <int N, typename T>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col(
+    cpx<T>* __restrict__ spec, const double* __restrict__ partials,
+    const cpx<T>* __restrict__ tw_g, const double* __restrict__ s2_g, StepParams sp) {
+  using C = cpx<T>;
+  constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
+  constexpr int TILES = RowCfg<N, T>::TILES;
+  constexpr int EPT = CT * N / NT;  // = 8
+  __shared__ C panel[CT * N];
+  __shared__ C tw[N];
+  __shared__ double s2[N];
+  __shared__ double corr_sh;
+
+  const int tid = threadIdx.x;
+  const int64_t f = blockIdx.x / BLK;
+  const int c0 = (blockIdx.x % BLK) * CT;
+  C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
+  for (int t = tid; t < N; t += NT) {
+    tw[t] = tw_g[t];
+    s2[t] = s2_g[t];
+  }
+  for (int e = tid; e < CT * N; e += NT) panel[e] = P[e];
+  if (tid == 0) {
+    double corr = 0.0;
+    if (c0 == 0 && sp.conservative) {
+      double s = 0.0;
+      for (int t = 0; t < TILES; ++t) s += partials[f * TILES + t];
+      corr = sp.dt * s;  // dt * N^2 * mean f
+    }
+    corr_sh = corr;
+  }
+  __syncthreads();
+  fft_lines<N, -1, NT, T>(panel, tw, LinePanel<N>{}, tid);
+
+  const double corr = corr_sh;
+  C vals[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = tid + q * NT;
+    const int line = e / N, ky = e % N, col = c0 + line;
+    C z = panel[e];
+    if (col == 0) {
+      // packed column: z = A + iB with A the kx = 0 and B the kx = N/2
+      // column spectra (both Hermitian in ky); scale A and B separately
+      const int kr = (N - ky) % N;
+      C w = panel[kr];
+      if (ky == 0) z.x = (T)((double)z.x - corr);
+      if (kr == 0) w.x = (T)((double)w.x - corr);
+      const double d0 = sp.inv_n2 / (sp.a + sp.lam * (s2[0] + s2[ky]));
+      const double dn = sp.inv_n2 / (sp.a + sp.lam * (s2[N / 2] + s2[ky]));
+      const T pp = (T)(0.5 * (d0 + dn)), mm = (T)(0.5 * (d0 - dn));
+      z = C{z.x * pp + w.x * mm, z.y * pp - w.y * mm};
+    } else {
+      const T d = (T)(sp.inv_n2 / (sp.a + sp.lam * (s2[col] + s2[ky])));
+      z = C{z.x * d, z.y * d};
+    }
+    vals[q] = z;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) panel[tid + q * NT] = vals[q];
+  __syncthreads();
+  fft_lines<N, +1, NT, T>(panel, tw, LinePanel<N>{}, tid);
+  for (int e = tid; e < CT * N; e += NT) P[e] = panel[e];
+}
+
+// ------------------------------------------------------------- launchers
+
+template <int N, typename T>
+static hipError_t launch_steps_n(const StepJob& job, hipStream_t st) {
+  using RC = RowCfg<N, T>;
+  using CC = ColCfg<N>;
+  const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)job.ws.tw64 : (const void*)job.ws.tw32);
+  cpx<T>* spec = (cpx<T>*)job.ws.spec;
+  const dim3 grow((unsigned)(job.nfields * RC::TILES)), brow(RC::NT);
+  const dim3 gcol((unsigned)(job.nfields * CC::BLOCKS)), bcol(CC::NT);
+  k_row<N, T, ROW_FIRST><<<grow, brow, 0, st>>>(job.in_base, job.in_offs, spec, job.ws.partials,
+                                                nullptr, nullptr, 0, tw, job.sp);
+  for (int s = 0; s < job.steps; ++s) {
+    k_col<N, T><<<gcol, bcol, 0, st>>>(spec, job.ws.partials, tw, job.ws.s2, job.sp);
+    if (s + 1 < job.steps)
+      k_row<N, T, ROW_MID><<<grow, brow, 0, st>>>(nullptr, nullptr, spec, job.ws.partials,
+                                                  nullptr, nullptr, 0, tw, job.sp);
+  }
+  k_row<N, T, ROW_LAST><<<grow, brow, 0, st>>>(nullptr, nullptr, spec, job.ws.partials,
+                                               job.out_base, job.out_offs, job.out_f32, tw, job.sp);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_steps_t(const StepJob& job, hipStream_t st) {
+  switch (job.n) {
+    case 16: return launch_steps_n<16, T>(job, st);
+    case 32: return launch_steps_n<32, T>(job, st);
+    case 64: return launch_steps_n<64, T>(job, st);
+    case 128: return launch_steps_n<128, T>(job, st);
+    case 256: return launch_steps_n<256, T>(job, st);
+    case 512: return launch_steps_n<512, T>(job, st);
+    case 1024: return launch_steps_n<1024, T>(job, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_tables(int n, const FineWs& ws, hipStream_t st) {
+  k_tables<<<dim3((n + 255) / 256), dim3(256), 0, st>>>(n, ws.tw64, ws.tw32, ws.s2);
+  return hipGetLastError();
+}
+
+hipError_t launch_steps(const StepJob& job, hipStream_t st) {
+  if (job.nfields <= 0 || job.steps <= 0) return hipSuccess;
+  return job.f32 ? launch_steps_t<float>(job, st) : launch_steps_t<double>(job, st);
+}
+
+int row_tiles(int n, bool f32) {
+  switch (n) {
+#define PR_CASE(NN) \
+  case NN: return f32 ? RowCfg<NN, float>::TILES : RowCfg<NN, double>::TILES;
+    PR_CASE(16) PR_CASE(32) PR_CASE(64) PR_CASE(128) PR_CASE(256) PR_CASE(512) PR_CASE(1024)
+#undef PR_CASE
+    default: return 0;
+  }
+}
+
+// ------------------------------------------------- correction and norm
+
+template <typename TF>
+__global__ __launch_bounds__(256) void k_correct(
+    int64_t n2, const TF* __restrict__ fb, const int64_t* __restrict__ f_offs,
+    const double* __restrict__ gnb, const int64_t* __restrict__ gn_offs,
+    double* __restrict__ gob, const int64_t* __restrict__ go_offs,
+    double* __restrict__ ub, const int64_t* __restrict__ u_offs,
+    unsigned long long* __restrict__ upd, const int32_t* __restrict__ upd_idx,
+    int update_cache, int blocks_per_field) {
+  const int64_t fld = blockIdx.x / blocks_per_field;
+  const int64_t part = blockIdx.x % blocks_per_field;
+  const TF* fp = fb + (f_offs ? f_offs[fld] : fld * n2);
+  const double* gn = gnb + (gn_offs ? gn_offs[fld] : fld * n2);
+  double* go = gob + (go_offs ? go_offs[fld] : fld * n2);
+  double* u = ub + (u_offs ? u_offs[fld] : fld * n2);
+  unsigned long long m = 0;
+  const int64_t stride = (int64_t)blocks_per_field * blockDim.x;
+  for (int64_t i = part * blockDim.x + threadIdx.x; i < n2; i += stride) {
+    const double g1 = gn[i];
+    // U^k_{j+1} = F(U^{k-1}_j) + (G(U^k_j) - G(U^{k-1}_j)), in this order
+    const double un = (double)fp[i] + (g1 - go[i]);
+    const double d = fabs(un - u[i]);
+    u[i] = un;
+    if (update_cache) go[i] = g1;
+    // |d| >= 0, so its bit pattern orders like its value; NaN (sign
+    // cleared) sorts above +Inf and therefore survives the max
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(d);
+    m = bits > m ? bits : m;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long t = __shfl_xor(m, o, 64);
+    m = t > m ? t : m;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(&upd[upd_idx ? upd_idx[fld] : fld], m);
+}
+
+hipError_t launch_correct(const CorrectJob& j, hipStream_t st) {
+  if (j.nfields <= 0) return hipSuccess;
+  const int64_t n2 = (int64_t)j.n * j.n;
+  int bpf = (int)((n2 + 256 * 8 - 1) / (256 * 8));
+  if (bpf < 1) bpf = 1;
+  const dim3 grid((unsigned)(j.nfields * bpf)), block(256);
+  if (j.f_f32)
+    k_correct<float><<<grid, block, 0, st>>>(n2, (const float*)j.f, j.f_offs, j.g_new, j.gn_offs,
+                                             j.g_old, j.go_offs, j.u, j.u_offs, j.upd, j.upd_idx,
+                                             j.update_cache, bpf);
+  else
+    k_correct<double><<<grid, block, 0, st>>>(n2, (const double*)j.f, j.f_offs, j.g_new, j.gn_offs,
+                                              j.g_old, j.go_offs, j.u, j.u_offs, j.upd, j.upd_idx,
+                                              j.update_cache, bpf);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- copies
+
+__global__ __launch_bounds__(256) void k_copy_fields(int64_t n2, const double* __restrict__ src,
+                                                     const int64_t* __restrict__ s_offs,
+                                                     double* __restrict__ dst,
+                                                     const int64_t* __restrict__ d_offs,
+                                                     int blocks_per_field) {
+  const int64_t fld = blockIdx.x / blocks_per_field;
+  const int64_t part = blockIdx.x % blocks_per_field;
+  const double* s = src + (s_offs ? s_offs[fld] : fld * n2);
+  double* d = dst + (d_offs ? d_offs[fld] : fld * n2);
+  const int64_t stride = (int64_t)blocks_per_field * blockDim.x;
+  for (int64_t i = part * blockDim.x + threadIdx.x; i < n2; i += stride) d[i] = s[i];
+}
+
+hipError_t launch_copy(int64_t nfields, int n, const double* src, const int64_t* s_offs,
+                       double* dst, const int64_t* d_offs, hipStream_t st) {
+  if (nfields <= 0) return hipSuccess;
+  const int64_t n2 = (int64_t)n * n;
+  int bpf = (int)((n2 + 256 * 8 - 1) / (256 * 8));
+  if (bpf < 1) bpf = 1;
+  k_copy_fields<<<dim3((unsigned)(nfields * bpf)), dim3(256), 0, st>>>(n2, src, s_offs, dst,
+                                                                       d_offs, bpf);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill_u64<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace pr

@@ -1,0 +1,85 @@
+// Internal interface between the C ABI (api.hip) and the kernels
+// (fine_kernels.hip).  Not installed; include/pr.h is the public header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pr {
+
+enum { ROW_FIRST = 0, ROW_MID = 1, ROW_LAST = 2 };
+
+// Row pass tiling: TR rows (TR/2 complex row pairs) of one field per block,
+// one radix-8 group of eight elements per thread per FFT stage.  TR is the
+// smallest even count that gives >= 256 threads and >= 128-byte contiguous
+// runs per spectral column, capped at N.
+template <int N, typename T> struct RowCfg {
+  static constexpr int kThreads = 4096 / N;
+  static constexpr int kCoalesce = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int kT0 = kThreads > kCoalesce ? kThreads : kCoalesce;
+  static constexpr int TR = kT0 < N ? kT0 : N;
+  static constexpr int PAIRS = TR / 2;
+  static constexpr int NT = PAIRS * N / 8;
+  static constexpr int TILES = N / TR;
+};
+
+// Column pass tiling: CT whole columns of one field per block.
+template <int N> struct ColCfg {
+  static constexpr int kC0 = 2048 / N;
+  static constexpr int CT = kC0 < N / 2 ? kC0 : N / 2;
+  static constexpr int NT = CT * N / 8;
+  static constexpr int BLOCKS = (N / 2) / CT;
+};
+
+struct StepParams {
+  double a;       // 1 + S dt
+  double dt;      // step
+  double lam;     // dt eps^2 4 / h^2
+  double inv_n2;  // 1 / N^2
+  int conservative;
+};
+
+// Per-call device workspace of the step kernels.
+struct FineWs {
+  double2* tw64;     // [N]  exp(-2 pi i t / N)
+  float2* tw32;      // [N]  same, rounded
+  double* s2;        // [N]  sin^2(pi t / N)
+  double* partials;  // [nfields * row tiles] FP64 partial sums of f
+  void* spec;        // [nfields][N/2][N] complex in the step precision
+};
+
+struct StepJob {
+  int n;
+  bool f32;
+  int steps;
+  int64_t nfields;
+  StepParams sp;
+  const double* in_base;     // field i at in_base + (in_offs ? in_offs[i] : i N^2)
+  const int64_t* in_offs;    // device or null
+  void* out_base;            // field i at out_base + (out_offs ? out_offs[i] : i N^2)
+  const int64_t* out_offs;   // device or null
+  int out_f32;
+  FineWs ws;
+};
+
+struct CorrectJob {
+  int64_t nfields;
+  int n;
+  const void* f; const int64_t* f_offs; int f_f32;
+  const double* g_new; const int64_t* gn_offs;
+  double* g_old; const int64_t* go_offs;
+  double* u; const int64_t* u_offs;
+  unsigned long long* upd; const int32_t* upd_idx;
+  int update_cache;
+};
+
+hipError_t launch_tables(int n, const FineWs& ws, hipStream_t st);
+hipError_t launch_steps(const StepJob& job, hipStream_t st);
+hipError_t launch_correct(const CorrectJob& job, hipStream_t st);
+hipError_t launch_copy(int64_t nfields, int n, const double* src, const int64_t* s_offs,
+                       double* dst, const int64_t* d_offs, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v,
+                           hipStream_t st);
+int row_tiles(int n, bool f32);
+
+}  // namespace pr
