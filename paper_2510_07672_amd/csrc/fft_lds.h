@@ -15,10 +15,22 @@
 // elements into registers, the block synchronises, then every thread
 // writes.  So a block of NT threads handles NT * 8 complex elements at a
 // time, and the panel it works on must hold exactly that many.
+//
+// The first stage may take its inputs from a prologue functor instead of
+// LDS (e.g. straight from global memory, whose addresses j + r N/R are
+// consecutive across threads), and the last stage may hand its outputs to
+// an epilogue functor that either modifies them before the LDS write or
+// stores them to global memory itself (addresses j + r N/R again).
+//
+// LDS layout.  Element e of line l sits at l * LS + e + e / 8: one pad slot
+// after every eight elements, so the stride-8 writes of the first stage
+// and the stride-LS accesses across lines (LS odd) spread over the banks.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace pr {
 
@@ -81,17 +93,36 @@ __device__ __forceinline__ void dft_r(C* v) {
   else if constexpr (R == 2) dft2<SIGN>(v[0], v[1]);
 }
 
-// Panel layout: element e of line l lives at l * LS + e.
-template <int LS> struct LinePanel {
-  __device__ __forceinline__ int operator()(int line, int e) const { return line * LS + e; }
+// Padded line stride for lines of N elements: N + N/8 pad slots, made odd.
+template <int N> struct PadLS {
+  static constexpr int value = N + N / 8 + 1;
 };
 
-// One Stockham stage over LINES lines of length N held in `buf`.
-// tw[t] = exp(-2 pi i t / N) (forward table); SIGN = -1 forward, +1 inverse.
-template <int N, int R, int NS, int SIGN, int NT, typename T, class Lay>
-__device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid) {
+// Panel layout: element e of line l at l * LS + e + e / 8.
+template <int LS> struct LinePanel {
+  __device__ __forceinline__ int operator()(int line, int e) const { return line * LS + e + (e >> 3); }
+};
+
+// Hooks.  A prologue provides `C load(int line, int e)`; an epilogue
+// provides `void apply(int line, int e, C& v)` and a constexpr
+// kWritesLds telling whether the (possibly modified) value is still
+// written to LDS afterwards.
+struct NoPro {};
+struct NoEpi {
+  static constexpr bool kWritesLds = true;
+};
+
+// One Stockham stage over the panel.  tw[t] = exp(-2 pi i t / N) (forward
+// table); SIGN = -1 forward, +1 inverse.
+template <int N, int R, int NS, int SIGN, int NT, typename T, class Lay, class Pro, class Epi>
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid,
+                                          Pro& pro, Epi& epi) {
   constexpr int NB = N / R;    // butterflies per line
   constexpr int BPT = 8 / R;   // butterflies per thread
+  constexpr bool kFirst = NS == 1;
+  constexpr bool kLast = NS * R == N;
+  constexpr bool kFromPro = kFirst && !std::is_same<Pro, NoPro>::value;
+  constexpr bool kToLds = !kLast || Epi::kWritesLds;
   cpx<T> v[8];
   int line[BPT], jj[BPT];
 #pragma unroll
@@ -100,9 +131,12 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay
     line[q] = b / NB;
     jj[q] = b % NB;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[q * R + r] = buf[lay(line[q], jj[q] + r * NB)];
+    for (int r = 0; r < R; ++r) {
+      if constexpr (kFromPro) v[q * R + r] = pro.load(line[q], jj[q] + r * NB);
+      else v[q * R + r] = buf[lay(line[q], jj[q] + r * NB)];
+    }
   }
-  __syncthreads();
+  if constexpr (kToLds) __syncthreads();
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
     const int k = jj[q] % NS;
@@ -117,26 +151,32 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay
     dft_r<R, SIGN>(&v[q * R]);
     const int base = (jj[q] / NS) * NS * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[lay(line[q], base + r * NS)] = v[q * R + r];
+    for (int r = 0; r < R; ++r) {
+      if constexpr (kLast && !std::is_same<Epi, NoEpi>::value) epi.apply(line[q], base + r * NS, v[q * R + r]);
+      if constexpr (kToLds) buf[lay(line[q], base + r * NS)] = v[q * R + r];
+    }
   }
-  __syncthreads();
+  if constexpr (kToLds) __syncthreads();
 }
 
-template <int N, int NS, int SIGN, int NT, typename T, class Lay>
-__device__ __forceinline__ void fft_from(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid) {
+template <int N, int NS, int SIGN, int NT, typename T, class Lay, class Pro, class Epi>
+__device__ __forceinline__ void fft_from(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid, Pro& pro,
+                                         Epi& epi) {
   if constexpr (NS < N) {
     constexpr int R = (N / NS) >= 8 ? 8 : (N / NS);
-    fft_stage<N, R, NS, SIGN, NT, T>(buf, tw, lay, tid);
-    fft_from<N, NS * R, SIGN, NT, T>(buf, tw, lay, tid);
+    fft_stage<N, R, NS, SIGN, NT, T>(buf, tw, lay, tid, pro, epi);
+    fft_from<N, NS * R, SIGN, NT, T>(buf, tw, lay, tid, pro, epi);
   }
 }
 
 // Unnormalised length-N DFT of every line in the panel, in place.
-// Requires NT * 8 == (number of lines) * N, and a __syncthreads() before
-// the call if `buf` was just written.
-template <int N, int SIGN, int NT, typename T, class Lay>
-__device__ __forceinline__ void fft_lines(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid) {
-  fft_from<N, 1, SIGN, NT, T>(buf, tw, lay, tid);
+// Requires NT * 8 == (number of lines) * N.  Unless a prologue supplies
+// the inputs, `buf` must be complete (synchronised) on entry.  On exit the
+// block is synchronised if the last stage wrote LDS.
+template <int N, int SIGN, int NT, typename T, class Lay, class Pro = NoPro, class Epi = NoEpi>
+__device__ __forceinline__ void fft_lines(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid,
+                                          Pro pro = Pro{}, Epi epi = Epi{}) {
+  fft_from<N, 1, SIGN, NT, T>(buf, tw, lay, tid, pro, epi);
 }
 
 // Deterministic block sum of one double per thread (fixed tree order).

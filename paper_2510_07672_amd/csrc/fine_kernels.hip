@@ -50,6 +50,57 @@ __global__ void k_tables(int n, double2* tw64, float2* tw32, double* s2) {
 
 // --------------------------------------------------------------- row pass
 
+// Right-hand side of the step, r = (1 + S dt) v + dt f(v), on the two rows
+// carried by one complex value; f is also summed in FP64.
+template <typename T>
+__device__ __forceinline__ cpx<T> rhs_pair(cpx<T> z, T a, T dt, double& fsum) {
+  const T f0 = z.x - z.x * z.x * z.x, f1 = z.y - z.y * z.y * z.y;
+  fsum += (double)f0 + (double)f1;
+  return cpx<T>{a * z.x + dt * f0, a * z.y + dt * f1};
+}
+
+// First forward stage reads rows r0+2p and r0+2p+1 of the real FP64 state,
+// rounds them to T and forms the right-hand side.
+template <int N, typename T> struct RealRowsPro {
+  const double* u;
+  int r0;
+  T a, dt;
+  double* fsum;
+  __device__ __forceinline__ cpx<T> load(int p, int x) const {
+    const cpx<T> z{(T)u[(int64_t)(r0 + 2 * p) * N + x], (T)u[(int64_t)(r0 + 2 * p + 1) * N + x]};
+    return rhs_pair<T>(z, a, dt, *fsum);
+  }
+};
+
+// Last inverse stage: right-hand side of the next step, kept in LDS.
+template <typename T> struct RhsEpi {
+  static constexpr bool kWritesLds = true;
+  T a, dt;
+  double* fsum;
+  __device__ __forceinline__ void apply(int, int, cpx<T>& v) const { v = rhs_pair<T>(v, a, dt, *fsum); }
+};
+
+// Last inverse stage: the two real rows go straight to the output state.
+template <int N, typename T> struct RealRowsStore {
+  static constexpr bool kWritesLds = false;
+  void* out;
+  int64_t ob;
+  int r0;
+  int f32;
+  __device__ __forceinline__ void apply(int p, int x, cpx<T>& v) const {
+    const int64_t i0 = ob + (int64_t)(r0 + 2 * p) * N + x;
+    if (f32) {
+      float* o = (float*)out;
+      o[i0] = (float)v.x;
+      o[i0 + N] = (float)v.y;
+    } else {
+      double* o = (double*)out;
+      o[i0] = (double)v.x;
+      o[i0 + N] = (double)v.y;
+    }
+  }
+};
+
 template <int N, typename T, int MODE>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
     const double* __restrict__ in_base, const int64_t* __restrict__ in_offs,
@@ -59,7 +110,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
-  constexpr int LS = N;
+  constexpr int LS = PadLS<N>::value;
+  using Lay = LinePanel<LS>;
   __shared__ C panel[PAIRS * LS];
   __shared__ C tw[N];
   __shared__ double red[NT / 64 + 1];
@@ -68,23 +120,16 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   const int64_t f = blockIdx.x / TILES;
   const int tile = blockIdx.x % TILES;
   const int r0 = tile * TR;
+  const Lay lay{};
   for (int t = tid; t < N; t += NT) tw[t] = tw_g[t];
   C* S = spec + f * (int64_t)(N / 2) * N;
   const T a = (T)sp.a, dt = (T)sp.dt;
   double fsum = 0.0;
 
   if constexpr (MODE == ROW_FIRST) {
-    // stage-in: real rows (FP64) rounded to T, right-hand side
     const double* u = in_base + (in_offs ? in_offs[f] : f * (int64_t)N * N);
-    for (int e = tid; e < PAIRS * N; e += NT) {
-      const int p = e / N, x = e % N;
-      const T v0 = (T)u[(int64_t)(r0 + 2 * p) * N + x];
-      const T v1 = (T)u[(int64_t)(r0 + 2 * p + 1) * N + x];
-      const T f0 = v0 - v0 * v0 * v0, f1 = v1 - v1 * v1 * v1;
-      fsum += (double)f0 + (double)f1;
-      panel[p * LS + x] = C{a * v0 + dt * f0, a * v1 + dt * f1};
-    }
     __syncthreads();
+    fft_lines<N, -1, NT, T>(panel, tw, lay, tid, RealRowsPro<N, T>{u, r0, a, dt, &fsum});
   } else {
     // rebuild Z_j[kx] = R_2j[kx] + i R_2j+1[kx] for kx = 0..N-1
     for (int e = tid; e < PAIRS * (N / 2); e += NT) {
@@ -92,59 +137,38 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
       const C A = S[(int64_t)c * N + r0 + 2 * p];
       const C B = S[(int64_t)c * N + r0 + 2 * p + 1];
       if (c == 0) {
-        panel[p * LS] = C{A.x, B.x};
-        panel[p * LS + N / 2] = C{A.y, B.y};
+        panel[lay(p, 0)] = C{A.x, B.x};
+        panel[lay(p, N / 2)] = C{A.y, B.y};
       } else {
-        panel[p * LS + c] = C{A.x - B.y, A.y + B.x};
-        panel[p * LS + N - c] = C{A.x + B.y, B.x - A.y};
+        panel[lay(p, c)] = C{A.x - B.y, A.y + B.x};
+        panel[lay(p, N - c)] = C{A.x + B.y, B.x - A.y};
       }
     }
     __syncthreads();
-    fft_lines<N, +1, NT, T>(panel, tw, LinePanel<LS>{}, tid);
     if constexpr (MODE == ROW_LAST) {
       const int64_t ob = out_offs ? out_offs[f] : f * (int64_t)N * N;
-      for (int e = tid; e < PAIRS * N; e += NT) {
-        const int p = e / N, x = e % N;
-        const C z = panel[p * LS + x];
-        const int64_t i0 = ob + (int64_t)(r0 + 2 * p) * N + x;
-        if (out_f32) {
-          float* o = (float*)out_base;
-          o[i0] = (float)z.x;
-          o[i0 + N] = (float)z.y;
-        } else {
-          double* o = (double*)out_base;
-          o[i0] = (double)z.x;
-          o[i0 + N] = (double)z.y;
-        }
-      }
+      fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{},
+                              RealRowsStore<N, T>{out_base, ob, r0, out_f32});
       return;
     }
-    for (int e = tid; e < PAIRS * N; e += NT) {
-      const C z = panel[e];
-      const T v0 = z.x, v1 = z.y;
-      const T f0 = v0 - v0 * v0 * v0, f1 = v1 - v1 * v1 * v1;
-      fsum += (double)f0 + (double)f1;
-      panel[e] = C{a * v0 + dt * f0, a * v1 + dt * f1};
-    }
-    __syncthreads();
+    fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, RhsEpi<T>{a, dt, &fsum});
+    fft_lines<N, -1, NT, T>(panel, tw, lay, tid);
   }
-
   if (sp.conservative) {
     const double s = block_sum<NT>(fsum, red, tid);
     if (tid == 0) partials[f * TILES + tile] = s;
   }
-  fft_lines<N, -1, NT, T>(panel, tw, LinePanel<LS>{}, tid);
 
   // split Z back into the two rows' half spectra and store column-major
   for (int e = tid; e < PAIRS * (N / 2); e += NT) {
     const int p = e % PAIRS, c = e / PAIRS;
     C A, B;
     if (c == 0) {
-      const C z0 = panel[p * LS], zn = panel[p * LS + N / 2];
+      const C z0 = panel[lay(p, 0)], zn = panel[lay(p, N / 2)];
       A = C{z0.x, zn.x};
       B = C{z0.y, zn.y};
     } else {
-      const C z = panel[p * LS + c], w = panel[p * LS + N - c];
+      const C z = panel[lay(p, c)], w = panel[lay(p, N - c)];
       const T h = (T)0.5;
       A = C{h * (z.x + w.x), h * (z.y - w.y)};
       B = C{h * (z.y + w.y), h * (w.x - z.x)};
@@ -156,6 +180,39 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
 
 // ------------------------------------------------------------ column pass
 
+template <typename T> struct ColLoad {
+  const cpx<T>* P;
+  int n;
+  __device__ __forceinline__ cpx<T> load(int line, int e) const { return P[line * n + e]; }
+};
+
+template <typename T> struct ColStore {
+  static constexpr bool kWritesLds = false;
+  cpx<T>* P;
+  int n;
+  __device__ __forceinline__ void apply(int line, int e, cpx<T>& v) const { P[line * n + e] = v; }
+};
+
+// 1 / (N^2 ((1 + S dt) + dt eps^2 mu_k)) for bin (ky, kx)
+__device__ __forceinline__ double inv_symbol(const StepParams& sp, const double* s2, int ky, int kx) {
+  return sp.inv_n2 / (sp.a + sp.lam * (s2[kx] + s2[ky]));
+}
+
+// Last forward stage: divide every column except the packed one (c = 0).
+template <typename T> struct DivideEpi {
+  static constexpr bool kWritesLds = true;
+  const double* s2;
+  StepParams sp;
+  int c0;
+  __device__ __forceinline__ void apply(int line, int ky, cpx<T>& v) const {
+    const int col = c0 + line;
+    if (col != 0) {
+      const T d = (T)inv_symbol(sp, s2, ky, col);
+      v = cpx<T>{v.x * d, v.y * d};
+    }
+  }
+};
+
 template <int N, typename T>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col(
     cpx<T>* __restrict__ spec, const double* __restrict__ partials,
@@ -163,8 +220,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   using C = cpx<T>;
   constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
   constexpr int TILES = RowCfg<N, T>::TILES;
-  constexpr int EPT = CT * N / NT;  // = 8
-  __shared__ C panel[CT * N];
+  constexpr int LS = PadLS<N>::value;
+  constexpr int E0 = (N + NT - 1) / NT;  // packed-column elements per thread
+  using Lay = LinePanel<LS>;
+  __shared__ C panel[CT * LS];
   __shared__ C tw[N];
   __shared__ double s2[N];
   __shared__ double corr_sh;
@@ -172,12 +231,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / BLK;
   const int c0 = (blockIdx.x % BLK) * CT;
+  const Lay lay{};
   C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
   for (int t = tid; t < N; t += NT) {
     tw[t] = tw_g[t];
     s2[t] = s2_g[t];
   }
-  for (int e = tid; e < CT * N; e += NT) panel[e] = P[e];
   if (tid == 0) {
     double corr = 0.0;
     if (c0 == 0 && sp.conservative) {
@@ -188,38 +247,35 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
     corr_sh = corr;
   }
   __syncthreads();
-  fft_lines<N, -1, NT, T>(panel, tw, LinePanel<N>{}, tid);
+  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, ColLoad<T>{P, N}, DivideEpi<T>{s2, sp, c0});
 
-  const double corr = corr_sh;
-  C vals[EPT];
+  if (c0 == 0) {
+    // packed column: z = A + iB with A the kx = 0 and B the kx = N/2
+    // column spectra (both Hermitian in ky); scale A and B separately
+    const double corr = corr_sh;
+    C vals[E0];
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = tid + q * NT;
-    const int line = e / N, ky = e % N, col = c0 + line;
-    C z = panel[e];
-    if (col == 0) {
-      // packed column: z = A + iB with A the kx = 0 and B the kx = N/2
-      // column spectra (both Hermitian in ky); scale A and B separately
-      const int kr = (N - ky) % N;
-      C w = panel[kr];
-      if (ky == 0) z.x = (T)((double)z.x - corr);
-      if (kr == 0) w.x = (T)((double)w.x - corr);
-      const double d0 = sp.inv_n2 / (sp.a + sp.lam * (s2[0] + s2[ky]));
-      const double dn = sp.inv_n2 / (sp.a + sp.lam * (s2[N / 2] + s2[ky]));
-      const T pp = (T)(0.5 * (d0 + dn)), mm = (T)(0.5 * (d0 - dn));
-      z = C{z.x * pp + w.x * mm, z.y * pp - w.y * mm};
-    } else {
-      const T d = (T)(sp.inv_n2 / (sp.a + sp.lam * (s2[col] + s2[ky])));
-      z = C{z.x * d, z.y * d};
+    for (int q = 0; q < E0; ++q) {
+      const int ky = tid + q * NT;
+      if (ky < N) {
+        const int kr = (N - ky) % N;
+        C z = panel[lay(0, ky)], w = panel[lay(0, kr)];
+        if (ky == 0) z.x = (T)((double)z.x - corr);
+        if (kr == 0) w.x = (T)((double)w.x - corr);
+        const double d0 = inv_symbol(sp, s2, ky, 0), dn = inv_symbol(sp, s2, ky, N / 2);
+        const T pp = (T)(0.5 * (d0 + dn)), mm = (T)(0.5 * (d0 - dn));
+        vals[q] = C{z.x * pp + w.x * mm, z.y * pp - w.y * mm};
+      }
     }
-    vals[q] = z;
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) panel[tid + q * NT] = vals[q];
-  __syncthreads();
-  fft_lines<N, +1, NT, T>(panel, tw, LinePanel<N>{}, tid);
-  for (int e = tid; e < CT * N; e += NT) P[e] = panel[e];
+    for (int q = 0; q < E0; ++q) {
+      const int ky = tid + q * NT;
+      if (ky < N) panel[lay(0, ky)] = vals[q];
+    }
+    __syncthreads();
+  }
+  fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, ColStore<T>{P, N});
 }
 
 // ------------------------------------------------------------- launchers
