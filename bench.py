@@ -50,6 +50,40 @@ def bytes_per_point_step(prec: str) -> int:
     return 32 if prec == "f64" else 16
 
 
+def kernel_src_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fine_kernels.hip", "fft_lds.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2510_07672_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cfg_name, prec, n):
+    """HBM bytes of one fine step (middle row pass + column pass of the
+    fine sweep) from the committed FETCH_SIZE / WRITE_SIZE counter summary,
+    already scaled by the plain-copy calibration; None if the kernels
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"fine_step_{cfg_name}_{prec}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("src_hash") != kernel_src_hash():
+        return None
+    per = d["per_dispatch"]
+    t = "double" if prec == "f64" else "float"
+
+    def biggest(prefix):
+        cands = [(int(k.split("@")[1]), v) for k, v in per.items() if k.split("@")[0] == prefix]
+        return max(cands)[1] if cands else None
+    row = biggest(f"pr::k_row<{n}, {t}, 1>")
+    col = biggest(f"pr::k_col<{n}, {t}>")
+    if row is None or col is None:
+        return None
+    return (row["fetch_MB"] + row["write_MB"] + col["fetch_MB"] + col["write_MB"]) * 1e6
+
+
 def cpu_baseline(cfg, prec, budget_s=12.0):
     """The FP64 oracle on host cores: fine steps of the same fields."""
     from oracle import allen_cahn as ac
@@ -72,6 +106,67 @@ def cpu_baseline(cfg, prec, budget_s=12.0):
                       f"(scipy.fft, workers={os.cpu_count()}) in {dt:.1f} s"}
 
 
+def parareal_vs_serial(api, p, g, u0, s, kmax, target=1e-6):
+    """Wall-clock of Parareal stopped after k iterations against the FP64
+    serial fine solve on the same GPU, for the smallest k whose trajectory
+    is within rel-L2 `target` of that serial solve."""
+    import dataclasses
+    import torch
+    p64 = dataclasses.replace(p, fine_prec="f64")
+
+    def timed(fn, reps=3):
+        best = None
+        out = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) * 1e3
+            best = dt if best is None else min(best, dt)
+        return out, best
+
+    ref, t_ser64 = timed(lambda: api.pr_serial_fine(p64, u0, s))
+    ser_same, t_ser = timed(lambda: api.pr_serial_fine(p, u0, s))
+    nref = torch.linalg.vector_norm(ref).item()
+    rel_same = torch.linalg.vector_norm(ser_same - ref).item() / nref
+    hist = []
+    found = None
+    for k in range(1, min(kmax, s) + 1):
+        (U, st), t = timed(lambda: api.pr_solve(p, g, u0, s, tol=0.0, max_iter=k,
+                                                allow_not_converged=True), reps=1)
+        err = torch.linalg.vector_norm(U - ref).item() / nref
+        hist.append({"k": k, "rel_l2": float(f"{err:.3e}"), "ms": round(t, 2)})
+        if err <= target:
+            _, t = timed(lambda: api.pr_solve(p, g, u0, s, tol=0.0, max_iter=k,
+                                              allow_not_converged=True), reps=3)
+            found = {"k": k, "ms": round(t, 2), "rel_l2": err}
+            break
+    res = {"target_rel_l2": target, "serial_fp64_ms": round(t_ser64, 2),
+           "serial_same_prec_ms": round(t_ser, 2), "serial_same_prec_rel_l2": float(f"{rel_same:.3e}"),
+           "history": hist}
+    if found:
+        res.update({"k": found["k"], "parareal_ms": found["ms"],
+                    "speedup_vs_serial_fp64": round(t_ser64 / found["ms"], 3),
+                    "speedup_vs_serial_same_prec": round(t_ser / found["ms"], 3)})
+    else:
+        res.update({"k": None, "speedup_vs_serial_fp64": None,
+                    "note": f"rel-L2 {target} not reached within {min(kmax, s)} iterations"})
+    return res
+
+
+def calib_copy(nbytes=1 << 30, reps=3):
+    """A plain copy of `nbytes` bytes: reads nbytes and writes nbytes per
+    launch, so HBM counters per dispatch can be scaled against it."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,7 +175,14 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-parareal", action="store_true")
+    ap.add_argument("--kmax", type=int, default=16)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
+    if args.calib_copy:
+        calib_copy()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the fine solves would shard by slice with no communication; see DESIGN.md)",
@@ -125,8 +227,13 @@ def main():
     fine_ms_avg = float(np.mean(fine_ms))
     bpp = bytes_per_point_step(args.prec)
     achieved = pts * bpp / (fine_ms_avg * 1e-3) / 1e9
+    traffic = measured_traffic(args.config, args.prec, n)
+    step_alg_bytes = B * s * n * n * bpp
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "traffic_unit": "bytes per fine step over the batch (row + column pass)",
+            "algorithmic_bytes_per_step": step_alg_bytes,
             "kernel": "fine step = k_col + k_row<MID> per step, over the whole F sweep",
             "bytes_per_point_step": bpp,
             "fine_sweep_ms": round(fine_ms_avg, 3), "sweep_ms": round(float(np.mean(sweep_ms)), 3)}
@@ -139,6 +246,8 @@ def main():
                    "fine_solves_per_launch": B * s, "fine_prec": args.prec},
         "roofline": roof,
     }
+    if not args.no_parareal:
+        out["parareal"] = parareal_vs_serial(api, p, g, u0, s, args.kmax)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.prec)
     print(json.dumps(out), flush=True)
