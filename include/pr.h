@@ -138,9 +138,10 @@ pr_status pr_coarse_apply(const pr_problem* p, const pr_coarse* g,
  *   u       device double[nfields][n][n]: in U^{k-1}_{j+1}, out U^k_{j+1}
  *   upd_max device double[nfields]: running sup norm, updated as
  *           upd_max[b] = max(upd_max[b], max_points |u_new - u_in|);
- *           a NaN anywhere makes it NaN.
- * No two of f, g_new, g_old, u may alias, except that g_new may equal
- * g_old when update_cache is 0 is meaningless and rejected. */
+ *           entries must be >= 0 (or NaN) on entry; a NaN anywhere in a
+ *           field's update makes its entry NaN.
+ * f, g_new, g_old and u must be four distinct arrays (PR_ERR_INVALID_ARG
+ * otherwise). */
 pr_status pr_correct(int64_t nfields, int32_t n, const void* f,
                      pr_dtype f_dtype, const double* g_new, double* g_old,
                      double* u, double* upd_max, int32_t update_cache,
@@ -177,6 +178,37 @@ size_t pr_serial_workspace_bytes(const pr_problem* p, int64_t n_ics);
 pr_status pr_serial_fine(const pr_problem* p, int64_t n_ics, int32_t n_slices,
                          const double* u0, double* U, void* ws,
                          size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------- launch plans --- */
+
+/* How the fine and coarse steps are launched for a given (N, precision),
+ * process-wide.  Both plans compute the same arithmetic (the classic model
+ * gives identical bits; the conservative one may differ in the last bit of
+ * the mass-multiplier sum, whose reduction order differs).
+ *   PR_PLAN_STREAM    each step is two launches (a column pass and a row
+ *                     pass) streaming every field's spectrum through HBM;
+ *   PR_PLAN_RESIDENT  one launch for all steps, one workgroup per field
+ *                     with the field's whole spectrum in LDS (N <= 128);
+ *   PR_PLAN_AUTO      the autotuner's measured choice if pr_autotune_fine
+ *                     ran for this (N, precision), else RESIDENT for
+ *                     N <= 128 and STREAM above. */
+typedef enum { PR_PLAN_AUTO = 0, PR_PLAN_STREAM = 1, PR_PLAN_RESIDENT = 2 } pr_plan;
+
+/* Set the plan for (n, prec).  PR_ERR_UNSUPPORTED for RESIDENT with n > 128. */
+pr_status pr_set_fine_plan(int32_t n, pr_dtype prec, int32_t plan);
+
+/* The plan that will be used for (n, prec) (STREAM or RESIDENT), or -1 for
+ * an unsupported (n, prec). */
+int32_t pr_get_fine_plan(int32_t n, pr_dtype prec);
+
+/* Autotuner: times one F call of p on `nfields` fields under each plan
+ * available for p->n (u_in read, u_out overwritten with scratch results;
+ * workspace as for pr_fine_propagate), records the faster one as the AUTO
+ * choice for (p->n, p->fine_prec) and returns it in *chosen (may be NULL).
+ * Blocks until the timing runs finish. */
+pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u_in,
+                           void* u_out, void* ws, size_t ws_bytes, void* stream,
+                           int32_t* chosen);
 
 /* ---------------------------------------------------------- helpers --- */
 

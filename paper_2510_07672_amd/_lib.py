@@ -22,8 +22,10 @@ EXPORTED = [
     "pr_correct",
     "pr_solve_workspace_bytes", "pr_solve",
     "pr_serial_workspace_bytes", "pr_serial_fine",
+    "pr_set_fine_plan", "pr_get_fine_plan", "pr_autotune_fine",
     "pr_status_string", "pr_last_error", "pr_abi_version",
 ]
+PR_PLAN_AUTO, PR_PLAN_STREAM, PR_PLAN_RESIDENT = 0, 1, 2
 
 
 class Problem(C.Structure):
@@ -66,6 +68,9 @@ def lib() -> C.CDLL:
             "pr_solve": (C.c_int, [P, G, i64, i32, vp, vp, C.c_double, i32, S, vp, sz, vp]),
             "pr_serial_workspace_bytes": (sz, [P, i64]),
             "pr_serial_fine": (C.c_int, [P, i64, i32, vp, vp, vp, sz, vp]),
+            "pr_set_fine_plan": (C.c_int, [i32, C.c_int, i32]),
+            "pr_get_fine_plan": (i32, [i32, C.c_int]),
+            "pr_autotune_fine": (C.c_int, [P, i64, vp, vp, vp, sz, vp, C.POINTER(i32)]),
             "pr_status_string": (C.c_char_p, [C.c_int]),
             "pr_last_error": (C.c_char_p, []),
             "pr_abi_version": (C.c_int, []),

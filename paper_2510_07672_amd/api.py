@@ -169,5 +169,30 @@ def pr_serial_fine(p: Problem, u0: torch.Tensor, n_slices: int,
     return U
 
 
+_PLAN = {"auto": L.PR_PLAN_AUTO, "stream": L.PR_PLAN_STREAM, "resident": L.PR_PLAN_RESIDENT}
+_PLAN_NAME = {v: k for k, v in _PLAN.items()}
+
+
+def pr_set_fine_plan(n: int, prec: str, plan: str) -> None:
+    """Launch plan for (n, prec): 'auto', 'stream' or 'resident' (n <= 128)."""
+    L.check(L.lib().pr_set_fine_plan(n, _PREC[prec], _PLAN[plan]), "pr_set_fine_plan")
+
+
+def pr_get_fine_plan(n: int, prec: str) -> str:
+    return _PLAN_NAME[L.lib().pr_get_fine_plan(n, _PREC[prec])]
+
+
+def pr_autotune_fine(p: Problem, u_in: torch.Tensor) -> str:
+    """Time both plans on u_in and keep the faster as the 'auto' choice."""
+    B = _fields(u_in, p.n, "u_in")
+    pc = p.c()
+    out = torch.empty_like(u_in)
+    ws = workspace(L.lib().pr_fine_workspace_bytes(C.byref(pc), B), u_in.device)
+    ch = C.c_int32(0)
+    L.check(L.lib().pr_autotune_fine(C.byref(pc), B, _ptr(u_in), _ptr(out), _ptr(ws), ws.numel(),
+                                     _stream(u_in.device), C.byref(ch)), "pr_autotune_fine")
+    return _PLAN_NAME[ch.value]
+
+
 def pr_abi_version() -> int:
     return L.lib().pr_abi_version()

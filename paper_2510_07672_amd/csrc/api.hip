@@ -3,6 +3,7 @@
 // kernels of fine_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -100,9 +101,32 @@ StepParams step_params(const pr_problem* p, double dt) {
   return sp;
 }
 
+// Process-wide plan per (N, precision): PR_PLAN_AUTO falls back to the
+// default rule (resident for N <= 128) unless pr_autotune_fine recorded a
+// measured choice.
+std::atomic<int> g_plan[11][2];     // [log2 N][f32], user setting
+std::atomic<int> g_tuned[11][2];    // [log2 N][f32], autotuner result (0 = none)
+
+int log2i(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+int effective_plan(int n, bool f32) {
+  const int l = log2i(n);
+  if (l < 0 || l > 10) return PR_PLAN_STREAM;
+  int pl = g_plan[l][f32 ? 1 : 0].load();
+  if (pl == PR_PLAN_AUTO) pl = g_tuned[l][f32 ? 1 : 0].load();
+  if (pl == PR_PLAN_AUTO) pl = n <= kResidentMaxN ? PR_PLAN_RESIDENT : PR_PLAN_STREAM;
+  if (pl == PR_PLAN_RESIDENT && n > kResidentMaxN) pl = PR_PLAN_STREAM;
+  return pl;
+}
+
 StepJob make_job(const pr_problem* p, double dt, int steps, bool f32, int64_t nfields,
                  const FineWs& ws) {
   StepJob j{};
+  j.resident = effective_plan(p->n, f32) == PR_PLAN_RESIDENT;
   j.n = p->n;
   j.f32 = f32;
   j.steps = steps;
@@ -450,6 +474,61 @@ pr_status pr_solve(const pr_problem* p, const pr_coarse* g, int64_t n_ics, int32
   if (result != PR_OK) return result;
   if (n_conv < B) return fail(PR_NOT_CONVERGED, "%lld of %lld ICs above tol after %d iterations",
                               (long long)(B - n_conv), (long long)B, iters);
+  return PR_OK;
+}
+
+pr_status pr_set_fine_plan(int32_t n, pr_dtype prec, int32_t plan) {
+  if (!is_pow2(n) || n < 16 || n > 1024) return fail(PR_ERR_UNSUPPORTED, "n=%d not supported", n);
+  if (prec != PR_F64 && prec != PR_F32) return fail(PR_ERR_INVALID_ARG, "prec must be PR_F64 or PR_F32");
+  if (plan != PR_PLAN_AUTO && plan != PR_PLAN_STREAM && plan != PR_PLAN_RESIDENT)
+    return fail(PR_ERR_INVALID_ARG, "plan %d unknown", plan);
+  if (plan == PR_PLAN_RESIDENT && n > kResidentMaxN)
+    return fail(PR_ERR_UNSUPPORTED, "resident plan needs n <= %d", kResidentMaxN);
+  g_plan[log2i(n)][prec == PR_F32 ? 1 : 0].store(plan);
+  return PR_OK;
+}
+
+int32_t pr_get_fine_plan(int32_t n, pr_dtype prec) {
+  if (!is_pow2(n) || n < 16 || n > 1024 || (prec != PR_F64 && prec != PR_F32)) return -1;
+  return effective_plan(n, prec == PR_F32);
+}
+
+pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u_in, void* u_out,
+                           void* ws, size_t ws_bytes, void* stream, int32_t* chosen) {
+  pr_status st = check_problem(p);
+  if (st != PR_OK) return st;
+  if (nfields < 1) return fail(PR_ERR_INVALID_ARG, "nfields must be >= 1");
+  if (!u_in || !u_out || (const void*)u_in == u_out) return fail(PR_ERR_INVALID_ARG, "bad u_in / u_out");
+  const bool f32 = p->fine_prec == PR_F32;
+  Carver c(ws);
+  FineWs w = carve_fine(c, p->n, f32, nfields);
+  if (!ws || ws_bytes < c.used)
+    return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, c.used);
+  hipStream_t s = (hipStream_t)stream;
+  const int l = log2i(p->n);
+  int best = PR_PLAN_STREAM;
+  if (p->n <= kResidentMaxN) {
+    Events ev;
+    if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
+    PR_HIP(launch_tables(p->n, w, s));
+    float ms[3] = {0, 0, 0};
+    for (int plan = PR_PLAN_STREAM; plan <= PR_PLAN_RESIDENT; ++plan) {
+      StepJob j = make_job(p, p->dt, p->steps, f32, nfields, w);
+      j.resident = plan == PR_PLAN_RESIDENT;
+      j.in_base = u_in;
+      j.out_base = u_out;
+      j.out_f32 = 0;
+      PR_HIP(launch_steps(j, s));  // warm-up
+      PR_HIP(hipEventRecord(ev.e[0], s));
+      PR_HIP(launch_steps(j, s));
+      PR_HIP(hipEventRecord(ev.e[1], s));
+      PR_HIP(hipEventSynchronize(ev.e[1]));
+      ms[plan] = event_ms(ev.e[0], ev.e[1]);
+    }
+    best = ms[PR_PLAN_RESIDENT] <= ms[PR_PLAN_STREAM] ? PR_PLAN_RESIDENT : PR_PLAN_STREAM;
+  }
+  g_tuned[l][f32 ? 1 : 0].store(best);
+  if (chosen) *chosen = best;
   return PR_OK;
 }
 

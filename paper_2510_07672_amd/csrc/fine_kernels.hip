@@ -278,6 +278,162 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, ColStore<T>{P, N});
 }
 
+// ---------------------------------------------------- on-chip resident step
+//
+// One block per field for all steps of the call, for N <= 128: the field's
+// spectrum (N/2 x N complex, the same column-major layout as in HBM) stays
+// in LDS.  The row pass runs in place on those slots: the complex row pair
+// p (rows 2p, 2p+1) occupies the 2 x N/2 slots of rows 2p and 2p+1, with
+// Z_p[kx] at slot (kx mod N/2, 2p + kx / (N/2)); packing into and splitting
+// out of that form permutes only those slots.  Slot (c, r) lives at
+// c * LS + c/8 + r + r/8 (LS odd), so unit and stride-8 walks along either
+// index spread over the LDS banks.
+
+template <int N> struct ResCfg {
+  static constexpr int H = N / 2;
+  static constexpr int NT = N * N / 16;   // 8 complex elements per thread
+  static constexpr int LS = PadLS<N>::value;
+  static constexpr int SLOTS = H * LS + H / 8 + 1;
+};
+
+template <int N> struct SlotAddr {
+  __device__ __forceinline__ static int at(int c, int r) {
+    return c * ResCfg<N>::LS + (c >> 3) + r + (r >> 3);
+  }
+};
+template <int N> struct ResColLay {   // line = column c, element = row r
+  __device__ __forceinline__ int operator()(int c, int r) const { return SlotAddr<N>::at(c, r); }
+};
+template <int N> struct ResRowLay {   // line = row pair p, element = kx
+  __device__ __forceinline__ int operator()(int p, int kx) const {
+    return SlotAddr<N>::at(kx & (N / 2 - 1), 2 * p + (kx >= N / 2 ? 1 : 0));
+  }
+};
+
+// (c, p) work items of the pack / split permutations, four per thread
+template <int N, typename T, bool PACK>
+__device__ __forceinline__ void res_permute(cpx<T>* S, int tid) {
+  using C = cpx<T>;
+  constexpr int H = N / 2, NT = ResCfg<N>::NT, IT = H * H / NT;  // = 4
+  C a[IT], b[IT];
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int item = tid + q * NT;
+    const int c = item % H, p = item / H;
+    if constexpr (PACK) {
+      a[q] = S[SlotAddr<N>::at(c, 2 * p)];
+      b[q] = S[SlotAddr<N>::at(c, 2 * p + 1)];
+    } else {
+      a[q] = S[SlotAddr<N>::at(c, 2 * p)];                         // Z[c] (Z[0] for c = 0)
+      b[q] = S[SlotAddr<N>::at(c == 0 ? 0 : H - c, 2 * p + 1)];   // Z[N-c] (Z[N/2] for c = 0)
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < IT; ++q) {
+    const int item = tid + q * NT;
+    const int c = item % H, p = item / H;
+    const C A = a[q], B = b[q];
+    if constexpr (PACK) {
+      if (c == 0) {
+        S[SlotAddr<N>::at(0, 2 * p)] = C{A.x, B.x};        // Z[0]
+        S[SlotAddr<N>::at(0, 2 * p + 1)] = C{A.y, B.y};    // Z[N/2]
+      } else {
+        S[SlotAddr<N>::at(c, 2 * p)] = C{A.x - B.y, A.y + B.x};          // Z[c]
+        S[SlotAddr<N>::at(H - c, 2 * p + 1)] = C{A.x + B.y, B.x - A.y};  // Z[N-c]
+      }
+    } else {
+      if (c == 0) {
+        S[SlotAddr<N>::at(0, 2 * p)] = C{A.x, B.x};
+        S[SlotAddr<N>::at(0, 2 * p + 1)] = C{A.y, B.y};
+      } else {
+        const T h = (T)0.5;
+        S[SlotAddr<N>::at(c, 2 * p)] = C{h * (A.x + B.x), h * (A.y - B.y)};
+        S[SlotAddr<N>::at(c, 2 * p + 1)] = C{h * (A.y + B.y), h * (B.x - A.x)};
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, typename T>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k_resident(
+    const double* __restrict__ in_base, const int64_t* __restrict__ in_offs,
+    void* __restrict__ out_base, const int64_t* __restrict__ out_offs, int out_f32,
+    const cpx<T>* __restrict__ tw_g, const double* __restrict__ s2_g, StepParams sp, int steps) {
+  using C = cpx<T>;
+  using Cfg = ResCfg<N>;
+  constexpr int NT = Cfg::NT, E0 = (N + NT - 1) / NT;
+  __shared__ C S[Cfg::SLOTS];
+  __shared__ C tw[N];
+  __shared__ double s2[N];
+  __shared__ double red[NT / 64 + 1];
+  __shared__ double corr_sh;
+
+  const int tid = threadIdx.x;
+  const int64_t f = blockIdx.x;
+  for (int t = tid; t < N; t += NT) {
+    tw[t] = tw_g[t];
+    s2[t] = s2_g[t];
+  }
+  const T a = (T)sp.a, dt = (T)sp.dt;
+  const ResRowLay<N> rlay{};
+  const ResColLay<N> clay{};
+  double fsum = 0.0;
+  __syncthreads();
+
+  // first right-hand side straight from the FP64 state
+  const double* u = in_base + (in_offs ? in_offs[f] : f * (int64_t)N * N);
+  fft_lines<N, -1, NT, T>(S, tw, rlay, tid, RealRowsPro<N, T>{u, 0, a, dt, &fsum});
+  res_permute<N, T, false>(S, tid);
+
+  for (int s = 0; s < steps; ++s) {
+    if (sp.conservative) {
+      const double tot = block_sum<NT>(fsum, red, tid);
+      if (tid == 0) corr_sh = sp.dt * tot;
+    } else if (tid == 0) {
+      corr_sh = 0.0;
+    }
+    fsum = 0.0;
+    // column pass
+    fft_lines<N, -1, NT, T>(S, tw, clay, tid, NoPro{}, DivideEpi<T>{s2, sp, 0});
+    {
+      const double corr = corr_sh;
+      C vals[E0];
+#pragma unroll
+      for (int q = 0; q < E0; ++q) {
+        const int ky = tid + q * NT;
+        if (ky < N) {
+          const int kr = (N - ky) % N;
+          C z = S[clay(0, ky)], w = S[clay(0, kr)];
+          if (ky == 0) z.x = (T)((double)z.x - corr);
+          if (kr == 0) w.x = (T)((double)w.x - corr);
+          const double d0 = inv_symbol(sp, s2, ky, 0), dn = inv_symbol(sp, s2, ky, N / 2);
+          const T pp = (T)(0.5 * (d0 + dn)), mm = (T)(0.5 * (d0 - dn));
+          vals[q] = C{z.x * pp + w.x * mm, z.y * pp - w.y * mm};
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < E0; ++q) {
+        const int ky = tid + q * NT;
+        if (ky < N) S[clay(0, ky)] = vals[q];
+      }
+      __syncthreads();
+    }
+    fft_lines<N, +1, NT, T>(S, tw, clay, tid);
+    // row pass
+    res_permute<N, T, true>(S, tid);
+    if (s + 1 < steps) {
+      fft_lines<N, +1, NT, T>(S, tw, rlay, tid, NoPro{}, RhsEpi<T>{a, dt, &fsum});
+      fft_lines<N, -1, NT, T>(S, tw, rlay, tid);
+      res_permute<N, T, false>(S, tid);
+    }
+  }
+  const int64_t ob = out_offs ? out_offs[f] : f * (int64_t)N * N;
+  fft_lines<N, +1, NT, T>(S, tw, rlay, tid, NoPro{}, RealRowsStore<N, T>{out_base, ob, 0, out_f32});
+}
+
 // ------------------------------------------------------------- launchers
 
 template <int N, typename T>
@@ -301,8 +457,33 @@ static hipError_t launch_steps_n(const StepJob& job, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int N, typename T>
+static hipError_t launch_resident_n(const StepJob& job, hipStream_t st) {
+  if constexpr (N <= kResidentMaxN) {
+    const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)job.ws.tw64 : (const void*)job.ws.tw32);
+    k_resident<N, T><<<dim3((unsigned)job.nfields), dim3(ResCfg<N>::NT), 0, st>>>(
+        job.in_base, job.in_offs, job.out_base, job.out_offs, job.out_f32, tw, job.ws.s2, job.sp,
+        job.steps);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+static hipError_t launch_resident_t(const StepJob& job, hipStream_t st) {
+  switch (job.n) {
+    case 16: return launch_resident_n<16, T>(job, st);
+    case 32: return launch_resident_n<32, T>(job, st);
+    case 64: return launch_resident_n<64, T>(job, st);
+    case 128: return launch_resident_n<128, T>(job, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
 static hipError_t launch_steps_t(const StepJob& job, hipStream_t st) {
+  if (job.resident) return launch_resident_t<T>(job, st);
   switch (job.n) {
     case 16: return launch_steps_n<16, T>(job, st);
     case 32: return launch_steps_n<32, T>(job, st);

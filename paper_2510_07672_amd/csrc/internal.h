@@ -31,6 +31,9 @@ template <int N> struct ColCfg {
   static constexpr int BLOCKS = (N / 2) / CT;
 };
 
+// Largest N whose whole spectrum one block keeps in LDS (FP64: 148 KB).
+constexpr int kResidentMaxN = 128;
+
 struct StepParams {
   double a;       // 1 + S dt
   double dt;      // step
@@ -59,6 +62,7 @@ struct StepJob {
   void* out_base;            // field i at out_base + (out_offs ? out_offs[i] : i N^2)
   const int64_t* out_offs;   // device or null
   int out_f32;
+  bool resident;             // one block per field, all steps in LDS (N <= 128)
   FineWs ws;
 };
 

@@ -271,3 +271,70 @@ def test_empty_batch_and_workspace_errors(api):
                                    need - 1, None)
     assert st == L.PR_ERR_WORKSPACE
     assert torch.count_nonzero(out) == 0
+
+
+# ------------------------------------------------------- launch plans
+
+@pytest.fixture
+def plan(api):
+    set_ = []
+
+    def use(n, prec, name):
+        api.pr_set_fine_plan(n, prec, name)
+        set_.append((n, prec))
+    yield use
+    for n, prec in set_:
+        api.pr_set_fine_plan(n, prec, "auto")
+
+
+@pytest.mark.parametrize("n,steps", [(16, 9), (32, 7), (64, 100), (128, 30)])
+@pytest.mark.parametrize("conservative", [False, True])
+@pytest.mark.parametrize("which", ["resident", "stream"])
+def test_small_n_plans_match_oracle_f64(api, plan, n, steps, conservative, which):
+    print(f"case plan={which} n={n} cons={conservative}", flush=True)
+    plan(n, "f64", which)
+    assert api.pr_get_fine_plan(n, "f64") == which
+    p = api.Problem(n=n, length=1.0, eps=0.02, conservative=conservative, stab=2.0, dt=1e-4,
+                    steps=steps)
+    u0 = synth.random_ic(n, [11, 12, 13, 14, 15])
+    out = api.pr_fine_propagate(p, dev(u0)).cpu().numpy()
+    ref = ac.fine(u0, oracle_problem(p))
+    assert max(field_rel(out, ref)) <= 1e-12
+    if conservative:
+        assert np.abs(out.mean(axis=(1, 2)) - u0.mean(axis=(1, 2))).max() <= 1e-13
+
+
+@pytest.mark.parametrize("n", [16, 64, 128])
+@pytest.mark.parametrize("conservative", [False, True])
+def test_resident_f32_one_step(api, plan, n, conservative):
+    plan(n, "f32", "resident")
+    p = api.Problem(n=n, length=1.0, eps=0.01, conservative=conservative, stab=2.0, dt=2e-5,
+                    steps=1, fine_prec="f32")
+    u0 = synth.random_ic(n, [5, 6])
+    out = api.pr_fine_propagate(p, dev(u0), out_dtype=torch.float32).cpu().numpy()
+    ref = ac.fine(u0.astype(np.float32).astype(np.float64), oracle_problem(p))
+    assert max(field_rel(out.astype(np.float64), ref)) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [32, 128])
+def test_resident_equals_stream_bitwise_classic(api, plan, n, prec):
+    p = api.Problem(n=n, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4, steps=13,
+                    fine_prec=prec)
+    u0 = dev(synth.random_ic(n, range(6)))
+    plan(n, prec, "resident")
+    a = api.pr_fine_propagate(p, u0)
+    plan(n, prec, "stream")
+    b = api.pr_fine_propagate(p, u0)
+    assert torch.equal(a, b)
+
+
+def test_autotune_picks_a_plan(api, plan):
+    p = api.Problem(n=64, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4, steps=20)
+    u0 = dev(synth.random_ic(64, range(4)))
+    choice = api.pr_autotune_fine(p, u0)
+    assert choice in ("resident", "stream")
+    assert api.pr_get_fine_plan(64, "f64") == choice
+    p2 = api.Problem(n=256, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4, steps=2)
+    assert api.pr_autotune_fine(p2, dev(synth.random_ic(256, [1]))) == "stream"
+    plan(64, "f64", "auto")
