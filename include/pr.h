@@ -210,6 +210,18 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
                            void* u_out, void* ws, size_t ws_bytes, void* stream,
                            int32_t* chosen);
 
+/* A streaming F (or numerical G) call is 2*steps + 1 launches.  With
+ * graphs on (the default), that sequence is captured once per (problem,
+ * steps, workspace) into a hipGraph and replayed; the batch size and the
+ * input/output field addresses are read from a descriptor in the
+ * workspace, so one capture serves every later call on the same
+ * workspace whose batch is no larger (e.g. every Parareal iteration).
+ * The library keeps at most 32 captures, evicting the least recently used
+ * (after a device-wide synchronisation).  pr_set_graphs(0) launches the
+ * kernels one by one instead; results are identical either way. */
+void pr_set_graphs(int32_t enabled);
+int32_t pr_get_graphs(void);
+
 /* ---------------------------------------------------------- helpers --- */
 
 const char* pr_status_string(pr_status s);

@@ -194,5 +194,14 @@ def pr_autotune_fine(p: Problem, u_in: torch.Tensor) -> str:
     return _PLAN_NAME[ch.value]
 
 
+def pr_set_graphs(enabled: bool) -> None:
+    """Replay captured launch sequences (True, default) or launch eagerly."""
+    L.lib().pr_set_graphs(int(bool(enabled)))
+
+
+def pr_get_graphs() -> bool:
+    return bool(L.lib().pr_get_graphs())
+
+
 def pr_abi_version() -> int:
     return L.lib().pr_abi_version()

@@ -82,6 +82,7 @@ struct Carver {
 
 FineWs carve_fine(Carver& c, int n, bool f32, int64_t nfields) {
   FineWs w;
+  w.desc = (CallDesc*)c.take(sizeof(CallDesc));
   w.tw64 = (double2*)c.take((size_t)n * sizeof(double2));
   w.tw32 = (float2*)c.take((size_t)n * sizeof(float2));
   w.s2 = (double*)c.take((size_t)n * sizeof(double));
@@ -487,6 +488,10 @@ pr_status pr_set_fine_plan(int32_t n, pr_dtype prec, int32_t plan) {
   g_plan[log2i(n)][prec == PR_F32 ? 1 : 0].store(plan);
   return PR_OK;
 }
+
+void pr_set_graphs(int32_t enabled) { set_graphs_enabled(enabled != 0); }
+
+int32_t pr_get_graphs(void) { return graphs_enabled() ? 1 : 0; }
 
 int32_t pr_get_fine_plan(int32_t n, pr_dtype prec) {
   if (!is_pow2(n) || n < 16 || n > 1024 || (prec != PR_F64 && prec != PR_F32)) return -1;

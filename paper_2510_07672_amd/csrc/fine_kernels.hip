@@ -29,6 +29,10 @@
 // column pass plus one row pass: two read+write sweeps of the field.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <mutex>
+#include <vector>
+
 #include "fft_lds.h"
 #include "internal.h"
 
@@ -103,10 +107,8 @@ template <int N, typename T> struct RealRowsStore {
 
 template <int N, typename T, int MODE>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
-    const double* __restrict__ in_base, const int64_t* __restrict__ in_offs,
-    cpx<T>* __restrict__ spec, double* __restrict__ partials,
-    void* __restrict__ out_base, const int64_t* __restrict__ out_offs,
-    int out_f32, const cpx<T>* __restrict__ tw_g, StepParams sp) {
+    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
+    const cpx<T>* __restrict__ tw_g, StepParams sp) {
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
@@ -118,6 +120,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
 
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / TILES;
+  if (f >= desc->nfields) return;
   const int tile = blockIdx.x % TILES;
   const int r0 = tile * TR;
   const Lay lay{};
@@ -127,7 +130,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   double fsum = 0.0;
 
   if constexpr (MODE == ROW_FIRST) {
-    const double* u = in_base + (in_offs ? in_offs[f] : f * (int64_t)N * N);
+    const double* u = desc->in_base + (desc->in_offs ? desc->in_offs[f] : f * (int64_t)N * N);
     __syncthreads();
     fft_lines<N, -1, NT, T>(panel, tw, lay, tid, RealRowsPro<N, T>{u, r0, a, dt, &fsum});
   } else {
@@ -146,9 +149,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
     }
     __syncthreads();
     if constexpr (MODE == ROW_LAST) {
-      const int64_t ob = out_offs ? out_offs[f] : f * (int64_t)N * N;
+      const int64_t ob = desc->out_offs ? desc->out_offs[f] : f * (int64_t)N * N;
       fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{},
-                              RealRowsStore<N, T>{out_base, ob, r0, out_f32});
+                              RealRowsStore<N, T>{desc->out_base, ob, r0, desc->out_f32});
       return;
     }
     fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, RhsEpi<T>{a, dt, &fsum});
@@ -215,8 +218,9 @@ template <typename T> struct DivideEpi {
 
 template <int N, typename T>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col(
-    cpx<T>* __restrict__ spec, const double* __restrict__ partials,
-    const cpx<T>* __restrict__ tw_g, const double* __restrict__ s2_g, StepParams sp) {
+    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec,
+    const double* __restrict__ partials, const cpx<T>* __restrict__ tw_g,
+    const double* __restrict__ s2_g, StepParams sp) {
   using C = cpx<T>;
   constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
   constexpr int TILES = RowCfg<N, T>::TILES;
@@ -230,6 +234,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
 
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / BLK;
+  if (f >= desc->nfields) return;
   const int c0 = (blockIdx.x % BLK) * CT;
   const Lay lay{};
   C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
@@ -358,9 +363,8 @@ __device__ __forceinline__ void res_permute(cpx<T>* S, int tid) {
 
 template <int N, typename T>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k_resident(
-    const double* __restrict__ in_base, const int64_t* __restrict__ in_offs,
-    void* __restrict__ out_base, const int64_t* __restrict__ out_offs, int out_f32,
-    const cpx<T>* __restrict__ tw_g, const double* __restrict__ s2_g, StepParams sp, int steps) {
+    const CallDesc* __restrict__ desc, const cpx<T>* __restrict__ tw_g,
+    const double* __restrict__ s2_g, StepParams sp, int steps) {
   using C = cpx<T>;
   using Cfg = ResCfg<N>;
   constexpr int NT = Cfg::NT, E0 = (N + NT - 1) / NT;
@@ -372,6 +376,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
 
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x;
+  if (f >= desc->nfields) return;
   for (int t = tid; t < N; t += NT) {
     tw[t] = tw_g[t];
     s2[t] = s2_g[t];
@@ -383,7 +388,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
   __syncthreads();
 
   // first right-hand side straight from the FP64 state
-  const double* u = in_base + (in_offs ? in_offs[f] : f * (int64_t)N * N);
+  const double* u = desc->in_base + (desc->in_offs ? desc->in_offs[f] : f * (int64_t)N * N);
   fft_lines<N, -1, NT, T>(S, tw, rlay, tid, RealRowsPro<N, T>{u, 0, a, dt, &fsum});
   res_permute<N, T, false>(S, tid);
 
@@ -430,30 +435,123 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
       res_permute<N, T, false>(S, tid);
     }
   }
-  const int64_t ob = out_offs ? out_offs[f] : f * (int64_t)N * N;
-  fft_lines<N, +1, NT, T>(S, tw, rlay, tid, NoPro{}, RealRowsStore<N, T>{out_base, ob, 0, out_f32});
+  const int64_t ob = desc->out_offs ? desc->out_offs[f] : f * (int64_t)N * N;
+  fft_lines<N, +1, NT, T>(S, tw, rlay, tid, NoPro{},
+                          RealRowsStore<N, T>{desc->out_base, ob, 0, desc->out_f32});
 }
 
 // ------------------------------------------------------------- launchers
 
+__global__ void k_set_desc(CallDesc* d, CallDesc v) { *d = v; }
+
+// The 2 * steps + 1 launches of one streaming F call, for a grid of
+// `grid_fields` fields (blocks of fields beyond desc->nfields exit).
 template <int N, typename T>
-static hipError_t launch_steps_n(const StepJob& job, hipStream_t st) {
+static void enqueue_stream_steps(const StepJob& job, int64_t grid_fields, hipStream_t st) {
   using RC = RowCfg<N, T>;
   using CC = ColCfg<N>;
   const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)job.ws.tw64 : (const void*)job.ws.tw32);
   cpx<T>* spec = (cpx<T>*)job.ws.spec;
-  const dim3 grow((unsigned)(job.nfields * RC::TILES)), brow(RC::NT);
-  const dim3 gcol((unsigned)(job.nfields * CC::BLOCKS)), bcol(CC::NT);
-  k_row<N, T, ROW_FIRST><<<grow, brow, 0, st>>>(job.in_base, job.in_offs, spec, job.ws.partials,
-                                                nullptr, nullptr, 0, tw, job.sp);
+  const CallDesc* d = job.ws.desc;
+  const dim3 grow((unsigned)(grid_fields * RC::TILES)), brow(RC::NT);
+  const dim3 gcol((unsigned)(grid_fields * CC::BLOCKS)), bcol(CC::NT);
+  k_row<N, T, ROW_FIRST><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
   for (int s = 0; s < job.steps; ++s) {
-    k_col<N, T><<<gcol, bcol, 0, st>>>(spec, job.ws.partials, tw, job.ws.s2, job.sp);
+    k_col<N, T><<<gcol, bcol, 0, st>>>(d, spec, job.ws.partials, tw, job.ws.s2, job.sp);
     if (s + 1 < job.steps)
-      k_row<N, T, ROW_MID><<<grow, brow, 0, st>>>(nullptr, nullptr, spec, job.ws.partials,
-                                                  nullptr, nullptr, 0, tw, job.sp);
+      k_row<N, T, ROW_MID><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
   }
-  k_row<N, T, ROW_LAST><<<grow, brow, 0, st>>>(nullptr, nullptr, spec, job.ws.partials,
-                                               job.out_base, job.out_offs, job.out_f32, tw, job.sp);
+  k_row<N, T, ROW_LAST><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
+}
+
+// ---- replay of captured launch sequences
+//
+// A streaming F call is 2c+1 launches whose arguments depend only on the
+// problem, the step count and the workspace (everything else is read from
+// the descriptor).  The sequence is captured once per such key and
+// replayed; a replay serves any batch no larger than the captured grid.
+
+struct GraphKey {
+  int n, f32, steps, conservative;
+  double a, dt, lam, inv_n2;
+  const void *desc, *spec, *partials, *tw, *s2;
+  bool same(const GraphKey& o) const {
+    return n == o.n && f32 == o.f32 && steps == o.steps && conservative == o.conservative &&
+           a == o.a && dt == o.dt && lam == o.lam && inv_n2 == o.inv_n2 && desc == o.desc &&
+           spec == o.spec && partials == o.partials && tw == o.tw && s2 == o.s2;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  int64_t grid_fields;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  uint64_t last_use;
+};
+
+static std::mutex g_graph_mu;
+static std::vector<GraphEntry> g_graphs;
+static uint64_t g_graph_clock = 0;
+static hipStream_t g_capture_stream = nullptr;
+static std::atomic<bool> g_graphs_on{true};
+constexpr size_t kMaxGraphs = 32;
+
+void set_graphs_enabled(bool on) { g_graphs_on.store(on); }
+bool graphs_enabled() { return g_graphs_on.load(); }
+
+template <int N, typename T>
+static hipError_t launch_stream_graph(const StepJob& job, hipStream_t st) {
+  GraphKey key{job.n, job.f32 ? 1 : 0, job.steps, job.sp.conservative, job.sp.a, job.sp.dt,
+               job.sp.lam, job.sp.inv_n2, job.ws.desc, job.ws.spec, job.ws.partials,
+               job.f32 ? (const void*)job.ws.tw32 : (const void*)job.ws.tw64, job.ws.s2};
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  GraphEntry* hit = nullptr;
+  for (auto& e : g_graphs)
+    if (e.key.same(key) && e.grid_fields >= job.nfields &&
+        (!hit || e.grid_fields < hit->grid_fields))
+      hit = &e;
+  if (!hit) {
+    hipError_t err;
+    if (!g_capture_stream) {
+      err = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking);
+      if (err != hipSuccess) return err;
+    }
+    if (g_graphs.size() >= kMaxGraphs) {
+      // evict the least recently used entry once nothing can still run it
+      size_t lru = 0;
+      for (size_t i = 1; i < g_graphs.size(); ++i)
+        if (g_graphs[i].last_use < g_graphs[lru].last_use) lru = i;
+      err = hipDeviceSynchronize();
+      if (err != hipSuccess) return err;
+      (void)hipGraphExecDestroy(g_graphs[lru].exec);
+      (void)hipGraphDestroy(g_graphs[lru].graph);
+      g_graphs.erase(g_graphs.begin() + lru);
+    }
+    GraphEntry e{key, job.nfields, nullptr, nullptr, 0};
+    err = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) return err;
+    enqueue_stream_steps<N, T>(job, job.nfields, g_capture_stream);
+    hipError_t lerr = hipGetLastError();
+    err = hipStreamEndCapture(g_capture_stream, &e.graph);
+    if (lerr != hipSuccess) return lerr;
+    if (err != hipSuccess) return err;
+    err = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+      (void)hipGraphDestroy(e.graph);
+      return err;
+    }
+    g_graphs.push_back(e);
+    hit = &g_graphs.back();
+  }
+  hit->last_use = ++g_graph_clock;
+  return hipGraphLaunch(hit->exec, st);
+}
+
+template <int N, typename T>
+static hipError_t launch_steps_n(const StepJob& job, hipStream_t st) {
+  if (graphs_enabled()) return launch_stream_graph<N, T>(job, st);
+  enqueue_stream_steps<N, T>(job, job.nfields, st);
   return hipGetLastError();
 }
 
@@ -462,8 +560,7 @@ static hipError_t launch_resident_n(const StepJob& job, hipStream_t st) {
   if constexpr (N <= kResidentMaxN) {
     const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)job.ws.tw64 : (const void*)job.ws.tw32);
     k_resident<N, T><<<dim3((unsigned)job.nfields), dim3(ResCfg<N>::NT), 0, st>>>(
-        job.in_base, job.in_offs, job.out_base, job.out_offs, job.out_f32, tw, job.ws.s2, job.sp,
-        job.steps);
+        job.ws.desc, tw, job.ws.s2, job.sp, job.steps);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -483,6 +580,10 @@ static hipError_t launch_resident_t(const StepJob& job, hipStream_t st) {
 
 template <typename T>
 static hipError_t launch_steps_t(const StepJob& job, hipStream_t st) {
+  CallDesc v{job.nfields, job.in_base, job.in_offs, job.out_base, job.out_offs, job.out_f32};
+  k_set_desc<<<dim3(1), dim3(1), 0, st>>>(job.ws.desc, v);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   if (job.resident) return launch_resident_t<T>(job, st);
   switch (job.n) {
     case 16: return launch_steps_n<16, T>(job, st);

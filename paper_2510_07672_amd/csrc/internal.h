@@ -42,8 +42,21 @@ struct StepParams {
   int conservative;
 };
 
+// What changes from one call of the step kernels to the next, kept in
+// device memory so that a captured launch sequence can be replayed for
+// any batch that fits its grid.
+struct CallDesc {
+  int64_t nfields;          // live fields; blocks beyond them exit
+  const double* in_base;    // field i at in_base + (in_offs ? in_offs[i] : i N^2)
+  const int64_t* in_offs;
+  void* out_base;           // field i at out_base + (out_offs ? out_offs[i] : i N^2)
+  const int64_t* out_offs;
+  int32_t out_f32;
+};
+
 // Per-call device workspace of the step kernels.
 struct FineWs {
+  CallDesc* desc;    // one descriptor
   double2* tw64;     // [N]  exp(-2 pi i t / N)
   float2* tw32;      // [N]  same, rounded
   double* s2;        // [N]  sin^2(pi t / N)
@@ -78,6 +91,9 @@ struct CorrectJob {
 };
 
 hipError_t launch_tables(int n, const FineWs& ws, hipStream_t st);
+// Process-wide switch for replaying captured launch sequences (default on).
+void set_graphs_enabled(bool on);
+bool graphs_enabled();
 hipError_t launch_steps(const StepJob& job, hipStream_t st);
 hipError_t launch_correct(const CorrectJob& job, hipStream_t st);
 hipError_t launch_copy(int64_t nfields, int n, const double* src, const int64_t* s_offs,

@@ -338,3 +338,53 @@ def test_autotune_picks_a_plan(api, plan):
     p2 = api.Problem(n=256, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4, steps=2)
     assert api.pr_autotune_fine(p2, dev(synth.random_ic(256, [1]))) == "stream"
     plan(64, "f64", "auto")
+
+
+# ------------------------------------------------------- graph replay
+
+@pytest.fixture
+def graphs(api):
+    yield api
+    api.pr_set_graphs(True)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_graph_replays_match_eager(graphs, prec):
+    api = graphs
+    p = api.Problem(n=256, length=1.0, eps=0.01, conservative=True, stab=2.0, dt=2e-5, steps=5,
+                    fine_prec=prec)
+    u0 = dev(synth.random_ic(256, range(6)))
+    api.pr_set_graphs(False)
+    ref = api.pr_fine_propagate(p, u0)
+    api.pr_set_graphs(True)
+    ws = None
+    import ctypes as C
+    from paper_2510_07672_amd import _lib as L
+    need = L.lib().pr_fine_workspace_bytes(C.byref(p.c()), 6)
+    ws = api.workspace(need, "cuda")
+    for rep in range(4):
+        out = api.pr_fine_propagate(p, u0, ws=ws)
+        # the program's own eager work between replays
+        x = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        _ = (x * x).sum().item()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {rep}"
+
+
+def test_graph_solve_matches_eager_solve(graphs):
+    api = graphs
+    p = api.Problem(n=256, length=1.0, eps=0.01, conservative=False, stab=2.0, dt=2e-5, steps=4)
+    g = api.Coarse(dt=8e-5, steps=1)
+    u0 = dev(synth.random_ic(256, [1, 2, 3]))
+    api.pr_set_graphs(False)
+    Ue, ste = api.pr_solve(p, g, u0, 5, tol=1e-9)
+    api.pr_set_graphs(True)
+    for rep in range(2):
+        Ug, stg = api.pr_solve(p, g, u0, 5, tol=1e-9)
+        assert torch.equal(Ug, Ue)
+        assert list(stg.ic_iterations) == list(ste.ic_iterations)
+    Se = None
+    api.pr_set_graphs(False)
+    Se = api.pr_serial_fine(p, u0, 5)
+    api.pr_set_graphs(True)
+    assert torch.equal(api.pr_serial_fine(p, u0, 5), Se)
