@@ -19,6 +19,9 @@ HIPCC_FLAGS = [
     "-shared",
     # no packed-FP32 instructions: plain scalar float arithmetic only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse multiply-adds only within one source expression, so the same
+    # inline arithmetic rounds identically in every kernel that uses it
+    "-ffp-contract=on",
     "-Wall",
 ]
 

@@ -103,8 +103,41 @@ template <int LS> struct LinePanel {
   __device__ __forceinline__ int operator()(int line, int e) const { return line * LS + e + (e >> 3); }
 };
 
-// Hooks.  A prologue provides `C load(int line, int e)`; an epilogue
-// provides `void apply(int line, int e, C& v)` and a constexpr
+// Twiddles.  Stage (Ns, R) needs w^(r k) = exp(-2 pi i r k / (Ns R)) for
+// r = 1..R-1, k = 0..Ns-1.  They are kept per stage as [r-1][k], so the
+// lanes of a wave (consecutive k) read consecutive entries.
+template <int N> constexpr int stage_radix(int ns) { return (N / ns) >= 8 ? 8 : N / ns; }
+
+template <int N> constexpr int tw_offset(int ns_target) {
+  int off = 0;
+  for (int ns = 1; ns < ns_target; ns *= stage_radix<N>(ns))
+    if (ns > 1) off += (stage_radix<N>(ns) - 1) * ns;
+  return off;
+}
+
+template <int N> struct TwSize {
+  static constexpr int value = tw_offset<N>(N) > 0 ? tw_offset<N>(N) : 1;
+};
+
+// Fill the per-stage table from g[t] = exp(-2 pi i t / N).  The caller
+// synchronises the block before the first transform.
+template <int N, int NT, typename C>
+__device__ __forceinline__ void load_stage_twiddles(C* tw, const C* g, int tid) {
+  for (int ns = 1; ns < N; ns *= stage_radix<N>(ns)) {
+    const int R = stage_radix<N>(ns);
+    if (ns == 1) continue;
+    const int off = tw_offset<N>(ns), cnt = (R - 1) * ns;
+    for (int i = tid; i < cnt; i += NT) {
+      const int r = i / ns + 1, k = i % ns;
+      tw[off + i] = g[r * k * (N / (ns * R))];
+    }
+  }
+}
+
+// Hooks.  A prologue provides `C load(int i, int line, int e)` for the
+// first stage's i-th input of this thread (line `line`, element `e`) and
+// `void after_reads()`, called once all of them have been taken; an
+// epilogue provides `void apply(int line, int e, C& v)` and a constexpr
 // kWritesLds telling whether the (possibly modified) value is still
 // written to LDS afterwards.
 struct NoPro {};
@@ -112,18 +145,20 @@ struct NoEpi {
   static constexpr bool kWritesLds = true;
 };
 
-// One Stockham stage over the panel.  tw[t] = exp(-2 pi i t / N) (forward
-// table); SIGN = -1 forward, +1 inverse.
-template <int N, int R, int NS, int SIGN, int NT, typename T, class Lay, class Pro, class Epi>
+// One Stockham stage over the panel.  tw holds the forward twiddles (laid
+// out per stage by load_stage_twiddles); SIGN = -1 forward,
+// +1 inverse.  Each of the NT threads owns
+// G groups of eight elements.
+template <int N, int R, int NS, int SIGN, int NT, int G, typename T, class Lay, class Pro, class Epi>
 __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid,
                                           Pro& pro, Epi& epi) {
-  constexpr int NB = N / R;    // butterflies per line
-  constexpr int BPT = 8 / R;   // butterflies per thread
+  constexpr int NB = N / R;        // butterflies per line
+  constexpr int BPT = G * 8 / R;   // butterflies per thread
   constexpr bool kFirst = NS == 1;
   constexpr bool kLast = NS * R == N;
   constexpr bool kFromPro = kFirst && !std::is_same<Pro, NoPro>::value;
   constexpr bool kToLds = !kLast || Epi::kWritesLds;
-  cpx<T> v[8];
+  cpx<T> v[8 * G];
   int line[BPT], jj[BPT];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
@@ -132,10 +167,11 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay
     jj[q] = b % NB;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if constexpr (kFromPro) v[q * R + r] = pro.load(line[q], jj[q] + r * NB);
+      if constexpr (kFromPro) v[q * R + r] = pro.load(q * R + r, line[q], jj[q] + r * NB);
       else v[q * R + r] = buf[lay(line[q], jj[q] + r * NB)];
     }
   }
+  if constexpr (kFromPro) pro.after_reads();
   if constexpr (kToLds) __syncthreads();
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
@@ -143,7 +179,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay
     if constexpr (NS > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        cpx<T> w = tw[r * k * (N / (NS * R))];
+        cpx<T> w = tw[tw_offset<N>(NS) + (r - 1) * NS + k];
         if constexpr (SIGN > 0) w.y = -w.y;
         v[q * R + r] = cmul(v[q * R + r], w);
       }
@@ -159,24 +195,25 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay
   if constexpr (kToLds) __syncthreads();
 }
 
-template <int N, int NS, int SIGN, int NT, typename T, class Lay, class Pro, class Epi>
+template <int N, int NS, int SIGN, int NT, int G, typename T, class Lay, class Pro, class Epi>
 __device__ __forceinline__ void fft_from(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid, Pro& pro,
                                          Epi& epi) {
   if constexpr (NS < N) {
     constexpr int R = (N / NS) >= 8 ? 8 : (N / NS);
-    fft_stage<N, R, NS, SIGN, NT, T>(buf, tw, lay, tid, pro, epi);
-    fft_from<N, NS * R, SIGN, NT, T>(buf, tw, lay, tid, pro, epi);
+    fft_stage<N, R, NS, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
+    fft_from<N, NS * R, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
   }
 }
 
 // Unnormalised length-N DFT of every line in the panel, in place.
-// Requires NT * 8 == (number of lines) * N.  Unless a prologue supplies
-// the inputs, `buf` must be complete (synchronised) on entry.  On exit the
-// block is synchronised if the last stage wrote LDS.
-template <int N, int SIGN, int NT, typename T, class Lay, class Pro = NoPro, class Epi = NoEpi>
+// Requires NT * 8 * G == (number of lines) * N.  Unless a prologue
+// supplies the inputs, `buf` must be complete (synchronised) on entry.  On
+// exit the block is synchronised if the last stage wrote LDS.
+template <int N, int SIGN, int NT, typename T, int G = 1, class Lay, class Pro = NoPro,
+          class Epi = NoEpi>
 __device__ __forceinline__ void fft_lines(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid,
                                           Pro pro = Pro{}, Epi epi = Epi{}) {
-  fft_from<N, 1, SIGN, NT, T>(buf, tw, lay, tid, pro, epi);
+  fft_from<N, 1, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
 }
 
 // Deterministic block sum of one double per thread (fixed tree order).

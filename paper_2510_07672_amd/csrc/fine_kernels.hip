@@ -29,6 +29,7 @@
 // column pass plus one row pass: two read+write sweeps of the field.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <vector>
@@ -52,6 +53,15 @@ __global__ void k_tables(int n, double2* tw64, float2* tw32, double* s2) {
   }
 }
 
+// The thread index, made opaque to the optimiser.  Used at the top of a
+// loop over steps or tiles so that the address arithmetic of the unrolled
+// FFT stages is recomputed per iteration instead of being hoisted out of
+// the loop and held in registers for its whole length.
+__device__ __forceinline__ int opaque_tid(int tid) {
+  asm volatile("" : "+v"(tid));
+  return tid;
+}
+
 // --------------------------------------------------------------- row pass
 
 // Right-hand side of the step, r = (1 + S dt) v + dt f(v), on the two rows
@@ -70,10 +80,11 @@ template <int N, typename T> struct RealRowsPro {
   int r0;
   T a, dt;
   double* fsum;
-  __device__ __forceinline__ cpx<T> load(int p, int x) const {
+  __device__ __forceinline__ cpx<T> load(int, int p, int x) const {
     const cpx<T> z{(T)u[(int64_t)(r0 + 2 * p) * N + x], (T)u[(int64_t)(r0 + 2 * p + 1) * N + x]};
     return rhs_pair<T>(z, a, dt, *fsum);
   }
+  __device__ __forceinline__ void after_reads() const {}
 };
 
 // Last inverse stage: right-hand side of the next step, kept in LDS.
@@ -105,64 +116,12 @@ template <int N, typename T> struct RealRowsStore {
   }
 };
 
-template <int N, typename T, int MODE>
-__global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
-    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
-    const cpx<T>* __restrict__ tw_g, StepParams sp) {
+// Split the pair-packed spectra Z of every row pair of the tile back into
+// the two rows' half spectra and store them column-major.
+template <int N, typename T, int PAIRS, int NT, class Lay>
+__device__ __forceinline__ void row_split_store(const cpx<T>* panel, cpx<T>* S, int r0, int tid,
+                                                Lay lay) {
   using C = cpx<T>;
-  using Cfg = RowCfg<N, T>;
-  constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
-  constexpr int LS = PadLS<N>::value;
-  using Lay = LinePanel<LS>;
-  __shared__ C panel[PAIRS * LS];
-  __shared__ C tw[N];
-  __shared__ double red[NT / 64 + 1];
-
-  const int tid = threadIdx.x;
-  const int64_t f = blockIdx.x / TILES;
-  if (f >= desc->nfields) return;
-  const int tile = blockIdx.x % TILES;
-  const int r0 = tile * TR;
-  const Lay lay{};
-  for (int t = tid; t < N; t += NT) tw[t] = tw_g[t];
-  C* S = spec + f * (int64_t)(N / 2) * N;
-  const T a = (T)sp.a, dt = (T)sp.dt;
-  double fsum = 0.0;
-
-  if constexpr (MODE == ROW_FIRST) {
-    const double* u = desc->in_base + (desc->in_offs ? desc->in_offs[f] : f * (int64_t)N * N);
-    __syncthreads();
-    fft_lines<N, -1, NT, T>(panel, tw, lay, tid, RealRowsPro<N, T>{u, r0, a, dt, &fsum});
-  } else {
-    // rebuild Z_j[kx] = R_2j[kx] + i R_2j+1[kx] for kx = 0..N-1
-    for (int e = tid; e < PAIRS * (N / 2); e += NT) {
-      const int p = e % PAIRS, c = e / PAIRS;
-      const C A = S[(int64_t)c * N + r0 + 2 * p];
-      const C B = S[(int64_t)c * N + r0 + 2 * p + 1];
-      if (c == 0) {
-        panel[lay(p, 0)] = C{A.x, B.x};
-        panel[lay(p, N / 2)] = C{A.y, B.y};
-      } else {
-        panel[lay(p, c)] = C{A.x - B.y, A.y + B.x};
-        panel[lay(p, N - c)] = C{A.x + B.y, B.x - A.y};
-      }
-    }
-    __syncthreads();
-    if constexpr (MODE == ROW_LAST) {
-      const int64_t ob = desc->out_offs ? desc->out_offs[f] : f * (int64_t)N * N;
-      fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{},
-                              RealRowsStore<N, T>{desc->out_base, ob, r0, desc->out_f32});
-      return;
-    }
-    fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, RhsEpi<T>{a, dt, &fsum});
-    fft_lines<N, -1, NT, T>(panel, tw, lay, tid);
-  }
-  if (sp.conservative) {
-    const double s = block_sum<NT>(fsum, red, tid);
-    if (tid == 0) partials[f * TILES + tile] = s;
-  }
-
-  // split Z back into the two rows' half spectra and store column-major
   for (int e = tid; e < PAIRS * (N / 2); e += NT) {
     const int p = e % PAIRS, c = e / PAIRS;
     C A, B;
@@ -181,12 +140,99 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   }
 }
 
+// First row pass of a call: the real FP64 state in, half spectra out.
+template <int N, typename T>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row_first(
+    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
+    const cpx<T>* __restrict__ tw_g, StepParams sp) {
+  using C = cpx<T>;
+  using Cfg = RowCfg<N, T>;
+  constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
+  constexpr int LS = PadLS<N>::value;
+  using Lay = LinePanel<LS>;
+  __shared__ C panel[PAIRS * LS];
+  __shared__ C tw[TwSize<N>::value];
+  __shared__ double red[NT / 64 + 1];
+
+  const int tid = threadIdx.x;
+  const int64_t f = blockIdx.x / TILES;
+  if (f >= desc->nfields) return;
+  const int tile = blockIdx.x % TILES;
+  const int r0 = tile * TR;
+  const Lay lay{};
+  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  const T a = (T)sp.a, dt = (T)sp.dt;
+  double fsum = 0.0;
+  const double* u = desc->in_base + (desc->in_offs ? desc->in_offs[f] : f * (int64_t)N * N);
+  __syncthreads();
+  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, RealRowsPro<N, T>{u, r0, a, dt, &fsum});
+  if (sp.conservative) {
+    const double s = block_sum<NT>(fsum, red, tid);
+    if (tid == 0) partials[f * TILES + tile] = s;
+  }
+  row_split_store<N, T, PAIRS, NT>(panel, spec + f * (int64_t)(N / 2) * N, r0, tid, lay);
+}
+
+// Middle and last row passes: one block per tile of TR rows of one field.
+template <int N, typename T, int MODE>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
+    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
+    const cpx<T>* __restrict__ tw_g, StepParams sp) {
+  using C = cpx<T>;
+  using Cfg = RowCfg<N, T>;
+  constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
+  constexpr int LS = PadLS<N>::value;
+  using Lay = LinePanel<LS>;
+  __shared__ C panel[PAIRS * LS];
+  __shared__ C tw[TwSize<N>::value];
+  __shared__ double red[NT / 64 + 1];
+
+  const int tid = threadIdx.x;
+  const int64_t f = blockIdx.x / TILES;
+  if (f >= desc->nfields) return;
+  const int tile = blockIdx.x % TILES;
+  const int r0 = tile * TR;
+  const Lay lay{};
+  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  C* S = spec + f * (int64_t)(N / 2) * N;
+  const T a = (T)sp.a, dt = (T)sp.dt;
+  // rebuild Z_j[kx] = R_2j[kx] + i R_2j+1[kx] for kx = 0..N-1
+  for (int e = tid; e < PAIRS * (N / 2); e += NT) {
+    const int p = e % PAIRS, c = e / PAIRS;
+    const C A = S[(int64_t)c * N + r0 + 2 * p];
+    const C B = S[(int64_t)c * N + r0 + 2 * p + 1];
+    if (c == 0) {
+      panel[lay(p, 0)] = C{A.x, B.x};
+      panel[lay(p, N / 2)] = C{A.y, B.y};
+    } else {
+      panel[lay(p, c)] = C{A.x - B.y, A.y + B.x};
+      panel[lay(p, N - c)] = C{A.x + B.y, B.x - A.y};
+    }
+  }
+  __syncthreads();
+  if constexpr (MODE == ROW_LAST) {
+    const int64_t ob = desc->out_offs ? desc->out_offs[f] : f * (int64_t)N * N;
+    fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{},
+                            RealRowsStore<N, T>{desc->out_base, ob, r0, desc->out_f32});
+  } else {
+    double fsum = 0.0;
+    fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, RhsEpi<T>{a, dt, &fsum});
+    fft_lines<N, -1, NT, T>(panel, tw, lay, tid);
+    if (sp.conservative) {
+      const double s = block_sum<NT>(fsum, red, tid);
+      if (tid == 0) partials[f * TILES + tile] = s;
+    }
+    row_split_store<N, T, PAIRS, NT>(panel, S, r0, tid, lay);
+  }
+}
+
 // ------------------------------------------------------------ column pass
 
 template <typename T> struct ColLoad {
   const cpx<T>* P;
   int n;
-  __device__ __forceinline__ cpx<T> load(int line, int e) const { return P[line * n + e]; }
+  __device__ __forceinline__ cpx<T> load(int, int line, int e) const { return P[line * n + e]; }
+  __device__ __forceinline__ void after_reads() const {}
 };
 
 template <typename T> struct ColStore {
@@ -228,7 +274,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   constexpr int E0 = (N + NT - 1) / NT;  // packed-column elements per thread
   using Lay = LinePanel<LS>;
   __shared__ C panel[CT * LS];
-  __shared__ C tw[N];
+  __shared__ C tw[TwSize<N>::value];
   __shared__ double s2[N];
   __shared__ double corr_sh;
 
@@ -238,22 +284,19 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   const int c0 = (blockIdx.x % BLK) * CT;
   const Lay lay{};
   C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
-  for (int t = tid; t < N; t += NT) {
-    tw[t] = tw_g[t];
-    s2[t] = s2_g[t];
-  }
+  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
   if (tid == 0) {
     double corr = 0.0;
     if (c0 == 0 && sp.conservative) {
-      double s = 0.0;
-      for (int t = 0; t < TILES; ++t) s += partials[f * TILES + t];
-      corr = sp.dt * s;  // dt * N^2 * mean f
+      double sum = 0.0;
+      for (int i = 0; i < TILES; ++i) sum += partials[f * TILES + i];
+      corr = sp.dt * sum;  // dt * N^2 * mean f
     }
     corr_sh = corr;
   }
   __syncthreads();
   fft_lines<N, -1, NT, T>(panel, tw, lay, tid, ColLoad<T>{P, N}, DivideEpi<T>{s2, sp, c0});
-
   if (c0 == 0) {
     // packed column: z = A + iB with A the kx = 0 and B the kx = N/2
     // column spectra (both Hermitian in ky); scale A and B separately
@@ -296,7 +339,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
 
 template <int N> struct ResCfg {
   static constexpr int H = N / 2;
-  static constexpr int NT = N * N / 16;   // 8 complex elements per thread
+  static constexpr int G = N >= 128 ? 2 : 1;     // radix-8 groups per thread
+  static constexpr int NT = N * N / (16 * G);    // 8 G complex elements per thread
   static constexpr int LS = PadLS<N>::value;
   static constexpr int SLOTS = H * LS + H / 8 + 1;
 };
@@ -319,7 +363,7 @@ template <int N> struct ResRowLay {   // line = row pair p, element = kx
 template <int N, typename T, bool PACK>
 __device__ __forceinline__ void res_permute(cpx<T>* S, int tid) {
   using C = cpx<T>;
-  constexpr int H = N / 2, NT = ResCfg<N>::NT, IT = H * H / NT;  // = 4
+  constexpr int H = N / 2, NT = ResCfg<N>::NT, IT = H * H / NT;  // 4 G
   C a[IT], b[IT];
 #pragma unroll
   for (int q = 0; q < IT; ++q) {
@@ -369,7 +413,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
   using Cfg = ResCfg<N>;
   constexpr int NT = Cfg::NT, E0 = (N + NT - 1) / NT;
   __shared__ C S[Cfg::SLOTS];
-  __shared__ C tw[N];
+  __shared__ C tw[TwSize<N>::value];
   __shared__ double s2[N];
   __shared__ double red[NT / 64 + 1];
   __shared__ double corr_sh;
@@ -377,10 +421,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x;
   if (f >= desc->nfields) return;
-  for (int t = tid; t < N; t += NT) {
-    tw[t] = tw_g[t];
-    s2[t] = s2_g[t];
-  }
+  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  for (int t = tid; t < N; t += NT) s2[t] = s2_g[t];
   const T a = (T)sp.a, dt = (T)sp.dt;
   const ResRowLay<N> rlay{};
   const ResColLay<N> clay{};
@@ -389,10 +431,11 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
 
   // first right-hand side straight from the FP64 state
   const double* u = desc->in_base + (desc->in_offs ? desc->in_offs[f] : f * (int64_t)N * N);
-  fft_lines<N, -1, NT, T>(S, tw, rlay, tid, RealRowsPro<N, T>{u, 0, a, dt, &fsum});
+  fft_lines<N, -1, NT, T, Cfg::G>(S, tw, rlay, tid, RealRowsPro<N, T>{u, 0, a, dt, &fsum});
   res_permute<N, T, false>(S, tid);
 
   for (int s = 0; s < steps; ++s) {
+    const int tid = opaque_tid(threadIdx.x);
     if (sp.conservative) {
       const double tot = block_sum<NT>(fsum, red, tid);
       if (tid == 0) corr_sh = sp.dt * tot;
@@ -401,7 +444,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
     }
     fsum = 0.0;
     // column pass
-    fft_lines<N, -1, NT, T>(S, tw, clay, tid, NoPro{}, DivideEpi<T>{s2, sp, 0});
+    fft_lines<N, -1, NT, T, Cfg::G>(S, tw, clay, tid, NoPro{}, DivideEpi<T>{s2, sp, 0});
     {
       const double corr = corr_sh;
       C vals[E0];
@@ -426,17 +469,17 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
       }
       __syncthreads();
     }
-    fft_lines<N, +1, NT, T>(S, tw, clay, tid);
+    fft_lines<N, +1, NT, T, Cfg::G>(S, tw, clay, tid);
     // row pass
     res_permute<N, T, true>(S, tid);
     if (s + 1 < steps) {
-      fft_lines<N, +1, NT, T>(S, tw, rlay, tid, NoPro{}, RhsEpi<T>{a, dt, &fsum});
-      fft_lines<N, -1, NT, T>(S, tw, rlay, tid);
+      fft_lines<N, +1, NT, T, Cfg::G>(S, tw, rlay, tid, NoPro{}, RhsEpi<T>{a, dt, &fsum});
+      fft_lines<N, -1, NT, T, Cfg::G>(S, tw, rlay, tid);
       res_permute<N, T, false>(S, tid);
     }
   }
   const int64_t ob = desc->out_offs ? desc->out_offs[f] : f * (int64_t)N * N;
-  fft_lines<N, +1, NT, T>(S, tw, rlay, tid, NoPro{},
+  fft_lines<N, +1, NT, T, Cfg::G>(S, tw, rlay, tid, NoPro{},
                           RealRowsStore<N, T>{desc->out_base, ob, 0, desc->out_f32});
 }
 
@@ -453,15 +496,16 @@ static void enqueue_stream_steps(const StepJob& job, int64_t grid_fields, hipStr
   const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)job.ws.tw64 : (const void*)job.ws.tw32);
   cpx<T>* spec = (cpx<T>*)job.ws.spec;
   const CallDesc* d = job.ws.desc;
-  const dim3 grow((unsigned)(grid_fields * RC::TILES)), brow(RC::NT);
-  const dim3 gcol((unsigned)(grid_fields * CC::BLOCKS)), bcol(CC::NT);
-  k_row<N, T, ROW_FIRST><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
+  const int64_t row_tiles = grid_fields * RC::TILES, col_tiles = grid_fields * CC::BLOCKS;
+  const dim3 gfirst((unsigned)row_tiles), brow(RC::NT), bcol(CC::NT);
+  const dim3 grow((unsigned)row_tiles), glast((unsigned)row_tiles), gcol((unsigned)col_tiles);
+  k_row_first<N, T><<<gfirst, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
   for (int s = 0; s < job.steps; ++s) {
     k_col<N, T><<<gcol, bcol, 0, st>>>(d, spec, job.ws.partials, tw, job.ws.s2, job.sp);
     if (s + 1 < job.steps)
       k_row<N, T, ROW_MID><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
   }
-  k_row<N, T, ROW_LAST><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
+  k_row<N, T, ROW_LAST><<<glast, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
 }
 
 // ---- replay of captured launch sequences

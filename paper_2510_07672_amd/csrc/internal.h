@@ -13,11 +13,28 @@ enum { ROW_FIRST = 0, ROW_MID = 1, ROW_LAST = 2 };
 // one radix-8 group of eight elements per thread per FFT stage.  TR is the
 // smallest even count that gives >= 256 threads and >= 128-byte contiguous
 // runs per spectral column, capped at N.
+#ifndef PR_ROW_RUN_BYTES
+#define PR_ROW_RUN_BYTES 128   // contiguous bytes per spectral column in a row tile
+#endif
+#ifndef PR_COL_THREADS
+#define PR_COL_THREADS 256     // threads of a column-pass block (N <= 2048 / CT)
+#endif
+
+constexpr int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+
 template <int N, typename T> struct RowCfg {
-  static constexpr int kThreads = 4096 / N;
-  static constexpr int kCoalesce = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int kThreads = 4096 / N;                                   // >= 256 threads
+  static constexpr int kCoalesce = PR_ROW_RUN_BYTES / (2 * (int)sizeof(T));  // run length
+  static constexpr int kMaxThreads = 16384 / N;                               // <= 1024 threads
+  static constexpr int kMaxLds = 2 * (120 * 1024 / ((N + N / 8 + 1) * 2 * (int)sizeof(T)));
   static constexpr int kT0 = kThreads > kCoalesce ? kThreads : kCoalesce;
-  static constexpr int TR = kT0 < N ? kT0 : N;
+  static constexpr int kT1 = kT0 < kMaxThreads ? kT0 : kMaxThreads;
+  static constexpr int kT2 = pow2_floor(kT1 < kMaxLds ? kT1 : kMaxLds);
+  static constexpr int TR = kT2 < N ? kT2 : N;
   static constexpr int PAIRS = TR / 2;
   static constexpr int NT = PAIRS * N / 8;
   static constexpr int TILES = N / TR;
@@ -25,7 +42,7 @@ template <int N, typename T> struct RowCfg {
 
 // Column pass tiling: CT whole columns of one field per block.
 template <int N> struct ColCfg {
-  static constexpr int kC0 = 2048 / N;
+  static constexpr int kC0 = PR_COL_THREADS * 8 / N;
   static constexpr int CT = kC0 < N / 2 ? kC0 : N / 2;
   static constexpr int NT = CT * N / 8;
   static constexpr int BLOCKS = (N / 2) / CT;
