@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 1
+#define PR_ABI_VERSION 2
 
 typedef enum {
   PR_OK = 0,
@@ -58,7 +58,7 @@ typedef enum {
   PR_NOT_CONVERGED = 6     /* max_iter < slices stopped Parareal above tol */
 } pr_status;
 
-typedef enum { PR_F64 = 0, PR_F32 = 1, PR_BF16 = 2 } pr_dtype;
+typedef enum { PR_F64 = 0, PR_F32 = 1, PR_BF16 = 2, PR_BF16X2 = 3 } pr_dtype;
 
 /* The fine problem: Section 2 (model), Section 3.1 (grid and scheme). */
 typedef struct {
@@ -75,15 +75,49 @@ typedef struct {
                            stage-in, and carries a float state in between.  */
 } pr_problem;
 
-typedef enum { PR_G_SCHEME = 0 } pr_coarse_kind;
+typedef enum { PR_G_SCHEME = 0, PR_G_CNN = 1 } pr_coarse_kind;
+typedef enum { PR_ACT_GELU = 0, PR_ACT_TANH = 1 } pr_act;
 
-/* The coarse propagator G of Section 3.3.  PR_G_SCHEME is the numerical
- * coarse step: `steps` semi-implicit steps of `dt` in precision `prec`. */
+/* The coarse propagator G of Section 3.3.
+ *
+ * PR_G_SCHEME: the numerical coarse step, `steps` semi-implicit steps of
+ *   `dt` in precision `prec` (PR_F64 or PR_F32).
+ *
+ * PR_G_CNN: the convolutional network of Section 3.2, one application per
+ *   slice: 3x3 convolutions with circular padding 1 (torch.nn.Conv2d
+ *   cross-correlation), widths 1 -> C -> ... -> C -> 1 (`n_layers`
+ *   convolutions, hidden width `channels`), the activation `act` after
+ *   every convolution except the last, then
+ *     G(u) = u + net(u)             if residual (else net(u)),
+ *     G(u) += mean(u) - mean(G(u))  if mass_fix (the uniform shift that
+ *                                   keeps the mass, Section 3.2),
+ *     G(u) = clamp(G(u), lim_lo, lim_hi) if limiter (bound limiter).
+ *   weights: device float, the layers' torch Conv2d weights [Cout][Cin][3][3]
+ *            concatenated in layer order; biases: device float [Cout] per
+ *            layer, concatenated.  Read on every call; the library keeps a
+ *            packed copy in the workspace only for the duration of a call.
+ *   prec: PR_F32 (every layer in FP32 on the vector ALU), PR_BF16 (hidden
+ *         layers on the bf16 matrix cores with FP32 accumulation; weights
+ *         and activations rounded to bfloat16), or PR_BF16X2 (the same with
+ *         each activation carried as a hi + lo bfloat16 pair, two products
+ *         per term; needs channels <= 48).  The first layer reads the FP64
+ *         state unrounded and the last writes FP64.
+ *   Needs N >= 32, channels in {8, 16, 32, 48, 64} and, when n_layers > 2,
+ *   a multiple of 16; PR_ERR_UNSUPPORTED otherwise. */
 typedef struct {
-  int32_t kind;   /* PR_G_SCHEME                                */
-  double dt;      /* coarse step > 0 (one slice: c * dt*)       */
-  int32_t steps;  /* coarse steps per slice >= 1                */
-  int32_t prec;   /* PR_F64 or PR_F32                           */
+  int32_t kind;         /* PR_G_SCHEME or PR_G_CNN                      */
+  double dt;            /* scheme: coarse step > 0 (one slice: c * dt*)  */
+  int32_t steps;        /* scheme: coarse steps per slice >= 1           */
+  int32_t prec;         /* see above                                     */
+  int32_t n_layers;     /* CNN: convolutions, >= 2                       */
+  int32_t channels;     /* CNN: hidden width C                           */
+  const float* weights; /* CNN: device, concatenated Conv2d weights      */
+  const float* biases;  /* CNN: device, concatenated biases              */
+  int32_t act;          /* CNN: PR_ACT_GELU (exact erf) or PR_ACT_TANH   */
+  int32_t residual;     /* CNN: 1: G(u) = u + net(u)                     */
+  int32_t mass_fix;     /* CNN: 1: restore the input's mean              */
+  int32_t limiter;      /* CNN: 1: clamp to [lim_lo, lim_hi]             */
+  double lim_lo, lim_hi;
 } pr_coarse;
 
 /* Host-side report of pr_solve.  Pointers may be NULL. */

@@ -82,24 +82,28 @@ def bf16(x: torch.Tensor) -> torch.Tensor:
 
 
 def forward(u, weights: Sequence[torch.Tensor], biases: Sequence[torch.Tensor],
-            spec: CnnSpec, emulate_bf16: bool = False) -> np.ndarray:
+            spec: CnnSpec, emulate_bf16=False) -> np.ndarray:
     """G(u) for u [B, N, N] (numpy or torch); returns float64 numpy.
 
-    With emulate_bf16 the hidden activations and the weights of the hidden
-    and output layers are rounded to bfloat16 where a bfloat16 kernel
-    stores them (the first layer reads the state unrounded); all sums stay
-    float64."""
+    emulate_bf16 = True (or "all"): the activations after every layer but
+    the last, and the weights of the hidden (C -> C) layers, are rounded to
+    bfloat16 where a bfloat16 kernel stores them (the first and last layers
+    keep their weights and the first reads the state unrounded);
+    "weights": only those weights are rounded.
+    All sums stay float64."""
+    round_w = emulate_bf16 in (True, "all", "weights")
+    round_a = emulate_bf16 in (True, "all")
     ut = torch.as_tensor(np.asarray(u, dtype=np.float64))
     x = ut[:, None]
     L = spec.n_layers
     for l in range(L):
         W, b = weights[l].to(torch.float64), biases[l].to(torch.float64)
-        if emulate_bf16 and l > 0:
+        if round_w and 0 < l < L - 1:
             W = bf16(W)
         x = conv3x3_periodic(x, W, b)
         if l < L - 1:
             x = _act(x, spec.act)
-            if emulate_bf16:
+            if round_a:
                 x = bf16(x)
     net = x[:, 0]
     out = ut + net if spec.residual else net

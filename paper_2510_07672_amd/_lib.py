@@ -13,8 +13,9 @@ from .build import LIB
 
 PR_OK, PR_ERR_INVALID_ARG, PR_ERR_UNSUPPORTED, PR_ERR_WORKSPACE, PR_ERR_DEVICE, \
     PR_ERR_NUMERIC, PR_NOT_CONVERGED = range(7)
-PR_F64, PR_F32, PR_BF16 = 0, 1, 2
-PR_G_SCHEME = 0
+PR_F64, PR_F32, PR_BF16, PR_BF16X2 = 0, 1, 2, 3
+PR_G_SCHEME, PR_G_CNN = 0, 1
+PR_ACT_GELU, PR_ACT_TANH = 0, 1
 
 EXPORTED = [
     "pr_fine_workspace_bytes", "pr_fine_propagate",
@@ -36,7 +37,10 @@ class Problem(C.Structure):
 
 class Coarse(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("steps", C.c_int32),
-                ("prec", C.c_int32)]
+                ("prec", C.c_int32), ("n_layers", C.c_int32), ("channels", C.c_int32),
+                ("weights", C.c_void_p), ("biases", C.c_void_p), ("act", C.c_int32),
+                ("residual", C.c_int32), ("mass_fix", C.c_int32), ("limiter", C.c_int32),
+                ("lim_lo", C.c_double), ("lim_hi", C.c_double)]
 
 
 class Stats(C.Structure):

@@ -45,7 +45,42 @@ class Coarse:
     prec: str = "f64"
 
     def c(self) -> L.Coarse:
-        return L.Coarse(L.PR_G_SCHEME, self.dt, self.steps, _PREC[self.prec])
+        return L.Coarse(kind=L.PR_G_SCHEME, dt=self.dt, steps=self.steps, prec=_PREC[self.prec])
+
+
+_CNN_PREC = {"f32": L.PR_F32, "bf16": L.PR_BF16, "bf16x2": L.PR_BF16X2}
+
+
+class CnnCoarse:
+    """Convolutional coarse propagator (Section 3.2) with torch Conv2d
+    weights: weights[l] [Cout, Cin, 3, 3], biases[l] [Cout], widths
+    1 -> C -> ... -> C -> 1.  The tensors are concatenated into one FP32
+    device buffer each, which this object keeps alive."""
+
+    def __init__(self, weights, biases, act="gelu", residual=True, mass_fix=False,
+                 limiter=None, prec="bf16", device="cuda"):
+        if len(weights) != len(biases) or len(weights) < 2:
+            raise ValueError("need >= 2 layers with one bias each")
+        C = weights[0].shape[0]
+        for l, (w, b) in enumerate(zip(weights, biases)):
+            cin = 1 if l == 0 else C
+            cout = 1 if l == len(weights) - 1 else C
+            if tuple(w.shape) != (cout, cin, 3, 3) or tuple(b.shape) != (cout,):
+                raise ValueError(f"layer {l}: expected W {(cout, cin, 3, 3)} and b {(cout,)}")
+        self.n_layers, self.channels = len(weights), C
+        self.W = torch.cat([w.reshape(-1) for w in weights]).to(device=device, dtype=torch.float32).contiguous()
+        self.B = torch.cat([b.reshape(-1) for b in biases]).to(device=device, dtype=torch.float32).contiguous()
+        self.act, self.residual, self.mass_fix, self.limiter = act, residual, mass_fix, limiter
+        self.prec = prec
+
+    def c(self) -> L.Coarse:
+        lo, hi = self.limiter if self.limiter is not None else (0.0, 0.0)
+        return L.Coarse(kind=L.PR_G_CNN, prec=_CNN_PREC[self.prec], n_layers=self.n_layers,
+                        channels=self.channels, weights=self.W.data_ptr(),
+                        biases=self.B.data_ptr(),
+                        act=L.PR_ACT_GELU if self.act == "gelu" else L.PR_ACT_TANH,
+                        residual=int(self.residual), mass_fix=int(self.mass_fix),
+                        limiter=int(self.limiter is not None), lim_lo=lo, lim_hi=hi)
 
 
 @dataclass

@@ -9,7 +9,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpr.so")
-SOURCES = ["api.hip", "fine_kernels.hip"]
+SOURCES = ["api.hip", "fine_kernels.hip", "cnn_kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

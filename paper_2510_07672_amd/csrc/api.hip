@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -59,12 +60,28 @@ pr_status check_problem(const pr_problem* p) {
   return PR_OK;
 }
 
-pr_status check_coarse(const pr_coarse* g) {
+pr_status check_coarse(const pr_coarse* g, int n) {
   if (!g) return fail(PR_ERR_INVALID_ARG, "coarse is NULL");
-  if (g->kind != PR_G_SCHEME) return fail(PR_ERR_UNSUPPORTED, "coarse kind %d not supported", g->kind);
-  if (!(g->dt > 0) || !std::isfinite(g->dt)) return fail(PR_ERR_INVALID_ARG, "coarse dt must be finite and > 0");
-  if (g->steps < 1) return fail(PR_ERR_INVALID_ARG, "coarse steps must be >= 1");
-  if (g->prec != PR_F64 && g->prec != PR_F32) return fail(PR_ERR_UNSUPPORTED, "coarse prec must be PR_F64 or PR_F32");
+  if (g->kind == PR_G_SCHEME) {
+    if (!(g->dt > 0) || !std::isfinite(g->dt)) return fail(PR_ERR_INVALID_ARG, "coarse dt must be finite and > 0");
+    if (g->steps < 1) return fail(PR_ERR_INVALID_ARG, "coarse steps must be >= 1");
+    if (g->prec != PR_F64 && g->prec != PR_F32) return fail(PR_ERR_UNSUPPORTED, "coarse prec must be PR_F64 or PR_F32");
+    return PR_OK;
+  }
+  if (g->kind != PR_G_CNN) return fail(PR_ERR_UNSUPPORTED, "coarse kind %d not supported", g->kind);
+  if (n < 32) return fail(PR_ERR_UNSUPPORTED, "the CNN coarse propagator needs N >= 32");
+  if (g->n_layers < 2 || g->n_layers > 64) return fail(PR_ERR_INVALID_ARG, "n_layers must be in [2, 64]");
+  const int C = g->channels;
+  if (C != 8 && C != 16 && C != 32 && C != 48 && C != 64)
+    return fail(PR_ERR_UNSUPPORTED, "channels=%d: must be 8, 16, 32, 48 or 64", C);
+  if (g->n_layers > 2 && C % 16 != 0)
+    return fail(PR_ERR_UNSUPPORTED, "hidden layers need channels to be a multiple of 16");
+  if (g->prec != PR_F32 && g->prec != PR_BF16 && g->prec != PR_BF16X2)
+    return fail(PR_ERR_UNSUPPORTED, "CNN prec must be PR_F32, PR_BF16 or PR_BF16X2");
+  if (g->prec == PR_BF16X2 && C > 48) return fail(PR_ERR_UNSUPPORTED, "PR_BF16X2 needs channels <= 48");
+  if (!g->weights || !g->biases) return fail(PR_ERR_INVALID_ARG, "CNN weights / biases are NULL");
+  if (g->act != PR_ACT_GELU && g->act != PR_ACT_TANH) return fail(PR_ERR_INVALID_ARG, "act must be PR_ACT_GELU or PR_ACT_TANH");
+  if (g->limiter && !(g->lim_lo <= g->lim_hi)) return fail(PR_ERR_INVALID_ARG, "limiter needs lim_lo <= lim_hi");
   return PR_OK;
 }
 
@@ -137,8 +154,72 @@ StepJob make_job(const pr_problem* p, double dt, int steps, bool f32, int64_t nf
   return j;
 }
 
+CnnWs carve_cnn(Carver& c, int n, const pr_coarse* g, int64_t nfields) {
+  CnnWs w{};
+  const int C = g->channels, L = g->n_layers;
+  const int kp = (9 * C + 31) / 32 * 32;
+  const bool f32 = g->prec == PR_F32, split = g->prec == PR_BF16X2;
+  w.wpack = c.take(f32 || L < 3 ? 16 : (size_t)(L - 2) * C * kp * 2);
+  const size_t act = (size_t)nfields * n * n * C * (f32 ? 4 : 2) * (split ? 2 : 1);
+  w.act[0] = c.take(act);
+  w.act[1] = c.take(act);
+  w.partials = (double*)c.take((size_t)nfields * (n / 16) * (n / 16) * 8);
+  return w;
+}
+
+// Workspace of one coarse propagator call on up to `nfields` fields.
+struct CoarseWs {
+  FineWs fine;   // numerical coarse step
+  CnnWs cnn;     // network
+};
+
+CoarseWs carve_coarse(Carver& c, const pr_problem* p, const pr_coarse* g, int64_t nfields) {
+  CoarseWs w{};
+  if (g->kind == PR_G_CNN) w.cnn = carve_cnn(c, p->n, g, nfields);
+  else w.fine = carve_fine(c, p->n, g->prec == PR_F32, nfields);
+  return w;
+}
+
+pr_status cnn_lds_once() {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] { err = cnn_set_lds_limits(); });
+  if (err != hipSuccess) return fail(PR_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(err));
+  return PR_OK;
+}
+
+CnnJob make_cnn_job(const pr_problem* p, const pr_coarse* g, const CnnWs& w) {
+  CnnJob j{};
+  j.n = p->n;
+  j.n_layers = g->n_layers;
+  j.channels = g->channels;
+  j.prec = g->prec;
+  j.act = g->act;
+  j.residual = g->residual;
+  j.mass_fix = g->mass_fix;
+  j.limiter = g->limiter;
+  j.lim_lo = g->lim_lo;
+  j.lim_hi = g->lim_hi;
+  j.W = g->weights;
+  j.B = g->biases;
+  j.ws = w;
+  return j;
+}
+
+// Per-call set-up of a coarse propagator (tables or packed weights).
+hipError_t coarse_setup(const pr_problem* p, const pr_coarse* g, const CoarseWs& w, hipStream_t s) {
+  if (g->kind == PR_G_CNN) return launch_cnn_pack(make_cnn_job(p, g, w.cnn), s);
+  return launch_tables(p->n, w.fine, s);
+}
+
+// G on `nfields` fields addressed through optional offset tables.
+hipError_t coarse_run(const pr_problem* p, const pr_coarse* g, const CoarseWs& w, int64_t nfields,
+                      const double* in_base, const int64_t* in_offs, double* out_base,
+                      const int64_t* out_offs, hipStream_t s);
+
 struct SolveWs {
-  FineWs fine, coarse;
+  FineWs fine;
+  CoarseWs coarse;
   double* gcache;          // [B][s][N][N]
   void* fbuf;              // [B][s][N][N] fine precision
   double* gtmp;            // [B][N][N]
@@ -157,7 +238,7 @@ SolveWs carve_solve(void* base, const pr_problem* p, const pr_coarse* g, int64_t
   const size_t n2 = (size_t)p->n * p->n;
   const bool f32 = p->fine_prec == PR_F32;
   w.fine = carve_fine(c, p->n, f32, B * s);
-  w.coarse = carve_fine(c, p->n, g->prec == PR_F32, B);
+  w.coarse = carve_coarse(c, p, g, B);
   w.gcache = (double*)c.take((size_t)B * s * n2 * 8);
   w.fbuf = c.take((size_t)B * s * n2 * (f32 ? 4 : 8));
   w.gtmp = (double*)c.take((size_t)B * n2 * 8);
@@ -189,6 +270,27 @@ struct Events {
       if (x) (void)hipEventDestroy(x);
   }
 };
+
+hipError_t coarse_run(const pr_problem* p, const pr_coarse* g, const CoarseWs& w, int64_t nfields,
+                      const double* in_base, const int64_t* in_offs, double* out_base,
+                      const int64_t* out_offs, hipStream_t s) {
+  if (g->kind == PR_G_CNN) {
+    CnnJob j = make_cnn_job(p, g, w.cnn);
+    j.nfields = nfields;
+    j.in_base = in_base;
+    j.in_offs = in_offs;
+    j.out_base = out_base;
+    j.out_offs = out_offs;
+    return launch_cnn(j, s);
+  }
+  StepJob j = make_job(p, g->dt, g->steps, g->prec == PR_F32, nfields, w.fine);
+  j.in_base = in_base;
+  j.in_offs = in_offs;
+  j.out_base = out_base;
+  j.out_offs = out_offs;
+  j.out_f32 = 0;
+  return launch_steps(j, s);
+}
 
 }  // namespace
 
@@ -243,9 +345,9 @@ pr_status pr_fine_propagate(const pr_problem* p, int64_t nfields, const double* 
 }
 
 size_t pr_coarse_workspace_bytes(const pr_problem* p, const pr_coarse* g, int64_t nfields) {
-  if (check_problem(p) != PR_OK || check_coarse(g) != PR_OK || nfields < 0) return 0;
+  if (check_problem(p) != PR_OK || check_coarse(g, p->n) != PR_OK || nfields < 0) return 0;
   Carver c(nullptr);
-  carve_fine(c, p->n, g->prec == PR_F32, nfields);
+  carve_coarse(c, p, g, nfields);
   return c.used;
 }
 
@@ -254,23 +356,19 @@ pr_status pr_coarse_apply(const pr_problem* p, const pr_coarse* g, int64_t nfiel
                           void* stream) {
   pr_status st = check_problem(p);
   if (st != PR_OK) return st;
-  if ((st = check_coarse(g)) != PR_OK) return st;
+  if ((st = check_coarse(g, p->n)) != PR_OK) return st;
   if (nfields < 0) return fail(PR_ERR_INVALID_ARG, "nfields < 0");
   if (nfields == 0) return PR_OK;
   if (!u_in || !g_out) return fail(PR_ERR_INVALID_ARG, "u_in / g_out is NULL");
   if (u_in == g_out) return fail(PR_ERR_INVALID_ARG, "g_out may not alias u_in");
-  const bool f32 = g->prec == PR_F32;
   Carver c(ws);
-  FineWs w = carve_fine(c, p->n, f32, nfields);
+  CoarseWs w = carve_coarse(c, p, g, nfields);
   if (!ws || ws_bytes < c.used)
     return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, c.used);
+  if (g->kind == PR_G_CNN && (st = cnn_lds_once()) != PR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  StepJob j = make_job(p, g->dt, g->steps, f32, nfields, w);
-  j.in_base = u_in;
-  j.out_base = g_out;
-  j.out_f32 = 0;
-  PR_HIP(launch_tables(p->n, w, s));
-  PR_HIP(launch_steps(j, s));
+  PR_HIP(coarse_setup(p, g, w, s));
+  PR_HIP(coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s));
   return PR_OK;
 }
 
@@ -302,7 +400,7 @@ pr_status pr_correct(int64_t nfields, int32_t n, const void* f, pr_dtype f_dtype
 
 size_t pr_solve_workspace_bytes(const pr_problem* p, const pr_coarse* g, int64_t n_ics,
                                 int32_t n_slices) {
-  if (check_problem(p) != PR_OK || check_coarse(g) != PR_OK || n_ics < 0 || n_slices < 1) return 0;
+  if (check_problem(p) != PR_OK || check_coarse(g, p->n) != PR_OK || n_ics < 0 || n_slices < 1) return 0;
   return carve_solve(nullptr, p, g, n_ics, n_slices).bytes;
 }
 
@@ -311,7 +409,7 @@ pr_status pr_solve(const pr_problem* p, const pr_coarse* g, int64_t n_ics, int32
                    void* ws, size_t ws_bytes, void* stream) {
   pr_status st = check_problem(p);
   if (st != PR_OK) return st;
-  if ((st = check_coarse(g)) != PR_OK) return st;
+  if ((st = check_coarse(g, p->n)) != PR_OK) return st;
   if (n_ics < 0) return fail(PR_ERR_INVALID_ARG, "n_ics < 0");
   if (n_slices < 1) return fail(PR_ERR_INVALID_ARG, "n_slices < 1");
   if (!(tol >= 0)) return fail(PR_ERR_INVALID_ARG, "tol must be >= 0");
@@ -355,20 +453,14 @@ pr_status pr_solve(const pr_problem* p, const pr_coarse* g, int64_t n_ics, int32
   PR_HIP(hipMemcpyAsync(w.off_s, off_s.data(), B * 8, hipMemcpyHostToDevice, hs));
   PR_HIP(hipMemcpyAsync(w.act, act.data(), B * 4, hipMemcpyHostToDevice, hs));
   PR_HIP(launch_tables(N, w.fine, hs));
-  PR_HIP(launch_tables(N, w.coarse, hs));
+  if (g->kind == PR_G_CNN && (st = cnn_lds_once()) != PR_OK) return st;
+  PR_HIP(coarse_setup(p, g, w.coarse, hs));
   // U_0 = u0
   PR_HIP(launch_copy(B, N, u0, nullptr, U, w.off_u, hs));
 
-  StepJob gj = make_job(p, g->dt, g->steps, g->prec == PR_F32, B, w.coarse);
   // initial coarse sweep: U^0_{j+1} = G(U^0_j), kept as the cache G(U^0_j)
   for (int32_t j = 0; j < s; ++j) {
-    gj.nfields = B;
-    gj.in_base = U + j * n2;
-    gj.in_offs = w.off_u;
-    gj.out_base = w.gcache + j * n2;
-    gj.out_offs = w.off_s;
-    gj.out_f32 = 0;
-    PR_HIP(launch_steps(gj, hs));
+    PR_HIP(coarse_run(p, g, w.coarse, B, U + j * n2, w.off_u, w.gcache + j * n2, w.off_s, hs));
     PR_HIP(launch_copy(B, N, w.gcache + j * n2, w.off_s, U + (j + 1) * n2, w.off_u, hs));
   }
   PR_HIP(hipStreamSynchronize(hs));
@@ -415,13 +507,7 @@ pr_status pr_solve(const pr_problem* p, const pr_coarse* g, int64_t n_ics, int32
     PR_HIP(hipEventRecord(ev.e[1], hs));
     // sequential correction sweep
     for (int32_t j = k - 1; j < s; ++j) {
-      gj.nfields = n_act;
-      gj.in_base = U + j * n2;
-      gj.in_offs = w.off_u;
-      gj.out_base = w.gtmp;
-      gj.out_offs = nullptr;
-      gj.out_f32 = 0;
-      PR_HIP(launch_steps(gj, hs));
+      PR_HIP(coarse_run(p, g, w.coarse, n_act, U + j * n2, w.off_u, w.gtmp, nullptr, hs));
       CorrectJob cj{};
       cj.nfields = n_act;
       cj.n = N;

@@ -107,6 +107,35 @@ struct CorrectJob {
   int update_cache;
 };
 
+// ---- convolutional coarse propagator
+
+enum { kActGelu = 0, kActTanh = 1 };
+enum { kCnnF32 = 1, kCnnBf16 = 2, kCnnBf16x2 = 3 };   // same values as pr_dtype
+
+struct CnnWs {
+  void* wpack;       // bfloat16 [L-2][C][KP] packed hidden-layer weights
+  void* act[2];      // ping-pong activations [nfields][N][N][C] (x2 for hi+lo)
+  double* partials;  // [nfields][(N/16)^2] FP64 sums of G(u) - u
+};
+
+struct CnnJob {
+  int n, n_layers, channels, prec, act, residual, mass_fix, limiter;
+  double lim_lo, lim_hi;
+  int64_t nfields;
+  const float* W;            // concatenated torch Conv2d weights
+  const float* B;            // concatenated biases
+  const double* in_base;     // field i at in_base + (in_offs ? in_offs[i] : i N^2)
+  const int64_t* in_offs;
+  double* out_base;
+  const int64_t* out_offs;
+  CnnWs ws;
+};
+
+hipError_t launch_cnn_pack(const CnnJob& j, hipStream_t st);
+hipError_t launch_cnn(const CnnJob& j, hipStream_t st);
+size_t cnn_lds_bytes(int C, bool split);
+hipError_t cnn_set_lds_limits();
+
 hipError_t launch_tables(int n, const FineWs& ws, hipStream_t st);
 // Process-wide switch for replaying captured launch sequences (default on).
 void set_graphs_enabled(bool on);

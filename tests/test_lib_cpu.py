@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 1
+    assert lib.pr_abi_version() == 2
 
 
 def test_library_exports_match_nm(L):
@@ -94,8 +94,8 @@ def test_correct_rejects_aliases(L):
 def test_solve_validation(L):
     lib = L.lib()
     p = _prob(L)
-    g = L.Coarse(L.PR_G_SCHEME, 1e-2, 1, L.PR_F64)
-    bad_g = L.Coarse(7, 1e-2, 1, L.PR_F64)
+    g = L.Coarse(kind=L.PR_G_SCHEME, dt=1e-2, steps=1, prec=L.PR_F64)
+    bad_g = L.Coarse(kind=7, dt=1e-2, steps=1, prec=L.PR_F64)
     args = (2, 8, C.c_void_p(16), C.c_void_p(32), 1e-10, 8, None, C.c_void_p(64), 1 << 40, None)
     assert lib.pr_solve(C.byref(p), C.byref(bad_g), *args) == L.PR_ERR_UNSUPPORTED
     assert lib.pr_solve(C.byref(p), C.byref(g), 2, 0, *args[2:]) == L.PR_ERR_INVALID_ARG
@@ -112,3 +112,24 @@ def test_status_strings(L):
     lib = L.lib()
     for s in range(7):
         assert lib.pr_status_string(s).startswith(b"PR_")
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(channels=24), 2), (dict(channels=8, n_layers=3), 2), (dict(prec=0), 2),
+    (dict(prec=3, channels=64), 2), (dict(n_layers=1), 1), (dict(act=5), 1),
+    (dict(limiter=1, lim_lo=1.0, lim_hi=0.0), 1), (dict(weights=None), 1),
+])
+def test_cnn_coarse_validation(L, kw, status):
+    lib = L.lib()
+    p = _prob(L)
+    d = dict(kind=L.PR_G_CNN, prec=L.PR_BF16, n_layers=4, channels=32, weights=64, biases=128,
+             act=L.PR_ACT_GELU, residual=1)
+    d.update(kw)
+    g = L.Coarse(**d)
+    st = lib.pr_coarse_apply(C.byref(p), C.byref(g), 1, C.c_void_p(16), C.c_void_p(32),
+                             C.c_void_p(64), 1 << 40, None)
+    assert st == status, lib.pr_last_error()
+    p16 = _prob(L, n=16)
+    g_ok = L.Coarse(**dict(d, **{k: v for k, v in dict(channels=32, n_layers=4, prec=L.PR_BF16, act=0, limiter=0, weights=64).items()}))
+    assert lib.pr_coarse_apply(C.byref(p16), C.byref(g_ok), 1, C.c_void_p(16), C.c_void_p(32),
+                               C.c_void_p(64), 1 << 40, None) == L.PR_ERR_UNSUPPORTED
