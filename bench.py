@@ -32,15 +32,15 @@ CONFIGS = {
     "c1": dict(workload="classic AC 64x64 eps=0.02 FP64, 1 IC x 8 slices x 100 steps dt=1e-4, "
                         "numerical G (1 step of 0.01)",
                n=64, eps=0.02, dt=1e-4, steps=100, slices=8, ics=1, conservative=False,
-               seed0=0, g_steps=1),
+               seed0=0, g_steps=1, cnn=(4, 32)),
     "c2": dict(workload="classic AC 256x256 eps=0.01, 8 ICs x 64 slices x 200 steps dt=2e-5 "
                         "(512 fine solves per launch), numerical G (1 step of 4e-3)",
                n=256, eps=0.01, dt=2e-5, steps=200, slices=64, ics=8, conservative=False,
-               seed0=0, g_steps=1),
+               seed0=0, g_steps=1, cnn=(4, 32)),
     "c3": dict(workload="mass-conservative AC 512x512 eps=0.01, 16 ICs x 128 slices x 100 steps "
                         "dt=1e-5 (2048 fine solves per launch), numerical G (1 step of 1e-3)",
                n=512, eps=0.01, dt=1e-5, steps=100, slices=128, ics=16, conservative=True,
-               seed0=0, g_steps=1),
+               seed0=0, g_steps=1, cnn=(6, 48)),
 }
 
 
@@ -167,6 +167,49 @@ def calib_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"calib_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def make_cnn(api, cfg, prec):
+    """The workload's network with torch Conv2d default initialisation under
+    a fixed seed (no trained weights are available)."""
+    import math
+    import torch
+    L, C = cfg["cnn"]
+    gen = torch.Generator().manual_seed(0)
+    widths = [1] + [C] * (L - 1) + [1]
+    ws, bs = [], []
+    for l in range(L):
+        bound = 1.0 / math.sqrt(widths[l] * 9)
+        ws.append((torch.rand((widths[l + 1], widths[l], 3, 3), generator=gen) * 2 - 1) * bound)
+        bs.append((torch.rand((widths[l + 1],), generator=gen) * 2 - 1) * bound)
+    return api.CnnCoarse(ws, bs, act="gelu", residual=True, prec=prec)
+
+
+def cnn_kernel_rate(api, p, g, u0, reps=20):
+    """Average duration of one network application on the batch (torch events
+    on the launch stream) and its matrix-core rate: the hidden layers'
+    2 * 9 * C^2 flops per pixel run on bf16 MFMA."""
+    import torch
+    out = torch.empty_like(u0)
+    api.pr_coarse_apply(p, g, u0, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        api.pr_coarse_apply(p, g, u0, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    B, n = u0.shape[0], u0.shape[-1]
+    L, C = g.n_layers, g.channels
+    mfma_flops = 2 * 9 * C * C * (L - 2) * B * n * n
+    all_flops = 2 * 9 * (C + C * C * (L - 2) + C) * B * n * n
+    peak = {"bf16": 2500.0, "bf16x2": 2500.0, "f32": 157.3}[g.prec]
+    eff = mfma_flops * (2 if g.prec == "bf16x2" else 1)
+    return {"ms_per_call": round(ms, 4), "fields": B, "layers": L, "channels": C, "prec": g.prec,
+            "model_tflops": round(all_flops / ms / 1e9, 1),
+            "mfma_tflops": round(eff / ms / 1e9, 1), "peak_tflops": peak,
+            "mfma_frac": round(eff / ms / 1e9 / peak, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +220,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--kmax", type=int, default=16)
+    ap.add_argument("--coarse", default="num", choices=["num", "cnn"],
+                    help="numerical coarse step, or the convolutional network of the workload")
+    ap.add_argument("--cnn-prec", default="bf16", choices=["bf16", "bf16x2", "f32"])
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -196,7 +242,10 @@ def main():
     n, s, B, c = cfg["n"], cfg["slices"], cfg["ics"], cfg["steps"]
     p = api.Problem(n=n, length=1.0, eps=cfg["eps"], conservative=cfg["conservative"], stab=2.0,
                     dt=cfg["dt"], steps=c, fine_prec=args.prec)
-    g = api.Coarse(dt=cfg["dt"] * c / cfg["g_steps"], steps=cfg["g_steps"], prec="f64")
+    if args.coarse == "cnn":
+        g = make_cnn(api, cfg, args.cnn_prec)
+    else:
+        g = api.Coarse(dt=cfg["dt"] * c / cfg["g_steps"], steps=cfg["g_steps"], prec="f64")
     u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
     U = torch.empty((B, s + 1, n, n), dtype=torch.float64, device="cuda")
     ws = None
@@ -246,6 +295,9 @@ def main():
                    "fine_solves_per_launch": B * s, "fine_prec": args.prec},
         "roofline": roof,
     }
+    if args.coarse == "cnn":
+        out["coarse_kernel"] = cnn_kernel_rate(api, p, g, u0)
+        out["config"]["coarse"] = f"u + CNN(u), {g.n_layers} conv layers x {g.channels} ch, GELU, {g.prec}, seed-0 weights"
     if not args.no_parareal:
         out["parareal"] = parareal_vs_serial(api, p, g, u0, s, args.kmax)
     if not args.no_cpu:

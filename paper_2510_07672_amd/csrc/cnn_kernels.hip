@@ -68,16 +68,19 @@ __global__ void k_cnn_pack(const float* __restrict__ W, int cin, int cout, int k
 
 constexpr int kTile = 16;  // output tile side of the first and last layers
 
+// Each thread produces 8 consecutive channels of one pixel (one 16-byte
+// store in bfloat16), so consecutive threads write consecutive memory.
 template <int C, typename TO>
 __global__ __launch_bounds__(256) void k_cnn_first(const double* __restrict__ u_base,
                                                    const int64_t* __restrict__ u_offs, int n,
                                                    const float* __restrict__ W,
                                                    const float* __restrict__ b, int act,
                                                    TO* __restrict__ out, TO* __restrict__ out_lo) {
+  static_assert(C % 8 == 0, "width must be a multiple of 8");
   __shared__ float sw[C * 9], sb[C];
   __shared__ float tile[(kTile + 2) * (kTile + 2)];
   const int tid = threadIdx.x;
-  const int tpr = n / kTile;
+  const int tpr = n / kTile, m = n - 1;
   const int64_t f = blockIdx.x / (tpr * tpr);
   const int t = (int)(blockIdx.x % (tpr * tpr));
   const int y0 = (t / tpr) * kTile, x0 = (t % tpr) * kTile;
@@ -86,21 +89,39 @@ __global__ __launch_bounds__(256) void k_cnn_first(const double* __restrict__ u_
   for (int i = tid; i < C; i += 256) sb[i] = b[i];
   for (int i = tid; i < (kTile + 2) * (kTile + 2); i += 256) {
     const int ty = i / (kTile + 2), tx = i % (kTile + 2);
-    const int gy = (y0 + ty - 1 + n) % n, gx = (x0 + tx - 1 + n) % n;
-    tile[i] = (float)u[(int64_t)gy * n + gx];
+    tile[i] = (float)u[(int64_t)((y0 + ty - 1) & m) * n + ((x0 + tx - 1) & m)];
   }
   __syncthreads();
-  const int py = tid / kTile, px = tid % kTile;
-  float v[9];
+  constexpr int C8 = C / 8;
+  for (int item = tid; item < kTile * kTile * C8; item += 256) {
+    const int c8 = item % C8, px = item / C8;
+    const int py = px / kTile, pxx = px % kTile;
+    float v[9];
 #pragma unroll
-  for (int tp = 0; tp < 9; ++tp) v[tp] = tile[(py + tp / 3) * (kTile + 2) + px + tp % 3];
-  const int64_t o = ((f * n + y0 + py) * (int64_t)n + x0 + px) * C;
-#pragma unroll 4
-  for (int co = 0; co < C; ++co) {
-    float s = sb[co];
+    for (int tp = 0; tp < 9; ++tp) v[tp] = tile[(py + tp / 3) * (kTile + 2) + pxx + tp % 3];
+    float r8[8];
 #pragma unroll
-    for (int tp = 0; tp < 9; ++tp) s += sw[co * 9 + tp] * v[tp];
-    store_act(out, out_lo, o + co, act_fn(s, act));
+    for (int j = 0; j < 8; ++j) {
+      const int co = c8 * 8 + j;
+      float s = sb[co];
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp) s += sw[co * 9 + tp] * v[tp];
+      r8[j] = act_fn(s, act);
+    }
+    const int64_t o = ((f * n + y0 + py) * (int64_t)n + x0 + pxx) * C + c8 * 8;
+    if constexpr (sizeof(TO) == 2) {
+      bf16x8 h, l;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        h[j] = (__bf16)r8[j];
+        l[j] = (__bf16)(r8[j] - (float)h[j]);
+      }
+      *(bf16x8*)&out[o] = h;
+      if (out_lo) *(bf16x8*)&out_lo[o] = l;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) out[o + j] = r8[j];
+    }
   }
 }
 
@@ -111,101 +132,111 @@ template <int C> struct HidCfg {
   static constexpr int NW = 4, NT = 64 * NW;         // waves, threads
   static constexpr int CS = C + 8;                   // LDS pixel stride (elements)
   static constexpr int KP = (9 * C + 31) / 32 * 32;  // K padded to the MFMA depth
-  static constexpr int KS = KP + 8;                  // LDS weight-row stride
   static constexpr int MB = TH * TW / 16;            // 16-pixel blocks per tile
   static constexpr int MBW = MB / NW;                // per wave
   static constexpr int NB = C / 16;                  // 16-channel blocks
   static constexpr int KB = KP / 32;                 // K steps
   static constexpr int TPIX = (TH + 2) * (TW + 2);
+  static constexpr int OS = C + 8;                   // LDS stride of the output staging rows
 };
 
+// Persistent over tiles: each wave keeps the whole layer's weight fragments
+// (KB x NB bfloat16x8 B operands) in registers, the block stages one input
+// tile at a time in LDS, and each 16-pixel output block is staged in LDS
+// (per wave) so that it leaves as 16-byte coalesced stores.
 template <int C, bool SPLIT>
 __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
-    const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n,
+    const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
     const __bf16* __restrict__ Wp, const float* __restrict__ b, int act,
     __bf16* __restrict__ out, __bf16* __restrict__ out_lo) {
   using H = HidCfg<C>;
   static_assert(C % 16 == 0, "hidden width must be a multiple of 16");
   extern __shared__ __align__(16) unsigned char smem[];
-  __bf16* tile = (__bf16*)smem;                                 // [TPIX][CS]
-  __bf16* tile_lo = tile + H::TPIX * H::CS;                     // SPLIT only
-  __bf16* wl = tile + (SPLIT ? 2 : 1) * H::TPIX * H::CS;        // [C][KS]
-  __shared__ float sb[C];
+  __bf16* tile = (__bf16*)smem;                               // [TPIX][CS]
+  __bf16* tile_lo = tile + H::TPIX * H::CS;                   // SPLIT only
+  __bf16* stage = tile + (SPLIT ? 2 : 1) * H::TPIX * H::CS;   // [NW][(SPLIT?2:1)*16][OS]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tpy = n / H::TH, tpx = n / H::TW;
-  const int64_t f = blockIdx.x / (tpy * tpx);
-  const int t = (int)(blockIdx.x % (tpy * tpx));
-  const int y0 = (t / tpx) * H::TH, x0 = (t % tpx) * H::TW;
-
-  // weights and bias
-  constexpr int WCH = C * H::KP / 8;
-  for (int i = tid; i < WCH; i += H::NT) {
-    const int co = i / (H::KP / 8), k8 = i % (H::KP / 8);
-    *(bf16x8*)&wl[co * H::KS + k8 * 8] = *(const bf16x8*)&Wp[(int64_t)co * H::KP + k8 * 8];
-  }
-  for (int i = tid; i < C; i += H::NT) sb[i] = b[i];
-  // input tile with a one-pixel periodic halo
-  constexpr int TCH = H::TPIX * (C / 8);
-  for (int i = tid; i < TCH; i += H::NT) {
-    const int p = i / (C / 8), c8 = i % (C / 8);
-    const int ty = p / (H::TW + 2), tx = p % (H::TW + 2);
-    const int gy = (y0 + ty - 1 + n) % n, gx = (x0 + tx - 1 + n) % n;
-    const int64_t g = ((f * n + gy) * (int64_t)n + gx) * C + c8 * 8;
-    *(bf16x8*)&tile[p * H::CS + c8 * 8] = *(const bf16x8*)&in[g];
-    if constexpr (SPLIT) *(bf16x8*)&tile_lo[p * H::CS + c8 * 8] = *(const bf16x8*)&in_lo[g];
-  }
-  __syncthreads();
-
-  f32x4 acc[H::MBW][H::NB];
-#pragma unroll
-  for (int m = 0; m < H::MBW; ++m)
-#pragma unroll
-    for (int nb = 0; nb < H::NB; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
   const int r = lane & 15, g = lane >> 4;
-  for (int kb = 0; kb < H::KB; ++kb) {
-    const int k0 = kb * 32 + 8 * g;
-    bf16x8 bfr[H::NB];
+  const int tpy = n / H::TH, tpx = n / H::TW;
+  const int64_t tiles = nfields * tpy * tpx;
+
+  // this lane's weight fragments and biases, for the whole kernel
+  bf16x8 bfr[H::KB][H::NB];
+  float bias[H::NB];
 #pragma unroll
-    for (int nb = 0; nb < H::NB; ++nb) bfr[nb] = *(const bf16x8*)&wl[(nb * 16 + r) * H::KS + k0];
-    const bool live = k0 < 9 * C;
-    const int tap = live ? k0 / C : 0, ci0 = live ? k0 % C : 0;
-    const int ky = tap / 3, kx = tap % 3;
+  for (int nb = 0; nb < H::NB; ++nb) {
+    bias[nb] = b[nb * 16 + r];
 #pragma unroll
+    for (int kb = 0; kb < H::KB; ++kb)
+      bfr[kb][nb] = *(const bf16x8*)&Wp[(int64_t)(nb * 16 + r) * H::KP + kb * 32 + 8 * g];
+  }
+  __bf16* st = stage + wave * (SPLIT ? 2 : 1) * 16 * H::OS;
+
+  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int64_t f = t / (tpy * tpx);
+    const int tt = (int)(t % (tpy * tpx));
+    const int y0 = (tt / tpx) * H::TH, x0 = (tt % tpx) * H::TW;
+    __syncthreads();  // the previous tile is no longer read
+    constexpr int TCH = H::TPIX * (C / 8);
+    for (int i = tid; i < TCH; i += H::NT) {
+      const int p = i / (C / 8), c8 = i % (C / 8);
+      const int ty = p / (H::TW + 2), tx = p % (H::TW + 2);
+      const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (n - 1);
+      const int64_t gi = ((f * n + gy) * (int64_t)n + gx) * C + c8 * 8;
+      *(bf16x8*)&tile[p * H::CS + c8 * 8] = *(const bf16x8*)&in[gi];
+      if constexpr (SPLIT) *(bf16x8*)&tile_lo[p * H::CS + c8 * 8] = *(const bf16x8*)&in_lo[gi];
+    }
+    __syncthreads();
+
     for (int m = 0; m < H::MBW; ++m) {
       const int mb = wave * H::MBW + m;
       const int oy = mb / (H::TW / 16), ox0 = (mb % (H::TW / 16)) * 16;
-      const int a_off = ((oy + ky) * (H::TW + 2) + ox0 + r + kx) * H::CS + ci0;
-      bf16x8 afr = *(const bf16x8*)&tile[a_off];
-      if (!live) afr = bf16x8{};
+      f32x4 acc[H::NB];
 #pragma unroll
-      for (int nb = 0; nb < H::NB; ++nb)
-        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[nb], acc[m][nb], 0, 0, 0);
-      if constexpr (SPLIT) {
-        bf16x8 alo = *(const bf16x8*)&tile_lo[a_off];
-        if (!live) alo = bf16x8{};
+      for (int nb = 0; nb < H::NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < H::KB; ++kb) {
+        const int k0 = kb * 32 + 8 * g;
+        const bool live = k0 < 9 * C;
+        const int tap = live ? k0 / C : 0, ci0 = live ? k0 % C : 0;
+        const int a_off = ((oy + tap / 3) * (H::TW + 2) + ox0 + r + tap % 3) * H::CS + ci0;
+        bf16x8 afr = *(const bf16x8*)&tile[a_off];
+        if (!live) afr = bf16x8{};
 #pragma unroll
         for (int nb = 0; nb < H::NB; ++nb)
-          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bfr[nb], acc[m][nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[kb][nb], acc[nb], 0, 0, 0);
+        if constexpr (SPLIT) {
+          bf16x8 alo = *(const bf16x8*)&tile_lo[a_off];
+          if (!live) alo = bf16x8{};
+#pragma unroll
+          for (int nb = 0; nb < H::NB; ++nb)
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bfr[kb][nb], acc[nb], 0, 0, 0);
+        }
       }
-    }
-  }
-
-  // bias, activation, store: lane holds pixels 4 g + i of the block, channel r
+      // bias + activation into the wave's staging rows: pixel 4 g + i, channel nb 16 + r
 #pragma unroll
-  for (int m = 0; m < H::MBW; ++m) {
-    const int mb = wave * H::MBW + m;
-    const int oy = mb / (H::TW / 16), ox0 = (mb % (H::TW / 16)) * 16;
+      for (int nb = 0; nb < H::NB; ++nb)
 #pragma unroll
-    for (int nb = 0; nb < H::NB; ++nb) {
-      const int co = nb * 16 + r;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int x = x0 + ox0 + 4 * g + i;
-        const int64_t o = ((f * n + y0 + oy) * (int64_t)n + x) * C + co;
-        store_act<__bf16>(out, SPLIT ? out_lo : nullptr, o, act_fn(acc[m][nb][i] + sb[co], act));
+        for (int i = 0; i < 4; ++i) {
+          const float v = act_fn(acc[nb][i] + bias[nb], act);
+          const __bf16 h = (__bf16)v;
+          st[(4 * g + i) * H::OS + nb * 16 + r] = h;
+          if constexpr (SPLIT) st[(16 + 4 * g + i) * H::OS + nb * 16 + r] = (__bf16)(v - (float)h);
+        }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): staged values visible to the wave
+      __builtin_amdgcn_wave_barrier();
+      // 16 pixels x C channels are contiguous in the output: 16-byte stores
+      const int64_t ob = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0) * C;
+      constexpr int CH = 16 * C / 8;
+      for (int i = lane; i < CH; i += 64) {
+        const int px = i / (C / 8), c8 = i % (C / 8);
+        *(bf16x8*)&out[ob + px * C + c8 * 8] = *(const bf16x8*)&st[px * H::OS + c8 * 8];
+        if constexpr (SPLIT)
+          *(bf16x8*)&out_lo[ob + px * C + c8 * 8] = *(const bf16x8*)&st[(16 + px) * H::OS + c8 * 8];
       }
+      __builtin_amdgcn_wave_barrier();
     }
   }
 }
@@ -226,7 +257,7 @@ __global__ __launch_bounds__(256) void k_cnn_hidden_f32(const float* __restrict_
   for (int i = tid; i < (kTile + 2) * (kTile + 2) * C; i += 256) {
     const int p = i / C, c = i % C;
     const int ty = p / (kTile + 2), tx = p % (kTile + 2);
-    const int gy = (y0 + ty - 1 + n) % n, gx = (x0 + tx - 1 + n) % n;
+    const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (n - 1);
     tile[p * (C + 1) + c] = in[((f * n + gy) * (int64_t)n + gx) * C + c];
   }
   __syncthreads();
@@ -249,37 +280,63 @@ __global__ __launch_bounds__(256) void k_cnn_hidden_f32(const float* __restrict_
 
 // ------------------------------------------------------------- last layer
 
+// One pixel per thread.  The input tile is loaded with 16-byte vectors
+// (8 channels) and kept in the input precision; the weights are read with
+// wave-uniform addresses (scalar loads).
 template <int C, typename TI>
 __global__ __launch_bounds__(256) void k_cnn_last(
     const TI* __restrict__ in, const TI* __restrict__ in_lo, int n, const float* __restrict__ W,
     const float* __restrict__ b, const double* __restrict__ u_base,
     const int64_t* __restrict__ u_offs, double* __restrict__ g_base,
     const int64_t* __restrict__ g_offs, int residual, double* __restrict__ partials) {
-  __shared__ float tile[(kTile + 2) * (kTile + 2) * (C + 1)];
-  __shared__ float sw[C * 9];
+  constexpr int C8 = C / 8;
+  constexpr int PS = C + (sizeof(TI) == 2 ? 8 : 4);  // LDS pixel stride (elements)
+  constexpr int TP = (kTile + 2) * (kTile + 2);
+  __shared__ __align__(16) TI tile[TP * PS];
+  __shared__ __align__(16) TI tile_lo[(sizeof(TI) == 2 ? TP * PS : 1)];
   __shared__ double red[4];
   const int tid = threadIdx.x;
-  const int tpr = n / kTile;
+  const int tpr = n / kTile, m = n - 1;
   const int64_t f = blockIdx.x / (tpr * tpr);
   const int t = (int)(blockIdx.x % (tpr * tpr));
   const int y0 = (t / tpr) * kTile, x0 = (t % tpr) * kTile;
-  for (int i = tid; i < C * 9; i += 256) sw[i] = W[i];
-  for (int i = tid; i < (kTile + 2) * (kTile + 2) * C; i += 256) {
-    const int p = i / C, c = i % C;
+  const bool split = sizeof(TI) == 2 && in_lo != nullptr;
+  for (int i = tid; i < TP * C8; i += 256) {
+    const int p = i / C8, c8 = i % C8;
     const int ty = p / (kTile + 2), tx = p % (kTile + 2);
-    const int gy = (y0 + ty - 1 + n) % n, gx = (x0 + tx - 1 + n) % n;
-    const int64_t g = ((f * n + gy) * (int64_t)n + gx) * C + c;
-    float v = to_f(in[g]);
-    if (in_lo) v += to_f(in_lo[g]);
-    tile[p * (C + 1) + c] = v;
+    const int64_t gi = ((f * n + ((y0 + ty - 1) & m)) * (int64_t)n + ((x0 + tx - 1) & m)) * C + c8 * 8;
+    if constexpr (sizeof(TI) == 2) {
+      *(bf16x8*)&tile[p * PS + c8 * 8] = *(const bf16x8*)&in[gi];
+      if (split) *(bf16x8*)&tile_lo[p * PS + c8 * 8] = *(const bf16x8*)&in_lo[gi];
+    } else {
+      *(float4*)&tile[p * PS + c8 * 8] = *(const float4*)&in[gi];
+      *(float4*)&tile[p * PS + c8 * 8 + 4] = *(const float4*)&in[gi + 4];
+    }
   }
   __syncthreads();
   const int py = tid / kTile, px = tid % kTile;
   float s = b[0];
   for (int tp = 0; tp < 9; ++tp) {
     const int p = (py + tp / 3) * (kTile + 2) + px + tp % 3;
-#pragma unroll 8
-    for (int ci = 0; ci < C; ++ci) s += sw[ci * 9 + tp] * tile[p * (C + 1) + ci];
+#pragma unroll
+    for (int c8 = 0; c8 < C8; ++c8) {
+      float x[8];
+      if constexpr (sizeof(TI) == 2) {
+        const bf16x8 h = *(const bf16x8*)&tile[p * PS + c8 * 8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = (float)h[j];
+        if (split) {
+          const bf16x8 l = *(const bf16x8*)&tile_lo[p * PS + c8 * 8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) x[j] += (float)l[j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = tile[p * PS + c8 * 8 + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s += W[(c8 * 8 + j) * 9 + tp] * x[j];
+    }
   }
   const int64_t gi = (int64_t)(y0 + py) * n + x0 + px;
   const double u = u_base[(u_offs ? u_offs[f] : f * (int64_t)n * n) + gi];
@@ -323,6 +380,21 @@ __global__ __launch_bounds__(256) void k_cnn_fix(double* __restrict__ g_base,
 }
 
 // --------------------------------------------------------------- launch
+
+size_t cnn_lds_bytes(int C, bool split);
+
+// Blocks of the persistent hidden-layer kernel that fill the GPU once.
+template <int C, bool SPLIT>
+static int hidden_cap() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 512;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cnn_hidden<C, SPLIT>,
+                                                   HidCfg<C>::NT, cnn_lds_bytes(C, SPLIT)) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return cus * per_cu;
+}
 
 template <int C>
 static hipError_t launch_cnn_c(const CnnJob& j, hipStream_t st) {
@@ -368,13 +440,16 @@ static hipError_t launch_cnn_c(const CnnJob& j, hipStream_t st) {
       if constexpr (C % 16 == 0) {
         using H = HidCfg<C>;
         const __bf16* wp = (const __bf16*)j.ws.wpack + (int64_t)(l - 1) * C * H::KP;
-        const size_t lds = ((split ? 2 : 1) * H::TPIX * H::CS + C * H::KS) * sizeof(__bf16);
-        const dim3 gh((unsigned)(j.nfields * (n / H::TH) * (n / H::TW))), bh(H::NT);
+        const size_t lds = cnn_lds_bytes(C, split);
+        const int64_t tiles = j.nfields * (n / H::TH) * (n / H::TW);
+        static const int cap0 = hidden_cap<C, false>(), cap1 = hidden_cap<C, true>();
+        const dim3 gh((unsigned)std::min<int64_t>(tiles, split ? cap1 : cap0)), bh(H::NT);
         if (split)
-          k_cnn_hidden<C, true><<<gh, bh, lds, st>>>(a0, l0, n, wp, j.B + boff(l), j.act, a1, l1);
+          k_cnn_hidden<C, true><<<gh, bh, lds, st>>>(a0, l0, n, j.nfields, wp, j.B + boff(l), j.act,
+                                                     a1, l1);
         else
-          k_cnn_hidden<C, false><<<gh, bh, lds, st>>>(a0, nullptr, n, wp, j.B + boff(l), j.act, a1,
-                                                      nullptr);
+          k_cnn_hidden<C, false><<<gh, bh, lds, st>>>(a0, nullptr, n, j.nfields, wp, j.B + boff(l),
+                                                      j.act, a1, nullptr);
       } else {
         return hipErrorInvalidValue;
       }
@@ -424,7 +499,8 @@ size_t cnn_lds_bytes(int C, bool split) {
   switch (C) {
 #define PR_L(CC)                                                                               \
   case CC:                                                                                     \
-    return ((split ? 2 : 1) * HidCfg<CC>::TPIX * HidCfg<CC>::CS + CC * HidCfg<CC>::KS) * 2;
+    return ((split ? 2 : 1) * (HidCfg<CC>::TPIX * HidCfg<CC>::CS +                             \
+                               HidCfg<CC>::NW * 16 * HidCfg<CC>::OS)) * 2;
     PR_L(16) PR_L(32) PR_L(48) PR_L(64)
 #undef PR_L
     default: return 0;
