@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 2
+#define PR_ABI_VERSION 3
 
 typedef enum {
   PR_OK = 0,
@@ -92,18 +92,20 @@ typedef enum { PR_ACT_GELU = 0, PR_ACT_TANH = 1 } pr_act;
  *     G(u) += mean(u) - mean(G(u))  if mass_fix (the uniform shift that
  *                                   keeps the mass, Section 3.2),
  *     G(u) = clamp(G(u), lim_lo, lim_hi) if limiter (bound limiter).
- *   weights: device float, the layers' torch Conv2d weights [Cout][Cin][3][3]
- *            concatenated in layer order; biases: device float [Cout] per
- *            layer, concatenated.  Read on every call; the library keeps a
- *            packed copy in the workspace only for the duration of a call.
- *   prec: PR_F32 (every layer in FP32 on the vector ALU), PR_BF16 (hidden
- *         layers on the bf16 matrix cores with FP32 accumulation; weights
- *         and activations rounded to bfloat16), or PR_BF16X2 (the same with
+ *   weights: device array of the layers' torch Conv2d weights
+ *            [Cout][Cin][3][3] concatenated in layer order; biases: device
+ *            array of [Cout] per layer, concatenated.  Both are double for
+ *            prec PR_F64 and float otherwise.  Read on every call; the
+ *            library keeps a packed copy in the workspace only during a call.
+ *   prec: PR_F64 or PR_F32 (every layer in that precision on the vector
+ *         ALU; PR_F64 needs channels <= 32), PR_BF16 (hidden layers on the
+ *         bf16 matrix cores with FP32 accumulation; hidden weights and
+ *         activations rounded to bfloat16), or PR_BF16X2 (the same with
  *         each activation carried as a hi + lo bfloat16 pair, two products
  *         per term; needs channels <= 48).  The first layer reads the FP64
  *         state unrounded and the last writes FP64.
- *   Needs N >= 32, channels in {8, 16, 32, 48, 64} and, when n_layers > 2,
- *   a multiple of 16; PR_ERR_UNSUPPORTED otherwise. */
+ *   Needs N >= 32, channels in {8, 16, 32, 48, 64} and, for bfloat16 with
+ *   n_layers > 2, a multiple of 16; PR_ERR_UNSUPPORTED otherwise. */
 typedef struct {
   int32_t kind;         /* PR_G_SCHEME or PR_G_CNN                      */
   double dt;            /* scheme: coarse step > 0 (one slice: c * dt*)  */
@@ -111,8 +113,8 @@ typedef struct {
   int32_t prec;         /* see above                                     */
   int32_t n_layers;     /* CNN: convolutions, >= 2                       */
   int32_t channels;     /* CNN: hidden width C                           */
-  const float* weights; /* CNN: device, concatenated Conv2d weights      */
-  const float* biases;  /* CNN: device, concatenated biases              */
+  const void* weights;  /* CNN: device, concatenated Conv2d weights      */
+  const void* biases;   /* CNN: device, concatenated biases              */
   int32_t act;          /* CNN: PR_ACT_GELU (exact erf) or PR_ACT_TANH   */
   int32_t residual;     /* CNN: 1: G(u) = u + net(u)                     */
   int32_t mass_fix;     /* CNN: 1: restore the input's mean              */
@@ -160,6 +162,28 @@ size_t pr_coarse_workspace_bytes(const pr_problem* p, const pr_coarse* g,
 pr_status pr_coarse_apply(const pr_problem* p, const pr_coarse* g,
                           int64_t nfields, const double* u_in, double* g_out,
                           void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of the convolutional G (Section 3.2), for training it on
+ * trajectories of F (Algorithm 1).  Given the input u_in and dL/dG(u_in)
+ * (grad_out), all device double[nfields][N][N] and contiguous, writes
+ *   grad_in  device double[nfields][N][N]: dL/du_in (through the network,
+ *            the residual, the mass fix and the limiter, whose derivative is
+ *            0 where it clamps);
+ *   grad_w, grad_b: dL/dweights and dL/dbiases, laid out like g->weights
+ *            and g->biases (double for PR_F64, float otherwise), summed
+ *            over all fields -- overwritten, not accumulated.
+ * The forward pass is recomputed inside (only u_in is kept between the two
+ * passes).  For the bfloat16 precisions the recomputed forward is the
+ * bfloat16 one and the backward runs in FP32 with the FP32 weights (the
+ * rounding of the hidden weights is passed straight through).  All
+ * parameter-gradient sums are tile partials added in a fixed order, so
+ * results are deterministic.  The arrays must be distinct. */
+size_t pr_cnn_backward_workspace_bytes(const pr_problem* p, const pr_coarse* g,
+                                       int64_t nfields);
+pr_status pr_cnn_backward(const pr_problem* p, const pr_coarse* g, int64_t nfields,
+                          const double* u_in, const double* grad_out, double* grad_in,
+                          void* grad_w, void* grad_b, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* ------------------------------------------------------- correction --- */
 

@@ -20,6 +20,7 @@ PR_ACT_GELU, PR_ACT_TANH = 0, 1
 EXPORTED = [
     "pr_fine_workspace_bytes", "pr_fine_propagate",
     "pr_coarse_workspace_bytes", "pr_coarse_apply",
+    "pr_cnn_backward_workspace_bytes", "pr_cnn_backward",
     "pr_correct",
     "pr_solve_workspace_bytes", "pr_solve",
     "pr_serial_workspace_bytes", "pr_serial_fine",
@@ -67,6 +68,8 @@ def lib() -> C.CDLL:
             "pr_fine_propagate": (C.c_int, [P, i64, vp, vp, C.c_int, vp, sz, vp]),
             "pr_coarse_workspace_bytes": (sz, [P, G, i64]),
             "pr_coarse_apply": (C.c_int, [P, G, i64, vp, vp, vp, sz, vp]),
+            "pr_cnn_backward_workspace_bytes": (sz, [P, G, i64]),
+            "pr_cnn_backward": (C.c_int, [P, G, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
             "pr_correct": (C.c_int, [i64, i32, vp, C.c_int, vp, vp, vp, vp, i32, vp]),
             "pr_solve_workspace_bytes": (sz, [P, G, i64, i32]),
             "pr_solve": (C.c_int, [P, G, i64, i32, vp, vp, C.c_double, i32, S, vp, sz, vp]),

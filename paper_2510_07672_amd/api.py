@@ -48,7 +48,7 @@ class Coarse:
         return L.Coarse(kind=L.PR_G_SCHEME, dt=self.dt, steps=self.steps, prec=_PREC[self.prec])
 
 
-_CNN_PREC = {"f32": L.PR_F32, "bf16": L.PR_BF16, "bf16x2": L.PR_BF16X2}
+_CNN_PREC = {"f64": L.PR_F64, "f32": L.PR_F32, "bf16": L.PR_BF16, "bf16x2": L.PR_BF16X2}
 
 
 class CnnCoarse:
@@ -68,10 +68,25 @@ class CnnCoarse:
             if tuple(w.shape) != (cout, cin, 3, 3) or tuple(b.shape) != (cout,):
                 raise ValueError(f"layer {l}: expected W {(cout, cin, 3, 3)} and b {(cout,)}")
         self.n_layers, self.channels = len(weights), C
-        self.W = torch.cat([w.reshape(-1) for w in weights]).to(device=device, dtype=torch.float32).contiguous()
-        self.B = torch.cat([b.reshape(-1) for b in biases]).to(device=device, dtype=torch.float32).contiguous()
+        dt = torch.float64 if prec == "f64" else torch.float32
+        # flat parameter buffers, in the layout the library reads (and that
+        # pr_cnn_backward's gradients use)
+        self.W = torch.cat([w.reshape(-1) for w in weights]).to(device=device, dtype=dt).contiguous()
+        self.B = torch.cat([b.reshape(-1) for b in biases]).to(device=device, dtype=dt).contiguous()
         self.act, self.residual, self.mass_fix, self.limiter = act, residual, mass_fix, limiter
         self.prec = prec
+
+    def layers(self):
+        """Views of the flat buffers as per-layer (W [Cout,Cin,3,3], b [Cout])."""
+        out, wo, bo = [], 0, 0
+        C, L = self.channels, self.n_layers
+        for l in range(L):
+            cin, cout = (1 if l == 0 else C), (1 if l == L - 1 else C)
+            out.append((self.W[wo:wo + cout * cin * 9].view(cout, cin, 3, 3),
+                        self.B[bo:bo + cout]))
+            wo += cout * cin * 9
+            bo += cout
+        return out
 
     def c(self) -> L.Coarse:
         lo, hi = self.limiter if self.limiter is not None else (0.0, 0.0)
@@ -144,6 +159,25 @@ def pr_coarse_apply(p: Problem, g: Coarse, u_in: torch.Tensor,
                                     _ptr(ws), ws.numel(), _stream(u_in.device)),
             "pr_coarse_apply")
     return out
+
+
+def pr_cnn_backward(p: Problem, g: "CnnCoarse", u_in: torch.Tensor, grad_out: torch.Tensor,
+                    ws: Optional[torch.Tensor] = None):
+    """(dL/du, dL/dW, dL/db) of the network at u_in for dL/dG = grad_out; the
+    parameter gradients are flat, laid out like g.W and g.B."""
+    B = _fields(u_in, p.n, "u_in")
+    _fields(grad_out, p.n, "grad_out")
+    pc, gc = p.c(), g.c()
+    du = torch.empty_like(u_in)
+    dW = torch.empty_like(g.W)
+    dB = torch.empty_like(g.B)
+    need = L.lib().pr_cnn_backward_workspace_bytes(C.byref(pc), C.byref(gc), B)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, u_in.device)
+    L.check(L.lib().pr_cnn_backward(C.byref(pc), C.byref(gc), B, _ptr(u_in), _ptr(grad_out),
+                                    _ptr(du), _ptr(dW), _ptr(dB), _ptr(ws), ws.numel(),
+                                    _stream(u_in.device)), "pr_cnn_backward")
+    return du, dW, dB
 
 
 def pr_correct(f: torch.Tensor, g_new: torch.Tensor, g_old: torch.Tensor, u: torch.Tensor,

@@ -3,6 +3,7 @@
 // kernels of fine_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <mutex>
@@ -74,10 +75,13 @@ pr_status check_coarse(const pr_coarse* g, int n) {
   const int C = g->channels;
   if (C != 8 && C != 16 && C != 32 && C != 48 && C != 64)
     return fail(PR_ERR_UNSUPPORTED, "channels=%d: must be 8, 16, 32, 48 or 64", C);
-  if (g->n_layers > 2 && C % 16 != 0)
-    return fail(PR_ERR_UNSUPPORTED, "hidden layers need channels to be a multiple of 16");
-  if (g->prec != PR_F32 && g->prec != PR_BF16 && g->prec != PR_BF16X2)
-    return fail(PR_ERR_UNSUPPORTED, "CNN prec must be PR_F32, PR_BF16 or PR_BF16X2");
+  if (g->prec != PR_F64 && g->prec != PR_F32 && g->prec != PR_BF16 && g->prec != PR_BF16X2)
+    return fail(PR_ERR_UNSUPPORTED, "CNN prec must be PR_F64, PR_F32, PR_BF16 or PR_BF16X2");
+  const bool mfma = g->prec == PR_BF16 || g->prec == PR_BF16X2;
+  if (mfma && g->n_layers > 2 && C % 16 != 0)
+    return fail(PR_ERR_UNSUPPORTED, "bfloat16 hidden layers need channels to be a multiple of 16");
+  if (g->prec == PR_F64 && C > kCnnF64MaxC)
+    return fail(PR_ERR_UNSUPPORTED, "PR_F64 networks need channels <= %d", kCnnF64MaxC);
   if (g->prec == PR_BF16X2 && C > 48) return fail(PR_ERR_UNSUPPORTED, "PR_BF16X2 needs channels <= 48");
   if (!g->weights || !g->biases) return fail(PR_ERR_INVALID_ARG, "CNN weights / biases are NULL");
   if (g->act != PR_ACT_GELU && g->act != PR_ACT_TANH) return fail(PR_ERR_INVALID_ARG, "act must be PR_ACT_GELU or PR_ACT_TANH");
@@ -154,16 +158,28 @@ StepJob make_job(const pr_problem* p, double dt, int steps, bool f32, int64_t nf
   return j;
 }
 
-CnnWs carve_cnn(Carver& c, int n, const pr_coarse* g, int64_t nfields) {
+CnnWs carve_cnn(Carver& c, int n, const pr_coarse* g, int64_t nfields, bool train = false) {
   CnnWs w{};
   const int C = g->channels, L = g->n_layers;
   const int kp = (9 * C + 31) / 32 * 32;
-  const bool f32 = g->prec == PR_F32, split = g->prec == PR_BF16X2;
-  w.wpack = c.take(f32 || L < 3 ? 16 : (size_t)(L - 2) * C * kp * 2);
-  const size_t act = (size_t)nfields * n * n * C * (f32 ? 4 : 2) * (split ? 2 : 1);
-  w.act[0] = c.take(act);
-  w.act[1] = c.take(act);
-  w.partials = (double*)c.take((size_t)nfields * (n / 16) * (n / 16) * 8);
+  const bool mfma = g->prec == PR_BF16 || g->prec == PR_BF16X2;
+  w.wpack = c.take(!mfma || L < 3 ? 16 : (size_t)(L - 2) * C * kp * 2);
+  const size_t act = (size_t)nfields * n * n * C * cnn_act_bytes(g->prec);
+  const size_t tiles = (size_t)nfields * (n / 16) * (n / 16);
+  w.partials = (double*)c.take(tiles * 8);
+  if (!train) {
+    w.act[0] = c.take(act);
+    w.act[1] = c.take(act);
+    return w;
+  }
+  const size_t grad = (size_t)nfields * n * n * C * cnn_grad_bytes(g->prec);
+  w.acts = c.take((size_t)(L - 1) * act);
+  w.zs = c.take((size_t)(L - 1) * grad);
+  w.o1 = (double*)c.take((size_t)nfields * n * n * 8);
+  w.wpart = (double*)c.take(tiles * (size_t)(C * C * 9 + C) * 8);
+  w.d[0] = c.take(grad);
+  w.d[1] = c.take(grad);
+  w.fpart = (double*)c.take((size_t)nfields * std::max<int64_t>(1, (int64_t)n * n / 2048) * 8);
   return w;
 }
 
@@ -369,6 +385,49 @@ pr_status pr_coarse_apply(const pr_problem* p, const pr_coarse* g, int64_t nfiel
   hipStream_t s = (hipStream_t)stream;
   PR_HIP(coarse_setup(p, g, w, s));
   PR_HIP(coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s));
+  return PR_OK;
+}
+
+size_t pr_cnn_backward_workspace_bytes(const pr_problem* p, const pr_coarse* g, int64_t nfields) {
+  if (check_problem(p) != PR_OK || check_coarse(g, p->n) != PR_OK || g->kind != PR_G_CNN ||
+      nfields < 0)
+    return 0;
+  Carver c(nullptr);
+  carve_cnn(c, p->n, g, nfields, true);
+  return c.used;
+}
+
+pr_status pr_cnn_backward(const pr_problem* p, const pr_coarse* g, int64_t nfields,
+                          const double* u_in, const double* grad_out, double* grad_in,
+                          void* grad_w, void* grad_b, void* ws, size_t ws_bytes, void* stream) {
+  pr_status st = check_problem(p);
+  if (st != PR_OK) return st;
+  if ((st = check_coarse(g, p->n)) != PR_OK) return st;
+  if (g->kind != PR_G_CNN) return fail(PR_ERR_INVALID_ARG, "pr_cnn_backward needs a PR_G_CNN coarse");
+  if (nfields < 0) return fail(PR_ERR_INVALID_ARG, "nfields < 0");
+  if (nfields == 0) return PR_OK;
+  if (!u_in || !grad_out || !grad_in || !grad_w || !grad_b)
+    return fail(PR_ERR_INVALID_ARG, "NULL array");
+  const void* ptrs[5] = {u_in, grad_out, grad_in, grad_w, grad_b};
+  for (int i = 0; i < 5; ++i)
+    for (int k = i + 1; k < 5; ++k)
+      if (ptrs[i] == ptrs[k]) return fail(PR_ERR_INVALID_ARG, "arrays must be distinct");
+  Carver c(ws);
+  CnnWs w = carve_cnn(c, p->n, g, nfields, true);
+  if (!ws || ws_bytes < c.used)
+    return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, c.used);
+  if ((st = cnn_lds_once()) != PR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  CoarseWs cw{};
+  cw.cnn = w;
+  PR_HIP(coarse_setup(p, g, cw, s));
+  CnnJob j = make_cnn_job(p, g, w);
+  j.nfields = nfields;
+  j.in_base = u_in;
+  j.in_offs = nullptr;
+  j.out_base = nullptr;
+  j.out_offs = nullptr;
+  PR_HIP(launch_cnn_backward(j, grad_out, grad_in, grad_w, grad_b, s));
   return PR_OK;
 }
 

@@ -39,6 +39,25 @@ __device__ __forceinline__ float act_fn(float x, int act) {
 
 template <typename T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
 
+// activation in the reference precisions (float or double)
+template <typename T>
+__device__ __forceinline__ T act_ref(T x, int act) {
+  if (act == kActTanh) return tanh(x);
+  return (T)0.5 * x * ((T)1 + erf(x * (T)0.70710678118654752440));
+}
+
+// derivative of the activation at the pre-activation z
+template <typename T>
+__device__ __forceinline__ T act_grad(T z, int act) {
+  if (act == kActTanh) {
+    const T t = tanh(z);
+    return (T)1 - t * t;
+  }
+  // d/dz z Phi(z) = Phi(z) + z phi(z)
+  const T phi = exp((T)-0.5 * z * z) * (T)0.39894228040143267794;
+  return (T)0.5 * ((T)1 + erf(z * (T)0.70710678118654752440)) + z * phi;
+}
+
 // store a value as hi (and, with lo != nullptr, the bfloat16 remainder)
 template <typename T>
 __device__ __forceinline__ void store_act(T* hi, T* lo, int64_t i, float v) {
@@ -75,7 +94,8 @@ __global__ __launch_bounds__(256) void k_cnn_first(const double* __restrict__ u_
                                                    const int64_t* __restrict__ u_offs, int n,
                                                    const float* __restrict__ W,
                                                    const float* __restrict__ b, int act,
-                                                   TO* __restrict__ out, TO* __restrict__ out_lo) {
+                                                   TO* __restrict__ out, TO* __restrict__ out_lo,
+                                                   float* __restrict__ zout) {
   static_assert(C % 8 == 0, "width must be a multiple of 8");
   __shared__ float sw[C * 9], sb[C];
   __shared__ float tile[(kTile + 2) * (kTile + 2)];
@@ -99,16 +119,21 @@ __global__ __launch_bounds__(256) void k_cnn_first(const double* __restrict__ u_
     float v[9];
 #pragma unroll
     for (int tp = 0; tp < 9; ++tp) v[tp] = tile[(py + tp / 3) * (kTile + 2) + pxx + tp % 3];
-    float r8[8];
+    float r8[8], z8[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int co = c8 * 8 + j;
       float s = sb[co];
 #pragma unroll
       for (int tp = 0; tp < 9; ++tp) s += sw[co * 9 + tp] * v[tp];
+      z8[j] = s;
       r8[j] = act_fn(s, act);
     }
     const int64_t o = ((f * n + y0 + py) * (int64_t)n + x0 + pxx) * C + c8 * 8;
+    if (zout) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) zout[o + j] = z8[j];
+    }
     if constexpr (sizeof(TO) == 2) {
       bf16x8 h, l;
 #pragma unroll
@@ -148,7 +173,7 @@ template <int C, bool SPLIT>
 __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
     const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
     const __bf16* __restrict__ Wp, const float* __restrict__ b, int act,
-    __bf16* __restrict__ out, __bf16* __restrict__ out_lo) {
+    __bf16* __restrict__ out, __bf16* __restrict__ out_lo, float* __restrict__ zout) {
   using H = HidCfg<C>;
   static_assert(C % 16 == 0, "hidden width must be a multiple of 16");
   extern __shared__ __align__(16) unsigned char smem[];
@@ -215,6 +240,13 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
         }
       }
       // bias + activation into the wave's staging rows: pixel 4 g + i, channel nb 16 + r
+      if (zout) {
+        const int64_t zb = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0 + 4 * g) * C + r;
+#pragma unroll
+        for (int nb = 0; nb < H::NB; ++nb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) zout[zb + (int64_t)i * C + nb * 16] = acc[nb][i] + bias[nb];
+      }
 #pragma unroll
       for (int nb = 0; nb < H::NB; ++nb)
 #pragma unroll
@@ -241,41 +273,120 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
   }
 }
 
-// FP32 reference-precision hidden layer on the vector ALU: one pixel per
-// thread, weights read uniformly across the wave (scalar loads).
-template <int C>
-__global__ __launch_bounds__(256) void k_cnn_hidden_f32(const float* __restrict__ in, int n,
-                                                        const float* __restrict__ W,
-                                                        const float* __restrict__ b, int act,
-                                                        float* __restrict__ out) {
-  __shared__ float tile[(kTile + 2) * (kTile + 2) * (C + 1)];
+// ------------------------------------------- reference-precision layers
+//
+// FP32 or FP64 throughout, on the vector ALU, with weights in the same
+// precision; optionally storing the pre-activations z for a backward pass.
+
+template <int C, typename T>
+__global__ __launch_bounds__(256) void k_cnn_first_ref(const double* __restrict__ u_base,
+                                                       const int64_t* __restrict__ u_offs, int n,
+                                                       const T* __restrict__ W,
+                                                       const T* __restrict__ b, int act,
+                                                       T* __restrict__ out, T* __restrict__ zout) {
+  __shared__ T tile[(kTile + 2) * (kTile + 2)];
   const int tid = threadIdx.x;
-  const int tpr = n / kTile;
+  const int tpr = n / kTile, m = n - 1;
+  const int64_t f = blockIdx.x / (tpr * tpr);
+  const int t = (int)(blockIdx.x % (tpr * tpr));
+  const int y0 = (t / tpr) * kTile, x0 = (t % tpr) * kTile;
+  const double* u = u_base + (u_offs ? u_offs[f] : f * (int64_t)n * n);
+  for (int i = tid; i < (kTile + 2) * (kTile + 2); i += 256) {
+    const int ty = i / (kTile + 2), tx = i % (kTile + 2);
+    tile[i] = (T)u[(int64_t)((y0 + ty - 1) & m) * n + ((x0 + tx - 1) & m)];
+  }
+  __syncthreads();
+  const int py = tid / kTile, px = tid % kTile;
+  T v[9];
+#pragma unroll
+  for (int tp = 0; tp < 9; ++tp) v[tp] = tile[(py + tp / 3) * (kTile + 2) + px + tp % 3];
+  const int64_t o = ((f * n + y0 + py) * (int64_t)n + x0 + px) * C;
+  for (int co = 0; co < C; ++co) {
+    T s = b[co];
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp) s += W[co * 9 + tp] * v[tp];
+    if (zout) zout[o + co] = s;
+    out[o + co] = act_ref<T>(s, act);
+  }
+}
+
+template <int C, typename T>
+__global__ __launch_bounds__(256) void k_cnn_hidden_ref(const T* __restrict__ in, int n,
+                                                        const T* __restrict__ W,
+                                                        const T* __restrict__ b, int act,
+                                                        T* __restrict__ out, T* __restrict__ zout) {
+  __shared__ T tile[(kTile + 2) * (kTile + 2) * (C + 1)];
+  const int tid = threadIdx.x;
+  const int tpr = n / kTile, m = n - 1;
   const int64_t f = blockIdx.x / (tpr * tpr);
   const int t = (int)(blockIdx.x % (tpr * tpr));
   const int y0 = (t / tpr) * kTile, x0 = (t % tpr) * kTile;
   for (int i = tid; i < (kTile + 2) * (kTile + 2) * C; i += 256) {
     const int p = i / C, c = i % C;
     const int ty = p / (kTile + 2), tx = p % (kTile + 2);
-    const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (n - 1);
-    tile[p * (C + 1) + c] = in[((f * n + gy) * (int64_t)n + gx) * C + c];
+    tile[p * (C + 1) + c] =
+        in[((f * n + ((y0 + ty - 1) & m)) * (int64_t)n + ((x0 + tx - 1) & m)) * C + c];
   }
   __syncthreads();
   const int py = tid / kTile, px = tid % kTile;
-  float acc[C];
+  T acc[C];
 #pragma unroll
   for (int co = 0; co < C; ++co) acc[co] = b[co];
   for (int tp = 0; tp < 9; ++tp) {
     const int p = (py + tp / 3) * (kTile + 2) + px + tp % 3;
     for (int ci = 0; ci < C; ++ci) {
-      const float x = tile[p * (C + 1) + ci];
+      const T x = tile[p * (C + 1) + ci];
 #pragma unroll
       for (int co = 0; co < C; ++co) acc[co] += W[(co * C + ci) * 9 + tp] * x;
     }
   }
   const int64_t o = ((f * n + y0 + py) * (int64_t)n + x0 + px) * C;
 #pragma unroll
-  for (int co = 0; co < C; ++co) out[o + co] = act_fn(acc[co], act);
+  for (int co = 0; co < C; ++co) {
+    if (zout) zout[o + co] = acc[co];
+    out[o + co] = act_ref<T>(acc[co], act);
+  }
+}
+
+template <int C, typename T>
+__global__ __launch_bounds__(256) void k_cnn_last_ref(
+    const T* __restrict__ in, int n, const T* __restrict__ W, const T* __restrict__ b,
+    const double* __restrict__ u_base, const int64_t* __restrict__ u_offs,
+    double* __restrict__ g_base, const int64_t* __restrict__ g_offs, int residual,
+    double* __restrict__ partials) {
+  __shared__ T tile[(kTile + 2) * (kTile + 2) * (C + 1)];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int tpr = n / kTile, m = n - 1;
+  const int64_t f = blockIdx.x / (tpr * tpr);
+  const int t = (int)(blockIdx.x % (tpr * tpr));
+  const int y0 = (t / tpr) * kTile, x0 = (t % tpr) * kTile;
+  for (int i = tid; i < (kTile + 2) * (kTile + 2) * C; i += 256) {
+    const int p = i / C, c = i % C;
+    const int ty = p / (kTile + 2), tx = p % (kTile + 2);
+    tile[p * (C + 1) + c] =
+        in[((f * n + ((y0 + ty - 1) & m)) * (int64_t)n + ((x0 + tx - 1) & m)) * C + c];
+  }
+  __syncthreads();
+  const int py = tid / kTile, px = tid % kTile;
+  T s = b[0];
+  for (int tp = 0; tp < 9; ++tp) {
+    const int p = (py + tp / 3) * (kTile + 2) + px + tp % 3;
+#pragma unroll 8
+    for (int ci = 0; ci < C; ++ci) s += W[ci * 9 + tp] * tile[p * (C + 1) + ci];
+  }
+  const int64_t gi = (int64_t)(y0 + py) * n + x0 + px;
+  const double u = u_base[(u_offs ? u_offs[f] : f * (int64_t)n * n) + gi];
+  const double out = residual ? u + (double)s : (double)s;
+  g_base[(g_offs ? g_offs[f] : f * (int64_t)n * n) + gi] = out;
+  if (partials) {
+    double d = out - u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = d;
+    __syncthreads();
+    if (tid == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
 }
 
 // ------------------------------------------------------------- last layer
@@ -379,6 +490,176 @@ __global__ __launch_bounds__(256) void k_cnn_fix(double* __restrict__ g_base,
   }
 }
 
+// --------------------------------------------------------------- backward
+//
+// For a convolution layer Y = conv(X, W) + b (3x3, circular, cross-
+// correlation), given dY:
+//   dX[q][ci] = sum_{co, ky, kx} W[co][ci][ky][kx] dY[q - (ky - 1, kx - 1)][co]
+//   dW[co][ci][ky][kx] = sum_p dY[p][co] X[p + (ky - 1, kx - 1)][ci]
+//   db[co] = sum_p dY[p][co]
+// Weight and bias gradients are summed per 16 x 16 tile into FP64 partials
+// and then over tiles in a fixed order, so results are deterministic.
+
+template <int CI, int CO, typename T, typename TW>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const T* __restrict__ dY, int n,
+                                                       const TW* __restrict__ W,
+                                                       T* __restrict__ dX) {
+  __shared__ T tile[(kTile + 2) * (kTile + 2) * (CO + 1)];
+  const int tid = threadIdx.x;
+  const int tpr = n / kTile, m = n - 1;
+  const int64_t f = blockIdx.x / (tpr * tpr);
+  const int t = (int)(blockIdx.x % (tpr * tpr));
+  const int y0 = (t / tpr) * kTile, x0 = (t % tpr) * kTile;
+  for (int i = tid; i < (kTile + 2) * (kTile + 2) * CO; i += 256) {
+    const int p = i / CO, c = i % CO;
+    const int ty = p / (kTile + 2), tx = p % (kTile + 2);
+    tile[p * (CO + 1) + c] =
+        dY[((f * n + ((y0 + ty - 1) & m)) * (int64_t)n + ((x0 + tx - 1) & m)) * CO + c];
+  }
+  __syncthreads();
+  const int py = tid / kTile, px = tid % kTile;
+  T acc[CI];
+#pragma unroll
+  for (int ci = 0; ci < CI; ++ci) acc[ci] = (T)0;
+  for (int tp = 0; tp < 9; ++tp) {
+    const int ky = tp / 3, kx = tp % 3;
+    // dY at q - (ky - 1, kx - 1): tile coordinates (py + 2 - ky, px + 2 - kx)
+    const int p = (py + 2 - ky) * (kTile + 2) + px + 2 - kx;
+    for (int co = 0; co < CO; ++co) {
+      const T d = tile[p * (CO + 1) + co];
+#pragma unroll
+      for (int ci = 0; ci < CI; ++ci) acc[ci] += (T)W[(co * CI + ci) * 9 + tp] * d;
+    }
+  }
+  const int64_t o = ((f * n + y0 + py) * (int64_t)n + x0 + px) * CI;
+#pragma unroll
+  for (int ci = 0; ci < CI; ++ci) dX[o + ci] = acc[ci];
+}
+
+// partial[block][q]: q < CO CI 9 weight entries ([co][ci][ky][kx]), then CO biases
+template <int CI, int CO, typename T, typename TX>
+__global__ __launch_bounds__(256) void k_conv_bwd_weight(const T* __restrict__ dY,
+                                                         const TX* __restrict__ X,
+                                                         const TX* __restrict__ X_lo, int n,
+                                                         double* __restrict__ partial) {
+  constexpr int NP = CO * CI * 9 + CO;
+  __shared__ T xt[(kTile + 2) * (kTile + 2) * (CI + 1)];
+  __shared__ T yt[kTile * kTile * (CO + 1)];
+  const int tid = threadIdx.x;
+  const int tpr = n / kTile, m = n - 1;
+  const int64_t f = blockIdx.x / (tpr * tpr);
+  const int t = (int)(blockIdx.x % (tpr * tpr));
+  const int y0 = (t / tpr) * kTile, x0 = (t % tpr) * kTile;
+  for (int i = tid; i < (kTile + 2) * (kTile + 2) * CI; i += 256) {
+    const int p = i / CI, c = i % CI;
+    const int ty = p / (kTile + 2), tx = p % (kTile + 2);
+    const int64_t gi = ((f * n + ((y0 + ty - 1) & m)) * (int64_t)n + ((x0 + tx - 1) & m)) * CI + c;
+    T v = (T)(float)0;
+    v = (T)X[gi];
+    if (X_lo) v += (T)X_lo[gi];
+    xt[p * (CI + 1) + c] = v;
+  }
+  for (int i = tid; i < kTile * kTile * CO; i += 256) {
+    const int p = i / CO, c = i % CO;
+    yt[p * (CO + 1) + c] = dY[((f * n + y0 + p / kTile) * (int64_t)n + x0 + p % kTile) * CO + c];
+  }
+  __syncthreads();
+  for (int q = tid; q < NP; q += 256) {
+    double s = 0.0;
+    if (q < CO * CI * 9) {
+      const int co = q / (CI * 9), ci = (q / 9) % CI, tp = q % 9;
+      const int ky = tp / 3, kx = tp % 3;
+      for (int p = 0; p < kTile * kTile; ++p) {
+        const int py = p / kTile, px = p % kTile;
+        s += (double)(yt[p * (CO + 1) + co] * xt[((py + ky) * (kTile + 2) + px + kx) * (CI + 1) + ci]);
+      }
+    } else {
+      const int co = q - CO * CI * 9;
+      for (int p = 0; p < kTile * kTile; ++p) s += (double)yt[p * (CO + 1) + co];
+    }
+    partial[(int64_t)blockIdx.x * NP + q] = s;
+  }
+}
+
+// out[q] = sum over blocks of partial[block][q], in block order
+template <typename T>
+__global__ void k_reduce_partials(const double* __restrict__ partial, int64_t blocks, int np,
+                                  T* __restrict__ out_w, int nw, T* __restrict__ out_b) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= np) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < blocks; ++b) s += partial[b * np + q];
+  if (q < nw) out_w[q] = (T)s;
+  else out_b[q - nw] = (T)s;
+}
+
+// dZ = dA * act'(z), in place on dA
+template <typename T, typename TZ>
+__global__ void k_act_bwd(T* __restrict__ dA, const TZ* __restrict__ z, int64_t count, int act) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dA[i] = dA[i] * (T)act_grad<T>((T)z[i], act);
+}
+
+// Backward of the output stage.  Forward: o0 = [residual] u + net; o1 = o0 -
+// mean(o0 - u) (mass fix); o2 = clamp(o1) (limiter).  Given dG = dL/do2 and
+// o1, writes dnet = dL/dnet and du = the direct part of dL/du.
+__global__ __launch_bounds__(256) void k_out_bwd_sum(const double* __restrict__ dG,
+                                                     const double* __restrict__ o1, int n,
+                                                     int limiter, double lo, double hi,
+                                                     double* __restrict__ partials, int bpf) {
+  __shared__ double red[4];
+  const int64_t f = blockIdx.x / bpf;
+  const int part = blockIdx.x % bpf;
+  const int64_t n2 = (int64_t)n * n;
+  double s = 0.0;
+  for (int64_t i = (int64_t)part * 256 + threadIdx.x; i < n2; i += (int64_t)bpf * 256) {
+    const double v = o1[f * n2 + i];
+    const bool pass = !limiter || (v > lo && v < hi);
+    s += pass ? dG[f * n2 + i] : 0.0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_out_bwd(const double* __restrict__ dG,
+                                                 const double* __restrict__ o1, int n,
+                                                 int residual, int mass_fix, int limiter,
+                                                 double lo, double hi,
+                                                 const double* __restrict__ partials, int bpf,
+                                                 T* __restrict__ dnet, double* __restrict__ du) {
+  __shared__ double mean_sh;
+  const int64_t f = blockIdx.x / bpf;
+  const int part = blockIdx.x % bpf;
+  const int64_t n2 = (int64_t)n * n;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    if (mass_fix)
+      for (int i = 0; i < bpf; ++i) s += partials[f * bpf + i];
+    mean_sh = s / (double)n2;
+  }
+  __syncthreads();
+  const double mean = mean_sh;
+  for (int64_t i = (int64_t)part * 256 + threadIdx.x; i < n2; i += (int64_t)bpf * 256) {
+    const double v = o1[f * n2 + i];
+    const bool pass = !limiter || (v > lo && v < hi);
+    const double d1 = pass ? dG[f * n2 + i] : 0.0;   // dL/do1
+    const double d0 = d1 - mean;                       // dL/do0 (mean = 0 without mass fix)
+    dnet[f * n2 + i] = (T)d0;
+    du[f * n2 + i] = (residual ? d0 : 0.0) + mean;
+  }
+}
+
+// du += dX of the first layer (one channel)
+template <typename T>
+__global__ void k_add_into(double* __restrict__ du, const T* __restrict__ d, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) du[i] += (double)d[i];
+}
+
 // --------------------------------------------------------------- launch
 
 size_t cnn_lds_bytes(int C, bool split);
@@ -396,88 +677,185 @@ static int hidden_cap() {
   return cus * per_cu;
 }
 
-template <int C>
-static hipError_t launch_cnn_c(const CnnJob& j, hipStream_t st) {
-  const int n = j.n;
-  const int64_t tiles16 = (int64_t)(n / kTile) * (n / kTile);
-  const int L = j.n_layers;
-  const int64_t act_elems = j.nfields * (int64_t)n * n * C;
-  const bool f32 = j.prec == kCnnF32;
-  const bool split = j.prec == kCnnBf16x2;
-  // weight / bias offsets of layer l in the concatenated arrays
-  auto woff = [&](int l) {
-    int64_t o = 0;
-    for (int i = 0; i < l; ++i) o += (int64_t)(i == 0 ? 1 : C) * (i == L - 1 ? 1 : C) * 9;
-    return o;
-  };
-  auto boff = [&](int l) { return (int64_t)l * C; };
-  const dim3 g16((unsigned)(j.nfields * tiles16)), b256(256);
+// offsets of layer l's weights / biases in the concatenated arrays
+static int64_t cnn_woff(int l, int L, int C) {
+  int64_t o = 0;
+  for (int i = 0; i < l; ++i) o += (int64_t)(i == 0 ? 1 : C) * (i == L - 1 ? 1 : C) * 9;
+  return o;
+}
+static int64_t cnn_boff(int l, int C) { return (int64_t)l * C; }
 
-  if (f32) {
-    float* a0 = (float*)j.ws.act[0];
-    float* a1 = (float*)j.ws.act[1];
-    k_cnn_first<C, float><<<g16, b256, 0, st>>>(j.in_base, j.in_offs, n, j.W, j.B, j.act, a0,
-                                                nullptr);
-    for (int l = 1; l < L - 1; ++l) {
-      if constexpr (C >= 16) {
-        k_cnn_hidden_f32<C><<<g16, b256, 0, st>>>(a0, n, j.W + woff(l), j.B + boff(l), j.act, a1);
-      } else {
-        return hipErrorInvalidValue;
-      }
-      std::swap(a0, a1);
+int cnn_act_bytes(int prec) { return prec == kCnnF64 ? 8 : prec == kCnnF32 ? 4 : prec == kCnnBf16x2 ? 4 : 2; }
+int cnn_grad_bytes(int prec) { return prec == kCnnF64 ? 8 : 4; }
+
+// activation (and pre-activation) buffer of layer l's output
+static void* act_buf(const CnnJob& j, int l, bool train) {
+  const size_t bytes = (size_t)j.nfields * j.n * j.n * j.channels * cnn_act_bytes(j.prec);
+  return train ? (char*)j.ws.acts + (size_t)l * bytes : j.ws.act[l & 1];
+}
+static void* z_buf(const CnnJob& j, int l, bool train) {
+  const size_t zb = (size_t)j.nfields * j.n * j.n * j.channels * cnn_grad_bytes(j.prec);
+  return train ? (char*)j.ws.zs + (size_t)l * zb : nullptr;
+}
+
+template <int C, typename T>
+static void cnn_fwd_ref(const CnnJob& j, bool train, double* g_out, hipStream_t st) {
+  const int n = j.n, L = j.n_layers;
+  const int64_t tiles16 = (int64_t)(n / kTile) * (n / kTile);
+  const dim3 g16((unsigned)(j.nfields * tiles16)), b256(256);
+  const T* W = (const T*)j.W;
+  const T* B = (const T*)j.B;
+  k_cnn_first_ref<C, T><<<g16, b256, 0, st>>>(j.in_base, j.in_offs, n, W, B, j.act,
+                                              (T*)act_buf(j, 0, train), (T*)z_buf(j, 0, train));
+  for (int l = 1; l < L - 1; ++l)
+    k_cnn_hidden_ref<C, T><<<g16, b256, 0, st>>>(
+        (const T*)act_buf(j, l - 1, train), n, W + cnn_woff(l, L, C), B + cnn_boff(l, C), j.act,
+        (T*)act_buf(j, l, train), (T*)z_buf(j, l, train));
+  k_cnn_last_ref<C, T><<<g16, b256, 0, st>>>((const T*)act_buf(j, L - 2, train), n,
+                                             W + cnn_woff(L - 1, L, C), B + cnn_boff(L - 1, C),
+                                             j.in_base, j.in_offs, g_out, train ? nullptr : j.out_offs,
+                                             j.residual, j.ws.partials);
+}
+
+template <int C>
+static void cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t st) {
+  const int n = j.n, L = j.n_layers;
+  const int64_t tiles16 = (int64_t)(n / kTile) * (n / kTile);
+  const dim3 g16((unsigned)(j.nfields * tiles16)), b256(256);
+  const bool split = j.prec == kCnnBf16x2;
+  const int64_t act_elems = j.nfields * (int64_t)n * n * C;
+  const float* W = (const float*)j.W;
+  const float* B = (const float*)j.B;
+  auto hi = [&](int l) { return (__bf16*)act_buf(j, l, train); };
+  auto lo = [&](int l) { return split ? hi(l) + act_elems : (__bf16*)nullptr; };
+  k_cnn_first<C, __bf16><<<g16, b256, 0, st>>>(j.in_base, j.in_offs, n, W, B, j.act, hi(0), lo(0),
+                                               (float*)z_buf(j, 0, train));
+  for (int l = 1; l < L - 1; ++l) {
+    if constexpr (C % 16 == 0) {
+      using H = HidCfg<C>;
+      const __bf16* wp = (const __bf16*)j.ws.wpack + (int64_t)(l - 1) * C * H::KP;
+      const size_t lds = cnn_lds_bytes(C, split);
+      const int64_t tiles = j.nfields * (n / H::TH) * (n / H::TW);
+      static const int cap0 = hidden_cap<C, false>(), cap1 = hidden_cap<C, true>();
+      const dim3 gh((unsigned)std::min<int64_t>(tiles, split ? cap1 : cap0)), bh(H::NT);
+      if (split)
+        k_cnn_hidden<C, true><<<gh, bh, lds, st>>>(hi(l - 1), lo(l - 1), n, j.nfields, wp,
+                                                   B + cnn_boff(l, C), j.act, hi(l), lo(l),
+                                                   (float*)z_buf(j, l, train));
+      else
+        k_cnn_hidden<C, false><<<gh, bh, lds, st>>>(hi(l - 1), nullptr, n, j.nfields, wp,
+                                                    B + cnn_boff(l, C), j.act, hi(l), nullptr,
+                                                    (float*)z_buf(j, l, train));
     }
-    k_cnn_last<C, float><<<g16, b256, 0, st>>>(a0, nullptr, n, j.W + woff(L - 1),
-                                               j.B + boff(L - 1), j.in_base, j.in_offs,
-                                               j.out_base, j.out_offs, j.residual,
-                                               j.ws.partials);
-  } else {
-    __bf16* a0 = (__bf16*)j.ws.act[0];
-    __bf16* a1 = (__bf16*)j.ws.act[1];
-    __bf16* l0 = split ? a0 + act_elems : nullptr;
-    __bf16* l1 = split ? a1 + act_elems : nullptr;
-    k_cnn_first<C, __bf16><<<g16, b256, 0, st>>>(j.in_base, j.in_offs, n, j.W, j.B, j.act, a0, l0);
-    for (int l = 1; l < L - 1; ++l) {
-      if constexpr (C % 16 == 0) {
-        using H = HidCfg<C>;
-        const __bf16* wp = (const __bf16*)j.ws.wpack + (int64_t)(l - 1) * C * H::KP;
-        const size_t lds = cnn_lds_bytes(C, split);
-        const int64_t tiles = j.nfields * (n / H::TH) * (n / H::TW);
-        static const int cap0 = hidden_cap<C, false>(), cap1 = hidden_cap<C, true>();
-        const dim3 gh((unsigned)std::min<int64_t>(tiles, split ? cap1 : cap0)), bh(H::NT);
-        if (split)
-          k_cnn_hidden<C, true><<<gh, bh, lds, st>>>(a0, l0, n, j.nfields, wp, j.B + boff(l), j.act,
-                                                     a1, l1);
-        else
-          k_cnn_hidden<C, false><<<gh, bh, lds, st>>>(a0, nullptr, n, j.nfields, wp, j.B + boff(l),
-                                                      j.act, a1, nullptr);
-      } else {
-        return hipErrorInvalidValue;
-      }
-      std::swap(a0, a1);
-      std::swap(l0, l1);
-    }
-    k_cnn_last<C, __bf16><<<g16, b256, 0, st>>>(a0, l0, n, j.W + woff(L - 1), j.B + boff(L - 1),
-                                                j.in_base, j.in_offs, j.out_base, j.out_offs,
-                                                j.residual, j.ws.partials);
   }
-  if (j.mass_fix || j.limiter) {
+  k_cnn_last<C, __bf16><<<g16, b256, 0, st>>>(hi(L - 2), lo(L - 2), n, W + cnn_woff(L - 1, L, C),
+                                              B + cnn_boff(L - 1, C), j.in_base, j.in_offs, g_out,
+                                              train ? nullptr : j.out_offs, j.residual,
+                                              j.ws.partials);
+}
+
+// Forward of G; in training mode every layer's activation and pre-activation
+// is kept and the output (before the limiter) goes to ws.o1.
+template <int C>
+static hipError_t launch_cnn_fwd_c(const CnnJob& j, bool train, hipStream_t st) {
+  const int n = j.n;
+  double* g_out = train ? j.ws.o1 : j.out_base;
+  if (j.prec == kCnnF64) {
+    if constexpr (C <= kCnnF64MaxC) cnn_fwd_ref<C, double>(j, train, g_out, st);
+    else return hipErrorInvalidValue;
+  } else if (j.prec == kCnnF32) {
+    cnn_fwd_ref<C, float>(j, train, g_out, st);
+  } else {
+    if (j.n_layers > 2 && C % 16 != 0) return hipErrorInvalidValue;
+    cnn_fwd_bf16<C>(j, train, g_out, st);
+  }
+  const int limiter = train ? 0 : j.limiter;
+  if (j.mass_fix || limiter) {
     const int bpf = (int)std::max<int64_t>(1, (int64_t)n * n / 2048);
-    k_cnn_fix<<<dim3((unsigned)(j.nfields * bpf)), b256, 0, st>>>(
-        j.out_base, j.out_offs, n, j.ws.partials, (int)tiles16, j.mass_fix, j.limiter, j.lim_lo,
-        j.lim_hi, bpf);
+    const int64_t tiles16 = (int64_t)(n / kTile) * (n / kTile);
+    k_cnn_fix<<<dim3((unsigned)(j.nfields * bpf)), dim3(256), 0, st>>>(
+        g_out, train ? nullptr : j.out_offs, n, j.ws.partials, (int)tiles16, j.mass_fix, limiter,
+        j.lim_lo, j.lim_hi, bpf);
   }
   return hipGetLastError();
 }
 
+template <int CI, int CO, typename TG, typename TX, typename TW>
+static void conv_bwd(const CnnJob& j, const TG* dY, const TX* X, const TX* X_lo, const TW* W,
+                     TW* dW, TW* db, TG* dX, hipStream_t st) {
+  const int n = j.n;
+  const int64_t tiles16 = j.nfields * (int64_t)(n / kTile) * (n / kTile);
+  const dim3 g16((unsigned)tiles16), b256(256);
+  constexpr int NP = CO * CI * 9 + CO;
+  k_conv_bwd_weight<CI, CO, TG, TX><<<g16, b256, 0, st>>>(dY, X, X_lo, n, j.ws.wpart);
+  k_reduce_partials<TW><<<dim3((NP + 255) / 256), b256, 0, st>>>(j.ws.wpart, tiles16, NP, dW,
+                                                                 CO * CI * 9, db);
+  if (dX) k_conv_bwd_data<CI, CO, TG, TW><<<g16, b256, 0, st>>>(dY, n, W, dX);
+}
+
+template <int C, typename TG, typename TA, typename TZ, typename TW>
+static hipError_t cnn_bwd_layers(const CnnJob& j, const double* dG, double* du, TW* gW, TW* gB,
+                                 hipStream_t st) {
+  const int n = j.n, L = j.n_layers;
+  const int64_t n2 = (int64_t)n * n, pix = j.nfields * n2;
+  const bool split = j.prec == kCnnBf16x2;
+  const int64_t act_elems = pix * C;
+  const TW* W = (const TW*)j.W;
+  auto A = [&](int l) { return (const TA*)act_buf(j, l, true); };
+  auto Alo = [&](int l) { return split ? A(l) + act_elems : (const TA*)nullptr; };
+  auto Z = [&](int l) { return (const TZ*)z_buf(j, l, true); };
+  TG* d0 = (TG*)j.ws.d[0];
+  TG* d1 = (TG*)j.ws.d[1];
+  // output stage
+  const int bpf = (int)std::max<int64_t>(1, n2 / 2048);
+  k_out_bwd_sum<<<dim3((unsigned)(j.nfields * bpf)), dim3(256), 0, st>>>(
+      dG, j.ws.o1, n, j.limiter, j.lim_lo, j.lim_hi, j.ws.fpart, bpf);
+  k_out_bwd<TG><<<dim3((unsigned)(j.nfields * bpf)), dim3(256), 0, st>>>(
+      dG, j.ws.o1, n, j.residual, j.mass_fix, j.limiter, j.lim_lo, j.lim_hi, j.ws.fpart, bpf, d0,
+      du);
+  // last layer: C -> 1
+  conv_bwd<C, 1, TG, TA, TW>(j, d0, A(L - 2), Alo(L - 2), W + cnn_woff(L - 1, L, C),
+                             gW + cnn_woff(L - 1, L, C), gB + cnn_boff(L - 1, C), d1, st);
+  const dim3 ge((unsigned)((act_elems + 255) / 256)), b256(256);
+  k_act_bwd<TG, TZ><<<ge, b256, 0, st>>>(d1, Z(L - 2), act_elems, j.act);
+  std::swap(d0, d1);  // d0 = dZ of layer L-2
+  for (int l = L - 2; l >= 1; --l) {
+    conv_bwd<C, C, TG, TA, TW>(j, d0, A(l - 1), Alo(l - 1), W + cnn_woff(l, L, C),
+                               gW + cnn_woff(l, L, C), gB + cnn_boff(l, C), d1, st);
+    k_act_bwd<TG, TZ><<<ge, b256, 0, st>>>(d1, Z(l - 1), act_elems, j.act);
+    std::swap(d0, d1);
+  }
+  // first layer: 1 -> C, its input is the state itself
+  conv_bwd<1, C, TG, double, TW>(j, d0, j.in_base, nullptr, W, gW, gB, d1, st);
+  k_add_into<TG><<<dim3((unsigned)((pix + 255) / 256)), b256, 0, st>>>(du, d1, pix);
+  return hipGetLastError();
+}
+
+template <int C>
+static hipError_t launch_cnn_bwd_c(const CnnJob& j, const double* dG, double* du, void* gW,
+                                   void* gB, hipStream_t st) {
+  hipError_t e = launch_cnn_fwd_c<C>(j, true, st);
+  if (e != hipSuccess) return e;
+  if (j.prec == kCnnF64) {
+    if constexpr (C <= kCnnF64MaxC)
+      return cnn_bwd_layers<C, double, double, double, double>(j, dG, du, (double*)gW, (double*)gB, st);
+    else
+      return hipErrorInvalidValue;
+  }
+  if (j.prec == kCnnF32)
+    return cnn_bwd_layers<C, float, float, float, float>(j, dG, du, (float*)gW, (float*)gB, st);
+  return cnn_bwd_layers<C, float, __bf16, float, float>(j, dG, du, (float*)gW, (float*)gB, st);
+}
+
 hipError_t launch_cnn_pack(const CnnJob& j, hipStream_t st) {
-  if (j.prec == kCnnF32 || j.n_layers < 3) return hipSuccess;
+  if (j.prec == kCnnF32 || j.prec == kCnnF64 || j.n_layers < 3) return hipSuccess;
   const int C = j.channels, L = j.n_layers;
   const int kp = (9 * C + 31) / 32 * 32;
   int64_t wo = (int64_t)C * 9;  // layer 0 is 1 -> C
   for (int l = 1; l < L - 1; ++l) {
     const int64_t cnt = (int64_t)C * kp;
     k_cnn_pack<<<dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st>>>(
-        j.W + wo, C, C, kp, (__bf16*)j.ws.wpack + (int64_t)(l - 1) * C * kp);
+        (const float*)j.W + wo, C, C, kp, (__bf16*)j.ws.wpack + (int64_t)(l - 1) * C * kp);
     wo += (int64_t)C * C * 9;
   }
   return hipGetLastError();
@@ -486,11 +864,24 @@ hipError_t launch_cnn_pack(const CnnJob& j, hipStream_t st) {
 hipError_t launch_cnn(const CnnJob& j, hipStream_t st) {
   if (j.nfields <= 0) return hipSuccess;
   switch (j.channels) {
-    case 8: return launch_cnn_c<8>(j, st);
-    case 16: return launch_cnn_c<16>(j, st);
-    case 32: return launch_cnn_c<32>(j, st);
-    case 48: return launch_cnn_c<48>(j, st);
-    case 64: return launch_cnn_c<64>(j, st);
+    case 8: return launch_cnn_fwd_c<8>(j, false, st);
+    case 16: return launch_cnn_fwd_c<16>(j, false, st);
+    case 32: return launch_cnn_fwd_c<32>(j, false, st);
+    case 48: return launch_cnn_fwd_c<48>(j, false, st);
+    case 64: return launch_cnn_fwd_c<64>(j, false, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_cnn_backward(const CnnJob& j, const double* dG, double* du, void* gW, void* gB,
+                               hipStream_t st) {
+  if (j.nfields <= 0) return hipSuccess;
+  switch (j.channels) {
+    case 8: return launch_cnn_bwd_c<8>(j, dG, du, gW, gB, st);
+    case 16: return launch_cnn_bwd_c<16>(j, dG, du, gW, gB, st);
+    case 32: return launch_cnn_bwd_c<32>(j, dG, du, gW, gB, st);
+    case 48: return launch_cnn_bwd_c<48>(j, dG, du, gW, gB, st);
+    case 64: return launch_cnn_bwd_c<64>(j, dG, du, gW, gB, st);
     default: return hipErrorInvalidValue;
   }
 }

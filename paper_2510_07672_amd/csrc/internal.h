@@ -110,20 +110,28 @@ struct CorrectJob {
 // ---- convolutional coarse propagator
 
 enum { kActGelu = 0, kActTanh = 1 };
-enum { kCnnF32 = 1, kCnnBf16 = 2, kCnnBf16x2 = 3 };   // same values as pr_dtype
+enum { kCnnF64 = 0, kCnnF32 = 1, kCnnBf16 = 2, kCnnBf16x2 = 3 };   // same values as pr_dtype
+constexpr int kCnnF64MaxC = 32;   // widest FP64 network whose tiles fit in LDS
 
 struct CnnWs {
   void* wpack;       // bfloat16 [L-2][C][KP] packed hidden-layer weights
   void* act[2];      // ping-pong activations [nfields][N][N][C] (x2 for hi+lo)
   double* partials;  // [nfields][(N/16)^2] FP64 sums of G(u) - u
+  // backward only
+  void* acts;        // [L-1] activations of every layer but the last
+  void* zs;          // [L-1] pre-activations
+  double* o1;        // [nfields][N][N] forward output before the limiter
+  double* wpart;     // [tiles][params] weight-gradient partial sums
+  void* d[2];        // gradient buffers [nfields][N][N][C]
+  double* fpart;     // per-field partial sums of the output-stage gradient
 };
 
 struct CnnJob {
   int n, n_layers, channels, prec, act, residual, mass_fix, limiter;
   double lim_lo, lim_hi;
   int64_t nfields;
-  const float* W;            // concatenated torch Conv2d weights
-  const float* B;            // concatenated biases
+  const void* W;             // concatenated torch Conv2d weights (double for F64, else float)
+  const void* B;             // concatenated biases
   const double* in_base;     // field i at in_base + (in_offs ? in_offs[i] : i N^2)
   const int64_t* in_offs;
   double* out_base;
@@ -133,6 +141,10 @@ struct CnnJob {
 
 hipError_t launch_cnn_pack(const CnnJob& j, hipStream_t st);
 hipError_t launch_cnn(const CnnJob& j, hipStream_t st);
+hipError_t launch_cnn_backward(const CnnJob& j, const double* dG, double* du, void* gW, void* gB,
+                               hipStream_t st);
+int cnn_act_bytes(int prec);
+int cnn_grad_bytes(int prec);
 size_t cnn_lds_bytes(int C, bool split);
 hipError_t cnn_set_lds_limits();
 

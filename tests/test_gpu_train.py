@@ -1,0 +1,140 @@
+"""GPU checks of the hand-written backward of the convolutional coarse
+propagator and of the checkpointed rollout (Section 3.2, Algorithm 1).
+
+  * FP64: torch.autograd.gradcheck (finite differences) at 32^2.
+  * FP32: against torch autograd through the FP64 oracle, rel 1e-5 for
+    dL/du and 1e-4 for the parameter gradients (FP32 sums over all pixels).
+  * bf16: against torch autograd through the oracle that rounds as the
+    bfloat16 kernels do (straight-through rounding), rel 2e-2.
+  * rollout: gradients identical for every checkpoint interval (the
+    recomputation is deterministic) and equal to the oracle rollout's.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cnn  # noqa: E402
+from paper_2510_07672_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    from paper_2510_07672_amd import api, autograd
+    return api, autograd
+
+
+def problem(api, n):
+    return api.Problem(n=n, length=1.0, eps=0.01, conservative=False, stab=2.0, dt=2e-5, steps=1)
+
+
+def rel(a, b):
+    a, b = torch.as_tensor(a).double().cpu(), torch.as_tensor(b).double().cpu()
+    return float((a - b).norm() / b.norm())
+
+
+@pytest.mark.parametrize("L,C,mass_fix,act", [(2, 8, False, "gelu"), (2, 8, True, "tanh"),
+                                              (3, 8, False, "gelu")])
+def test_gradcheck_fp64(mods, L, C, mass_fix, act):
+    api, ag = mods
+    spec = cnn.CnnSpec(n_layers=L, channels=C, act=act, mass_fix=mass_fix)
+    ws, bs = cnn.init_weights(spec, seed=4)
+    net = api.CnnCoarse(ws, bs, act=act, mass_fix=mass_fix, prec="f64")
+    net.W.requires_grad_(True)
+    net.B.requires_grad_(True)
+    p = problem(api, 32)
+    u = torch.from_numpy(synth.random_ic(32, [1])).cuda().requires_grad_(True)
+    f = lambda u, W, B: ag.CnnApply.apply(u, W, B, net, p)  # noqa: E731
+    assert torch.autograd.gradcheck(f, (u, net.W, net.B), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def oracle_grads(spec, ws, bs, u, r, emulate=False):
+    Wt = [w.clone().requires_grad_(True) for w in ws]
+    Bt = [b.clone().requires_grad_(True) for b in bs]
+    ut = torch.from_numpy(u).requires_grad_(True)
+    x = ut[:, None]
+    L = spec.n_layers
+    for l in range(L):
+        W = Wt[l]
+        if emulate and 0 < l < L - 1:
+            W = cnn.bf16(W)
+        x = cnn.conv3x3_periodic(x, W, Bt[l])
+        if l < L - 1:
+            x = cnn._act(x, spec.act)
+            if emulate:
+                x = cnn.bf16(x)
+    out = ut + x[:, 0]
+    (out * torch.from_numpy(r)).sum().backward()
+    return ut.grad, torch.cat([w.grad.reshape(-1) for w in Wt]), torch.cat([b.grad for b in Bt])
+
+
+@pytest.mark.parametrize("prec,C,L,n", [("f32", 32, 4, 64), ("f32", 16, 3, 128), ("bf16", 32, 4, 64),
+                                        ("bf16", 48, 3, 64)])
+def test_backward_matches_oracle_autograd(mods, prec, C, L, n):
+    api, _ = mods
+    spec = cnn.CnnSpec(n_layers=L, channels=C)
+    ws, bs = cnn.init_weights(spec, seed=8)
+    net = api.CnnCoarse(ws, bs, prec=prec)
+    u = synth.random_ic(n, [2, 3])
+    r = np.random.default_rng(5).standard_normal(u.shape)
+    du, dW, dB = api.pr_cnn_backward(problem(api, n), net, torch.from_numpy(u).cuda(),
+                                     torch.from_numpy(r).cuda())
+    gu, gW, gB = oracle_grads(spec, ws, bs, u, r, emulate=(prec == "bf16"))
+    tol_u, tol_p = (1e-5, 1e-4) if prec == "f32" else (2e-2, 2e-2)
+    assert rel(du, gu) <= tol_u
+    assert rel(dW, gW) <= tol_p
+    assert rel(dB, gB) <= tol_p
+
+
+def test_backward_deterministic(mods):
+    api, _ = mods
+    spec = cnn.CnnSpec(n_layers=4, channels=32)
+    ws, bs = cnn.init_weights(spec, seed=9)
+    net = api.CnnCoarse(ws, bs, prec="bf16")
+    u = torch.from_numpy(synth.random_ic(64, [4, 5])).cuda()
+    r = torch.randn_like(u)
+    a = api.pr_cnn_backward(problem(api, 64), net, u, r)
+    b = api.pr_cnn_backward(problem(api, 64), net, u, r)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_rollout_checkpointing(mods):
+    api, ag = mods
+    spec = cnn.CnnSpec(n_layers=3, channels=16)
+    ws, bs = cnn.init_weights(spec, seed=10, scale=0.3)
+    n, steps = 64, 8
+    p = problem(api, n)
+    u0 = torch.from_numpy(synth.random_ic(n, [6, 7])).cuda()
+    tgt = torch.randn((steps, 2, n, n), dtype=torch.float64, device="cuda")
+    grads = []
+    for ck in (1, 2, 8):
+        net = api.CnnCoarse(ws, bs, prec="f32")
+        net.W.requires_grad_(True)
+        net.B.requires_grad_(True)
+        u = u0.clone().requires_grad_(True)
+        out = ag.cnn_rollout(net, p, u, steps, ckpt=ck)
+        ((out - tgt) ** 2).mean().backward()
+        grads.append((u.grad, net.W.grad, net.B.grad))
+    for g in grads[1:]:
+        for x, y in zip(g, grads[0]):
+            assert torch.equal(x, y)
+    # against autograd through the FP64 oracle rollout
+    Wt = [w.clone().requires_grad_(True) for w in ws]
+    Bt = [b.clone().requires_grad_(True) for b in bs]
+    ut = u0.cpu().clone().requires_grad_(True)
+    x, outs = ut, []
+    for _ in range(steps):
+        h = x[:, None]
+        for l in range(3):
+            h = cnn.conv3x3_periodic(h, Wt[l], Bt[l])
+            if l < 2:
+                h = cnn.gelu_exact(h)
+        x = x + h[:, 0]
+        outs.append(x)
+    ((torch.stack(outs) - tgt.cpu()) ** 2).mean().backward()
+    assert rel(grads[0][0], ut.grad) <= 1e-4
+    assert rel(grads[0][1], torch.cat([w.grad.reshape(-1) for w in Wt])) <= 1e-4

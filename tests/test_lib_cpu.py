@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 2
+    assert lib.pr_abi_version() == 3
 
 
 def test_library_exports_match_nm(L):
@@ -115,7 +115,7 @@ def test_status_strings(L):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(channels=24), 2), (dict(channels=8, n_layers=3), 2), (dict(prec=0), 2),
+    (dict(channels=24), 2), (dict(channels=8, n_layers=3), 2), (dict(prec=0, channels=48), 2),
     (dict(prec=3, channels=64), 2), (dict(n_layers=1), 1), (dict(act=5), 1),
     (dict(limiter=1, lim_lo=1.0, lim_hi=0.0), 1), (dict(weights=None), 1),
 ])
