@@ -167,20 +167,56 @@ def calib_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"calib_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def make_cnn(api, cfg, prec):
-    """The workload's network with torch Conv2d default initialisation under
-    a fixed seed (no trained weights are available)."""
-    import math
-    import torch
+def trained_cnn(api, p, cfg, prec, steps, n_traj=256, n_slices=16):
+    """The workload's network, trained with Adam on fine-solver trajectories
+    from seeds 1000.. (bf16 forward, FP32 gradients, 8-step rollouts
+    checkpointed every 2), then evaluated in `prec`."""
+    from paper_2510_07672_amd import train
     L, C = cfg["cnn"]
-    gen = torch.Generator().manual_seed(0)
-    widths = [1] + [C] * (L - 1) + [1]
-    ws, bs = [], []
-    for l in range(L):
-        bound = 1.0 / math.sqrt(widths[l] * 9)
-        ws.append((torch.rand((widths[l + 1], widths[l], 3, 3), generator=gen) * 2 - 1) * bound)
-        bs.append((torch.rand((widths[l + 1],), generator=gen) * 2 - 1) * bound)
-    return api.CnnCoarse(ws, bs, act="gelu", residual=True, prec=prec)
+    net = train.init_network(L, C, seed=0, prec="bf16")
+    info = None
+    if steps > 0:
+        t0 = time.perf_counter()
+        data = train.make_dataset(p, range(1000, 1000 + n_traj), n_slices)
+        t_data = time.perf_counter() - t0
+        log = train.train(net, p, data, steps=steps, batch=32, rollout=8, ckpt=2, lr=1e-3)
+        info = {"steps": steps, "trajectories": n_traj, "slices_per_trajectory": n_slices,
+                "data_s": round(t_data, 2), "loss_first": log.loss[0], "loss_last": log.loss[-1],
+                "step_ms_median": round(sorted(log.step_ms)[len(log.step_ms) // 2], 2)}
+        del data
+    lay = net.layers()
+    ws = [w.detach().float().cpu() for w, _ in lay]
+    bs = [b.detach().float().cpu() for _, b in lay]
+    return api.CnnCoarse(ws, bs, act="gelu", residual=True, prec=prec), info
+
+
+def training_bench(args):
+    """Config 4: one training step = an 8-step rollout of the network on a
+    batch of 32 trajectories at 256^2 (bf16 forward, FP32 gradients,
+    checkpoints every 2 steps), the MSE against fine-solver states, the
+    backward through the hand-written kernels and an Adam update."""
+    import torch
+    from paper_2510_07672_amd import api, train
+    n = 256
+    p = api.Problem(n=n, length=1.0, eps=0.01, conservative=False, stab=2.0, dt=2e-5, steps=200)
+    data = train.make_dataset(p, range(2000, 2032), 16)
+    net = train.init_network(4, 32, seed=0, prec="bf16")
+    train.train(net, p, data, steps=args.warmup, batch=32)
+    log = train.train(net, p, data, steps=args.steps, batch=32, seed=1)
+    ms = float(np.median(log.step_ms))
+    # network applications per step: 8 forward + 8 recomputed in backward
+    # (inside pr_cnn_backward) + 4 segment recomputations
+    apps = 32 * (8 + 8 + 4)
+    return {"metric": "CNN coarse-propagator training steps/s (8-step rollout, batch 32, 256^2)",
+            "value": round(1e3 / ms, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16 forward, f32 grads",
+            "data": "synthetic",
+            "config": {"workload": "training: 8-step unrolled rollout, batch 32 trajectories, "
+                                   "256x256 classic AC, 4 conv x 32 ch GELU, MSE vs fine states, "
+                                   "checkpoint every 2 steps"},
+            "network_applications_per_s": round(apps / ms * 1e3, 1),
+            "loss_first": log.loss[0], "loss_last": log.loss[-1]}
 
 
 def cnn_kernel_rate(api, p, g, u0, reps=20):
@@ -215,14 +251,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + ["c4"])
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--kmax", type=int, default=16)
-    ap.add_argument("--coarse", default="num", choices=["num", "cnn"],
-                    help="numerical coarse step, or the convolutional network of the workload")
-    ap.add_argument("--cnn-prec", default="bf16", choices=["bf16", "bf16x2", "f32"])
+    ap.add_argument("--coarse", default=None, choices=["num", "cnn"],
+                    help="numerical coarse step, or the workload's convolutional network "
+                         "(default: the network for configs 2 and 3, the scheme for config 1)")
+    ap.add_argument("--cnn-prec", default="bf16x2", choices=["bf16", "bf16x2", "f32"])
+    ap.add_argument("--train-steps", type=int, default=200,
+                    help="Adam steps on fine trajectories before timing (network only)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -238,14 +277,20 @@ def main():
     import torch
     from paper_2510_07672_amd import api, synth
 
+    if args.config == "c4":
+        print(json.dumps(training_bench(args)), flush=True)
+        return
     cfg = CONFIGS[args.config]
     n, s, B, c = cfg["n"], cfg["slices"], cfg["ics"], cfg["steps"]
     p = api.Problem(n=n, length=1.0, eps=cfg["eps"], conservative=cfg["conservative"], stab=2.0,
                     dt=cfg["dt"], steps=c, fine_prec=args.prec)
-    if args.coarse == "cnn":
-        g = make_cnn(api, cfg, args.cnn_prec)
+    coarse = args.coarse or ("num" if args.config == "c1" else "cnn")
+    g_num = api.Coarse(dt=cfg["dt"] * c / cfg["g_steps"], steps=cfg["g_steps"], prec="f64")
+    train_info = None
+    if coarse == "cnn":
+        g, train_info = trained_cnn(api, p, cfg, args.cnn_prec, args.train_steps)
     else:
-        g = api.Coarse(dt=cfg["dt"] * c / cfg["g_steps"], steps=cfg["g_steps"], prec="f64")
+        g = g_num
     u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
     U = torch.empty((B, s + 1, n, n), dtype=torch.float64, device="cuda")
     ws = None
@@ -295,11 +340,20 @@ def main():
                    "fine_solves_per_launch": B * s, "fine_prec": args.prec},
         "roofline": roof,
     }
-    if args.coarse == "cnn":
+    if coarse == "cnn":
         out["coarse_kernel"] = cnn_kernel_rate(api, p, g, u0)
-        out["config"]["coarse"] = f"u + CNN(u), {g.n_layers} conv layers x {g.channels} ch, GELU, {g.prec}, seed-0 weights"
+        out["config"]["coarse"] = (f"u + CNN(u), {g.n_layers} conv layers x {g.channels} ch, GELU, "
+                                   f"{g.prec}; " + (f"trained {train_info['steps']} Adam steps on "
+                                   f"{train_info['trajectories']} fine trajectories"
+                                   if train_info else "seed-0 weights, untrained"))
+        if train_info:
+            out["training"] = train_info
+    else:
+        out["config"]["coarse"] = "numerical: one semi-implicit step per slice"
     if not args.no_parareal:
         out["parareal"] = parareal_vs_serial(api, p, g, u0, s, args.kmax)
+        if coarse == "cnn":
+            out["parareal_numerical_coarse"] = parareal_vs_serial(api, p, g_num, u0, s, args.kmax)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.prec)
     print(json.dumps(out), flush=True)

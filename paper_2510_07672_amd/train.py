@@ -1,0 +1,86 @@
+"""Training of the convolutional coarse propagator on trajectories of the
+fine propagator (Section 3.2, Algorithm 1, with the mean-squared loss
+against fine-solver states that the workloads fix).
+
+Data: R initial conditions, each advanced slice by slice with the FP64
+fine propagator (pr_serial_fine), so targets are U_{t+1} = F(U_t).
+Training step: a batch of trajectories, an unrolled rollout of `rollout`
+network applications from U_t (checkpointed every `ckpt` steps), the mean
+squared distance to U_{t+1..t+rollout}, and an Adam update of the flat
+parameter buffers.  The optimiser is torch's; forward and backward of the
+network run in libpr.
+"""
+
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import List
+
+import torch
+
+from . import api, autograd, synth
+
+
+def init_network(n_layers: int, channels: int, seed: int, prec: str = "bf16",
+                 act: str = "gelu", out_scale: float = 0.1, **kw) -> api.CnnCoarse:
+    """torch.nn.Conv2d default initialisation under a fixed seed; the last
+    layer is scaled by out_scale so the untrained G starts near u -> u."""
+    g = torch.Generator().manual_seed(seed)
+    widths = [1] + [channels] * (n_layers - 1) + [1]
+    ws, bs = [], []
+    for l in range(n_layers):
+        bound = 1.0 / math.sqrt(widths[l] * 9)
+        w = (torch.rand((widths[l + 1], widths[l], 3, 3), generator=g) * 2 - 1) * bound
+        b = (torch.rand((widths[l + 1],), generator=g) * 2 - 1) * bound
+        if l == n_layers - 1:
+            w, b = w * out_scale, b * out_scale
+        ws.append(w)
+        bs.append(b)
+    return api.CnnCoarse(ws, bs, act=act, prec=prec, **kw)
+
+
+def make_dataset(p: api.Problem, seeds, n_slices: int, device="cuda") -> torch.Tensor:
+    """[R, n_slices + 1, N, N] fine trajectories (FP64 fine propagator)."""
+    import dataclasses
+    p64 = dataclasses.replace(p, fine_prec="f64")
+    u0 = torch.from_numpy(synth.random_ic(p.n, seeds)).to(device)
+    return api.pr_serial_fine(p64, u0, n_slices)
+
+
+@dataclass
+class TrainLog:
+    loss: List[float] = field(default_factory=list)
+    step_ms: List[float] = field(default_factory=list)
+
+
+def train(net: api.CnnCoarse, p: api.Problem, data: torch.Tensor, steps: int, batch: int = 32,
+          rollout: int = 8, ckpt: int = 2, lr: float = 1e-3, seed: int = 0) -> TrainLog:
+    """`steps` Adam updates on random (trajectory, start) pairs."""
+    R, T1 = data.shape[0], data.shape[1]
+    if T1 - 1 < rollout:
+        raise ValueError("trajectories shorter than the rollout")
+    net.W.requires_grad_(True)
+    net.B.requires_grad_(True)
+    opt = torch.optim.Adam([net.W, net.B], lr=lr)
+    gen = torch.Generator().manual_seed(seed)
+    log = TrainLog()
+    for _ in range(steps):
+        idx = torch.randint(0, R, (batch,), generator=gen)
+        t0 = torch.randint(0, T1 - rollout, (batch,), generator=gen)
+        u0 = data[idx, t0].contiguous()
+        tgt = torch.stack([data[idx, t0 + k + 1] for k in range(rollout)])
+        torch.cuda.synchronize()
+        tic = time.perf_counter()
+        out = autograd.cnn_rollout(net, p, u0, rollout, ckpt)
+        loss = ((out - tgt) ** 2).mean()
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+        torch.cuda.synchronize()
+        log.step_ms.append((time.perf_counter() - tic) * 1e3)
+        log.loss.append(float(loss.item()))
+    net.W.requires_grad_(False)
+    net.B.requires_grad_(False)
+    return log

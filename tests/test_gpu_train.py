@@ -138,3 +138,26 @@ def test_rollout_checkpointing(mods):
     ((torch.stack(outs) - tgt.cpu()) ** 2).mean().backward()
     assert rel(grads[0][0], ut.grad) <= 1e-4
     assert rel(grads[0][1], torch.cat([w.grad.reshape(-1) for w in Wt])) <= 1e-4
+
+
+def test_training_reduces_loss_and_coarse_error(mods):
+    """A short run of the training loop: the rollout loss falls, and the
+    trained network predicts one slice of the fine propagator better than
+    the untrained one (measured against the FP64 oracle's F)."""
+    from oracle import allen_cahn as ac
+    from paper_2510_07672_amd import train
+    api, _ = mods
+    n, c, dt = 64, 50, 2e-5
+    p = api.Problem(n=n, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=dt, steps=c)
+    data = train.make_dataset(p, range(100, 116), 12)
+    net = train.init_network(3, 16, seed=0, prec="f32")
+    u_test = synth.random_ic(n, [999])
+    ref = ac.fine(u_test, ac.Problem(n=n, length=1.0, eps=0.02, conservative=False, stab=2.0,
+                                      dt=dt, steps=c))
+    ut = torch.from_numpy(u_test).cuda()
+    before = rel(api.pr_coarse_apply(p, net, ut), ref)
+    log = train.train(net, p, data, steps=60, batch=8, rollout=4, ckpt=2, lr=2e-3)
+    after = rel(api.pr_coarse_apply(p, net, ut), ref)
+    assert np.isfinite(log.loss).all()
+    assert np.mean(log.loss[-5:]) < 0.3 * np.mean(log.loss[:5])
+    assert after < 0.5 * before
