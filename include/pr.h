@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 3
+#define PR_ABI_VERSION 4
 
 typedef enum {
   PR_OK = 0,
@@ -73,6 +73,13 @@ typedef struct {
   int32_t fine_prec;    /* PR_F64 or PR_F32: arithmetic of the fine FFTs.
                            PR_F32 rounds its input state to float once, at
                            stage-in, and carries a float state in between.  */
+  int32_t f32_iters;    /* Parareal only (pr_solve, pr_solve_many), with
+                           fine_prec = PR_F64: the first f32_iters
+                           iterations use FP32 fine solves; the next one
+                           restarts the prefix with FP64 fine solves over
+                           every slice (see pr_solve).  0 <= f32_iters <
+                           n_slices; must be 0 with PR_F32.  Other calls
+                           ignore it.                                      */
 } pr_problem;
 
 typedef enum { PR_G_SCHEME = 0, PR_G_CNN = 1 } pr_coarse_kind;
@@ -210,7 +217,8 @@ pr_status pr_correct(int64_t nfields, int32_t n, const void* f,
 size_t pr_solve_workspace_bytes(const pr_problem* p, const pr_coarse* g,
                                 int64_t n_ics, int32_t n_slices);
 
-/* Algorithm 2 for n_ics initial conditions at once.
+/* Algorithm 2 for n_ics initial conditions at once (one pr_job of
+ * pr_solve_many; the two give the same bits).
  *   u0  device double[n_ics][N][N]
  *   U   device double[n_ics][n_slices+1][N][N]: out, the final iterate
  *       [U_0, U^1_1, ..., U^k_k, ..., U^k_s] of each IC.
@@ -222,11 +230,58 @@ size_t pr_solve_workspace_bytes(const pr_problem* p, const pr_coarse* g,
  * clamped to n_slices; after k iterations slices 0..k equal the serial
  * fine solve exactly, so k = n_slices always returns PR_OK.
  * Returns PR_NOT_CONVERGED if max_iter < n_slices stopped an IC above tol
- * (U still holds the last iterate), PR_ERR_NUMERIC on NaN/Inf. */
+ * (U still holds the last iterate), PR_ERR_NUMERIC on NaN/Inf.
+ *
+ * Precision schedule (p->f32_iters = K > 0, fine_prec = PR_F64): iterations
+ * 1..K run the fine solves in FP32 (16 instead of 32 bytes per point and
+ * step) and never freeze an IC, since their fixed point is the FP32 serial
+ * solve.  Iteration K+1 runs FP64 fine solves over slices 0..s-1 and so
+ * restarts the exact prefix; FP64 iteration j = k - K covers slices
+ * j-1..s-1, and after it slices 0..j equal the FP64 serial fine solve
+ * exactly.  The FP32 iterations only give the FP64 phase a better start:
+ * the converged result is the FP64 one, max_iter is clamped to K + s, and
+ * k = K + s returns the FP64 serial solve bit for bit. */
 pr_status pr_solve(const pr_problem* p, const pr_coarse* g, int64_t n_ics,
                    int32_t n_slices, const double* u0, double* U, double tol,
                    int32_t max_iter, pr_stats* stats, void* ws,
                    size_t ws_bytes, void* stream);
+
+/* One Parareal solve of a heterogeneous batch: its own problem (any N, eps,
+ * dt, S, model, fine precision and schedule), coarse propagator, initial
+ * conditions, slice count, tolerance and iteration cap. */
+typedef struct {
+  pr_problem problem;
+  pr_coarse coarse;
+  int64_t n_ics;        /* >= 0                                          */
+  int32_t n_slices;     /* s >= 1                                        */
+  int32_t max_iter;     /* >= 0; clamped to f32_iters + s                */
+  double tol;           /* >= 0, sup-norm update per IC                  */
+  const double* u0;     /* device double[n_ics][N][N]                    */
+  double* U;            /* device double[n_ics][s+1][N][N], out          */
+  pr_stats* stats;      /* host, may be NULL (as for pr_solve; fine_ms and
+                           sweep_ms add the whole batch's sweep times of
+                           the iterations this job took part in)         */
+  int32_t status;       /* out: PR_OK, PR_NOT_CONVERGED or PR_ERR_NUMERIC */
+} pr_job;
+
+size_t pr_solve_many_workspace_bytes(int32_t n_jobs, const pr_job* jobs);
+
+/* Algorithm 2 (Section 3.3) for n_jobs independent solves at once: the
+ * uneven batching of the method's data parallelism.  Every job runs
+ * exactly what pr_solve would run for it (same bits), but in each
+ * iteration the fine solves of all jobs that share (N, precision, steps
+ * per slice) go into one launch sequence, whatever their eps, dt, S or
+ * model (per-field step parameters), and the sequential sweeps of all
+ * jobs advance together: step j of the sweep applies every job's G to its
+ * slice j (one launch per coarse propagator and N) and corrects all of
+ * them (one launch per N and fine precision).  Jobs converge, freeze and
+ * stop independently; the call returns when every job has.
+ * All arrays must be 8-byte aligned; no job's U may overlap another's U
+ * or any u0 (PR_ERR_INVALID_ARG).  jobs[i].status receives each job's
+ * result; the return value is PR_ERR_NUMERIC if any job hit NaN/Inf,
+ * else PR_NOT_CONVERGED if any job stopped above tol, else PR_OK. */
+pr_status pr_solve_many(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* The serial fine solve U_{j+1} = F(U_j), j = 0..n_slices-1, for n_ics ICs
  * batched per slice (the reference Parareal converges to).

@@ -23,6 +23,7 @@ EXPORTED = [
     "pr_cnn_backward_workspace_bytes", "pr_cnn_backward",
     "pr_correct",
     "pr_solve_workspace_bytes", "pr_solve",
+    "pr_solve_many_workspace_bytes", "pr_solve_many",
     "pr_serial_workspace_bytes", "pr_serial_fine",
     "pr_set_fine_plan", "pr_get_fine_plan", "pr_autotune_fine", "pr_set_graphs", "pr_get_graphs",
     "pr_status_string", "pr_last_error", "pr_abi_version",
@@ -33,7 +34,8 @@ PR_PLAN_AUTO, PR_PLAN_STREAM, PR_PLAN_RESIDENT = 0, 1, 2
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("length", C.c_double),
                 ("eps", C.c_double), ("conservative", C.c_int32), ("stab", C.c_double),
-                ("dt", C.c_double), ("steps", C.c_int32), ("fine_prec", C.c_int32)]
+                ("dt", C.c_double), ("steps", C.c_int32), ("fine_prec", C.c_int32),
+                ("f32_iters", C.c_int32)]
 
 
 class Coarse(C.Structure):
@@ -50,6 +52,13 @@ class Stats(C.Structure):
                 ("fine_ms", C.c_double), ("sweep_ms", C.c_double)]
 
 
+class Job(C.Structure):
+    _fields_ = [("problem", Problem), ("coarse", Coarse), ("n_ics", C.c_int64),
+                ("n_slices", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
+                ("u0", C.c_void_p), ("U", C.c_void_p), ("stats", C.POINTER(Stats)),
+                ("status", C.c_int32)]
+
+
 _lib = None
 
 
@@ -62,6 +71,7 @@ def lib() -> C.CDLL:
                 "(hipcc --offload-arch=gfx950) first")
         L = C.CDLL(LIB)
         P, G, S = C.POINTER(Problem), C.POINTER(Coarse), C.POINTER(Stats)
+        Jp = C.POINTER(Job)
         vp, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
         sig = {
             "pr_fine_workspace_bytes": (sz, [P, i64]),
@@ -73,6 +83,8 @@ def lib() -> C.CDLL:
             "pr_correct": (C.c_int, [i64, i32, vp, C.c_int, vp, vp, vp, vp, i32, vp]),
             "pr_solve_workspace_bytes": (sz, [P, G, i64, i32]),
             "pr_solve": (C.c_int, [P, G, i64, i32, vp, vp, C.c_double, i32, S, vp, sz, vp]),
+            "pr_solve_many_workspace_bytes": (sz, [i32, Jp]),
+            "pr_solve_many": (C.c_int, [i32, Jp, vp, sz, vp]),
             "pr_serial_workspace_bytes": (sz, [P, i64]),
             "pr_serial_fine": (C.c_int, [P, i64, i32, vp, vp, vp, sz, vp]),
             "pr_set_fine_plan": (C.c_int, [i32, C.c_int, i32]),

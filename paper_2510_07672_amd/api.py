@@ -31,10 +31,11 @@ class Problem:
     dt: float
     steps: int
     fine_prec: str = "f64"
+    f32_iters: int = 0      # Parareal precision schedule (see pr_solve)
 
     def c(self) -> L.Problem:
         return L.Problem(2, self.n, self.length, self.eps, int(self.conservative), self.stab,
-                         self.dt, self.steps, _PREC[self.fine_prec])
+                         self.dt, self.steps, _PREC[self.fine_prec], int(self.f32_iters))
 
 
 @dataclass(frozen=True)
@@ -202,7 +203,7 @@ def pr_solve(p: Problem, g: Coarse, u0: torch.Tensor, n_slices: int, tol: float,
     """Algorithm 2 on every IC of u0 [B, N, N]; returns (U [B, s+1, N, N], stats)."""
     B = _fields(u0, p.n, "u0")
     pc, gc = p.c(), g.c()
-    max_iter = n_slices if max_iter is None else int(max_iter)
+    max_iter = n_slices + p.f32_iters if max_iter is None else int(max_iter)
     if U is None:
         U = torch.empty((B, n_slices + 1, p.n, p.n), dtype=torch.float64, device=u0.device)
     need = L.lib().pr_solve_workspace_bytes(C.byref(pc), C.byref(gc), B, n_slices)
@@ -221,6 +222,58 @@ def pr_solve(p: Problem, g: Coarse, u0: torch.Tensor, n_slices: int, tol: float,
     stats = SolveStats(k, st.n_converged, ic_it.copy(), hist[:k * B].reshape(k, B).copy(),
                        st.fine_ms, st.sweep_ms, status)
     return U, stats
+
+
+@dataclass
+class Job:
+    """One solve of a pr_solve_many batch."""
+    problem: Problem
+    coarse: object            # Coarse or CnnCoarse
+    u0: torch.Tensor          # [B, N, N] float64
+    n_slices: int
+    tol: float
+    max_iter: Optional[int] = None
+    U: Optional[torch.Tensor] = None
+
+
+def _job_c(j: Job):
+    B = _fields(j.u0, j.problem.n, "u0")
+    mi = j.n_slices + j.problem.f32_iters if j.max_iter is None else int(j.max_iter)
+    if j.U is None:
+        j.U = torch.empty((B, j.n_slices + 1, j.problem.n, j.problem.n), dtype=torch.float64,
+                          device=j.u0.device)
+    ic_it = np.zeros(B, dtype=np.int32)
+    hist = np.zeros(max(mi, 1) * B, dtype=np.float64)
+    st = L.Stats(0, 0, ic_it.ctypes.data_as(C.POINTER(C.c_int32)),
+                 hist.ctypes.data_as(C.POINTER(C.c_double)), 0.0, 0.0)
+    jc = L.Job(problem=j.problem.c(), coarse=j.coarse.c(), n_ics=B, n_slices=j.n_slices,
+               max_iter=mi, tol=float(j.tol), u0=j.u0.data_ptr(), U=j.U.data_ptr(),
+               stats=C.pointer(st), status=0)
+    return jc, st, ic_it, hist, B
+
+
+def pr_solve_many(jobs, ws: Optional[torch.Tensor] = None, allow_not_converged: bool = False):
+    """Algorithm 2 for a heterogeneous batch of jobs; returns [(U, stats)] in job order."""
+    if not jobs:
+        return []
+    keep = [_job_c(j) for j in jobs]
+    arr = (L.Job * len(jobs))(*[k[0] for k in keep])
+    need = L.lib().pr_solve_many_workspace_bytes(len(jobs), arr)
+    if need == 0:
+        raise ValueError("pr_solve_many_workspace_bytes rejected the batch")
+    dev = jobs[0].u0.device
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    allow = (L.PR_OK, L.PR_NOT_CONVERGED) if allow_not_converged else (L.PR_OK,)
+    L.check(L.lib().pr_solve_many(len(jobs), arr, _ptr(ws), ws.numel(), _stream(dev)),
+            "pr_solve_many", allow)
+    out = []
+    for j, (jc, st, ic_it, hist, B), a in zip(jobs, keep, arr):
+        k = st.iterations
+        out.append((j.U, SolveStats(k, st.n_converged, ic_it.copy(),
+                                    hist[:k * B].reshape(k, B).copy(), st.fine_ms, st.sweep_ms,
+                                    a.status)))
+    return out
 
 
 def pr_serial_fine(p: Problem, u0: torch.Tensor, n_slices: int,

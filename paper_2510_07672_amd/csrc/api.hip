@@ -58,6 +58,9 @@ pr_status check_problem(const pr_problem* p) {
     return fail(PR_ERR_INVALID_ARG, "conservative must be 0 or 1");
   if (p->fine_prec != PR_F64 && p->fine_prec != PR_F32)
     return fail(PR_ERR_UNSUPPORTED, "fine_prec must be PR_F64 or PR_F32");
+  if (p->f32_iters < 0) return fail(PR_ERR_INVALID_ARG, "f32_iters must be >= 0");
+  if (p->f32_iters > 0 && p->fine_prec != PR_F64)
+    return fail(PR_ERR_INVALID_ARG, "f32_iters > 0 needs fine_prec = PR_F64");
   return PR_OK;
 }
 
@@ -233,41 +236,6 @@ hipError_t coarse_run(const pr_problem* p, const pr_coarse* g, const CoarseWs& w
                       const double* in_base, const int64_t* in_offs, double* out_base,
                       const int64_t* out_offs, hipStream_t s);
 
-struct SolveWs {
-  FineWs fine;
-  CoarseWs coarse;
-  double* gcache;          // [B][s][N][N]
-  void* fbuf;              // [B][s][N][N] fine precision
-  double* gtmp;            // [B][N][N]
-  unsigned long long* upd; // [B]
-  int64_t* off_u;          // [B] IC offsets into U (elements)
-  int64_t* off_s;          // [B] IC offsets into gcache / fbuf
-  int64_t* win_in;         // [B*s] window offsets into U
-  int64_t* win_out;        // [B*s] window offsets into fbuf
-  int32_t* act;            // [B] active IC ids
-  size_t bytes;
-};
-
-SolveWs carve_solve(void* base, const pr_problem* p, const pr_coarse* g, int64_t B, int32_t s) {
-  Carver c(base);
-  SolveWs w;
-  const size_t n2 = (size_t)p->n * p->n;
-  const bool f32 = p->fine_prec == PR_F32;
-  w.fine = carve_fine(c, p->n, f32, B * s);
-  w.coarse = carve_coarse(c, p, g, B);
-  w.gcache = (double*)c.take((size_t)B * s * n2 * 8);
-  w.fbuf = c.take((size_t)B * s * n2 * (f32 ? 4 : 8));
-  w.gtmp = (double*)c.take((size_t)B * n2 * 8);
-  w.upd = (unsigned long long*)c.take((size_t)B * 8);
-  w.off_u = (int64_t*)c.take((size_t)B * 8);
-  w.off_s = (int64_t*)c.take((size_t)B * 8);
-  w.win_in = (int64_t*)c.take((size_t)B * s * 8);
-  w.win_out = (int64_t*)c.take((size_t)B * s * 8);
-  w.act = (int32_t*)c.take((size_t)B * 4);
-  w.bytes = c.used;
-  return w;
-}
-
 float event_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
@@ -306,6 +274,582 @@ hipError_t coarse_run(const pr_problem* p, const pr_coarse* g, const CoarseWs& w
   j.out_offs = out_offs;
   j.out_f32 = 0;
   return launch_steps(j, s);
+}
+
+// ------------------------------------------------------ Parareal driver
+//
+// Algorithm 2 for a batch of jobs.  Fields of every job live in caller
+// arrays (u0, U) or in the workspace (G cache, fine outputs, coarse
+// outputs); kernels address them as element offsets from two bases, the
+// lowest caller array and the workspace, through tables uploaded once per
+// iteration.
+
+struct JobRun {
+  pr_job* J = nullptr;
+  int N = 0, s = 0, K32 = 0, cap = 0;
+  int64_t B = 0, ic0 = 0, n2 = 0;
+  bool f32_only = false;
+  double* gcache = nullptr;   // [B][s][N^2]
+  void* fbuf = nullptr;       // [B][s][N^2] in the iteration's fine precision
+  int fine_grp[2] = {-1, -1}; // by FP32
+  int coarse_grp = -1;
+  int pfine = 0, pcoarse = 0; // parameter table entries
+  // state
+  std::vector<char> active;
+  std::vector<int32_t> ic_iter;
+  bool done = false;
+  int iters = 0;
+  pr_status status = PR_OK;
+  bool f32_at(int k) const { return f32_only || k <= K32; }
+  // first slice of the window of iteration k
+  int win_at(int k) const { return f32_only || k <= K32 ? k - 1 : k - K32 - 1; }
+  // an IC may freeze once the iteration's fine solves are in the job's own
+  // precision (never in the FP32 iterations of an FP64 schedule)
+  bool may_freeze(int k) const { return k > K32; }
+};
+
+struct FineGroup {
+  int N;
+  bool f32;
+  int steps;
+  int64_t cap = 0;
+  FineWs ws{};
+};
+
+struct CoarseGroup {
+  const pr_problem* p;  // representative (N only)
+  const pr_coarse* g;   // representative
+  int64_t cap = 0;      // fields per sweep step (sum of member n_ics)
+  CoarseWs ws{};
+  double* gtmp = nullptr;  // [cap][N^2]
+};
+
+bool same_coarse(const pr_coarse& a, const pr_coarse& b, int na, int nb) {
+  if (na != nb || a.kind != b.kind) return false;
+  if (a.kind == PR_G_SCHEME) return a.prec == b.prec && a.steps == b.steps;
+  return a.prec == b.prec && a.n_layers == b.n_layers && a.channels == b.channels &&
+         a.weights == b.weights && a.biases == b.biases && a.act == b.act &&
+         a.residual == b.residual && a.mass_fix == b.mass_fix && a.limiter == b.limiter &&
+         (!a.limiter || (a.lim_lo == b.lim_lo && a.lim_hi == b.lim_hi));
+}
+
+struct SolvePlan {
+  std::vector<JobRun> jobs;
+  std::vector<FineGroup> fine;
+  std::vector<CoarseGroup> coarse;
+  StepParams* params = nullptr;         // [2 n_jobs]
+  unsigned long long* upd = nullptr;    // [sum B]
+  int64_t* t64 = nullptr;               // index tables
+  int32_t* t32 = nullptr;
+  int64_t n64 = 0, n32 = 0;
+  int64_t total_ics = 0;
+  size_t bytes = 0;
+};
+
+pr_status check_job(const pr_job& J, int i) {
+  pr_status st = check_problem(&J.problem);
+  if (st != PR_OK) return st;
+  if ((st = check_coarse(&J.coarse, J.problem.n)) != PR_OK) return st;
+  if (J.n_ics < 0) return fail(PR_ERR_INVALID_ARG, "job %d: n_ics < 0", i);
+  if (J.n_slices < 1) return fail(PR_ERR_INVALID_ARG, "job %d: n_slices < 1", i);
+  if (!(J.tol >= 0)) return fail(PR_ERR_INVALID_ARG, "job %d: tol must be >= 0", i);
+  if (J.max_iter < 0) return fail(PR_ERR_INVALID_ARG, "job %d: max_iter < 0", i);
+  if (J.problem.f32_iters >= J.n_slices && J.problem.f32_iters > 0)
+    return fail(PR_ERR_INVALID_ARG, "job %d: f32_iters must be < n_slices", i);
+  if (J.n_ics > 0) {
+    if (!J.u0 || !J.U) return fail(PR_ERR_INVALID_ARG, "job %d: u0 / U is NULL", i);
+    if (((uintptr_t)J.u0 | (uintptr_t)J.U) & 7)
+      return fail(PR_ERR_INVALID_ARG, "job %d: u0 / U not 8-byte aligned", i);
+  }
+  return PR_OK;
+}
+
+// Sizes (base == nullptr) or carves the workspace of a batch.
+pr_status plan_solve(int32_t n_jobs, pr_job* jobs, void* base, SolvePlan& P) {
+  Carver c(base);
+  P.jobs.assign(n_jobs, JobRun{});
+  P.fine.clear();
+  P.coarse.clear();
+  int64_t ics = 0, fields = 0;
+  for (int i = 0; i < n_jobs; ++i) {
+    JobRun& r = P.jobs[i];
+    pr_job& J = jobs[i];
+    r.J = &J;
+    r.N = J.problem.n;
+    r.s = J.n_slices;
+    r.B = J.n_ics;
+    r.n2 = (int64_t)r.N * r.N;
+    r.K32 = J.problem.f32_iters;
+    r.f32_only = J.problem.fine_prec == PR_F32;
+    r.cap = std::min<int64_t>(J.max_iter, (int64_t)r.K32 + r.s);
+    r.ic0 = ics;
+    r.pfine = 2 * i;
+    r.pcoarse = 2 * i + 1;
+    ics += r.B;
+    fields += r.B * r.s;
+    if (r.B == 0) continue;
+    for (int f32 = 0; f32 < 2; ++f32) {
+      const bool used = f32 ? (r.f32_only || r.K32 > 0) : !r.f32_only;
+      if (!used) continue;
+      int gi = -1;
+      for (size_t q = 0; q < P.fine.size(); ++q)
+        if (P.fine[q].N == r.N && P.fine[q].f32 == (bool)f32 && P.fine[q].steps == J.problem.steps)
+          gi = (int)q;
+      if (gi < 0) {
+        P.fine.push_back(FineGroup{r.N, (bool)f32, J.problem.steps});
+        gi = (int)P.fine.size() - 1;
+      }
+      P.fine[gi].cap += r.B * r.s;
+      r.fine_grp[f32] = gi;
+    }
+    int ci = -1;
+    for (size_t q = 0; q < P.coarse.size(); ++q)
+      if (same_coarse(*P.coarse[q].g, J.coarse, P.coarse[q].p->n, r.N)) ci = (int)q;
+    if (ci < 0) {
+      P.coarse.push_back(CoarseGroup{&J.problem, &J.coarse});
+      ci = (int)P.coarse.size() - 1;
+    }
+    P.coarse[ci].cap += r.B;
+    r.coarse_grp = ci;
+  }
+  P.total_ics = ics;
+  P.params = (StepParams*)c.take((size_t)std::max(1, 2 * n_jobs) * sizeof(StepParams));
+  P.upd = (unsigned long long*)c.take((size_t)std::max<int64_t>(1, ics) * 8);
+  for (auto& r : P.jobs) {
+    if (r.B == 0) continue;
+    r.gcache = (double*)c.take((size_t)(r.B * r.s * r.n2) * 8);
+    r.fbuf = c.take((size_t)(r.B * r.s * r.n2) * (r.f32_only ? 4 : 8));
+  }
+  for (auto& g : P.fine) g.ws = carve_fine(c, g.N, g.f32, g.cap);
+  for (auto& g : P.coarse) {
+    g.ws = carve_coarse(c, g.p, g.g, g.cap);
+    g.gtmp = (double*)c.take((size_t)g.cap * g.p->n * g.p->n * 8);
+  }
+  // fine: in, out, pidx per field; sweep: coarse in/out/pidx + correct
+  // f/gn/go/u/upd per field; initial sweep and u0 copy reuse that room
+  P.n64 = 8 * fields + 2 * ics + 1;
+  P.n32 = 3 * fields + 1;
+  P.t64 = (int64_t*)c.take((size_t)P.n64 * 8);
+  P.t32 = (int32_t*)c.take((size_t)P.n32 * 4);
+  P.bytes = c.used;
+  return PR_OK;
+}
+
+// Host-side builder of one upload of index tables.
+struct Tables {
+  std::vector<int64_t> v64;
+  std::vector<int32_t> v32;
+  size_t a64(int64_t x) { v64.push_back(x); return v64.size() - 1; }
+};
+
+struct Seg {
+  int grp;          // fine / coarse group, or N for copies and corrections
+  int f32;          // corrections: F precision
+  int64_t count;
+  size_t i64[6];    // table starts (element index into t64)
+  size_t i32[2];
+};
+
+hipError_t run_coarse_group(const CoarseGroup& G, const SolvePlan& P, int64_t nfields,
+                            const double* in_base, const int64_t* in_offs, double* out_base,
+                            const int64_t* out_offs, const int32_t* pidx, hipStream_t s) {
+  if (G.g->kind == PR_G_CNN) return coarse_run(G.p, G.g, G.ws, nfields, in_base, in_offs, out_base, out_offs, s);
+  StepJob j = make_job(G.p, G.g->dt, G.g->steps, G.g->prec == PR_F32, nfields, G.ws.fine);
+  j.in_base = in_base;
+  j.in_offs = in_offs;
+  j.out_base = out_base;
+  j.out_offs = out_offs;
+  j.out_f32 = 0;
+  j.params = P.params;
+  j.pidx = pidx;
+  return launch_steps(j, s);
+}
+
+pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hipStream_t hs) {
+  for (int i = 0; i < n_jobs; ++i) {
+    jobs[i].status = PR_OK;
+    pr_status st = check_job(jobs[i], i);
+    if (st != PR_OK) return st;
+  }
+  // no job's U may overlap another's U or any u0
+  for (int i = 0; i < n_jobs; ++i) {
+    const pr_job& A = jobs[i];
+    if (A.n_ics == 0) continue;
+    const uintptr_t a0 = (uintptr_t)A.U,
+                    a1 = a0 + (uintptr_t)(A.n_ics * (A.n_slices + 1)) * A.problem.n * A.problem.n * 8;
+    for (int k = 0; k < n_jobs; ++k) {
+      const pr_job& Bj = jobs[k];
+      if (Bj.n_ics == 0) continue;
+      const uintptr_t n2b = (uintptr_t)Bj.problem.n * Bj.problem.n * 8;
+      const uintptr_t u0 = (uintptr_t)Bj.u0, u1 = u0 + (uintptr_t)Bj.n_ics * n2b;
+      if (u0 < a1 && a0 < u1) return fail(PR_ERR_INVALID_ARG, "U of job %d overlaps u0 of job %d", i, k);
+      if (k != i) {
+        const uintptr_t b0 = (uintptr_t)Bj.U, b1 = b0 + (uintptr_t)(Bj.n_ics * (Bj.n_slices + 1)) * n2b;
+        if (b0 < a1 && a0 < b1) return fail(PR_ERR_INVALID_ARG, "U of jobs %d and %d overlap", i, k);
+      }
+    }
+  }
+  SolvePlan P;
+  plan_solve(n_jobs, jobs, nullptr, P);
+  if (!ws || ws_bytes < P.bytes)
+    return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, P.bytes);
+  plan_solve(n_jobs, jobs, ws, P);
+  for (auto& r : P.jobs) {
+    pr_stats* st = r.J->stats;
+    if (st) {
+      st->iterations = 0;
+      st->n_converged = 0;
+      st->fine_ms = 0;
+      st->sweep_ms = 0;
+      if (st->ic_iterations)
+        for (int64_t b = 0; b < r.B; ++b) st->ic_iterations[b] = 0;
+      if (st->history)
+        for (int64_t i = 0; i < (int64_t)r.J->max_iter * r.B; ++i) st->history[i] = 0.0;
+    }
+    r.active.assign(r.B, 1);
+    r.ic_iter.assign(r.B, 0);
+    r.done = r.B == 0;
+  }
+  if (P.total_ics == 0) return PR_OK;
+  Events ev;
+  if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
+
+  // bases: the lowest caller array, and the workspace
+  uintptr_t ubase = UINTPTR_MAX;
+  for (auto& r : P.jobs)
+    if (r.B > 0) ubase = std::min({ubase, (uintptr_t)r.J->U, (uintptr_t)r.J->u0});
+  const uintptr_t wbase = (uintptr_t)ws;
+  double* const UB = (double*)ubase;
+  double* const WB = (double*)wbase;
+  auto offU = [&](const JobRun& r, int64_t b, int64_t q) {
+    return (int64_t)(((uintptr_t)r.J->U - ubase) / 8) + (b * (r.s + 1) + q) * r.n2;
+  };
+  auto offU0 = [&](const JobRun& r, int64_t b) {
+    return (int64_t)(((uintptr_t)r.J->u0 - ubase) / 8) + b * r.n2;
+  };
+  auto offGC = [&](const JobRun& r, int64_t b, int64_t q) {
+    return (int64_t)(((uintptr_t)r.gcache - wbase) / 8) + (b * r.s + q) * r.n2;
+  };
+  auto offF = [&](const JobRun& r, int64_t b, int64_t q, bool f32) {
+    return (int64_t)(((uintptr_t)r.fbuf - wbase) / (f32 ? 4 : 8)) + (b * r.s + q) * r.n2;
+  };
+  auto offGT = [&](const CoarseGroup& g, int64_t i) {
+    return (int64_t)(((uintptr_t)g.gtmp - wbase) / 8) + i * (int64_t)g.p->n * g.p->n;
+  };
+
+  // set-up: parameter table, twiddles, packed weights
+  {
+    std::vector<StepParams> prm(2 * n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+      prm[2 * i] = step_params(&jobs[i].problem, jobs[i].problem.dt);
+      prm[2 * i + 1] = step_params(&jobs[i].problem, jobs[i].coarse.kind == PR_G_SCHEME ? jobs[i].coarse.dt : jobs[i].problem.dt);
+    }
+    PR_HIP(hipMemcpyAsync(P.params, prm.data(), prm.size() * sizeof(StepParams), hipMemcpyHostToDevice, hs));
+    for (auto& g : P.fine) PR_HIP(launch_tables(g.N, g.ws, hs));
+    for (auto& g : P.coarse) {
+      if (g.g->kind == PR_G_CNN) {
+        pr_status st = cnn_lds_once();
+        if (st != PR_OK) return st;
+      }
+      PR_HIP(coarse_setup(g.p, g.g, g.ws, hs));
+    }
+    PR_HIP(hipStreamSynchronize(hs));
+  }
+  int smax = 0;
+  for (auto& r : P.jobs) smax = std::max(smax, r.s);
+
+  Tables T;
+  std::vector<Seg> segs;
+  auto upload = [&]() -> pr_status {
+    if ((int64_t)T.v64.size() > P.n64 || (int64_t)T.v32.size() > P.n32)
+      return fail(PR_ERR_DEVICE, "internal: index tables exceed their workspace");
+    if (!T.v64.empty())
+      PR_HIP(hipMemcpyAsync(P.t64, T.v64.data(), T.v64.size() * 8, hipMemcpyHostToDevice, hs));
+    if (!T.v32.empty())
+      PR_HIP(hipMemcpyAsync(P.t32, T.v32.data(), T.v32.size() * 4, hipMemcpyHostToDevice, hs));
+    return PR_OK;
+  };
+
+  // ---- k = 0: U_0 = u0, then U^0_{j+1} = G(U^0_j), kept as G(U^0_j)
+  {
+    T.v64.clear();
+    T.v32.clear();
+    segs.clear();
+    // per distinct N: u0 copies
+    std::vector<int> Ns;
+    for (auto& r : P.jobs)
+      if (r.B > 0 && std::find(Ns.begin(), Ns.end(), r.N) == Ns.end()) Ns.push_back(r.N);
+    std::vector<Seg> copy0;
+    for (int N : Ns) {
+      Seg sg{N, 0, 0, {}, {}};
+      sg.i64[0] = T.v64.size();
+      for (auto& r : P.jobs)
+        if (r.N == N)
+          for (int64_t b = 0; b < r.B; ++b) T.v64.push_back(offU0(r, b));
+      sg.i64[1] = T.v64.size();
+      for (auto& r : P.jobs)
+        if (r.N == N)
+          for (int64_t b = 0; b < r.B; ++b) T.v64.push_back(offU(r, b, 0));
+      sg.count = (int64_t)(sg.i64[1] - sg.i64[0]);
+      copy0.push_back(sg);
+    }
+    pr_status st = upload();
+    if (st != PR_OK) return st;
+    for (auto& sg : copy0)
+      PR_HIP(launch_copy(sg.count, sg.grp, UB, P.t64 + sg.i64[0], UB, P.t64 + sg.i64[1], hs));
+    PR_HIP(hipStreamSynchronize(hs));
+    // the sweep, one upload for all steps
+    T.v64.clear();
+    T.v32.clear();
+    std::vector<std::vector<Seg>> csteps(smax), ksteps(smax);
+    for (int j = 0; j < smax; ++j) {
+      for (size_t gi = 0; gi < P.coarse.size(); ++gi) {
+        Seg sg{(int)gi, 0, 0, {}, {}};
+        std::vector<std::pair<const JobRun*, int64_t>> mem;
+        for (auto& r : P.jobs)
+          if (r.coarse_grp == (int)gi && j < r.s)
+            for (int64_t b = 0; b < r.B; ++b) mem.push_back({&r, b});
+        if (mem.empty()) continue;
+        sg.count = (int64_t)mem.size();
+        sg.i64[0] = T.v64.size();
+        for (auto& m : mem) T.v64.push_back(offU(*m.first, m.second, j));
+        sg.i64[1] = T.v64.size();
+        for (auto& m : mem) T.v64.push_back(offGC(*m.first, m.second, j));
+        sg.i32[0] = T.v32.size();
+        for (auto& m : mem) T.v32.push_back(m.first->pcoarse);
+        csteps[j].push_back(sg);
+        Seg cp{P.coarse[gi].p->n, 0, sg.count, {}, {}};
+        cp.i64[0] = sg.i64[1];
+        cp.i64[1] = T.v64.size();
+        for (auto& m : mem) T.v64.push_back(offU(*m.first, m.second, j + 1));
+        ksteps[j].push_back(cp);
+      }
+    }
+    st = upload();
+    if (st != PR_OK) return st;
+    for (int j = 0; j < smax; ++j) {
+      for (auto& sg : csteps[j])
+        PR_HIP(run_coarse_group(P.coarse[sg.grp], P, sg.count, UB, P.t64 + sg.i64[0], WB,
+                                P.t64 + sg.i64[1], P.t32 + sg.i32[0], hs));
+      for (auto& cp : ksteps[j])
+        PR_HIP(launch_copy(cp.count, cp.grp, WB, P.t64 + cp.i64[0], UB, P.t64 + cp.i64[1], hs));
+    }
+    PR_HIP(hipStreamSynchronize(hs));
+  }
+
+  std::vector<unsigned long long> upd_h(P.total_ics);
+  pr_status result = PR_OK;
+  for (int k = 1;; ++k) {
+    bool any = false;
+    for (auto& r : P.jobs) {
+      if (r.done) continue;
+      int64_t act = 0;
+      for (char a : r.active) act += a;
+      if (act == 0 || k > r.cap) r.done = true;
+      else any = true;
+    }
+    if (!any) break;
+    T.v64.clear();
+    T.v32.clear();
+    // fine solves: per group, every running job's active ICs x window
+    std::vector<Seg> fsegs;
+    for (size_t gi = 0; gi < P.fine.size(); ++gi) {
+      const FineGroup& G = P.fine[gi];
+      std::vector<const JobRun*> mem;
+      for (auto& r : P.jobs)
+        if (!r.done && r.fine_grp[r.f32_at(k) ? 1 : 0] == (int)gi) mem.push_back(&r);
+      if (mem.empty()) continue;
+      Seg sg{(int)gi, G.f32 ? 1 : 0, 0, {}, {}};
+      sg.i64[0] = T.v64.size();
+      for (auto* r : mem)
+        for (int64_t b = 0; b < r->B; ++b)
+          if (r->active[b])
+            for (int q = r->win_at(k); q < r->s; ++q) T.v64.push_back(offU(*r, b, q));
+      sg.i64[1] = T.v64.size();
+      sg.count = (int64_t)(sg.i64[1] - sg.i64[0]);
+      for (auto* r : mem)
+        for (int64_t b = 0; b < r->B; ++b)
+          if (r->active[b])
+            for (int q = r->win_at(k); q < r->s; ++q) T.v64.push_back(offF(*r, b, q, G.f32));
+      sg.i32[0] = T.v32.size();
+      for (auto* r : mem)
+        for (int64_t b = 0; b < r->B; ++b)
+          if (r->active[b])
+            for (int q = r->win_at(k); q < r->s; ++q) T.v32.push_back(r->pfine);
+      if (sg.count > 0) fsegs.push_back(sg);
+    }
+    // sweep: step j applies G (per coarse group) and corrects (per N, F precision)
+    std::vector<std::vector<Seg>> csteps(smax), ksteps(smax);
+    for (int j = 0; j < smax; ++j) {
+      struct Ent { const JobRun* r; int64_t b; int64_t gt; };
+      std::vector<Ent> ents;
+      for (size_t gi = 0; gi < P.coarse.size(); ++gi) {
+        std::vector<std::pair<const JobRun*, int64_t>> mem;
+        for (auto& r : P.jobs)
+          if (!r.done && r.coarse_grp == (int)gi && j >= r.win_at(k) && j < r.s)
+            for (int64_t b = 0; b < r.B; ++b)
+              if (r.active[b]) mem.push_back({&r, b});
+        if (mem.empty()) continue;
+        Seg sg{(int)gi, 0, (int64_t)mem.size(), {}, {}};
+        sg.i64[0] = T.v64.size();
+        for (auto& m : mem) T.v64.push_back(offU(*m.first, m.second, j));
+        sg.i64[1] = T.v64.size();
+        for (size_t i = 0; i < mem.size(); ++i) {
+          T.v64.push_back(offGT(P.coarse[gi], (int64_t)i));
+          ents.push_back({mem[i].first, mem[i].second, offGT(P.coarse[gi], (int64_t)i)});
+        }
+        sg.i32[0] = T.v32.size();
+        for (auto& m : mem) T.v32.push_back(m.first->pcoarse);
+        csteps[j].push_back(sg);
+      }
+      // corrections grouped by (N, F precision)
+      std::vector<std::pair<int, int>> keys;
+      for (auto& e : ents) {
+        std::pair<int, int> key{e.r->N, e.r->f32_at(k) ? 1 : 0};
+        if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
+      }
+      for (auto& key : keys) {
+        Seg sg{key.first, key.second, 0, {}, {}};
+        std::vector<const Ent*> sel;
+        for (auto& e : ents)
+          if (e.r->N == key.first && (e.r->f32_at(k) ? 1 : 0) == key.second) sel.push_back(&e);
+        sg.count = (int64_t)sel.size();
+        sg.i64[0] = T.v64.size();
+        for (auto* e : sel) T.v64.push_back(offF(*e->r, e->b, j, key.second != 0));
+        sg.i64[1] = T.v64.size();
+        for (auto* e : sel) T.v64.push_back(e->gt);
+        sg.i64[2] = T.v64.size();
+        for (auto* e : sel) T.v64.push_back(offGC(*e->r, e->b, j));
+        sg.i64[3] = T.v64.size();
+        for (auto* e : sel) T.v64.push_back(offU(*e->r, e->b, j + 1));
+        sg.i32[0] = T.v32.size();
+        for (auto* e : sel) T.v32.push_back((int32_t)(e->r->ic0 + e->b));
+        ksteps[j].push_back(sg);
+      }
+    }
+    pr_status st = upload();
+    if (st != PR_OK) return st;
+    PR_HIP(launch_fill_u64(P.upd, P.total_ics, 0ull, hs));
+    PR_HIP(hipEventRecord(ev.e[0], hs));
+    for (auto& sg : fsegs) {
+      const FineGroup& G = P.fine[sg.grp];
+      StepJob fj{};
+      fj.n = G.N;
+      fj.f32 = G.f32;
+      fj.steps = G.steps;
+      fj.nfields = sg.count;
+      fj.ws = G.ws;
+      fj.resident = effective_plan(G.N, G.f32) == PR_PLAN_RESIDENT;
+      fj.in_base = UB;
+      fj.in_offs = P.t64 + sg.i64[0];
+      fj.out_base = WB;
+      fj.out_offs = P.t64 + sg.i64[1];
+      fj.out_f32 = G.f32;
+      fj.params = P.params;
+      fj.pidx = P.t32 + sg.i32[0];
+      PR_HIP(launch_steps(fj, hs));
+    }
+    PR_HIP(hipEventRecord(ev.e[1], hs));
+    for (int j = 0; j < smax; ++j) {
+      for (auto& sg : csteps[j])
+        PR_HIP(run_coarse_group(P.coarse[sg.grp], P, sg.count, UB, P.t64 + sg.i64[0], WB,
+                                P.t64 + sg.i64[1], P.t32 + sg.i32[0], hs));
+      for (auto& sg : ksteps[j]) {
+        CorrectJob cj{};
+        cj.nfields = sg.count;
+        cj.n = sg.grp;
+        cj.f = WB;
+        cj.f_offs = P.t64 + sg.i64[0];
+        cj.f_f32 = sg.f32;
+        cj.g_new = WB;
+        cj.gn_offs = P.t64 + sg.i64[1];
+        cj.g_old = WB;
+        cj.go_offs = P.t64 + sg.i64[2];
+        cj.u = UB;
+        cj.u_offs = P.t64 + sg.i64[3];
+        cj.upd = P.upd;
+        cj.upd_idx = P.t32 + sg.i32[0];
+        cj.update_cache = 1;
+        PR_HIP(launch_correct(cj, hs));
+      }
+    }
+    PR_HIP(hipEventRecord(ev.e[2], hs));
+    PR_HIP(hipMemcpyAsync(upd_h.data(), P.upd, P.total_ics * 8, hipMemcpyDeviceToHost, hs));
+    PR_HIP(hipStreamSynchronize(hs));
+    const double fms = event_ms(ev.e[0], ev.e[1]), sms = event_ms(ev.e[1], ev.e[2]);
+    for (int ji = 0; ji < n_jobs; ++ji) {
+      JobRun& r = P.jobs[ji];
+      if (r.done) continue;
+      pr_stats* stt = r.J->stats;
+      if (stt) {
+        stt->fine_ms += fms;
+        stt->sweep_ms += sms;
+      }
+      r.iters = k;
+      for (int64_t b = 0; b < r.B; ++b) {
+        if (!r.active[b]) continue;
+        double d;
+        std::memcpy(&d, &upd_h[r.ic0 + b], 8);
+        r.ic_iter[b] = k;
+        if (stt && stt->history && k <= r.J->max_iter) stt->history[(int64_t)(k - 1) * r.B + b] = d;
+        if (!std::isfinite(d)) {
+          r.status = PR_ERR_NUMERIC;
+          result = fail(PR_ERR_NUMERIC, "job %d: non-finite update norm for IC %lld at iteration %d",
+                        ji, (long long)b, k);
+        } else if (d <= r.J->tol && r.may_freeze(k)) {
+          r.active[b] = 0;
+        }
+      }
+      if (r.status == PR_ERR_NUMERIC) r.done = true;
+    }
+  }
+  bool not_conv = false;
+  for (int ji = 0; ji < n_jobs; ++ji) {
+    JobRun& r = P.jobs[ji];
+    // exact once the FP64 phase (or the FP32-only run) has covered every slice
+    const int exact_at = r.f32_only ? r.s : r.K32 + r.s;
+    int n_conv = 0;
+    for (int64_t b = 0; b < r.B; ++b)
+      if (!r.active[b] || r.ic_iter[b] >= exact_at) ++n_conv;
+    if (pr_stats* stt = r.J->stats) {
+      stt->iterations = r.iters;
+      stt->n_converged = n_conv;
+      if (stt->ic_iterations)
+        for (int64_t b = 0; b < r.B; ++b) stt->ic_iterations[b] = r.ic_iter[b];
+    }
+    if (r.status == PR_OK && n_conv < r.B) {
+      r.status = PR_NOT_CONVERGED;
+      not_conv = true;
+    }
+    r.J->status = r.status;
+  }
+  if (result != PR_OK) return result;
+  if (not_conv) {
+    for (int ji = 0; ji < n_jobs; ++ji)
+      if (jobs[ji].status == PR_NOT_CONVERGED) {
+        const JobRun& r = P.jobs[ji];
+        int64_t left = 0;
+        for (char a : r.active) left += a;
+        return fail(PR_NOT_CONVERGED, "job %d: %lld of %lld ICs above tol after %d iterations", ji,
+                    (long long)left, (long long)r.B, r.iters);
+      }
+  }
+  return PR_OK;
+}
+
+pr_job single_job(const pr_problem* p, const pr_coarse* g, int64_t n_ics, int32_t n_slices,
+                  const double* u0, double* U, double tol, int32_t max_iter, pr_stats* stats) {
+  pr_job J{};
+  J.problem = *p;
+  J.coarse = *g;
+  J.n_ics = n_ics;
+  J.n_slices = n_slices;
+  J.max_iter = max_iter;
+  J.tol = tol;
+  J.u0 = u0;
+  J.U = U;
+  J.stats = stats;
+  return J;
 }
 
 }  // namespace
@@ -459,8 +1003,9 @@ pr_status pr_correct(int64_t nfields, int32_t n, const void* f, pr_dtype f_dtype
 
 size_t pr_solve_workspace_bytes(const pr_problem* p, const pr_coarse* g, int64_t n_ics,
                                 int32_t n_slices) {
-  if (check_problem(p) != PR_OK || check_coarse(g, p->n) != PR_OK || n_ics < 0 || n_slices < 1) return 0;
-  return carve_solve(nullptr, p, g, n_ics, n_slices).bytes;
+  if (!p || !g) return 0;
+  pr_job J = single_job(p, g, n_ics, n_slices, nullptr, nullptr, 0.0, 0, nullptr);
+  return pr_solve_many_workspace_bytes(1, &J);
 }
 
 pr_status pr_solve(const pr_problem* p, const pr_coarse* g, int64_t n_ics, int32_t n_slices,
@@ -469,158 +1014,28 @@ pr_status pr_solve(const pr_problem* p, const pr_coarse* g, int64_t n_ics, int32
   pr_status st = check_problem(p);
   if (st != PR_OK) return st;
   if ((st = check_coarse(g, p->n)) != PR_OK) return st;
-  if (n_ics < 0) return fail(PR_ERR_INVALID_ARG, "n_ics < 0");
-  if (n_slices < 1) return fail(PR_ERR_INVALID_ARG, "n_slices < 1");
-  if (!(tol >= 0)) return fail(PR_ERR_INVALID_ARG, "tol must be >= 0");
-  if (max_iter < 0) return fail(PR_ERR_INVALID_ARG, "max_iter < 0");
-  if (n_ics == 0) return PR_OK;
-  if (!u0 || !U) return fail(PR_ERR_INVALID_ARG, "u0 / U is NULL");
-  const int64_t B = n_ics;
-  const int32_t s = n_slices;
-  SolveWs w = carve_solve(ws, p, g, B, s);
-  if (!ws || ws_bytes < w.bytes)
-    return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, w.bytes);
-  const int K = max_iter < s ? max_iter : s;
-  hipStream_t hs = (hipStream_t)stream;
-  const int64_t n2 = (int64_t)p->n * p->n;
-  const int N = p->n;
-  const bool f32 = p->fine_prec == PR_F32;
-  const size_t fesz = f32 ? 4 : 8;
-  Events ev;
-  if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
+  pr_job J = single_job(p, g, n_ics, n_slices, u0, U, tol, max_iter, stats);
+  return solve_jobs(1, &J, ws, ws_bytes, (hipStream_t)stream);
+}
 
-  if (stats) {
-    stats->iterations = 0;
-    stats->n_converged = 0;
-    stats->fine_ms = 0;
-    stats->sweep_ms = 0;
-    if (stats->ic_iterations)
-      for (int64_t b = 0; b < B; ++b) stats->ic_iterations[b] = 0;
-    if (stats->history)
-      for (int64_t i = 0; i < (int64_t)max_iter * B; ++i) stats->history[i] = 0.0;
-  }
+size_t pr_solve_many_workspace_bytes(int32_t n_jobs, const pr_job* jobs) {
+  if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return 0;
+  // sizing needs a valid problem, coarse propagator and counts per job
+  std::vector<pr_job> copy(jobs, jobs + n_jobs);
+  for (const pr_job& J : copy)
+    if (check_problem(&J.problem) != PR_OK || check_coarse(&J.coarse, J.problem.n) != PR_OK ||
+        J.n_slices < 1 || J.n_ics < 0 || J.max_iter < 0)
+      return 0;
+  SolvePlan P;
+  plan_solve(n_jobs, copy.data(), nullptr, P);
+  return P.bytes;
+}
 
-  // host copies of the index tables, uploaded once per iteration
-  std::vector<int64_t> off_u(B), off_s(B), win_in, win_out;
-  std::vector<int32_t> act(B);
-  for (int64_t b = 0; b < B; ++b) {
-    act[b] = (int32_t)b;
-    off_u[b] = b * (int64_t)(s + 1) * n2;
-    off_s[b] = b * (int64_t)s * n2;
-  }
-  PR_HIP(hipMemcpyAsync(w.off_u, off_u.data(), B * 8, hipMemcpyHostToDevice, hs));
-  PR_HIP(hipMemcpyAsync(w.off_s, off_s.data(), B * 8, hipMemcpyHostToDevice, hs));
-  PR_HIP(hipMemcpyAsync(w.act, act.data(), B * 4, hipMemcpyHostToDevice, hs));
-  PR_HIP(launch_tables(N, w.fine, hs));
-  if (g->kind == PR_G_CNN && (st = cnn_lds_once()) != PR_OK) return st;
-  PR_HIP(coarse_setup(p, g, w.coarse, hs));
-  // U_0 = u0
-  PR_HIP(launch_copy(B, N, u0, nullptr, U, w.off_u, hs));
-
-  // initial coarse sweep: U^0_{j+1} = G(U^0_j), kept as the cache G(U^0_j)
-  for (int32_t j = 0; j < s; ++j) {
-    PR_HIP(coarse_run(p, g, w.coarse, B, U + j * n2, w.off_u, w.gcache + j * n2, w.off_s, hs));
-    PR_HIP(launch_copy(B, N, w.gcache + j * n2, w.off_s, U + (j + 1) * n2, w.off_u, hs));
-  }
-  PR_HIP(hipStreamSynchronize(hs));
-
-  std::vector<unsigned long long> upd_h(B);
-  std::vector<char> active(B, 1);
-  std::vector<int32_t> ic_iter(B, 0);
-  int64_t n_act = B;
-  int iters = 0;
-  pr_status result = PR_OK;
-  StepJob fj = make_job(p, p->dt, p->steps, f32, 0, w.fine);
-  for (int k = 1; k <= K && n_act > 0; ++k) {
-    const int32_t W = s - k + 1;
-    int64_t i = 0;
-    for (int64_t b = 0; b < B; ++b)
-      if (active[b]) {
-        act[i] = (int32_t)b;
-        off_u[i] = b * (int64_t)(s + 1) * n2;
-        off_s[i] = b * (int64_t)s * n2;
-        ++i;
-      }
-    win_in.resize(n_act * W);
-    win_out.resize(n_act * W);
-    for (int64_t a = 0; a < n_act; ++a)
-      for (int32_t q = 0; q < W; ++q) {
-        win_in[a * W + q] = off_u[a] + (int64_t)(k - 1 + q) * n2;
-        win_out[a * W + q] = off_s[a] + (int64_t)(k - 1 + q) * n2;
-      }
-    PR_HIP(hipMemcpyAsync(w.act, act.data(), n_act * 4, hipMemcpyHostToDevice, hs));
-    PR_HIP(hipMemcpyAsync(w.off_u, off_u.data(), n_act * 8, hipMemcpyHostToDevice, hs));
-    PR_HIP(hipMemcpyAsync(w.off_s, off_s.data(), n_act * 8, hipMemcpyHostToDevice, hs));
-    PR_HIP(hipMemcpyAsync(w.win_in, win_in.data(), n_act * W * 8, hipMemcpyHostToDevice, hs));
-    PR_HIP(hipMemcpyAsync(w.win_out, win_out.data(), n_act * W * 8, hipMemcpyHostToDevice, hs));
-    PR_HIP(launch_fill_u64(w.upd, B, 0ull, hs));
-    PR_HIP(hipEventRecord(ev.e[0], hs));
-    // fine solves of slices k-1..s-1 of every active IC, one batch
-    fj.nfields = n_act * W;
-    fj.in_base = U;
-    fj.in_offs = w.win_in;
-    fj.out_base = w.fbuf;
-    fj.out_offs = w.win_out;
-    fj.out_f32 = f32;
-    PR_HIP(launch_steps(fj, hs));
-    PR_HIP(hipEventRecord(ev.e[1], hs));
-    // sequential correction sweep
-    for (int32_t j = k - 1; j < s; ++j) {
-      PR_HIP(coarse_run(p, g, w.coarse, n_act, U + j * n2, w.off_u, w.gtmp, nullptr, hs));
-      CorrectJob cj{};
-      cj.nfields = n_act;
-      cj.n = N;
-      cj.f = (const char*)w.fbuf + (size_t)j * n2 * fesz;
-      cj.f_offs = w.off_s;
-      cj.f_f32 = f32;
-      cj.g_new = w.gtmp;
-      cj.gn_offs = nullptr;
-      cj.g_old = w.gcache + j * n2;
-      cj.go_offs = w.off_s;
-      cj.u = U + (j + 1) * n2;
-      cj.u_offs = w.off_u;
-      cj.upd = w.upd;
-      cj.upd_idx = w.act;
-      cj.update_cache = 1;
-      PR_HIP(launch_correct(cj, hs));
-    }
-    PR_HIP(hipEventRecord(ev.e[2], hs));
-    PR_HIP(hipMemcpyAsync(upd_h.data(), w.upd, B * 8, hipMemcpyDeviceToHost, hs));
-    PR_HIP(hipStreamSynchronize(hs));
-    if (stats) {
-      stats->fine_ms += event_ms(ev.e[0], ev.e[1]);
-      stats->sweep_ms += event_ms(ev.e[1], ev.e[2]);
-    }
-    iters = k;
-    for (int64_t a = 0; a < n_act; ++a) {
-      const int32_t b = act[a];
-      double d;
-      std::memcpy(&d, &upd_h[b], 8);
-      ic_iter[b] = k;
-      if (stats && stats->history && k <= max_iter) stats->history[(int64_t)(k - 1) * B + b] = d;
-      if (!std::isfinite(d)) {
-        result = fail(PR_ERR_NUMERIC, "non-finite update norm for IC %d at iteration %d", b, k);
-      } else if (d <= tol) {
-        active[b] = 0;
-      }
-    }
-    if (result != PR_OK) break;
-    n_act = 0;
-    for (int64_t b = 0; b < B; ++b) n_act += active[b];
-  }
-  int n_conv = 0;
-  for (int64_t b = 0; b < B; ++b)
-    if (!active[b] || ic_iter[b] >= s) ++n_conv;
-  if (stats) {
-    stats->iterations = iters;
-    stats->n_converged = n_conv;
-    if (stats->ic_iterations)
-      for (int64_t b = 0; b < B; ++b) stats->ic_iterations[b] = ic_iter[b];
-  }
-  if (result != PR_OK) return result;
-  if (n_conv < B) return fail(PR_NOT_CONVERGED, "%lld of %lld ICs above tol after %d iterations",
-                              (long long)(B - n_conv), (long long)B, iters);
-  return PR_OK;
+pr_status pr_solve_many(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, void* stream) {
+  if (n_jobs < 0) return fail(PR_ERR_INVALID_ARG, "n_jobs < 0");
+  if (n_jobs == 0) return PR_OK;
+  if (!jobs) return fail(PR_ERR_INVALID_ARG, "jobs is NULL");
+  return solve_jobs(n_jobs, jobs, ws, ws_bytes, (hipStream_t)stream);
 }
 
 pr_status pr_set_fine_plan(int32_t n, pr_dtype prec, int32_t plan) {

@@ -140,11 +140,19 @@ __device__ __forceinline__ void row_split_store(const cpx<T>* panel, cpx<T>* S, 
   }
 }
 
+// The step parameters of field f: the launch argument, or the field's entry
+// of the descriptor's parameter table.
+__device__ __forceinline__ StepParams field_params(const CallDesc* desc, int64_t f,
+                                                   const StepParams& arg) {
+  if (!desc->params) return arg;
+  return desc->params[desc->pidx ? desc->pidx[f] : 0];
+}
+
 // First row pass of a call: the real FP64 state in, half spectra out.
 template <int N, typename T>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row_first(
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
-    const cpx<T>* __restrict__ tw_g, StepParams sp) {
+    const cpx<T>* __restrict__ tw_g, StepParams sp_arg) {
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
@@ -157,6 +165,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / TILES;
   if (f >= desc->nfields) return;
+  const StepParams sp = field_params(desc, f, sp_arg);
   const int tile = blockIdx.x % TILES;
   const int r0 = tile * TR;
   const Lay lay{};
@@ -177,7 +186,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
 template <int N, typename T, int MODE>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
-    const cpx<T>* __restrict__ tw_g, StepParams sp) {
+    const cpx<T>* __restrict__ tw_g, StepParams sp_arg) {
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
@@ -190,6 +199,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / TILES;
   if (f >= desc->nfields) return;
+  const StepParams sp = field_params(desc, f, sp_arg);
   const int tile = blockIdx.x % TILES;
   const int r0 = tile * TR;
   const Lay lay{};
@@ -266,7 +276,7 @@ template <int N, typename T>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col(
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec,
     const double* __restrict__ partials, const cpx<T>* __restrict__ tw_g,
-    const double* __restrict__ s2_g, StepParams sp) {
+    const double* __restrict__ s2_g, StepParams sp_arg) {
   using C = cpx<T>;
   constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
   constexpr int TILES = RowCfg<N, T>::TILES;
@@ -281,6 +291,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / BLK;
   if (f >= desc->nfields) return;
+  const StepParams sp = field_params(desc, f, sp_arg);
   const int c0 = (blockIdx.x % BLK) * CT;
   const Lay lay{};
   C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
@@ -408,7 +419,7 @@ __device__ __forceinline__ void res_permute(cpx<T>* S, int tid) {
 template <int N, typename T>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k_resident(
     const CallDesc* __restrict__ desc, const cpx<T>* __restrict__ tw_g,
-    const double* __restrict__ s2_g, StepParams sp, int steps) {
+    const double* __restrict__ s2_g, StepParams sp_arg, int steps) {
   using C = cpx<T>;
   using Cfg = ResCfg<N>;
   constexpr int NT = Cfg::NT, E0 = (N + NT - 1) / NT;
@@ -421,6 +432,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x;
   if (f >= desc->nfields) return;
+  const StepParams sp = field_params(desc, f, sp_arg);
   load_stage_twiddles<N, NT>(tw, tw_g, tid);
   for (int t = tid; t < N; t += NT) s2[t] = s2_g[t];
   const T a = (T)sp.a, dt = (T)sp.dt;
@@ -546,8 +558,11 @@ bool graphs_enabled() { return g_graphs_on.load(); }
 
 template <int N, typename T>
 static hipError_t launch_stream_graph(const StepJob& job, hipStream_t st) {
-  GraphKey key{job.n, job.f32 ? 1 : 0, job.steps, job.sp.conservative, job.sp.a, job.sp.dt,
-               job.sp.lam, job.sp.inv_n2, job.ws.desc, job.ws.spec, job.ws.partials,
+  // with per-field parameters the launch argument is unused, and every
+  // such sequence with the same shape and workspace is the same graph
+  const StepParams sp = job.params ? StepParams{0, 0, 0, 0, -1} : job.sp;
+  GraphKey key{job.n, job.f32 ? 1 : 0, job.steps, sp.conservative, sp.a, sp.dt,
+               sp.lam, sp.inv_n2, job.ws.desc, job.ws.spec, job.ws.partials,
                job.f32 ? (const void*)job.ws.tw32 : (const void*)job.ws.tw64, job.ws.s2};
   std::lock_guard<std::mutex> lock(g_graph_mu);
   GraphEntry* hit = nullptr;
@@ -624,7 +639,8 @@ static hipError_t launch_resident_t(const StepJob& job, hipStream_t st) {
 
 template <typename T>
 static hipError_t launch_steps_t(const StepJob& job, hipStream_t st) {
-  CallDesc v{job.nfields, job.in_base, job.in_offs, job.out_base, job.out_offs, job.out_f32};
+  CallDesc v{job.nfields, job.in_base, job.in_offs, job.out_base, job.out_offs, job.out_f32,
+             job.params, job.pidx};
   k_set_desc<<<dim3(1), dim3(1), 0, st>>>(job.ws.desc, v);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -69,6 +69,9 @@ struct CallDesc {
   void* out_base;           // field i at out_base + (out_offs ? out_offs[i] : i N^2)
   const int64_t* out_offs;
   int32_t out_f32;
+  const StepParams* params;  // per-field step parameters params[pidx[i]] (null:
+  const int32_t* pidx;       // the launch argument); lets one launch carry fields
+                             // of problems with different eps, dt, S or model
 };
 
 // Per-call device workspace of the step kernels.
@@ -92,6 +95,8 @@ struct StepJob {
   void* out_base;            // field i at out_base + (out_offs ? out_offs[i] : i N^2)
   const int64_t* out_offs;   // device or null
   int out_f32;
+  const StepParams* params;  // device or null: per-field parameters (see CallDesc)
+  const int32_t* pidx;       // device or null
   bool resident;             // one block per field, all steps in LDS (N <= 128)
   FineWs ws;
 };

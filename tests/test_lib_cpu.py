@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 3
+    assert lib.pr_abi_version() == 4
 
 
 def test_library_exports_match_nm(L):
@@ -101,8 +101,11 @@ def test_solve_validation(L):
     assert lib.pr_solve(C.byref(p), C.byref(g), 2, 0, *args[2:]) == L.PR_ERR_INVALID_ARG
     assert lib.pr_solve(C.byref(p), C.byref(g), 2, 8, C.c_void_p(16), C.c_void_p(32), -1.0, 8,
                         None, C.c_void_p(64), 1 << 40, None) == L.PR_ERR_INVALID_ARG
-    assert lib.pr_solve(C.byref(p), C.byref(g), 2, 8, C.c_void_p(16), C.c_void_p(32), 1e-10, 8,
+    assert lib.pr_solve(C.byref(p), C.byref(g), 2, 8, C.c_void_p(16), C.c_void_p(1 << 30), 1e-10, 8,
                         None, C.c_void_p(64), 10, None) == L.PR_ERR_WORKSPACE
+    # U overlapping u0
+    assert lib.pr_solve(C.byref(p), C.byref(g), 2, 8, C.c_void_p(16), C.c_void_p(32), 1e-10, 8,
+                        None, C.c_void_p(64), 1 << 40, None) == L.PR_ERR_INVALID_ARG
     need = lib.pr_solve_workspace_bytes(C.byref(p), C.byref(g), 2, 8)
     # U, G cache and F buffers dominate: 3 * B * s * N^2 * 8 bytes at least
     assert need >= 3 * 2 * 8 * 64 * 64 * 8
@@ -133,3 +136,34 @@ def test_cnn_coarse_validation(L, kw, status):
     g_ok = L.Coarse(**dict(d, **{k: v for k, v in dict(channels=32, n_layers=4, prec=L.PR_BF16, act=0, limiter=0, weights=64).items()}))
     assert lib.pr_coarse_apply(C.byref(p16), C.byref(g_ok), 1, C.c_void_p(16), C.c_void_p(32),
                                C.c_void_p(64), 1 << 40, None) == L.PR_ERR_UNSUPPORTED
+
+
+def _job(L, u0, U, n=64, slices=8, **pkw):
+    p = _prob(L, n=n, **pkw)
+    g = L.Coarse(kind=L.PR_G_SCHEME, dt=1e-2, steps=1, prec=L.PR_F64)
+    return L.Job(problem=p, coarse=g, n_ics=2, n_slices=slices, max_iter=slices, tol=1e-10,
+                 u0=u0, U=U, stats=None, status=-1)
+
+
+def test_solve_many_validation(L):
+    lib = L.lib()
+    G = 1 << 30
+    jobs = (L.Job * 2)(_job(L, 16 * G, 17 * G), _job(L, 18 * G, 19 * G, n=128))
+    need = lib.pr_solve_many_workspace_bytes(2, jobs)
+    one = lib.pr_solve_many_workspace_bytes(1, jobs)
+    assert need > one > 0
+    assert lib.pr_solve_many(2, jobs, C.c_void_p(20 * G), need - 1, None) == L.PR_ERR_WORKSPACE
+    assert lib.pr_solve_many(0, None, None, 0, None) == L.PR_OK
+    assert lib.pr_solve_many(-1, jobs, None, 0, None) == L.PR_ERR_INVALID_ARG
+    # overlapping U of two jobs
+    bad = (L.Job * 2)(_job(L, 16 * G, 17 * G), _job(L, 18 * G, 17 * G + 4096))
+    assert lib.pr_solve_many(2, bad, C.c_void_p(20 * G), need, None) == L.PR_ERR_INVALID_ARG
+    assert b"overlap" in lib.pr_last_error()
+    # misaligned, schedule needs FP64 and fewer iterations than slices
+    for j in (_job(L, 16 * G + 4, 17 * G), _job(L, 16 * G, 17 * G, fine_prec=L.PR_F32, f32_iters=1),
+              _job(L, 16 * G, 17 * G, f32_iters=8), _job(L, 16 * G, 17 * G, f32_iters=-1)):
+        arr = (L.Job * 1)(j)
+        assert lib.pr_solve_many(1, arr, C.c_void_p(20 * G), 1 << 40, None) == L.PR_ERR_INVALID_ARG
+    # a schedule needs no more workspace than FP64 fine solves
+    arr = (L.Job * 1)(_job(L, 16 * G, 17 * G, f32_iters=3))
+    assert lib.pr_solve_many_workspace_bytes(1, arr) > 0
