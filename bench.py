@@ -34,11 +34,11 @@ CONFIGS = {
                n=64, eps=0.02, dt=1e-4, steps=100, slices=8, ics=1, conservative=False,
                seed0=0, g_steps=1, cnn=(4, 32)),
     "c2": dict(workload="classic AC 256x256 eps=0.01, 8 ICs x 64 slices x 200 steps dt=2e-5 "
-                        "(512 fine solves per launch), numerical G (1 step of 4e-3)",
+                        "(512 fine solves per launch), G = u + CNN(u) 4 conv x 32 ch",
                n=256, eps=0.01, dt=2e-5, steps=200, slices=64, ics=8, conservative=False,
                seed0=0, g_steps=1, cnn=(4, 32)),
     "c3": dict(workload="mass-conservative AC 512x512 eps=0.01, 16 ICs x 128 slices x 100 steps "
-                        "dt=1e-5 (2048 fine solves per launch), numerical G (1 step of 1e-3)",
+                        "dt=1e-5 (2048 fine solves per launch), G = u + CNN(u) 6 conv x 48 ch",
                n=512, eps=0.01, dt=1e-5, steps=100, slices=128, ics=16, conservative=True,
                seed0=0, g_steps=1, cnn=(6, 48)),
 }
@@ -109,10 +109,12 @@ def cpu_baseline(cfg, prec, budget_s=12.0):
 def parareal_vs_serial(api, p, g, u0, s, kmax, target=1e-6):
     """Wall-clock of Parareal stopped after k iterations against the FP64
     serial fine solve on the same GPU, for the smallest k whose trajectory
-    is within rel-L2 `target` of that serial solve."""
+    is within rel-L2 `target` of that serial solve.  With p.f32_iters = K
+    the first K iterations run FP32 fine solves (precision schedule), and
+    k counts them too."""
     import dataclasses
     import torch
-    p64 = dataclasses.replace(p, fine_prec="f64")
+    p64 = dataclasses.replace(p, fine_prec="f64", f32_iters=0)
 
     def timed(fn, reps=3):
         best = None
@@ -132,7 +134,7 @@ def parareal_vs_serial(api, p, g, u0, s, kmax, target=1e-6):
     rel_same = torch.linalg.vector_norm(ser_same - ref).item() / nref
     hist = []
     found = None
-    for k in range(1, min(kmax, s) + 1):
+    for k in range(1, min(kmax, s) + p.f32_iters + 1):
         (U, st), t = timed(lambda: api.pr_solve(p, g, u0, s, tol=0.0, max_iter=k,
                                                 allow_not_converged=True), reps=1)
         err = torch.linalg.vector_norm(U - ref).item() / nref
@@ -152,7 +154,100 @@ def parareal_vs_serial(api, p, g, u0, s, kmax, target=1e-6):
     else:
         res.update({"k": None, "speedup_vs_serial_fp64": None,
                     "note": f"rel-L2 {target} not reached within {min(kmax, s)} iterations"})
+    if p.f32_iters:
+        res["f32_iters"] = p.f32_iters
     return res
+
+
+def schedule_compare(api, p, g, u0, s, kmax, schedules=(1, 2)):
+    """Parareal with FP64 fine solves from the start against the FP32-then-
+    FP64 schedule, each at its smallest k reaching rel-L2 1e-6."""
+    import dataclasses
+    out = {}
+    for K in schedules:
+        r = parareal_vs_serial(api, dataclasses.replace(p, f32_iters=K), g, u0, s, kmax)
+        out[f"f32_iters_{K}"] = r
+    return out
+
+
+# Config 5: 48 concurrent solves, the recipe fixed here (seeded, synthetic)
+def c5_jobs(api, torch, synth, f32_iters, fine_prec="f64", g_prec="f64"):
+    """Job i: N = (128, 256, 1024)[i % 3], slices = (16, 32, 64, 128, 256)[i % 5],
+    eps = 0.01 + 0.02 i / 47, classic for even i and mass-conservative for
+    odd i, S = 2, dt = 2e-5, 20 fine steps per slice, one IC (seed 5000 + i);
+    G = one semi-implicit step of the slice length."""
+    jobs = []
+    for i in range(48):
+        n = (128, 256, 1024)[i % 3]
+        s = (16, 32, 64, 128, 256)[i % 5]
+        eps = 0.01 + 0.02 * i / 47
+        p = api.Problem(n=n, length=1.0, eps=eps, conservative=bool(i % 2), stab=2.0, dt=2e-5,
+                        steps=20, fine_prec=fine_prec, f32_iters=f32_iters)
+        u0 = torch.from_numpy(synth.random_ic(n, [5000 + i])).to("cuda")
+        jobs.append(api.Job(p, api.Coarse(dt=20 * 2e-5, steps=1, prec=g_prec), u0, s, 5e-7))
+    return jobs
+
+
+def uneven_bench(args):
+    """Config 5: the 48-solve uneven batch through pr_solve_many, FP64 plain
+    form against the mixed form (FP32-then-FP64 fine schedule), each run
+    until every job's sup-norm update is <= 5e-7, then checked against each
+    job's FP64 serial fine solve (rel-L2 <= 1e-6 per job)."""
+    import dataclasses
+    import torch
+    from paper_2510_07672_amd import api, synth
+    ref_jobs = c5_jobs(api, torch, synth, 0)
+    refs, t_ser = [], 0.0
+    for j in ref_jobs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        refs.append(api.pr_serial_fine(j.problem, j.u0, j.n_slices))
+        torch.cuda.synchronize()
+        t_ser += time.perf_counter() - t0
+    pts = sum(j.n_slices * j.problem.steps * j.problem.n ** 2 for j in ref_jobs)
+
+    def run(f32_iters, g_prec, reps):
+        best, res = None, None
+        for _ in range(reps):
+            jobs = c5_jobs(api, torch, synth, f32_iters, g_prec=g_prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = api.pr_solve_many(jobs)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best:
+                best, res = dt, out
+        errs = [float(torch.linalg.vector_norm(U - r) / torch.linalg.vector_norm(r))
+                for (U, _), r in zip(res, refs)]
+        iters = [int(st.iterations) for _, st in res]
+        # the longest-running job took part in every iteration: its times
+        # are the batch's fine and sweep times
+        longest = max(res, key=lambda r: r[1].iterations)[1]
+        fine_pts = sum(sum(max(0, j.n_slices - (k - 1)) for k in range(1, it + 1))
+                       * j.problem.steps * j.problem.n ** 2
+                       for j, it in zip(ref_jobs, iters))
+        return {"ms": round(best * 1e3, 1), "max_rel_l2": float(f"{max(errs):.3e}"),
+                "jobs_within_1e-6": sum(e <= 1e-6 for e in errs),
+                "iterations_max": max(iters), "iterations_mean": round(float(np.mean(iters)), 2),
+                "fine_gpts_per_s": round(fine_pts / best / 1e9, 1),
+                "fine_ms": round(longest.fine_ms, 1), "sweep_ms": round(longest.sweep_ms, 1)}
+    plain = run(0, "f64", args.steps)
+    # G stays FP64: an FP32 coarse step puts ~1e-7 of rounding noise into
+    # G(U^k) - G(U^{k-1}), which keeps the sup-norm update from settling
+    mixed = {f"f32_iters_{K}": run(K, "f64", args.steps) for K in (1, 2)}
+    best_k = min(mixed, key=lambda k: mixed[k]["ms"] if mixed[k]["jobs_within_1e-6"] == 48 else 1e12)
+    best = mixed[best_k]
+    return {"metric": "uneven batched Parareal: speedup of the mixed-precision form over the "
+                      "FP64 plain form at rel-L2<=1e-6 (48 solves, one GPU)",
+            "value": round(plain["ms"] / best["ms"], 3), "unit": "x", "n_gpus": 1,
+            "steps": args.steps, "warmup": 0, "ms_per_step": best["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32 then f64", "data": "synthetic",
+            "config": {"workload": "48 solves: N in {128, 256, 1024}, slices in {16..256}, "
+                                   "eps 0.01..0.03, classic and conservative, dt 2e-5, 20 fine "
+                                   "steps per slice, numerical G; all in one pr_solve_many"},
+            "fine_point_steps_serial": pts, "serial_fp64_ms": round(t_ser * 1e3, 1),
+            "plain_fp64": plain, "mixed": mixed, "best_mixed": best_k,
+            "speedup_vs_serial_fp64": round(t_ser * 1e3 / best["ms"], 3)}
 
 
 def calib_copy(nbytes=1 << 30, reps=3):
@@ -167,7 +262,7 @@ def calib_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"calib_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def trained_cnn(api, p, cfg, prec, steps, n_traj=256, n_slices=16):
+def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16):
     """The workload's network, trained with Adam on fine-solver trajectories
     from seeds 1000.. (bf16 forward, FP32 gradients, 8-step rollouts
     checkpointed every 2), then evaluated in `prec`."""
@@ -251,7 +346,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + ["c4"])
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + ["c4", "c5"])
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
@@ -279,6 +374,9 @@ def main():
 
     if args.config == "c4":
         print(json.dumps(training_bench(args)), flush=True)
+        return
+    if args.config == "c5":
+        print(json.dumps(uneven_bench(args)), flush=True)
         return
     cfg = CONFIGS[args.config]
     n, s, B, c = cfg["n"], cfg["slices"], cfg["ics"], cfg["steps"]
@@ -352,6 +450,8 @@ def main():
         out["config"]["coarse"] = "numerical: one semi-implicit step per slice"
     if not args.no_parareal:
         out["parareal"] = parareal_vs_serial(api, p, g, u0, s, args.kmax)
+        if args.prec == "f64":
+            out["parareal_schedule"] = schedule_compare(api, p, g, u0, s, args.kmax)
         if coarse == "cnn":
             out["parareal_numerical_coarse"] = parareal_vs_serial(api, p, g_num, u0, s, args.kmax)
     if not args.no_cpu:
