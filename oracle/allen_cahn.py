@@ -25,6 +25,21 @@ discrete nonlocal term g of Section 3.1).  Lap_h is the periodic 5-point
 stencil, whose discrete Fourier symbol is -mu_k with
 mu_k = (4/h^2)(sin^2(pi kx/N) + sin^2(pi ky/N)); the linear system is
 therefore solved exactly by one forward and one inverse 2-D real DFT.
+
+The paper's own fine scheme (Section 3.1, eq. fully-discrete) is also
+here: Crank-Nicolson in time, solved by Picard iteration from
+U_{n+1,(0)} = U_n,
+
+    (I - dt/2 eps^2 Lap_h) U_{(m+1)} = U_n + dt/2 (eps^2 Lap_h U_n + f(U_n)
+                                       + f(U_{(m)})) - dt g(U_n, U_{(m)}),
+
+g = 0 (classic) or the grid mean of (f(U_n) + f(U_{(m)}))/2
+(conservative), taken with the full factor dt as in the paper's first
+displayed form of the scheme, which is the placement that keeps the mass
+(the later displays put g inside the dt/2 bracket).  A fixed number of
+Picard iterations stands in for the paper's unstated stopping rule.
+Either scheme may use the Fourier collocation Laplacian that Section 3.1
+also allows instead of the 5-point stencil.
 """
 
 from __future__ import annotations
@@ -64,6 +79,9 @@ class Problem:
     stab: float
     dt: float
     steps: int
+    scheme: str = "ssi"      # "ssi" (stabilised semi-implicit) or "cn" (CN + Picard)
+    picard: int = 3          # Picard iterations per CN step
+    laplacian: str = "fd"    # "fd" (5-point stencil) or "spectral" (Fourier collocation)
 
     @property
     def h(self) -> float:
@@ -103,13 +121,34 @@ def laplacian_stencil(u: np.ndarray, h: float) -> np.ndarray:
             - 4.0 * u) / (h * h)
 
 
-def symbol_mu(n: int, h: float) -> np.ndarray:
+def laplacian_spectral(u: np.ndarray, length: float) -> np.ndarray:
+    """Fourier collocation Laplacian (Section 3.1's alternative): multiply
+    the DFT coefficient of wavenumber (kx, ky) by -(2 pi / L)^2 (kx^2 + ky^2),
+    with k taken in -N/2..N/2-1 (numpy's fftfreq order)."""
+    n = u.shape[-1]
+    k = np.fft.fftfreq(n, d=1.0 / n)
+    k2 = k[:, None] ** 2 + k[None, :] ** 2
+    return np.real(np.fft.ifft2(-(2 * np.pi / length) ** 2 * k2 * np.fft.fft2(u)))
+
+
+def apply_laplacian(u: np.ndarray, p: "Problem") -> np.ndarray:
+    """Lap_h u with the problem's choice of discrete Laplacian."""
+    return laplacian_stencil(u, p.h) if p.laplacian == "fd" else laplacian_spectral(u, p.length)
+
+
+def symbol_mu(n: int, h: float, laplacian: str = "fd") -> np.ndarray:
     """mu_k >= 0 with Lap_h e_k = -mu_k e_k, on the rfft2 half grid.
 
     Shape [n, n//2 + 1]; row index ky = 0..n-1, column kx = 0..n/2.
+    5-point stencil: (4/h^2)(sin^2(pi kx/N) + sin^2(pi ky/N)); Fourier
+    collocation: (2 pi / L)^2 (kx^2 + ky^2) with wrapped wavenumbers.
     """
     ky = np.arange(n, dtype=np.float64)[:, None]
     kx = np.arange(n // 2 + 1, dtype=np.float64)[None, :]
+    if laplacian == "spectral":
+        ky = np.minimum(ky, n - ky)
+        L = n * h
+        return (2 * np.pi / L) ** 2 * (kx * kx + ky * ky)
     sy = np.sin(np.pi * ky / n)
     sx = np.sin(np.pi * kx / n)
     return (4.0 / (h * h)) * (sx * sx + sy * sy)
@@ -127,7 +166,7 @@ def _nonlocal_mean(fu: np.ndarray, conservative: bool) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def ssi_step(u: np.ndarray, n: int, h: float, eps: float, stab: float,
-             dt: float, conservative: bool) -> np.ndarray:
+             dt: float, conservative: bool, laplacian: str = "fd") -> np.ndarray:
     """One stabilised semi-implicit step; u has shape [..., n, n].
 
     Right-hand side (1 + S dt) u + dt (f(u) - m), then the exact solve of
@@ -136,24 +175,72 @@ def ssi_step(u: np.ndarray, n: int, h: float, eps: float, stab: float,
     a = 1.0 + stab * dt
     fu = f_double_well(u)
     rhs = a * u + dt * (fu - _nonlocal_mean(fu, conservative))
-    denom = a + dt * eps * eps * symbol_mu(n, h)
+    denom = a + dt * eps * eps * symbol_mu(n, h, laplacian)
     spec = sfft.rfft2(rhs, axes=(-2, -1), workers=_WORKERS)
     return sfft.irfft2(spec / denom, s=(n, n), axes=(-2, -1), workers=_WORKERS)
+
+
+def solve_cn_operator(rhs: np.ndarray, p: "Problem", dt: float) -> np.ndarray:
+    """v with (I - dt/2 eps^2 Lap_h) v = rhs (exact, by division in Fourier space)."""
+    denom = 1.0 + 0.5 * dt * p.eps * p.eps * symbol_mu(p.n, p.h, p.laplacian)
+    spec = sfft.rfft2(rhs, axes=(-2, -1), workers=_WORKERS)
+    return sfft.irfft2(spec / denom, s=(p.n, p.n), axes=(-2, -1), workers=_WORKERS)
+
+
+def cn_nonlocal(fn: np.ndarray, fv: np.ndarray, conservative: bool) -> np.ndarray:
+    """g(U_n, V): 0, or the grid mean of (f(U_n) + f(V)) / 2 (Section 3.1)."""
+    if not conservative:
+        return np.zeros(fn.shape[:-2] + (1, 1))
+    return 0.5 * (fn.mean(axis=(-2, -1), keepdims=True) + fv.mean(axis=(-2, -1), keepdims=True))
+
+
+def cn_picard_step(u: np.ndarray, p: "Problem", dt: float, iters: Optional[int] = None,
+                   trace: Optional[list] = None) -> np.ndarray:
+    """One Crank-Nicolson step (eq. fully-discrete) by `iters` Picard
+    iterations from V_(0) = U_n; each solves the linear system of the
+    Picard form of Section 3.1.  `trace`, if given, receives every iterate."""
+    iters = p.picard if iters is None else iters
+    u = np.asarray(u, dtype=np.float64)
+    fn = f_double_well(u)
+    explicit = u + 0.5 * dt * (p.eps * p.eps * apply_laplacian(u, p) + fn)
+    v = u.copy()
+    for _ in range(iters):
+        fv = f_double_well(v)
+        rhs = explicit + 0.5 * dt * fv - dt * cn_nonlocal(fn, fv, p.conservative)
+        v = solve_cn_operator(rhs, p, dt)
+        if trace is not None:
+            trace.append(v)
+    return v
+
+
+def cn_residual(u: np.ndarray, v: np.ndarray, p: "Problem", dt: float) -> np.ndarray:
+    """Residual of eq. fully-discrete (mass-keeping placement of g) for the
+    pair (U_n, U_{n+1}) = (u, v), computed pointwise with no solve."""
+    fu, fv = f_double_well(u), f_double_well(v)
+    return (v - u - 0.5 * dt * (p.eps * p.eps * (apply_laplacian(v, p) + apply_laplacian(u, p))
+                                + fu + fv) + dt * cn_nonlocal(fu, fv, p.conservative))
+
+
+def step(u: np.ndarray, p: "Problem", dt: float) -> np.ndarray:
+    """One step of the problem's fine scheme with step size dt."""
+    if p.scheme == "cn":
+        return cn_picard_step(u, p, dt)
+    return ssi_step(u, p.n, p.h, p.eps, p.stab, dt, p.conservative, p.laplacian)
 
 
 def fine(u: np.ndarray, p: Problem) -> np.ndarray:
     """Fine propagator F(t_n, t_{n+1}, U_n): p.steps steps of p.dt."""
     v = np.array(u, dtype=np.float64, copy=True)
     for _ in range(p.steps):
-        v = ssi_step(v, p.n, p.h, p.eps, p.stab, p.dt, p.conservative)
+        v = step(v, p, p.dt)
     return v
 
 
 def coarse_num(u: np.ndarray, p: Problem, g: Coarse) -> np.ndarray:
-    """Numerical coarse propagator: g.steps semi-implicit steps of g.dt."""
+    """Numerical coarse propagator: g.steps steps of g.dt of the fine scheme."""
     v = np.array(u, dtype=np.float64, copy=True)
     for _ in range(g.steps):
-        v = ssi_step(v, p.n, p.h, p.eps, p.stab, g.dt, p.conservative)
+        v = step(v, p, g.dt)
     return v
 
 
