@@ -290,7 +290,7 @@ def test_pins_catch_wrong_sign_in_nonlinearity(monkeypatch):
 def test_pins_catch_transposed_symbol(monkeypatch):
     real = ac.symbol_mu
 
-    def wrong(n, h):   # drop the y contribution
+    def wrong(n, h, laplacian="fd"):   # drop the y contribution
         m = real(n, h)
         kx = np.arange(n // 2 + 1)
         return np.broadcast_to((4 / h ** 2) * np.sin(np.pi * kx / n) ** 2, m.shape).copy()
