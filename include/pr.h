@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 4
+#define PR_ABI_VERSION 5
 
 typedef enum {
   PR_OK = 0,
@@ -59,6 +59,24 @@ typedef enum {
 } pr_status;
 
 typedef enum { PR_F64 = 0, PR_F32 = 1, PR_BF16 = 2, PR_BF16X2 = 3 } pr_dtype;
+
+/* Fine schemes (Section 3.1).
+ *   PR_SCHEME_SSI  the stabilised semi-implicit step above (S = stab).
+ *   PR_SCHEME_CN   the paper's Crank-Nicolson scheme (eq. fully-discrete)
+ *                  solved by picard_iters Picard iterations from
+ *                  U_{n+1,(0)} = U_n, each an exact solve of
+ *                    (I - dt/2 eps^2 Lap_h) V_(m+1) = U_n + dt/2 (eps^2
+ *                    Lap_h U_n + f(U_n) + f(V_(m))) - dt g,
+ *                  g = 0 (classic) or the grid mean of (f(U_n) +
+ *                  f(V_(m)))/2 (conservative; with the factor dt, the
+ *                  placement that keeps the mass).  stab is unused.
+ *                  Runs on the streaming plan at every N.
+ * Discrete Laplacians (Section 3.1 allows either):
+ *   PR_LAP_FD5       the periodic 5-point stencil;
+ *   PR_LAP_SPECTRAL  Fourier collocation, symbol -(2 pi / L)^2 |k|^2 with
+ *                    wavenumbers wrapped to |k_i| <= N/2. */
+typedef enum { PR_SCHEME_SSI = 0, PR_SCHEME_CN = 1 } pr_scheme;
+typedef enum { PR_LAP_FD5 = 0, PR_LAP_SPECTRAL = 1 } pr_laplacian;
 
 /* The fine problem: Section 2 (model), Section 3.1 (grid and scheme). */
 typedef struct {
@@ -80,6 +98,9 @@ typedef struct {
                            every slice (see pr_solve).  0 <= f32_iters <
                            n_slices; must be 0 with PR_F32.  Other calls
                            ignore it.                                      */
+  int32_t scheme;       /* pr_scheme                                        */
+  int32_t picard_iters; /* PR_SCHEME_CN: Picard iterations per step, 1..64  */
+  int32_t laplacian;    /* pr_laplacian                                     */
 } pr_problem;
 
 typedef enum { PR_G_SCHEME = 0, PR_G_CNN = 1 } pr_coarse_kind;

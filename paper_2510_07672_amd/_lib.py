@@ -16,6 +16,8 @@ PR_OK, PR_ERR_INVALID_ARG, PR_ERR_UNSUPPORTED, PR_ERR_WORKSPACE, PR_ERR_DEVICE, 
 PR_F64, PR_F32, PR_BF16, PR_BF16X2 = 0, 1, 2, 3
 PR_G_SCHEME, PR_G_CNN = 0, 1
 PR_ACT_GELU, PR_ACT_TANH = 0, 1
+PR_SCHEME_SSI, PR_SCHEME_CN = 0, 1
+PR_LAP_FD5, PR_LAP_SPECTRAL = 0, 1
 
 EXPORTED = [
     "pr_fine_workspace_bytes", "pr_fine_propagate",
@@ -35,7 +37,8 @@ class Problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("length", C.c_double),
                 ("eps", C.c_double), ("conservative", C.c_int32), ("stab", C.c_double),
                 ("dt", C.c_double), ("steps", C.c_int32), ("fine_prec", C.c_int32),
-                ("f32_iters", C.c_int32)]
+                ("f32_iters", C.c_int32), ("scheme", C.c_int32), ("picard_iters", C.c_int32),
+                ("laplacian", C.c_int32)]
 
 
 class Coarse(C.Structure):

@@ -32,10 +32,15 @@ class Problem:
     steps: int
     fine_prec: str = "f64"
     f32_iters: int = 0      # Parareal precision schedule (see pr_solve)
+    scheme: str = "ssi"     # "ssi" or "cn" (Crank-Nicolson + Picard)
+    picard: int = 3         # Picard iterations per CN step
+    laplacian: str = "fd"   # "fd" (5-point) or "spectral" (Fourier collocation)
 
     def c(self) -> L.Problem:
         return L.Problem(2, self.n, self.length, self.eps, int(self.conservative), self.stab,
-                         self.dt, self.steps, _PREC[self.fine_prec], int(self.f32_iters))
+                         self.dt, self.steps, _PREC[self.fine_prec], int(self.f32_iters),
+                         {"ssi": L.PR_SCHEME_SSI, "cn": L.PR_SCHEME_CN}[self.scheme],
+                         int(self.picard), {"fd": L.PR_LAP_FD5, "spectral": L.PR_LAP_SPECTRAL}[self.laplacian])
 
 
 @dataclass(frozen=True)

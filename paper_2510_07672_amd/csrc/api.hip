@@ -58,6 +58,12 @@ pr_status check_problem(const pr_problem* p) {
     return fail(PR_ERR_INVALID_ARG, "conservative must be 0 or 1");
   if (p->fine_prec != PR_F64 && p->fine_prec != PR_F32)
     return fail(PR_ERR_UNSUPPORTED, "fine_prec must be PR_F64 or PR_F32");
+  if (p->scheme != PR_SCHEME_SSI && p->scheme != PR_SCHEME_CN)
+    return fail(PR_ERR_INVALID_ARG, "scheme must be PR_SCHEME_SSI or PR_SCHEME_CN");
+  if (p->scheme == PR_SCHEME_CN && (p->picard_iters < 1 || p->picard_iters > 64))
+    return fail(PR_ERR_INVALID_ARG, "picard_iters must be in [1, 64] for PR_SCHEME_CN");
+  if (p->laplacian != PR_LAP_FD5 && p->laplacian != PR_LAP_SPECTRAL)
+    return fail(PR_ERR_INVALID_ARG, "laplacian must be PR_LAP_FD5 or PR_LAP_SPECTRAL");
   if (p->f32_iters < 0) return fail(PR_ERR_INVALID_ARG, "f32_iters must be >= 0");
   if (p->f32_iters > 0 && p->fine_prec != PR_F64)
     return fail(PR_ERR_INVALID_ARG, "f32_iters > 0 needs fine_prec = PR_F64");
@@ -104,16 +110,19 @@ struct Carver {
   }
 };
 
-FineWs carve_fine(Carver& c, int n, bool f32, int64_t nfields) {
-  FineWs w;
+FineWs carve_fine(Carver& c, int n, bool f32, int64_t nfields, bool cn = false) {
+  FineWs w{};
   w.desc = (CallDesc*)c.take(sizeof(CallDesc));
   w.tw64 = (double2*)c.take((size_t)n * sizeof(double2));
   w.tw32 = (float2*)c.take((size_t)n * sizeof(float2));
   w.s2 = (double*)c.take((size_t)n * sizeof(double));
   w.partials = (double*)c.take((size_t)nfields * row_tiles(n, f32) * sizeof(double));
   w.spec = c.take((size_t)nfields * n * (n / 2) * (f32 ? 8 : 16));
+  if (cn) w.xspec = c.take((size_t)nfields * n * (n / 2) * (f32 ? 8 : 16));
   return w;
 }
+
+bool is_cn(const pr_problem* p) { return p->scheme == PR_SCHEME_CN; }
 
 StepParams step_params(const pr_problem* p, double dt) {
   StepParams sp;
@@ -151,7 +160,9 @@ int effective_plan(int n, bool f32) {
 StepJob make_job(const pr_problem* p, double dt, int steps, bool f32, int64_t nfields,
                  const FineWs& ws) {
   StepJob j{};
-  j.resident = effective_plan(p->n, f32) == PR_PLAN_RESIDENT;
+  j.scheme = p->scheme;
+  j.picard = p->picard_iters;
+  j.resident = p->scheme == PR_SCHEME_SSI && effective_plan(p->n, f32) == PR_PLAN_RESIDENT;
   j.n = p->n;
   j.f32 = f32;
   j.steps = steps;
@@ -195,7 +206,7 @@ struct CoarseWs {
 CoarseWs carve_coarse(Carver& c, const pr_problem* p, const pr_coarse* g, int64_t nfields) {
   CoarseWs w{};
   if (g->kind == PR_G_CNN) w.cnn = carve_cnn(c, p->n, g, nfields);
-  else w.fine = carve_fine(c, p->n, g->prec == PR_F32, nfields);
+  else w.fine = carve_fine(c, p->n, g->prec == PR_F32, nfields, is_cn(p));
   return w;
 }
 
@@ -228,7 +239,7 @@ CnnJob make_cnn_job(const pr_problem* p, const pr_coarse* g, const CnnWs& w) {
 // Per-call set-up of a coarse propagator (tables or packed weights).
 hipError_t coarse_setup(const pr_problem* p, const pr_coarse* g, const CoarseWs& w, hipStream_t s) {
   if (g->kind == PR_G_CNN) return launch_cnn_pack(make_cnn_job(p, g, w.cnn), s);
-  return launch_tables(p->n, w.fine, s);
+  return launch_tables(p->n, p->laplacian, w.fine, s);
 }
 
 // G on `nfields` fields addressed through optional offset tables.
@@ -312,6 +323,7 @@ struct FineGroup {
   int N;
   bool f32;
   int steps;
+  int scheme, picard, lap;
   int64_t cap = 0;
   FineWs ws{};
 };
@@ -324,9 +336,12 @@ struct CoarseGroup {
   double* gtmp = nullptr;  // [cap][N^2]
 };
 
-bool same_coarse(const pr_coarse& a, const pr_coarse& b, int na, int nb) {
-  if (na != nb || a.kind != b.kind) return false;
-  if (a.kind == PR_G_SCHEME) return a.prec == b.prec && a.steps == b.steps;
+bool same_coarse(const pr_coarse& a, const pr_coarse& b, const pr_problem& pa,
+                 const pr_problem& pb) {
+  if (pa.n != pb.n || a.kind != b.kind) return false;
+  if (a.kind == PR_G_SCHEME)
+    return a.prec == b.prec && a.steps == b.steps && pa.scheme == pb.scheme &&
+           pa.laplacian == pb.laplacian && (pa.scheme != PR_SCHEME_CN || pa.picard_iters == pb.picard_iters);
   return a.prec == b.prec && a.n_layers == b.n_layers && a.channels == b.channels &&
          a.weights == b.weights && a.biases == b.biases && a.act == b.act &&
          a.residual == b.residual && a.mass_fix == b.mass_fix && a.limiter == b.limiter &&
@@ -392,11 +407,15 @@ pr_status plan_solve(int32_t n_jobs, pr_job* jobs, void* base, SolvePlan& P) {
       const bool used = f32 ? (r.f32_only || r.K32 > 0) : !r.f32_only;
       if (!used) continue;
       int gi = -1;
+      const int pic = is_cn(&J.problem) ? J.problem.picard_iters : 0;
       for (size_t q = 0; q < P.fine.size(); ++q)
-        if (P.fine[q].N == r.N && P.fine[q].f32 == (bool)f32 && P.fine[q].steps == J.problem.steps)
+        if (P.fine[q].N == r.N && P.fine[q].f32 == (bool)f32 && P.fine[q].steps == J.problem.steps &&
+            P.fine[q].scheme == J.problem.scheme && P.fine[q].picard == pic &&
+            P.fine[q].lap == J.problem.laplacian)
           gi = (int)q;
       if (gi < 0) {
-        P.fine.push_back(FineGroup{r.N, (bool)f32, J.problem.steps});
+        P.fine.push_back(FineGroup{r.N, (bool)f32, J.problem.steps, J.problem.scheme, pic,
+                                   J.problem.laplacian});
         gi = (int)P.fine.size() - 1;
       }
       P.fine[gi].cap += r.B * r.s;
@@ -404,7 +423,7 @@ pr_status plan_solve(int32_t n_jobs, pr_job* jobs, void* base, SolvePlan& P) {
     }
     int ci = -1;
     for (size_t q = 0; q < P.coarse.size(); ++q)
-      if (same_coarse(*P.coarse[q].g, J.coarse, P.coarse[q].p->n, r.N)) ci = (int)q;
+      if (same_coarse(*P.coarse[q].g, J.coarse, *P.coarse[q].p, J.problem)) ci = (int)q;
     if (ci < 0) {
       P.coarse.push_back(CoarseGroup{&J.problem, &J.coarse});
       ci = (int)P.coarse.size() - 1;
@@ -420,7 +439,7 @@ pr_status plan_solve(int32_t n_jobs, pr_job* jobs, void* base, SolvePlan& P) {
     r.gcache = (double*)c.take((size_t)(r.B * r.s * r.n2) * 8);
     r.fbuf = c.take((size_t)(r.B * r.s * r.n2) * (r.f32_only ? 4 : 8));
   }
-  for (auto& g : P.fine) g.ws = carve_fine(c, g.N, g.f32, g.cap);
+  for (auto& g : P.fine) g.ws = carve_fine(c, g.N, g.f32, g.cap, g.scheme == PR_SCHEME_CN);
   for (auto& g : P.coarse) {
     g.ws = carve_coarse(c, g.p, g.g, g.cap);
     g.gtmp = (double*)c.take((size_t)g.cap * g.p->n * g.p->n * 8);
@@ -545,7 +564,7 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
       prm[2 * i + 1] = step_params(&jobs[i].problem, jobs[i].coarse.kind == PR_G_SCHEME ? jobs[i].coarse.dt : jobs[i].problem.dt);
     }
     PR_HIP(hipMemcpyAsync(P.params, prm.data(), prm.size() * sizeof(StepParams), hipMemcpyHostToDevice, hs));
-    for (auto& g : P.fine) PR_HIP(launch_tables(g.N, g.ws, hs));
+    for (auto& g : P.fine) PR_HIP(launch_tables(g.N, g.lap, g.ws, hs));
     for (auto& g : P.coarse) {
       if (g.g->kind == PR_G_CNN) {
         pr_status st = cnn_lds_once();
@@ -737,9 +756,11 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
       fj.n = G.N;
       fj.f32 = G.f32;
       fj.steps = G.steps;
+      fj.scheme = G.scheme;
+      fj.picard = G.picard;
       fj.nfields = sg.count;
       fj.ws = G.ws;
-      fj.resident = effective_plan(G.N, G.f32) == PR_PLAN_RESIDENT;
+      fj.resident = G.scheme == PR_SCHEME_SSI && effective_plan(G.N, G.f32) == PR_PLAN_RESIDENT;
       fj.in_base = UB;
       fj.in_offs = P.t64 + sg.i64[0];
       fj.out_base = WB;
@@ -876,7 +897,7 @@ const char* pr_status_string(pr_status s) {
 size_t pr_fine_workspace_bytes(const pr_problem* p, int64_t nfields) {
   if (check_problem(p) != PR_OK || nfields < 0) return 0;
   Carver c(nullptr);
-  carve_fine(c, p->n, p->fine_prec == PR_F32, nfields);
+  carve_fine(c, p->n, p->fine_prec == PR_F32, nfields, is_cn(p));
   return c.used;
 }
 
@@ -891,7 +912,7 @@ pr_status pr_fine_propagate(const pr_problem* p, int64_t nfields, const double* 
   if (out_dtype != PR_F64 && out_dtype != PR_F32) return fail(PR_ERR_INVALID_ARG, "out_dtype must be PR_F64 or PR_F32");
   const bool f32 = p->fine_prec == PR_F32;
   Carver c(ws);
-  FineWs w = carve_fine(c, p->n, f32, nfields);
+  FineWs w = carve_fine(c, p->n, f32, nfields, is_cn(p));
   if (!ws || ws_bytes < c.used)
     return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, c.used);
   hipStream_t s = (hipStream_t)stream;
@@ -899,7 +920,7 @@ pr_status pr_fine_propagate(const pr_problem* p, int64_t nfields, const double* 
   j.in_base = u_in;
   j.out_base = u_out;
   j.out_f32 = out_dtype == PR_F32;
-  PR_HIP(launch_tables(p->n, w, s));
+  PR_HIP(launch_tables(p->n, p->laplacian, w, s));
   PR_HIP(launch_steps(j, s));
   return PR_OK;
 }
@@ -1066,16 +1087,17 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
   if (!u_in || !u_out || (const void*)u_in == u_out) return fail(PR_ERR_INVALID_ARG, "bad u_in / u_out");
   const bool f32 = p->fine_prec == PR_F32;
   Carver c(ws);
-  FineWs w = carve_fine(c, p->n, f32, nfields);
+  FineWs w = carve_fine(c, p->n, f32, nfields, is_cn(p));
   if (!ws || ws_bytes < c.used)
     return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, c.used);
   hipStream_t s = (hipStream_t)stream;
   const int l = log2i(p->n);
   int best = PR_PLAN_STREAM;
-  if (p->n <= kResidentMaxN) {
+  // the resident plan exists for the semi-implicit step only
+  if (p->n <= kResidentMaxN && !is_cn(p)) {
     Events ev;
     if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
-    PR_HIP(launch_tables(p->n, w, s));
+    PR_HIP(launch_tables(p->n, p->laplacian, w, s));
     float ms[3] = {0, 0, 0};
     for (int plan = PR_PLAN_STREAM; plan <= PR_PLAN_RESIDENT; ++plan) {
       StepJob j = make_job(p, p->dt, p->steps, f32, nfields, w);
@@ -1092,7 +1114,7 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
     }
     best = ms[PR_PLAN_RESIDENT] <= ms[PR_PLAN_STREAM] ? PR_PLAN_RESIDENT : PR_PLAN_STREAM;
   }
-  g_tuned[l][f32 ? 1 : 0].store(best);
+  if (!is_cn(p)) g_tuned[l][f32 ? 1 : 0].store(best);
   if (chosen) *chosen = best;
   return PR_OK;
 }
@@ -1100,7 +1122,7 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
 size_t pr_serial_workspace_bytes(const pr_problem* p, int64_t n_ics) {
   if (check_problem(p) != PR_OK || n_ics < 0) return 0;
   Carver c(nullptr);
-  carve_fine(c, p->n, p->fine_prec == PR_F32, n_ics);
+  carve_fine(c, p->n, p->fine_prec == PR_F32, n_ics, is_cn(p));
   c.take((size_t)n_ics * 8);
   return c.used;
 }
@@ -1115,7 +1137,7 @@ pr_status pr_serial_fine(const pr_problem* p, int64_t n_ics, int32_t n_slices, c
   if (!u0 || !U) return fail(PR_ERR_INVALID_ARG, "u0 / U is NULL");
   const bool f32 = p->fine_prec == PR_F32;
   Carver c(ws);
-  FineWs w = carve_fine(c, p->n, f32, n_ics);
+  FineWs w = carve_fine(c, p->n, f32, n_ics, is_cn(p));
   int64_t* off_u = (int64_t*)c.take((size_t)n_ics * 8);
   if (!ws || ws_bytes < c.used)
     return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, c.used);
@@ -1124,7 +1146,7 @@ pr_status pr_serial_fine(const pr_problem* p, int64_t n_ics, int32_t n_slices, c
   std::vector<int64_t> off(n_ics);
   for (int64_t b = 0; b < n_ics; ++b) off[b] = b * (int64_t)(n_slices + 1) * n2;
   PR_HIP(hipMemcpyAsync(off_u, off.data(), n_ics * 8, hipMemcpyHostToDevice, hs));
-  PR_HIP(launch_tables(p->n, w, hs));
+  PR_HIP(launch_tables(p->n, p->laplacian, w, hs));
   PR_HIP(launch_copy(n_ics, p->n, u0, nullptr, U, off_u, hs));
   StepJob j = make_job(p, p->dt, p->steps, f32, n_ics, w);
   for (int32_t q = 0; q < n_slices; ++q) {

@@ -41,15 +41,25 @@ namespace pr {
 
 // ------------------------------------------------------------------ tables
 
-__global__ void k_tables(int n, double2* tw64, float2* tw32, double* s2) {
+// Twiddles exp(-2 pi i t / N) and the per-axis symbol table s2: the
+// symbol of the discrete Laplacian is -(4/h^2)(s2[kx] + s2[ky]) with
+// s2[t] = sin^2(pi t / N) for the 5-point stencil and (pi t~ / N)^2,
+// t~ = min(t, N - t), for Fourier collocation ((4/h^2)(pi t~/N)^2 =
+// (2 pi t~ / L)^2).
+__global__ void k_tables(int n, int laplacian, double2* tw64, float2* tw32, double* s2) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) {
     double s, c;
     sincospi(2.0 * (double)t / (double)n, &s, &c);
     tw64[t] = double2{c, -s};
     tw32[t] = float2{(float)c, (float)-s};
-    const double sn = sinpi((double)t / (double)n);
-    s2[t] = sn * sn;
+    if (laplacian == LAP_SPECTRAL) {
+      const double k = 3.141592653589793 * (double)(t <= n - t ? t : n - t) / (double)n;
+      s2[t] = k * k;
+    } else {
+      const double sn = sinpi((double)t / (double)n);
+      s2[t] = sn * sn;
+    }
   }
 }
 
@@ -64,35 +74,46 @@ __device__ __forceinline__ int opaque_tid(int tid) {
 
 // --------------------------------------------------------------- row pass
 
-// Right-hand side of the step, r = (1 + S dt) v + dt f(v), on the two rows
-// carried by one complex value; f is also summed in FP64.
-template <typename T>
+// What the row pass transforms, on the two rows carried by one complex
+// value: the semi-implicit right-hand side r = (1 + S dt) v + dt f(v) (f
+// also summed in FP64 for the mass multiplier), f(v), or v.
+template <int RHS, typename T>
 __device__ __forceinline__ cpx<T> rhs_pair(cpx<T> z, T a, T dt, double& fsum) {
-  const T f0 = z.x - z.x * z.x * z.x, f1 = z.y - z.y * z.y * z.y;
-  fsum += (double)f0 + (double)f1;
-  return cpx<T>{a * z.x + dt * f0, a * z.y + dt * f1};
+  if constexpr (RHS == RHS_U) {
+    return z;
+  } else {
+    const T f0 = z.x - z.x * z.x * z.x, f1 = z.y - z.y * z.y * z.y;
+    if constexpr (RHS == RHS_F) {
+      return cpx<T>{f0, f1};
+    } else {
+      fsum += (double)f0 + (double)f1;
+      return cpx<T>{a * z.x + dt * f0, a * z.y + dt * f1};
+    }
+  }
 }
 
 // First forward stage reads rows r0+2p and r0+2p+1 of the real FP64 state,
 // rounds them to T and forms the right-hand side.
-template <int N, typename T> struct RealRowsPro {
+template <int N, typename T, int RHS = RHS_SSI> struct RealRowsPro {
   const double* u;
   int r0;
   T a, dt;
   double* fsum;
   __device__ __forceinline__ cpx<T> load(int, int p, int x) const {
     const cpx<T> z{(T)u[(int64_t)(r0 + 2 * p) * N + x], (T)u[(int64_t)(r0 + 2 * p + 1) * N + x]};
-    return rhs_pair<T>(z, a, dt, *fsum);
+    return rhs_pair<RHS, T>(z, a, dt, *fsum);
   }
   __device__ __forceinline__ void after_reads() const {}
 };
 
 // Last inverse stage: right-hand side of the next step, kept in LDS.
-template <typename T> struct RhsEpi {
+template <typename T, int RHS = RHS_SSI> struct RhsEpi {
   static constexpr bool kWritesLds = true;
   T a, dt;
   double* fsum;
-  __device__ __forceinline__ void apply(int, int, cpx<T>& v) const { v = rhs_pair<T>(v, a, dt, *fsum); }
+  __device__ __forceinline__ void apply(int, int, cpx<T>& v) const {
+    v = rhs_pair<RHS, T>(v, a, dt, *fsum);
+  }
 };
 
 // Last inverse stage: the two real rows go straight to the output state.
@@ -149,7 +170,7 @@ __device__ __forceinline__ StepParams field_params(const CallDesc* desc, int64_t
 }
 
 // First row pass of a call: the real FP64 state in, half spectra out.
-template <int N, typename T>
+template <int N, typename T, int RHS = RHS_SSI>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row_first(
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
     const cpx<T>* __restrict__ tw_g, StepParams sp_arg) {
@@ -174,8 +195,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   double fsum = 0.0;
   const double* u = desc->in_base + (desc->in_offs ? desc->in_offs[f] : f * (int64_t)N * N);
   __syncthreads();
-  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, RealRowsPro<N, T>{u, r0, a, dt, &fsum});
-  if (sp.conservative) {
+  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, RealRowsPro<N, T, RHS>{u, r0, a, dt, &fsum});
+  if (RHS == RHS_SSI && sp.conservative) {
     const double s = block_sum<NT>(fsum, red, tid);
     if (tid == 0) partials[f * TILES + tile] = s;
   }
@@ -183,7 +204,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
 }
 
 // Middle and last row passes: one block per tile of TR rows of one field.
-template <int N, typename T, int MODE>
+template <int N, typename T, int MODE, int RHS = RHS_SSI>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
     const cpx<T>* __restrict__ tw_g, StepParams sp_arg) {
@@ -226,9 +247,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
                             RealRowsStore<N, T>{desc->out_base, ob, r0, desc->out_f32});
   } else {
     double fsum = 0.0;
-    fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, RhsEpi<T>{a, dt, &fsum});
+    fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, RhsEpi<T, RHS>{a, dt, &fsum});
     fft_lines<N, -1, NT, T>(panel, tw, lay, tid);
-    if (sp.conservative) {
+    if (RHS == RHS_SSI && sp.conservative) {
       const double s = block_sum<NT>(fsum, red, tid);
       if (tid == 0) partials[f * TILES + tile] = s;
     }
@@ -331,6 +352,156 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
     for (int q = 0; q < E0; ++q) {
       const int ky = tid + q * NT;
       if (ky < N) panel[lay(0, ky)] = vals[q];
+    }
+    __syncthreads();
+  }
+  fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, ColStore<T>{P, N});
+}
+
+// ------------------------------------------------ Crank-Nicolson + Picard
+//
+// The paper's fine scheme (Section 3.1, eq. fully-discrete) solved by
+// Picard iteration from V_(0) = U_n.  In Fourier space, with
+// q_k = (dt eps^2 / 2) mu_k, A_k = 1 - q_k, D_k = 1 + q_k and F^(m) the
+// DFT of f(V_(m)), iteration m is
+//     D V^_(m+1) = K + (dt/2) F^(m),   K = A U^_n + (dt/2) F^_n,
+// with F^(0) = F^_n since V_(0) = U_n.  In the conservative model the
+// nonlocal term dt g removes the means of f(U_n)/2 and f(V_(m))/2, i.e.
+// exactly the DC bins of both F terms, so V keeps the DC of U_n.
+//
+// The row passes transform f(v) (RHS_F).  The column pass of Picard
+// iteration m transforms those row spectra along the columns, forms
+// V^_(m+1) from them and the field's second spectral buffer X, and
+// stores V^_(m+1) / N^2 as row spectra for the next row pass.  X holds
+// U^_n (2-D layout) between steps and K during a step's iterations:
+//     m = 0:   K = A X + (dt/2) F^,  V^ = (K + (dt/2) F^) / D,  X <- K;
+//     m > 0:   V^ = (X + (dt/2) F^) / D;
+// and at the last m, X <- V^ (= U^_{n+1}).  Stage-in transforms U_0 into
+// X (a row pass with RHS_U, then k_col_fwd) and f(U_0) into the row
+// spectra.
+
+enum { CN_FIRST = 1, CN_LAST = 2 };
+
+// Forward column transform in place: row spectra -> 2-D spectrum.
+template <int N, typename T>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col_fwd(
+    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ xspec, const cpx<T>* __restrict__ tw_g) {
+  using C = cpx<T>;
+  constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
+  constexpr int LS = PadLS<N>::value;
+  using Lay = LinePanel<LS>;
+  __shared__ C panel[CT * LS];
+  __shared__ C tw[TwSize<N>::value];
+  const int tid = threadIdx.x;
+  const int64_t f = blockIdx.x / BLK;
+  if (f >= desc->nfields) return;
+  const int c0 = (blockIdx.x % BLK) * CT;
+  C* P = xspec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
+  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  __syncthreads();
+  fft_lines<N, -1, NT, T>(panel, tw, Lay{}, tid, ColLoad<T>{P, N}, ColStore<T>{P, N});
+}
+
+// Last forward stage of a Picard column pass, for every column but the
+// packed one: combine with X, update X, scale by 1/N^2 for the inverse.
+template <int N, typename T, int MODE> struct CnEpi {
+  static constexpr bool kWritesLds = true;
+  cpx<T>* X;           // column c0 of the field's X
+  const double* s2;
+  StepParams sp;
+  int c0;
+  __device__ __forceinline__ void apply(int line, int ky, cpx<T>& v) const {
+    const int col = c0 + line;
+    if (col == 0) return;  // the packed column is done after the transform
+    const double q = 0.5 * sp.lam * (s2[col] + s2[ky]);
+    const T h = (T)(0.5 * sp.dt);
+    cpx<T>* xp = X + (int64_t)line * N + ky;
+    const cpx<T> x = *xp;
+    cpx<T> K = x;
+    if constexpr ((MODE & CN_FIRST) != 0) {
+      const T A = (T)(1.0 - q);
+      K = cpx<T>{A * x.x + h * v.x, A * x.y + h * v.y};
+    }
+    const T dinv = (T)(1.0 / (1.0 + q));
+    const cpx<T> V{(K.x + h * v.x) * dinv, (K.y + h * v.y) * dinv};
+    if constexpr ((MODE & CN_LAST) != 0) *xp = V;
+    else if constexpr ((MODE & CN_FIRST) != 0) *xp = K;
+    const T sc = (T)sp.inv_n2;
+    v = cpx<T>{V.x * sc, V.y * sc};
+  }
+};
+
+// a (m0 + mn)/2 + conj(b) (m0 - mn)/2: multiplies the kx = 0 part of a
+// packed column value a by m0 and its kx = N/2 part by mn, for real
+// multipliers even in ky, given b = the value at -ky.
+template <typename T>
+__device__ __forceinline__ cpx<T> packed_mul(cpx<T> a, cpx<T> b, double m0, double mn) {
+  const T pp = (T)(0.5 * (m0 + mn)), mm = (T)(0.5 * (m0 - mn));
+  return cpx<T>{a.x * pp + b.x * mm, a.y * pp - b.y * mm};
+}
+
+template <int N, typename T, int MODE>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col_cn(
+    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, cpx<T>* __restrict__ xspec,
+    const cpx<T>* __restrict__ tw_g, const double* __restrict__ s2_g, StepParams sp_arg) {
+  using C = cpx<T>;
+  constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
+  constexpr int LS = PadLS<N>::value;
+  constexpr int E0 = (N + NT - 1) / NT;
+  using Lay = LinePanel<LS>;
+  __shared__ C panel[CT * LS];
+  __shared__ C tw[TwSize<N>::value];
+  __shared__ double s2[N];
+
+  const int tid = threadIdx.x;
+  const int64_t f = blockIdx.x / BLK;
+  if (f >= desc->nfields) return;
+  const StepParams sp = field_params(desc, f, sp_arg);
+  const int c0 = (blockIdx.x % BLK) * CT;
+  const Lay lay{};
+  C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
+  C* X = xspec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
+  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
+  __syncthreads();
+  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, ColLoad<T>{P, N}, CnEpi<N, T, MODE>{X, s2, sp, c0});
+  if (c0 == 0) {
+    const double h = 0.5 * sp.dt;
+    C vals[E0], xnew[E0];
+#pragma unroll
+    for (int q = 0; q < E0; ++q) {
+      const int ky = tid + q * NT;
+      if (ky < N) {
+        const int kr = (N - ky) % N;
+        C z = panel[lay(0, ky)], w = panel[lay(0, kr)];
+        if (sp.conservative) {   // drop F^(0, 0)
+          if (ky == 0) z.x = (T)0;
+          if (kr == 0) w.x = (T)0;
+        }
+        const C x = X[ky], xr = X[kr];
+        const double q0 = 0.5 * sp.lam * (s2[0] + s2[ky]), qn = 0.5 * sp.lam * (s2[N / 2] + s2[ky]);
+        C K = x, Kr = xr;
+        if constexpr ((MODE & CN_FIRST) != 0) {
+          K = packed_mul<T>(x, xr, 1.0 - q0, 1.0 - qn);
+          Kr = packed_mul<T>(xr, x, 1.0 - q0, 1.0 - qn);
+          K = C{K.x + (T)h * z.x, K.y + (T)h * z.y};
+          Kr = C{Kr.x + (T)h * w.x, Kr.y + (T)h * w.y};
+        }
+        const C Y{K.x + (T)h * z.x, K.y + (T)h * z.y}, Yr{Kr.x + (T)h * w.x, Kr.y + (T)h * w.y};
+        const C V = packed_mul<T>(Y, Yr, 1.0 / (1.0 + q0), 1.0 / (1.0 + qn));
+        xnew[q] = (MODE & CN_LAST) != 0 ? V : K;
+        const T sc = (T)sp.inv_n2;
+        vals[q] = C{V.x * sc, V.y * sc};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < E0; ++q) {
+      const int ky = tid + q * NT;
+      if (ky < N) {
+        panel[lay(0, ky)] = vals[q];
+        if constexpr (MODE != 0) X[ky] = xnew[q];
+      }
     }
     __syncthreads();
   }
@@ -520,6 +691,52 @@ static void enqueue_stream_steps(const StepJob& job, int64_t grid_fields, hipStr
   k_row<N, T, ROW_LAST><<<glast, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
 }
 
+template <int N, typename T, int MODE>
+static void launch_col_cn(const StepJob& job, dim3 g, dim3 b, hipStream_t st) {
+  const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)job.ws.tw64 : (const void*)job.ws.tw32);
+  k_col_cn<N, T, MODE><<<g, b, 0, st>>>(job.ws.desc, (cpx<T>*)job.ws.spec, (cpx<T>*)job.ws.xspec,
+                                        tw, job.ws.s2, job.sp);
+}
+
+// The launches of one Crank-Nicolson F call: stage-in (3), then per step
+// and Picard iteration a column pass and (except at the very end) a row
+// pass, then the final row pass that writes the state.
+template <int N, typename T>
+static void enqueue_cn_steps(const StepJob& job, int64_t grid_fields, hipStream_t st) {
+  using RC = RowCfg<N, T>;
+  using CC = ColCfg<N>;
+  const cpx<T>* tw = (const cpx<T>*)(sizeof(T) == 8 ? (const void*)job.ws.tw64 : (const void*)job.ws.tw32);
+  cpx<T>* spec = (cpx<T>*)job.ws.spec;
+  cpx<T>* xs = (cpx<T>*)job.ws.xspec;
+  const CallDesc* d = job.ws.desc;
+  const dim3 grow((unsigned)(grid_fields * RC::TILES)), brow(RC::NT);
+  const dim3 gcol((unsigned)(grid_fields * CC::BLOCKS)), bcol(CC::NT);
+  k_row_first<N, T, RHS_U><<<grow, brow, 0, st>>>(d, xs, job.ws.partials, tw, job.sp);
+  k_col_fwd<N, T><<<gcol, bcol, 0, st>>>(d, xs, tw);
+  k_row_first<N, T, RHS_F><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
+  const int M = job.picard;
+  for (int s = 0; s < job.steps; ++s) {
+    for (int m = 0; m < M; ++m) {
+      const int mode = (m == 0 ? CN_FIRST : 0) | (m == M - 1 ? CN_LAST : 0);
+      switch (mode) {
+        case 0: launch_col_cn<N, T, 0>(job, gcol, bcol, st); break;
+        case CN_FIRST: launch_col_cn<N, T, CN_FIRST>(job, gcol, bcol, st); break;
+        case CN_LAST: launch_col_cn<N, T, CN_LAST>(job, gcol, bcol, st); break;
+        default: launch_col_cn<N, T, CN_FIRST | CN_LAST>(job, gcol, bcol, st); break;
+      }
+      if (s + 1 < job.steps || m + 1 < M)
+        k_row<N, T, ROW_MID, RHS_F><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
+    }
+  }
+  k_row<N, T, ROW_LAST><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
+}
+
+template <int N, typename T>
+static void enqueue_steps(const StepJob& job, int64_t grid_fields, hipStream_t st) {
+  if (job.scheme == SCHEME_CN) enqueue_cn_steps<N, T>(job, grid_fields, st);
+  else enqueue_stream_steps<N, T>(job, grid_fields, st);
+}
+
 // ---- replay of captured launch sequences
 //
 // A streaming F call is 2c+1 launches whose arguments depend only on the
@@ -528,13 +745,14 @@ static void enqueue_stream_steps(const StepJob& job, int64_t grid_fields, hipStr
 // replayed; a replay serves any batch no larger than the captured grid.
 
 struct GraphKey {
-  int n, f32, steps, conservative;
+  int n, f32, steps, conservative, scheme, picard;
   double a, dt, lam, inv_n2;
-  const void *desc, *spec, *partials, *tw, *s2;
+  const void *desc, *spec, *xspec, *partials, *tw, *s2;
   bool same(const GraphKey& o) const {
     return n == o.n && f32 == o.f32 && steps == o.steps && conservative == o.conservative &&
-           a == o.a && dt == o.dt && lam == o.lam && inv_n2 == o.inv_n2 && desc == o.desc &&
-           spec == o.spec && partials == o.partials && tw == o.tw && s2 == o.s2;
+           scheme == o.scheme && picard == o.picard && a == o.a && dt == o.dt && lam == o.lam &&
+           inv_n2 == o.inv_n2 && desc == o.desc && spec == o.spec && xspec == o.xspec &&
+           partials == o.partials && tw == o.tw && s2 == o.s2;
   }
 };
 
@@ -561,9 +779,11 @@ static hipError_t launch_stream_graph(const StepJob& job, hipStream_t st) {
   // with per-field parameters the launch argument is unused, and every
   // such sequence with the same shape and workspace is the same graph
   const StepParams sp = job.params ? StepParams{0, 0, 0, 0, -1} : job.sp;
-  GraphKey key{job.n, job.f32 ? 1 : 0, job.steps, sp.conservative, sp.a, sp.dt,
-               sp.lam, sp.inv_n2, job.ws.desc, job.ws.spec, job.ws.partials,
-               job.f32 ? (const void*)job.ws.tw32 : (const void*)job.ws.tw64, job.ws.s2};
+  GraphKey key{job.n, job.f32 ? 1 : 0, job.steps, sp.conservative, job.scheme,
+               job.scheme == SCHEME_CN ? job.picard : 0, sp.a, sp.dt, sp.lam, sp.inv_n2,
+               job.ws.desc, job.ws.spec, job.scheme == SCHEME_CN ? job.ws.xspec : nullptr,
+               job.ws.partials, job.f32 ? (const void*)job.ws.tw32 : (const void*)job.ws.tw64,
+               job.ws.s2};
   std::lock_guard<std::mutex> lock(g_graph_mu);
   GraphEntry* hit = nullptr;
   for (auto& e : g_graphs)
@@ -590,7 +810,7 @@ static hipError_t launch_stream_graph(const StepJob& job, hipStream_t st) {
     GraphEntry e{key, job.nfields, nullptr, nullptr, 0};
     err = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
     if (err != hipSuccess) return err;
-    enqueue_stream_steps<N, T>(job, job.nfields, g_capture_stream);
+    enqueue_steps<N, T>(job, job.nfields, g_capture_stream);
     hipError_t lerr = hipGetLastError();
     err = hipStreamEndCapture(g_capture_stream, &e.graph);
     if (lerr != hipSuccess) return lerr;
@@ -610,7 +830,7 @@ static hipError_t launch_stream_graph(const StepJob& job, hipStream_t st) {
 template <int N, typename T>
 static hipError_t launch_steps_n(const StepJob& job, hipStream_t st) {
   if (graphs_enabled()) return launch_stream_graph<N, T>(job, st);
-  enqueue_stream_steps<N, T>(job, job.nfields, st);
+  enqueue_steps<N, T>(job, job.nfields, st);
   return hipGetLastError();
 }
 
@@ -644,7 +864,7 @@ static hipError_t launch_steps_t(const StepJob& job, hipStream_t st) {
   k_set_desc<<<dim3(1), dim3(1), 0, st>>>(job.ws.desc, v);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (job.resident) return launch_resident_t<T>(job, st);
+  if (job.resident && job.scheme == SCHEME_SSI) return launch_resident_t<T>(job, st);
   switch (job.n) {
     case 16: return launch_steps_n<16, T>(job, st);
     case 32: return launch_steps_n<32, T>(job, st);
@@ -657,8 +877,8 @@ static hipError_t launch_steps_t(const StepJob& job, hipStream_t st) {
   }
 }
 
-hipError_t launch_tables(int n, const FineWs& ws, hipStream_t st) {
-  k_tables<<<dim3((n + 255) / 256), dim3(256), 0, st>>>(n, ws.tw64, ws.tw32, ws.s2);
+hipError_t launch_tables(int n, int laplacian, const FineWs& ws, hipStream_t st) {
+  k_tables<<<dim3((n + 255) / 256), dim3(256), 0, st>>>(n, laplacian, ws.tw64, ws.tw32, ws.s2);
   return hipGetLastError();
 }
 

@@ -9,6 +9,14 @@ namespace pr {
 
 enum { ROW_FIRST = 0, ROW_MID = 1, ROW_LAST = 2 };
 
+// Fine schemes and discrete Laplacians (same values as in include/pr.h).
+enum { SCHEME_SSI = 0, SCHEME_CN = 1 };
+enum { LAP_FD5 = 0, LAP_SPECTRAL = 1 };
+
+// What a row pass transforms: the semi-implicit right-hand side
+// (1 + S dt) v + dt f(v), f(v) alone, or v itself.
+enum { RHS_SSI = 0, RHS_F = 1, RHS_U = 2 };
+
 // Row pass tiling: TR rows (TR/2 complex row pairs) of one field per block,
 // one radix-8 group of eight elements per thread per FFT stage.  TR is the
 // smallest even count that gives >= 256 threads and >= 128-byte contiguous
@@ -82,12 +90,16 @@ struct FineWs {
   double* s2;        // [N]  sin^2(pi t / N)
   double* partials;  // [nfields * row tiles] FP64 partial sums of f
   void* spec;        // [nfields][N/2][N] complex in the step precision
+  void* xspec;       // Crank-Nicolson only: [nfields][N/2][N] 2-D spectra
+                     // (U_n between steps, the fixed part K during Picard)
 };
 
 struct StepJob {
   int n;
   bool f32;
   int steps;
+  int scheme = SCHEME_SSI;
+  int picard = 1;            // Crank-Nicolson: Picard iterations per step
   int64_t nfields;
   StepParams sp;
   const double* in_base;     // field i at in_base + (in_offs ? in_offs[i] : i N^2)
@@ -153,7 +165,7 @@ int cnn_grad_bytes(int prec);
 size_t cnn_lds_bytes(int C, bool split);
 hipError_t cnn_set_lds_limits();
 
-hipError_t launch_tables(int n, const FineWs& ws, hipStream_t st);
+hipError_t launch_tables(int n, int laplacian, const FineWs& ws, hipStream_t st);
 // Process-wide switch for replaying captured launch sequences (default on).
 void set_graphs_enabled(bool on);
 bool graphs_enabled();

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 4
+    assert lib.pr_abi_version() == 5
 
 
 def test_library_exports_match_nm(L):
@@ -58,6 +58,8 @@ def _prob(L, **kw):
     (dict(n=60), 2), (dict(n=8), 2), (dict(n=2048), 2), (dict(dim=3), 2),
     (dict(eps=0.0), 1), (dict(dt=-1.0), 1), (dict(steps=0), 1), (dict(length=float("nan")), 1),
     (dict(conservative=2), 1), (dict(stab=-1.0), 1), (dict(fine_prec=2), 2),
+    (dict(scheme=2), 1), (dict(scheme=1, picard_iters=0), 1), (dict(scheme=1, picard_iters=65), 1),
+    (dict(laplacian=2), 1),
 ])
 def test_problem_validation(L, kw, status):
     lib = L.lib()
