@@ -44,10 +44,19 @@ CONFIGS = {
 }
 
 
-def bytes_per_point_step(prec: str) -> int:
-    # each step: one column pass and one row pass, each reading and writing
-    # the field's N*N real numbers once (as N/2 x N complex values)
-    return 32 if prec == "f64" else 16
+def bytes_per_point_step(prec: str, scheme: str = "ssi", picard: int = 1) -> int:
+    """Algorithmic HBM bytes per grid point and fine step.
+
+    Semi-implicit step: one column pass and one row pass, each reading and
+    writing the field's N*N real numbers once (as N/2 x N complex values):
+    4 words.  Crank-Nicolson with M Picard iterations: per iteration a
+    column pass (read and write the row spectra, read the second spectral
+    buffer, and write it at the first and the last iteration) and a row
+    pass (read and write): 5 M + 2 words (6 for M = 1)."""
+    w = 8 if prec == "f64" else 4
+    if scheme == "cn":
+        return w * (5 * picard + (1 if picard == 1 else 2))
+    return 4 * w
 
 
 def kernel_src_hash() -> str:
@@ -348,6 +357,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + ["c4", "c5"])
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--scheme", default="ssi", choices=["ssi", "cn"],
+                    help="fine scheme: the semi-implicit step the workloads fix, or the paper's "
+                         "Crank-Nicolson + Picard")
+    ap.add_argument("--picard", type=int, default=2, help="Picard iterations per CN step")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--kmax", type=int, default=16)
@@ -381,7 +394,8 @@ def main():
     cfg = CONFIGS[args.config]
     n, s, B, c = cfg["n"], cfg["slices"], cfg["ics"], cfg["steps"]
     p = api.Problem(n=n, length=1.0, eps=cfg["eps"], conservative=cfg["conservative"], stab=2.0,
-                    dt=cfg["dt"], steps=c, fine_prec=args.prec)
+                    dt=cfg["dt"], steps=c, fine_prec=args.prec, scheme=args.scheme,
+                    picard=args.picard)
     coarse = args.coarse or ("num" if args.config == "c1" else "cnn")
     g_num = api.Coarse(dt=cfg["dt"] * c / cfg["g_steps"], steps=cfg["g_steps"], prec="f64")
     train_info = None
@@ -417,16 +431,18 @@ def main():
     value = pts / (ms_per_step * 1e-3) / 1e9
 
     fine_ms_avg = float(np.mean(fine_ms))
-    bpp = bytes_per_point_step(args.prec)
+    bpp = bytes_per_point_step(args.prec, args.scheme, args.picard)
     achieved = pts * bpp / (fine_ms_avg * 1e-3) / 1e9
-    traffic = measured_traffic(args.config, args.prec, n)
+    traffic = measured_traffic(args.config, args.prec, n) if args.scheme == "ssi" else None
     step_alg_bytes = B * s * n * n * bpp
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
             "traffic_unit": "bytes per fine step over the batch (row + column pass)",
             "algorithmic_bytes_per_step": step_alg_bytes,
-            "kernel": "fine step = k_col + k_row<MID> per step, over the whole F sweep",
+            "kernel": ("fine step = k_col + k_row<MID> per step, over the whole F sweep"
+                       if args.scheme == "ssi" else
+                       f"fine step = {args.picard} x (k_col_cn + k_row<MID, f(v)>), over the F sweep"),
             "bytes_per_point_step": bpp,
             "fine_sweep_ms": round(fine_ms_avg, 3), "sweep_ms": round(float(np.mean(sweep_ms)), 3)}
     out = {
@@ -434,8 +450,10 @@ def main():
         "value": round(value, 2), "unit": "Gpts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": cfg["workload"], "n": n, "ics": B, "slices": s, "fine_steps": c,
-                   "fine_solves_per_launch": B * s, "fine_prec": args.prec},
+        "config": {"workload": cfg["workload"] + ("" if args.scheme == "ssi" else
+                                                  f"; fine scheme CN + {args.picard} Picard iterations"),
+                   "n": n, "ics": B, "slices": s, "fine_steps": c,
+                   "fine_solves_per_launch": B * s, "fine_prec": args.prec, "scheme": args.scheme},
         "roofline": roof,
     }
     if coarse == "cnn":
