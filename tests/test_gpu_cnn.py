@@ -62,6 +62,17 @@ def test_cnn_f32_matches_oracle(api, L, C):
     assert net_rel(out, ref, u0) <= 1e-5
 
 
+@pytest.mark.parametrize("L,C,n", [(2, 8, 32), (4, 32, 64), (3, 16, 64), (5, 8, 128)])
+def test_cnn_f64_matches_oracle(api, L, C, n):
+    print(f"case cnn f64 L={L} C={C} n={n}", flush=True)
+    spec = cnn.CnnSpec(n_layers=L, channels=C)
+    ws, bs, g = make(api, spec, seed=L * 10 + C, prec="f64")
+    u0 = synth.random_ic(n, [1, 2])
+    out = api.pr_coarse_apply(problem(api, n), g, dev(u0)).cpu().numpy()
+    ref = cnn.forward(u0, ws, bs, spec)
+    assert net_rel(out, ref, u0) <= 1e-12
+
+
 @pytest.mark.parametrize("L,C,n", [(4, 32, 64), (4, 32, 256), (6, 48, 128), (3, 16, 32), (3, 64, 64)])
 def test_cnn_bf16_matches_oracle(api, L, C, n):
     print(f"case cnn bf16 L={L} C={C} n={n}", flush=True)
