@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 5
+#define PR_ABI_VERSION 6
 
 typedef enum {
   PR_OK = 0,
@@ -327,6 +327,35 @@ pr_status pr_serial_fine(const pr_problem* p, int64_t n_ics, int32_t n_slices,
  *                     ran for this (N, precision), else RESIDENT for
  *                     N <= 128 and STREAM above. */
 typedef enum { PR_PLAN_AUTO = 0, PR_PLAN_STREAM = 1, PR_PLAN_RESIDENT = 2 } pr_plan;
+
+/* How a bfloat16 network (PR_BF16, PR_BF16X2) is evaluated for inference,
+ * process-wide.  Both plans compute the same arithmetic; they differ in
+ * where the activations live.
+ *   PR_CNN_PLAN_LAYERED  one launch per layer, activations through HBM;
+ *   PR_CNN_PLAN_FUSED    all layers in one launch per call, a 16 x 16
+ *                        output tile per work-group with the activations
+ *                        (and recomputed halos) in LDS and every hidden
+ *                        layer's weights in registers; available for
+ *                        C = 16 (1..4 hidden layers), C = 32 (1..2) and
+ *                        C = 48 (1, PR_BF16 only); other shapes fall back
+ *                        to LAYERED;
+ *   PR_CNN_PLAN_AUTO     the autotuner's measured choice for the shape if
+ *                        pr_autotune_coarse ran, else LAYERED.
+ * Training (pr_cnn_backward) always runs layer by layer. */
+typedef enum { PR_CNN_PLAN_AUTO = 0, PR_CNN_PLAN_LAYERED = 1, PR_CNN_PLAN_FUSED = 2 } pr_cnn_plan;
+
+pr_status pr_set_coarse_plan(int32_t plan);
+
+/* The plan pr_coarse_apply will use for g on N x N fields (LAYERED or FUSED),
+ * or -1 if g is not a valid network. */
+int32_t pr_get_coarse_plan(const pr_coarse* g, int32_t n);
+
+/* Times both plans for g on the caller's batch (u_in -> g_out, workspace
+ * as for pr_coarse_apply) and records the faster as the AUTO choice for
+ * the shape (channels, n_layers, prec).  *chosen receives it. */
+pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nfields,
+                             const double* u_in, double* g_out, void* ws, size_t ws_bytes,
+                             void* stream, int32_t* chosen);
 
 /* Set the plan for (n, prec).  PR_ERR_UNSUPPORTED for RESIDENT with n > 128. */
 pr_status pr_set_fine_plan(int32_t n, pr_dtype prec, int32_t plan);

@@ -28,9 +28,11 @@ EXPORTED = [
     "pr_solve_many_workspace_bytes", "pr_solve_many",
     "pr_serial_workspace_bytes", "pr_serial_fine",
     "pr_set_fine_plan", "pr_get_fine_plan", "pr_autotune_fine", "pr_set_graphs", "pr_get_graphs",
+    "pr_set_coarse_plan", "pr_get_coarse_plan", "pr_autotune_coarse",
     "pr_status_string", "pr_last_error", "pr_abi_version",
 ]
 PR_PLAN_AUTO, PR_PLAN_STREAM, PR_PLAN_RESIDENT = 0, 1, 2
+PR_CNN_PLAN_AUTO, PR_CNN_PLAN_LAYERED, PR_CNN_PLAN_FUSED = 0, 1, 2
 
 
 class Problem(C.Structure):
@@ -94,6 +96,9 @@ def lib() -> C.CDLL:
             "pr_get_fine_plan": (i32, [i32, C.c_int]),
             "pr_autotune_fine": (C.c_int, [P, i64, vp, vp, vp, sz, vp, C.POINTER(i32)]),
             "pr_set_graphs": (None, [i32]),
+            "pr_set_coarse_plan": (C.c_int, [i32]),
+            "pr_get_coarse_plan": (i32, [G, i32]),
+            "pr_autotune_coarse": (C.c_int, [P, G, i64, vp, vp, vp, sz, vp, C.POINTER(i32)]),
             "pr_get_graphs": (i32, []),
             "pr_status_string": (C.c_char_p, [C.c_int]),
             "pr_last_error": (C.c_char_p, []),

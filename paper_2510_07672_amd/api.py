@@ -321,6 +321,32 @@ def pr_autotune_fine(p: Problem, u_in: torch.Tensor) -> str:
     return _PLAN_NAME[ch.value]
 
 
+_CPLAN = {"auto": L.PR_CNN_PLAN_AUTO, "layered": L.PR_CNN_PLAN_LAYERED, "fused": L.PR_CNN_PLAN_FUSED}
+_CPLAN_NAME = {v: k for k, v in _CPLAN.items()}
+
+
+def pr_set_coarse_plan(plan: str) -> None:
+    """Network inference plan, process-wide: 'auto', 'layered' or 'fused'."""
+    L.check(L.lib().pr_set_coarse_plan(_CPLAN[plan]), "pr_set_coarse_plan")
+
+
+def pr_get_coarse_plan(g: "CnnCoarse", n: int) -> str:
+    return _CPLAN_NAME[L.lib().pr_get_coarse_plan(C.byref(g.c()), n)]
+
+
+def pr_autotune_coarse(p: Problem, g: "CnnCoarse", u_in: torch.Tensor) -> str:
+    """Time both network plans on u_in and keep the faster as the 'auto' choice."""
+    B = _fields(u_in, p.n, "u_in")
+    pc, gc = p.c(), g.c()
+    out = torch.empty_like(u_in)
+    ws = workspace(L.lib().pr_coarse_workspace_bytes(C.byref(pc), C.byref(gc), B), u_in.device)
+    ch = C.c_int32(0)
+    L.check(L.lib().pr_autotune_coarse(C.byref(pc), C.byref(gc), B, _ptr(u_in), _ptr(out),
+                                       _ptr(ws), ws.numel(), _stream(u_in.device), C.byref(ch)),
+            "pr_autotune_coarse")
+    return _CPLAN_NAME[ch.value]
+
+
 def pr_set_graphs(enabled: bool) -> None:
     """Replay captured launch sequences (True, default) or launch eagerly."""
     L.lib().pr_set_graphs(int(bool(enabled)))

@@ -1070,6 +1070,62 @@ pr_status pr_set_fine_plan(int32_t n, pr_dtype prec, int32_t plan) {
   return PR_OK;
 }
 
+pr_status pr_set_coarse_plan(int32_t plan) {
+  if (plan != PR_CNN_PLAN_AUTO && plan != PR_CNN_PLAN_LAYERED && plan != PR_CNN_PLAN_FUSED)
+    return fail(PR_ERR_INVALID_ARG, "coarse plan %d unknown", plan);
+  cnn_set_plan(plan);
+  return PR_OK;
+}
+
+int32_t pr_get_coarse_plan(const pr_coarse* g, int32_t n) {
+  if (!g || g->kind != PR_G_CNN || check_coarse(g, n) != PR_OK) return -1;
+  return cnn_effective_plan(g->channels, g->n_layers, g->prec);
+}
+
+pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nfields,
+                             const double* u_in, double* g_out, void* ws, size_t ws_bytes,
+                             void* stream, int32_t* chosen) {
+  pr_status st = check_problem(p);
+  if (st != PR_OK) return st;
+  if ((st = check_coarse(g, p->n)) != PR_OK) return st;
+  if (g->kind != PR_G_CNN) return fail(PR_ERR_INVALID_ARG, "pr_autotune_coarse needs a PR_G_CNN coarse");
+  if (nfields < 1) return fail(PR_ERR_INVALID_ARG, "nfields must be >= 1");
+  if (!u_in || !g_out || u_in == g_out) return fail(PR_ERR_INVALID_ARG, "bad u_in / g_out");
+  Carver c(ws);
+  CoarseWs w = carve_coarse(c, p, g, nfields);
+  if (!ws || ws_bytes < c.used)
+    return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, c.used);
+  if ((st = cnn_lds_once()) != PR_OK) return st;
+  int best = PR_CNN_PLAN_LAYERED;
+  if (cnn_fused_available(g->channels, g->n_layers, g->prec)) {
+    hipStream_t s = (hipStream_t)stream;
+    Events ev;
+    if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
+    const int saved = cnn_get_plan();
+    PR_HIP(coarse_setup(p, g, w, s));
+    float ms[3] = {0, 0, 0};
+    for (int plan = PR_CNN_PLAN_LAYERED; plan <= PR_CNN_PLAN_FUSED; ++plan) {
+      cnn_set_plan(plan);
+      hipError_t e = coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(ev.e[0], s);
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+        e = coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s);
+      if (e == hipSuccess) e = hipEventRecord(ev.e[1], s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev.e[1]);
+      if (e != hipSuccess) {
+        cnn_set_plan(saved);
+        return fail(PR_ERR_DEVICE, "autotune: %s", hipGetErrorString(e));
+      }
+      ms[plan] = event_ms(ev.e[0], ev.e[1]);
+    }
+    cnn_set_plan(saved);
+    best = ms[PR_CNN_PLAN_FUSED] <= ms[PR_CNN_PLAN_LAYERED] ? PR_CNN_PLAN_FUSED : PR_CNN_PLAN_LAYERED;
+  }
+  cnn_record_tuned(g->channels, g->n_layers, g->prec, best);
+  if (chosen) *chosen = best;
+  return PR_OK;
+}
+
 void pr_set_graphs(int32_t enabled) { set_graphs_enabled(enabled != 0); }
 
 int32_t pr_get_graphs(void) { return graphs_enabled() ? 1 : 0; }

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <utility>
 
 #include "internal.h"
@@ -269,6 +270,200 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
           *(bf16x8*)&out_lo[ob + px * C + c8 * 8] = *(const bf16x8*)&st[(16 + px) * H::OS + c8 * 8];
       }
       __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+// ---------------------------------------------------------- fused network
+//
+// Inference with every layer of a network with NH hidden layers in one
+// persistent kernel.  A work-group takes a 16 x 16 output tile, loads the
+// (16 + 2L)^2 region of u around it, and computes each layer on the region
+// the layers after it need (the halo shrinks by one pixel per layer), with
+// the activations in LDS as bfloat16 (hi and lo planes with SPLIT),
+// channels last.  Hidden layers run on the 16x16x32 bf16 MFMA with the
+// weights as the A operand, held in registers for the whole kernel, and
+// the activations as the B operand: lane l then receives output channels
+// 4 (l / 16) .. +3 of pixel l % 16, one 8-byte LDS store per 16 channels.
+// HBM traffic is u in and G(u) out; the layer-by-layer path instead moves
+// 2 C (L - 1) activation words per pixel.
+
+template <int C, int NH, bool SPLIT> struct FusedCfg {
+  static constexpr int T = 16, NW = 4, NT = 256;
+  static constexpr int CS = C + 8;                   // LDS pixel stride (elements)
+  static constexpr int KP = (9 * C + 31) / 32 * 32, KB = KP / 32, NB = C / 16;
+  static constexpr int W0 = T + 2 * (NH + 1);       // first layer's output region side
+  static constexpr int WU = W0 + 2;                 // region of u
+  static constexpr int PLANE_A = W0 * W0 * CS;      // one plane of buffer A (layer 0, 2, ...)
+  static constexpr int PLANE_B = (W0 - 2) * (W0 - 2) * CS;   // buffer B (layer 1, 3, ...)
+  static constexpr int P = SPLIT ? 2 : 1;
+  static constexpr size_t LDS = (size_t)P * (PLANE_A + PLANE_B) * 2 + (size_t)WU * WU * 4 +
+                                (size_t)C * 10 * 4 + 4 * 8;
+  static constexpr bool kFits = LDS <= 160 * 1024;
+};
+
+template <int C, int NH, bool SPLIT>
+__global__ __launch_bounds__(256) void k_cnn_fused(
+    const double* __restrict__ u_base, const int64_t* __restrict__ u_offs, int n, int64_t nfields,
+    const float* __restrict__ W0g, const float* __restrict__ b0g, const __bf16* __restrict__ Wp,
+    const float* __restrict__ bh, const float* __restrict__ WL, const float* __restrict__ bL,
+    int act, int residual, double* __restrict__ g_base, const int64_t* __restrict__ g_offs,
+    double* __restrict__ partials) {
+  using F = FusedCfg<C, NH, SPLIT>;
+  static_assert(C % 16 == 0, "hidden width must be a multiple of 16");
+  extern __shared__ __align__(16) unsigned char smem[];
+  __bf16* bufA = (__bf16*)smem;                          // [P][W0^2][CS]
+  __bf16* bufB = bufA + F::P * F::PLANE_A;               // [P][(W0-2)^2][CS]
+  double* red = (double*)(bufB + F::P * F::PLANE_B);     // [4]
+  float* ut = (float*)(red + 4);                         // [WU][WU]
+  float* sw0 = ut + F::WU * F::WU;                       // [C][9]
+  float* sb0 = sw0 + C * 9;                              // [C]
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int tpr = n / F::T, m = n - 1;
+  const int64_t tiles = nfields * tpr * tpr;
+
+  bf16x8 wfr[NH][F::KB][F::NB];
+  float bias[NH][F::NB][4];
+#pragma unroll
+  for (int h = 0; h < NH; ++h)
+#pragma unroll
+    for (int nb = 0; nb < F::NB; ++nb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bias[h][nb][i] = bh[h * C + nb * 16 + 4 * g + i];
+#pragma unroll
+      for (int kb = 0; kb < F::KB; ++kb)
+        wfr[h][kb][nb] = *(const bf16x8*)&Wp[((int64_t)h * C + nb * 16 + r) * F::KP + kb * 32 + 8 * g];
+    }
+  for (int i = tid; i < C * 9; i += F::NT) sw0[i] = W0g[i];
+  for (int i = tid; i < C; i += F::NT) sb0[i] = b0g[i];
+
+  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int64_t f = t / (tpr * tpr);
+    const int tt = (int)(t % (tpr * tpr));
+    const int y0 = (tt / tpr) * F::T, x0 = (tt % tpr) * F::T;
+    const double* u = u_base + (u_offs ? u_offs[f] : f * (int64_t)n * n);
+    __syncthreads();  // the previous tile is no longer read
+    constexpr int HU = NH + 2;
+    for (int i = tid; i < F::WU * F::WU; i += F::NT) {
+      const int ty = i / F::WU, tx = i % F::WU;
+      ut[i] = (float)u[(int64_t)((y0 + ty - HU) & m) * n + ((x0 + tx - HU) & m)];
+    }
+    __syncthreads();
+    // layer 0: 1 -> C on the W0 x W0 region, 8 channels per item
+    {
+      constexpr int C8 = C / 8, ITEMS = F::W0 * F::W0 * C8;
+      for (int item = tid; item < ITEMS; item += F::NT) {
+        const int c8 = item % C8, p = item / C8;
+        const int py = p / F::W0, px = p % F::W0;
+        float v[9];
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp) v[tp] = ut[(py + tp / 3) * F::WU + px + tp % 3];
+        bf16x8 hv, lv;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int co = c8 * 8 + j;
+          float s = sb0[co];
+#pragma unroll
+          for (int tp = 0; tp < 9; ++tp) s += sw0[co * 9 + tp] * v[tp];
+          const float a = act_fn(s, act);
+          hv[j] = (__bf16)a;
+          lv[j] = (__bf16)(a - (float)hv[j]);
+        }
+        *(bf16x8*)&bufA[p * F::CS + c8 * 8] = hv;
+        if constexpr (SPLIT) *(bf16x8*)&bufA[F::PLANE_A + p * F::CS + c8 * 8] = lv;
+      }
+    }
+    __syncthreads();
+    // hidden layers: layer h reads A (h even) or B and writes the other
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const __bf16* in = (h & 1) ? bufB : bufA;
+      __bf16* out = (h & 1) ? bufA : bufB;
+      const int in_plane = (h & 1) ? F::PLANE_B : F::PLANE_A;
+      const int out_plane = (h & 1) ? F::PLANE_A : F::PLANE_B;
+      const int Wi = F::W0 - 2 * h, Wo = Wi - 2, npx = Wo * Wo, nblk = (npx + 15) / 16;
+      for (int mb = wave; mb < nblk; mb += F::NW) {
+        const int p = mb * 16 + r, pc = p < npx ? p : npx - 1;
+        const int py = pc / Wo, px = pc % Wo;
+        f32x4 acc[F::NB];
+#pragma unroll
+        for (int nb = 0; nb < F::NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < F::KB; ++kb) {
+          const int k0 = kb * 32 + 8 * g;
+          const bool live = k0 < 9 * C;
+          const int tap = live ? k0 / C : 0, ci0 = live ? k0 % C : 0;
+          const int a = ((py + tap / 3) * Wi + px + tap % 3) * F::CS + ci0;
+          bf16x8 b = *(const bf16x8*)&in[a];
+          if (!live) b = bf16x8{};
+#pragma unroll
+          for (int nb = 0; nb < F::NB; ++nb)
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfr[h][kb][nb], b, acc[nb], 0, 0, 0);
+          if constexpr (SPLIT) {
+            bf16x8 bl = *(const bf16x8*)&in[in_plane + a];
+            if (!live) bl = bf16x8{};
+#pragma unroll
+            for (int nb = 0; nb < F::NB; ++nb)
+              acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfr[h][kb][nb], bl, acc[nb], 0, 0, 0);
+          }
+        }
+        if (p < npx) {
+#pragma unroll
+          for (int nb = 0; nb < F::NB; ++nb) {
+            typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+            bf16x4 hv, lv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float v = act_fn(acc[nb][i] + bias[h][nb][i], act);
+              hv[i] = (__bf16)v;
+              lv[i] = (__bf16)(v - (float)hv[i]);
+            }
+            const int o = p * F::CS + nb * 16 + 4 * g;
+            *(bf16x4*)&out[o] = hv;
+            if constexpr (SPLIT) *(bf16x4*)&out[out_plane + o] = lv;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // last layer: C -> 1 on the tile, residual and mass partials in FP64
+    {
+      const __bf16* in = (NH & 1) ? bufB : bufA;
+      const int plane = (NH & 1) ? F::PLANE_B : F::PLANE_A;
+      constexpr int Wi = F::T + 2;
+      const int py = tid / F::T, px = tid % F::T;
+      float s = bL[0];
+      for (int tp = 0; tp < 9; ++tp) {
+        const int q = (py + tp / 3) * Wi + px + tp % 3;
+#pragma unroll
+        for (int c8 = 0; c8 < C / 8; ++c8) {
+          float x[8];
+          const bf16x8 hv = *(const bf16x8*)&in[q * F::CS + c8 * 8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) x[j] = (float)hv[j];
+          if constexpr (SPLIT) {
+            const bf16x8 lv = *(const bf16x8*)&in[plane + q * F::CS + c8 * 8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) x[j] += (float)lv[j];
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j) s += WL[(c8 * 8 + j) * 9 + tp] * x[j];
+        }
+      }
+      const int64_t gi = (int64_t)(y0 + py) * n + x0 + px;
+      const double uc = u[gi];
+      const double o = residual ? uc + (double)s : (double)s;
+      g_base[(g_offs ? g_offs[f] : f * (int64_t)n * n) + gi] = o;
+      if (partials) {
+        double d = o - uc;
+#pragma unroll
+        for (int sh = 32; sh > 0; sh >>= 1) d += __shfl_xor(d, sh, 64);
+        if (lane == 0) red[wave] = d;
+        __syncthreads();
+        if (tid == 0) partials[t] = ((red[0] + red[1]) + red[2]) + red[3];
+      }
     }
   }
 }
@@ -717,9 +912,116 @@ static void cnn_fwd_ref(const CnnJob& j, bool train, double* g_out, hipStream_t 
                                              j.residual, j.ws.partials);
 }
 
+std::atomic<int> g_cnn_plan{0};          // pr_cnn_plan, process-wide setting
+std::atomic<int> g_cnn_tuned[5][8][2];     // [C index][L - 3][split]: measured choice (0 = none)
+
+static int c_index(int C) { return C == 8 ? 0 : C == 16 ? 1 : C == 32 ? 2 : C == 48 ? 3 : 4; }
+
+template <int C, int NH, bool SPLIT>
+static int fused_cap() {
+  using F = FusedCfg<C, NH, SPLIT>;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cnn_fused<C, NH, SPLIT>, F::NT, F::LDS) !=
+          hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return cus * per_cu;
+}
+
+// The fused kernel for (C, NH, SPLIT), if one is built and fits in LDS.
+template <int C, int NH, bool SPLIT>
+static bool launch_fused_nh(const CnnJob& j, double* g_out, hipStream_t st) {
+  using F = FusedCfg<C, NH, SPLIT>;
+  if constexpr (!F::kFits || C % 16 != 0) {
+    return false;
+  } else {
+    if (j.n % F::T != 0) return false;
+    const int L = j.n_layers;
+    const float* W = (const float*)j.W;
+    const float* B = (const float*)j.B;
+    const int64_t tiles = j.nfields * (int64_t)(j.n / F::T) * (j.n / F::T);
+    static const int cap = fused_cap<C, NH, SPLIT>();
+    const dim3 grid((unsigned)std::min<int64_t>(tiles, cap)), block(F::NT);
+    k_cnn_fused<C, NH, SPLIT><<<grid, block, F::LDS, st>>>(
+        j.in_base, j.in_offs, j.n, j.nfields, W, B, (const __bf16*)j.ws.wpack, B + C,
+        W + cnn_woff(L - 1, L, C), B + cnn_boff(L - 1, C), j.act, j.residual, g_out, j.out_offs,
+        j.ws.partials);
+    return true;
+  }
+}
+
+template <int C, bool SPLIT>
+static bool launch_fused_c(const CnnJob& j, double* g_out, hipStream_t st) {
+  if constexpr (C == 16) {
+    switch (j.n_layers - 2) {
+      case 1: return launch_fused_nh<16, 1, SPLIT>(j, g_out, st);
+      case 2: return launch_fused_nh<16, 2, SPLIT>(j, g_out, st);
+      case 3: return launch_fused_nh<16, 3, SPLIT>(j, g_out, st);
+      case 4: return launch_fused_nh<16, 4, SPLIT>(j, g_out, st);
+      default: return false;
+    }
+  } else if constexpr (C == 32) {
+    switch (j.n_layers - 2) {
+      case 1: return launch_fused_nh<32, 1, SPLIT>(j, g_out, st);
+      case 2: return launch_fused_nh<32, 2, SPLIT>(j, g_out, st);
+      default: return false;
+    }
+  } else if constexpr (C == 48 && !SPLIT) {
+    return j.n_layers == 3 && launch_fused_nh<48, 1, false>(j, g_out, st);
+  } else {
+    return false;
+  }
+}
+
+// Whether a fused kernel exists for this network (inference, bf16 kinds).
+template <int C, bool SPLIT>
+static constexpr bool fused_exists(int nh) {
+  if (C % 16 != 0 || C > 48) return false;
+  switch (nh) {
+    case 1: return (C <= 32 || !SPLIT) && FusedCfg<C, 1, SPLIT>::kFits;
+    case 2: return C <= 32 && FusedCfg<C, 2, SPLIT>::kFits;
+    case 3: return C <= 16 && FusedCfg<C, 3, SPLIT>::kFits;
+    case 4: return C <= 16 && FusedCfg<C, 4, SPLIT>::kFits;
+    default: return false;
+  }
+}
+
+bool cnn_fused_available(int C, int L, int prec) {
+  if (prec != kCnnBf16 && prec != kCnnBf16x2) return false;
+  const bool sp = prec == kCnnBf16x2;
+  switch (C) {
+    case 16: return sp ? fused_exists<16, true>(L - 2) : fused_exists<16, false>(L - 2);
+    case 32: return sp ? fused_exists<32, true>(L - 2) : fused_exists<32, false>(L - 2);
+    case 48: return sp ? fused_exists<48, true>(L - 2) : fused_exists<48, false>(L - 2);
+    default: return false;
+  }
+}
+
+int cnn_effective_plan(int C, int L, int prec) {
+  if (!cnn_fused_available(C, L, prec) || L < 3 || L > 10) return CNN_PLAN_LAYERED;
+  int pl = g_cnn_plan.load();
+  if (pl == CNN_PLAN_AUTO) pl = g_cnn_tuned[c_index(C)][L - 3][prec == kCnnBf16x2 ? 1 : 0].load();
+  // untuned default: layer by layer (measured faster for the 4 x 32 network
+  // at 256^2, where the halo recomputation adds more activation work than
+  // the saved HBM traffic is worth)
+  return pl == CNN_PLAN_FUSED ? CNN_PLAN_FUSED : CNN_PLAN_LAYERED;
+}
+
+void cnn_set_plan(int plan) { g_cnn_plan.store(plan); }
+int cnn_get_plan() { return g_cnn_plan.load(); }
+void cnn_record_tuned(int C, int L, int prec, int plan) {
+  if (L >= 3 && L <= 10) g_cnn_tuned[c_index(C)][L - 3][prec == kCnnBf16x2 ? 1 : 0].store(plan);
+}
+
 template <int C>
 static void cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t st) {
   const int n = j.n, L = j.n_layers;
+  if (!train && cnn_effective_plan(C, L, j.prec) == CNN_PLAN_FUSED) {
+    const bool done = j.prec == kCnnBf16x2 ? launch_fused_c<C, true>(j, g_out, st)
+                                           : launch_fused_c<C, false>(j, g_out, st);
+    if (done) return;
+  }
   const int64_t tiles16 = (int64_t)(n / kTile) * (n / kTile);
   const dim3 g16((unsigned)(j.nfields * tiles16)), b256(256);
   const bool split = j.prec == kCnnBf16x2;
@@ -898,11 +1200,28 @@ size_t cnn_lds_bytes(int C, bool split) {
   }
 }
 
+template <int C, int NH, bool SPLIT>
+static hipError_t fused_lds_limit() {
+  using F = FusedCfg<C, NH, SPLIT>;
+  if constexpr (!F::kFits) {
+    return hipSuccess;
+  } else {
+    return hipFuncSetAttribute((const void*)k_cnn_fused<C, NH, SPLIT>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)F::LDS);
+  }
+}
+
 hipError_t cnn_set_lds_limits() {
   // raise the dynamic-LDS limit of each hidden-layer kernel to what it
   // uses; configurations beyond the 160 KB of a CU are rejected earlier
   constexpr size_t kMaxLds = 160 * 1024;
   hipError_t e = hipSuccess;
+#define PR_F(CC, NH)                                                        \
+  if (e == hipSuccess) e = fused_lds_limit<CC, NH, false>();                \
+  if (e == hipSuccess) e = fused_lds_limit<CC, NH, true>();
+  PR_F(16, 1) PR_F(16, 2) PR_F(16, 3) PR_F(16, 4) PR_F(32, 1) PR_F(32, 2)
+#undef PR_F
+  if (e == hipSuccess) e = fused_lds_limit<48, 1, false>();
 #define PR_A(CC, SP)                                                                         \
   if (e == hipSuccess && cnn_lds_bytes(CC, SP) <= kMaxLds)                                   \
     e = hipFuncSetAttribute((const void*)k_cnn_hidden<CC, SP>,                               \

@@ -156,6 +156,15 @@ struct CnnJob {
   CnnWs ws;
 };
 
+// Inference plan of the network: one layer per launch, or all layers in
+// one fused kernel (bf16 kinds, shapes with a fused instantiation).
+enum { CNN_PLAN_AUTO = 0, CNN_PLAN_LAYERED = 1, CNN_PLAN_FUSED = 2 };
+bool cnn_fused_available(int C, int L, int prec);
+int cnn_effective_plan(int C, int L, int prec);
+void cnn_set_plan(int plan);
+int cnn_get_plan();
+void cnn_record_tuned(int C, int L, int prec, int plan);
+
 hipError_t launch_cnn_pack(const CnnJob& j, hipStream_t st);
 hipError_t launch_cnn(const CnnJob& j, hipStream_t st);
 hipError_t launch_cnn_backward(const CnnJob& j, const double* dG, double* du, void* gW, void* gB,

@@ -151,3 +151,48 @@ def test_parareal_with_cnn_coarse(api):
     _, _, gb = make(api, spec, seed=2, prec="bf16", scale=0.1)
     Ub, _ = api.pr_solve(p, gb, dev(u0), s, tol=0.0)
     assert torch.equal(Ub, U)
+
+
+@pytest.mark.parametrize("L,C,prec,n", [(4, 32, "bf16", 64), (4, 32, "bf16x2", 256),
+                                        (3, 16, "bf16", 32), (6, 16, "bf16x2", 64),
+                                        (3, 48, "bf16", 128), (3, 32, "bf16x2", 64)])
+def test_fused_plan_matches_layered_and_oracle(api, L, C, prec, n):
+    print(f"case fused L={L} C={C} {prec} n={n}", flush=True)
+    spec = cnn.CnnSpec(n_layers=L, channels=C)
+    ws, bs, g = make(api, spec, seed=5 * L + C, prec=prec)
+    u0 = synth.random_ic(n, [21, 22, 23])
+    p = problem(api, n)
+    try:
+        api.pr_set_coarse_plan("fused")
+        assert api.pr_get_coarse_plan(g, n) == "fused"
+        fused = api.pr_coarse_apply(p, g, dev(u0)).cpu().numpy()
+        api.pr_set_coarse_plan("layered")
+        assert api.pr_get_coarse_plan(g, n) == "layered"
+        layered = api.pr_coarse_apply(p, g, dev(u0)).cpu().numpy()
+    finally:
+        api.pr_set_coarse_plan("auto")
+    assert net_rel(fused, layered, u0) <= 1e-6
+    emu = cnn.forward(u0, ws, bs, spec, emulate_bf16=True if prec == "bf16" else "weights")
+    assert net_rel(fused, emu, u0) <= (2e-3 if prec == "bf16" else 2e-4)
+
+
+def test_fused_plan_mass_fix_limiter_and_autotune(api):
+    spec = cnn.CnnSpec(n_layers=4, channels=32, mass_fix=True, limiter=(-0.95, 0.95))
+    ws, bs, g = make(api, spec, seed=31, prec="bf16x2")
+    n = 64
+    u0 = synth.random_ic(n, [24, 25])
+    p = problem(api, n)
+    out = api.pr_coarse_apply(p, g, dev(u0)).cpu().numpy()
+    assert np.abs(out.mean(axis=(1, 2)) - u0.mean(axis=(1, 2))).max() <= 1e-14 or out.min() <= -0.95 \
+        or out.max() >= 0.95
+    assert out.min() >= -0.95 and out.max() <= 0.95
+    spec_nf = cnn.CnnSpec(n_layers=4, channels=32, mass_fix=True)
+    _, _, g2 = make(api, spec_nf, seed=31, prec="bf16x2")
+    o2 = api.pr_coarse_apply(p, g2, dev(u0)).cpu().numpy()
+    assert np.abs(o2.mean(axis=(1, 2)) - u0.mean(axis=(1, 2))).max() <= 1e-14
+    choice = api.pr_autotune_coarse(p, g2, dev(u0))
+    assert choice in ("fused", "layered")
+    assert api.pr_get_coarse_plan(g2, n) == choice
+    # shapes without a fused kernel stay layered
+    _, _, g64 = make(api, cnn.CnnSpec(n_layers=4, channels=64), seed=1, prec="bf16")
+    assert api.pr_get_coarse_plan(g64, n) == "layered"
