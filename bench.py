@@ -44,6 +44,11 @@ CONFIGS = {
 }
 
 
+def note(msg: str) -> None:
+    """Progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def bytes_per_point_step(prec: str, scheme: str = "ssi", picard: int = 1) -> int:
     """Algorithmic HBM bytes per grid point and fine step.
 
@@ -138,6 +143,7 @@ def parareal_vs_serial(api, p, g, u0, s, kmax, target=1e-6):
         return out, best
 
     ref, t_ser64 = timed(lambda: api.pr_serial_fine(p64, u0, s))
+    note(f"serial FP64 fine solve: {t_ser64:.1f} ms")
     ser_same, t_ser = timed(lambda: api.pr_serial_fine(p, u0, s))
     nref = torch.linalg.vector_norm(ref).item()
     rel_same = torch.linalg.vector_norm(ser_same - ref).item() / nref
@@ -148,16 +154,23 @@ def parareal_vs_serial(api, p, g, u0, s, kmax, target=1e-6):
                                                 allow_not_converged=True), reps=1)
         err = torch.linalg.vector_norm(U - ref).item() / nref
         hist.append({"k": k, "rel_l2": float(f"{err:.3e}"), "ms": round(t, 2)})
+        note(f"parareal f32_iters={p.f32_iters} k={k}: rel-L2 {err:.3e} in {t:.1f} ms")
         if err <= target:
             _, t = timed(lambda: api.pr_solve(p, g, u0, s, tol=0.0, max_iter=k,
                                               allow_not_converged=True), reps=3)
-            found = {"k": k, "ms": round(t, 2), "rel_l2": err}
+            # per-slice error against the FP64 serial solve, worst IC
+            d = torch.linalg.vector_norm(U - ref, dim=(-2, -1))
+            r = torch.linalg.vector_norm(ref, dim=(-2, -1))
+            per_slice = (d / r).max(dim=0).values[1:].tolist()
+            found = {"k": k, "ms": round(t, 2), "rel_l2": err,
+                     "per_slice": [float(f"{x:.2e}") for x in per_slice]}
             break
     res = {"target_rel_l2": target, "serial_fp64_ms": round(t_ser64, 2),
            "serial_same_prec_ms": round(t_ser, 2), "serial_same_prec_rel_l2": float(f"{rel_same:.3e}"),
            "history": hist}
     if found:
         res.update({"k": found["k"], "parareal_ms": found["ms"],
+                    "per_slice_rel_l2_max_over_ics": found["per_slice"],
                     "speedup_vs_serial_fp64": round(t_ser64 / found["ms"], 3),
                     "speedup_vs_serial_same_prec": round(t_ser / found["ms"], 3)})
     else:
@@ -240,7 +253,9 @@ def uneven_bench(args):
                 "iterations_max": max(iters), "iterations_mean": round(float(np.mean(iters)), 2),
                 "fine_gpts_per_s": round(fine_pts / best / 1e9, 1),
                 "fine_ms": round(longest.fine_ms, 1), "sweep_ms": round(longest.sweep_ms, 1)}
+    note(f"serial FP64 of 48 jobs: {t_ser * 1e3:.0f} ms")
     plain = run(0, "f64", args.steps)
+    note(f"plain FP64 form: {plain['ms']} ms")
     # G stays FP64: an FP32 coarse step puts ~1e-7 of rounding noise into
     # G(U^k) - G(U^{k-1}), which keeps the sup-norm update from settling
     mixed = {f"f32_iters_{K}": run(K, "f64", args.steps) for K in (1, 2)}
@@ -271,7 +286,7 @@ def calib_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"calib_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16):
+def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32):
     """The workload's network, trained with Adam on fine-solver trajectories
     from seeds 1000.. (bf16 forward, FP32 gradients, 8-step rollouts
     checkpointed every 2), then evaluated in `prec`."""
@@ -283,8 +298,15 @@ def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16):
         t0 = time.perf_counter()
         data = train.make_dataset(p, range(1000, 1000 + n_traj), n_slices)
         t_data = time.perf_counter() - t0
-        log = train.train(net, p, data, steps=steps, batch=32, rollout=8, ckpt=2, lr=1e-3)
+        note(f"training data: {n_traj} trajectories x {n_slices} slices in {t_data:.1f} s")
+
+        def progress(step, loss, ms):
+            if step % 10 == 0 or step == steps:
+                note(f"train step {step}/{steps} loss {loss:.3e} ({ms:.0f} ms)")
+        log = train.train(net, p, data, steps=steps, batch=batch, rollout=8, ckpt=2, lr=1e-3,
+                          progress=progress)
         info = {"steps": steps, "trajectories": n_traj, "slices_per_trajectory": n_slices,
+                "batch": batch,
                 "data_s": round(t_data, 2), "loss_first": log.loss[0], "loss_last": log.loss[-1],
                 "step_ms_median": round(sorted(log.step_ms)[len(log.step_ms) // 2], 2)}
         del data
@@ -370,6 +392,9 @@ def main():
     ap.add_argument("--cnn-prec", default="bf16x2", choices=["bf16", "bf16x2", "f32"])
     ap.add_argument("--train-steps", type=int, default=200,
                     help="Adam steps on fine trajectories before timing (network only)")
+    ap.add_argument("--train-traj", type=int, default=512,
+                    help="fine trajectories (16 slices each) the network is trained on")
+    ap.add_argument("--train-batch", type=int, default=32)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -400,7 +425,8 @@ def main():
     g_num = api.Coarse(dt=cfg["dt"] * c / cfg["g_steps"], steps=cfg["g_steps"], prec="f64")
     train_info = None
     if coarse == "cnn":
-        g, train_info = trained_cnn(api, p, cfg, args.cnn_prec, args.train_steps)
+        g, train_info = trained_cnn(api, p, cfg, args.cnn_prec, args.train_steps,
+                                    n_traj=args.train_traj, batch=args.train_batch)
     else:
         g = g_num
     u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
@@ -411,6 +437,7 @@ def main():
         return api.pr_solve(p, g, u0, s, tol=0.0, max_iter=1, U=U, ws=ws, allow_not_converged=True)
 
     _, st = one()
+    note("first step done")
     import ctypes
     from paper_2510_07672_amd import _lib as L
     need = L.lib().pr_solve_workspace_bytes(ctypes.byref(p.c()), ctypes.byref(g.c()), B, s)

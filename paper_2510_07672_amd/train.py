@@ -56,8 +56,10 @@ class TrainLog:
 
 
 def train(net: api.CnnCoarse, p: api.Problem, data: torch.Tensor, steps: int, batch: int = 32,
-          rollout: int = 8, ckpt: int = 2, lr: float = 1e-3, seed: int = 0) -> TrainLog:
-    """`steps` Adam updates on random (trajectory, start) pairs."""
+          rollout: int = 8, ckpt: int = 2, lr: float = 1e-3, seed: int = 0,
+          progress=None) -> TrainLog:
+    """`steps` Adam updates on random (trajectory, start) pairs; `progress`,
+    if given, is called as progress(step, loss, ms) after every update."""
     R, T1 = data.shape[0], data.shape[1]
     if T1 - 1 < rollout:
         raise ValueError("trajectories shorter than the rollout")
@@ -81,6 +83,8 @@ def train(net: api.CnnCoarse, p: api.Problem, data: torch.Tensor, steps: int, ba
         torch.cuda.synchronize()
         log.step_ms.append((time.perf_counter() - tic) * 1e3)
         log.loss.append(float(loss.item()))
+        if progress is not None:
+            progress(len(log.loss), log.loss[-1], log.step_ms[-1])
     net.W.requires_grad_(False)
     net.B.requires_grad_(False)
     return log
