@@ -93,14 +93,22 @@ __device__ __forceinline__ void dft_r(C* v) {
   else if constexpr (R == 2) dft2<SIGN>(v[0], v[1]);
 }
 
-// Padded line stride for lines of N elements: N + N/8 pad slots, made odd.
+// One pad slot after every 2^PR_PAD_SHIFT elements of a line.
+#ifndef PR_PAD_SHIFT
+#define PR_PAD_SHIFT 3
+#endif
+
+// Padded line stride for lines of N elements: N + N/2^PR_PAD_SHIFT pad
+// slots, made odd.
 template <int N> struct PadLS {
-  static constexpr int value = N + N / 8 + 1;
+  static constexpr int value = N + (N >> PR_PAD_SHIFT) + 1;
 };
 
-// Panel layout: element e of line l at l * LS + e + e / 8.
+// Panel layout: element e of line l at l * LS + e + (e >> PR_PAD_SHIFT).
 template <int LS> struct LinePanel {
-  __device__ __forceinline__ int operator()(int line, int e) const { return line * LS + e + (e >> 3); }
+  __device__ __forceinline__ int operator()(int line, int e) const {
+    return line * LS + e + (e >> PR_PAD_SHIFT);
+  }
 };
 
 // Twiddles.  Stage (Ns, R) needs w^(r k) = exp(-2 pi i r k / (Ns R)) for

@@ -37,6 +37,12 @@
 #include "fft_lds.h"
 #include "internal.h"
 
+// Whether the column passes stage the symbol table in LDS (1) or read it
+// from global memory through the cache (0).
+#ifndef PR_S2_LDS
+#define PR_S2_LDS 1
+#endif
+
 namespace pr {
 
 // ------------------------------------------------------------------ tables
@@ -306,7 +312,11 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   using Lay = LinePanel<LS>;
   __shared__ C panel[CT * LS];
   __shared__ C tw[TwSize<N>::value];
+#if PR_S2_LDS
   __shared__ double s2[N];
+#else
+  const double* s2 = s2_g;
+#endif
   __shared__ double corr_sh;
 
   const int tid = threadIdx.x;
@@ -317,7 +327,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   const Lay lay{};
   C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
   load_stage_twiddles<N, NT>(tw, tw_g, tid);
+#if PR_S2_LDS
   for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
+#endif
   if (tid == 0) {
     double corr = 0.0;
     if (c0 == 0 && sp.conservative) {
@@ -523,7 +535,7 @@ template <int N> struct ResCfg {
   static constexpr int H = N / 2;
   static constexpr int G = N >= 128 ? 2 : 1;     // radix-8 groups per thread
   static constexpr int NT = N * N / (16 * G);    // 8 G complex elements per thread
-  static constexpr int LS = PadLS<N>::value;
+  static constexpr int LS = N + N / 8 + 1;   // SlotAddr pads every 8 rows
   static constexpr int SLOTS = H * LS + H / 8 + 1;
 };
 

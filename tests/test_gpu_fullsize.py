@@ -1,0 +1,113 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times, on outputs the FP64 oracle can compute one by one.
+
+  * config 2: F (200 semi-implicit steps) on all 512 fields of 256^2 in one
+    call, two sampled fields against the oracle, rel-L2 <= 1e-12;
+  * config 3: F (100 steps, conservative) on all 2048 fields of 512^2,
+    sampled fields against the oracle, plus the mass of every field;
+  * the config-2 network (4 x 32, GELU) on the 8-field batch, sampled
+    fields against the oracle (FP32 <= 1e-5; split bf16 <= 2e-4 against
+    the oracle with bf16 hidden weights);
+  * Parareal at config-2 size: after k iterations the first k slices equal
+    the GPU's serial fine solve bit for bit (Section 3.3), for k = 1, 2;
+  * degenerate cases: one slice, no iterations, and a tolerance every
+    first update meets.
+
+Inputs are seeded synthetic fields (the oracle never sees a GPU result).
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import allen_cahn as ac  # noqa: E402
+from oracle import cnn  # noqa: E402
+from paper_2510_07672_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2510_07672_amd import api as A
+    return A
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def oracle_problem(p):
+    return ac.Problem(n=p.n, length=p.length, eps=p.eps, conservative=p.conservative,
+                      stab=p.stab, dt=p.dt, steps=p.steps)
+
+
+@pytest.mark.parametrize("cfg", ["c2", "c3"])
+def test_fine_full_batch_sampled(api, cfg):
+    if cfg == "c2":
+        n, nf, eps, dt, c, cons, samples = 256, 512, 0.01, 2e-5, 200, False, [0, 311]
+    else:
+        n, nf, eps, dt, c, cons, samples = 512, 2048, 0.01, 1e-5, 100, True, [5, 2047]
+    print(f"case full-size F {cfg}", flush=True)
+    p = api.Problem(n=n, length=1.0, eps=eps, conservative=cons, stab=2.0, dt=dt, steps=c)
+    u0 = torch.from_numpy(synth.random_ic(n, range(3000, 3000 + nf))).cuda()
+    out = api.pr_fine_propagate(p, u0)
+    if cons:
+        dm = (out.mean(dim=(1, 2)) - u0.mean(dim=(1, 2))).abs().max().item()
+        assert dm <= 1e-13
+    got = out[samples].cpu().numpy()
+    del out, u0
+    ref = ac.fine(synth.random_ic(n, [3000 + i for i in samples]), oracle_problem(p))
+    for i in range(len(samples)):
+        assert rel(got[i], ref[i]) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x2"])
+def test_network_full_batch_sampled(api, prec):
+    n, B = 256, 8
+    spec = cnn.CnnSpec(n_layers=4, channels=32)
+    ws, bs = cnn.init_weights(spec, seed=0, scale=0.1)
+    g = api.CnnCoarse(ws, bs, prec=prec)
+    p = api.Problem(n=n, length=1.0, eps=0.01, conservative=False, stab=2.0, dt=2e-5, steps=200)
+    u0 = synth.random_ic(n, range(B))
+    out = api.pr_coarse_apply(p, g, torch.from_numpy(u0).cuda()).cpu().numpy()
+    samples = [0, 7]
+    ref = cnn.forward(u0[samples], ws, bs, spec,
+                      emulate_bf16=False if prec == "f32" else "weights")
+    tol = 1e-5 if prec == "f32" else 2e-4
+    for k, i in enumerate(samples):
+        assert rel(out[i] - u0[i], ref[k] - u0[i]) <= tol
+
+
+def test_parareal_prefix_at_config2_size(api):
+    n, B, s = 256, 8, 64
+    p = api.Problem(n=n, length=1.0, eps=0.01, conservative=False, stab=2.0, dt=2e-5, steps=200)
+    g = api.Coarse(dt=4e-3)
+    u0 = torch.from_numpy(synth.random_ic(n, range(B))).cuda()
+    ser = api.pr_serial_fine(p, u0, s)
+    for k in (1, 2):
+        U, st = api.pr_solve(p, g, u0, s, tol=0.0, max_iter=k, allow_not_converged=True)
+        assert st.iterations == k
+        assert torch.equal(U[:, :k + 1], ser[:, :k + 1])
+        del U
+
+
+def test_degenerate_parareal_cases(api):
+    n = 32
+    p = api.Problem(n=n, length=1.0, eps=0.04, conservative=True, stab=2.0, dt=1e-3, steps=10)
+    g = api.Coarse(dt=1e-2)
+    u0 = torch.from_numpy(synth.random_ic(n, [1, 2])).cuda()
+    # one slice: one iteration gives the fine solve exactly
+    U1, st1 = api.pr_solve(p, g, u0, 1, tol=0.0)
+    assert st1.iterations == 1 and torch.equal(U1[:, 1], api.pr_fine_propagate(p, u0))
+    # no iterations: the coarse initial guess, reported as not converged
+    U0, st0 = api.pr_solve(p, g, u0, 4, tol=0.0, max_iter=0, allow_not_converged=True)
+    assert st0.iterations == 0 and st0.status == 6
+    Gs = [u0]
+    for _ in range(4):
+        Gs.append(api.pr_coarse_apply(p, g, Gs[-1].contiguous()))
+    assert torch.equal(U0, torch.stack(Gs, dim=1))
+    # a tolerance every first update meets: one iteration
+    _, stt = api.pr_solve(p, g, u0, 4, tol=1e3)
+    assert stt.iterations == 1 and (stt.ic_iterations == 1).all()
