@@ -383,6 +383,8 @@ def main():
                     help="fine scheme: the semi-implicit step the workloads fix, or the paper's "
                          "Crank-Nicolson + Picard")
     ap.add_argument("--picard", type=int, default=2, help="Picard iterations per CN step")
+    ap.add_argument("--overlap", type=int, default=1,
+                    help="fine-batch chunks overlapped with the sequential sweep (1 = none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--kmax", type=int, default=16)
@@ -409,6 +411,7 @@ def main():
 
     import torch
     from paper_2510_07672_amd import api, synth
+    api.pr_set_overlap(args.overlap)
 
     if args.config == "c4":
         print(json.dumps(training_bench(args)), flush=True)
@@ -480,7 +483,8 @@ def main():
         "config": {"workload": cfg["workload"] + ("" if args.scheme == "ssi" else
                                                   f"; fine scheme CN + {args.picard} Picard iterations"),
                    "n": n, "ics": B, "slices": s, "fine_steps": c,
-                   "fine_solves_per_launch": B * s, "fine_prec": args.prec, "scheme": args.scheme},
+                   "fine_solves_per_launch": B * s, "fine_prec": args.prec, "scheme": args.scheme,
+                   "overlap_chunks": args.overlap},
         "roofline": roof,
     }
     if coarse == "cnn":

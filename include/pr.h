@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 6
+#define PR_ABI_VERSION 7
 
 typedef enum {
   PR_OK = 0,
@@ -356,6 +356,21 @@ int32_t pr_get_coarse_plan(const pr_coarse* g, int32_t n);
 pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nfields,
                              const double* u_in, double* g_out, void* ws, size_t ws_bytes,
                              void* stream, int32_t* chosen);
+
+/* Overlap of the fine solves with the sequential sweep in pr_solve and
+ * pr_solve_many, process-wide.  With chunks > 1 each iteration's fine batch
+ * is split into that many slice ranges, run in order on a second stream
+ * of the library's (default priority), and the sweep on the caller's
+ * stream waits for a range only before the first correction that reads
+ * its results or overwrites its inputs (step j waits for every range that
+ * starts at or before slice j + 1).  The results are the same bits for
+ * any setting; stats.fine_ms then sums the ranges' own spans.  chunks = 1
+ * runs the fine batch, then the sweep, on the caller's stream.  Default 1:
+ * on one GPU a batch that fills HBM bandwidth gains nothing from sharing
+ * the device with the sweep, and splitting it costs launch efficiency.
+ * PR_ERR_INVALID_ARG outside [1, 16]. */
+pr_status pr_set_overlap(int32_t chunks);
+int32_t pr_get_overlap(void);
 
 /* Set the plan for (n, prec).  PR_ERR_UNSUPPORTED for RESIDENT with n > 128. */
 pr_status pr_set_fine_plan(int32_t n, pr_dtype prec, int32_t plan);

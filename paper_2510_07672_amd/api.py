@@ -347,6 +347,15 @@ def pr_autotune_coarse(p: Problem, g: "CnnCoarse", u_in: torch.Tensor) -> str:
     return _CPLAN_NAME[ch.value]
 
 
+def pr_set_overlap(chunks: int) -> None:
+    """Fine-batch chunks overlapped with the sequential sweep (1 = no overlap)."""
+    L.check(L.lib().pr_set_overlap(int(chunks)), "pr_set_overlap")
+
+
+def pr_get_overlap() -> int:
+    return int(L.lib().pr_get_overlap())
+
+
 def pr_set_graphs(enabled: bool) -> None:
     """Replay captured launch sequences (True, default) or launch eagerly."""
     L.lib().pr_set_graphs(int(bool(enabled)))

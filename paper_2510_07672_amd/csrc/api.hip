@@ -138,6 +138,10 @@ StepParams step_params(const pr_problem* p, double dt) {
 // Process-wide plan per (N, precision): PR_PLAN_AUTO falls back to the
 // default rule (resident for N <= 128) unless pr_autotune_fine recorded a
 // measured choice.
+// Chunks of the fine batch that overlap the sequential sweep (1 = none).
+std::atomic<int> g_overlap_chunks{1};
+constexpr int kMaxChunks = 16;
+
 std::atomic<int> g_plan[11][2];     // [log2 N][f32], user setting
 std::atomic<int> g_tuned[11][2];    // [log2 N][f32], autotuner result (0 = none)
 
@@ -294,6 +298,32 @@ hipError_t coarse_run(const pr_problem* p, const pr_coarse* g, const CoarseWs& w
 // outputs); kernels address them as element offsets from two bases, the
 // lowest caller array and the workspace, through tables uploaded once per
 // iteration.
+
+// Second stream and events of the overlapped sweep (default priority).
+struct Overlap {
+  hipStream_t stream = nullptr;
+  hipEvent_t ready = nullptr;
+  hipEvent_t start[kMaxChunks] = {}, end[kMaxChunks] = {};
+  bool init(bool with_stream) {
+    for (auto* e : {&ready})
+      if (hipEventCreate(e) != hipSuccess) return false;
+    for (int c = 0; c < kMaxChunks; ++c)
+      if (hipEventCreate(&start[c]) != hipSuccess || hipEventCreate(&end[c]) != hipSuccess)
+        return false;
+    return !with_stream || hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+  }
+  ~Overlap() {
+    if (stream) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipStreamDestroy(stream);
+    }
+    if (ready) (void)hipEventDestroy(ready);
+    for (int c = 0; c < kMaxChunks; ++c) {
+      if (start[c]) (void)hipEventDestroy(start[c]);
+      if (end[c]) (void)hipEventDestroy(end[c]);
+    }
+  }
+};
 
 struct JobRun {
   pr_job* J = nullptr;
@@ -532,6 +562,10 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
   if (P.total_ics == 0) return PR_OK;
   Events ev;
   if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
+  const int overlap_chunks = std::max(1, std::min(g_overlap_chunks.load(), kMaxChunks));
+  Overlap ovl;
+  if (!ovl.init(overlap_chunks > 1))
+    return fail(PR_ERR_DEVICE, "stream / event creation for the overlapped sweep failed");
 
   // bases: the lowest caller array, and the workspace
   uintptr_t ubase = UINTPTR_MAX;
@@ -670,33 +704,49 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
     if (!any) break;
     T.v64.clear();
     T.v32.clear();
-    // fine solves: per group, every running job's active ICs x window
-    std::vector<Seg> fsegs;
-    for (size_t gi = 0; gi < P.fine.size(); ++gi) {
-      const FineGroup& G = P.fine[gi];
-      std::vector<const JobRun*> mem;
-      for (auto& r : P.jobs)
-        if (!r.done && r.fine_grp[r.f32_at(k) ? 1 : 0] == (int)gi) mem.push_back(&r);
-      if (mem.empty()) continue;
-      Seg sg{(int)gi, G.f32 ? 1 : 0, 0, {}, {}};
-      sg.i64[0] = T.v64.size();
-      for (auto* r : mem)
-        for (int64_t b = 0; b < r->B; ++b)
-          if (r->active[b])
-            for (int q = r->win_at(k); q < r->s; ++q) T.v64.push_back(offU(*r, b, q));
-      sg.i64[1] = T.v64.size();
-      sg.count = (int64_t)(sg.i64[1] - sg.i64[0]);
-      for (auto* r : mem)
-        for (int64_t b = 0; b < r->B; ++b)
-          if (r->active[b])
-            for (int q = r->win_at(k); q < r->s; ++q) T.v64.push_back(offF(*r, b, q, G.f32));
-      sg.i32[0] = T.v32.size();
-      for (auto* r : mem)
-        for (int64_t b = 0; b < r->B; ++b)
-          if (r->active[b])
-            for (int q = r->win_at(k); q < r->s; ++q) T.v32.push_back(r->pfine);
-      if (sg.count > 0) fsegs.push_back(sg);
-    }
+    // The fine batch is split into slice ranges [cb[c], cb[c+1]) that run
+    // on a second stream while the sweep proceeds; the sweep waits for a
+    // chunk before the first correction that needs its results or would
+    // overwrite its inputs.
+    int wmin = smax, send = 0;
+    for (auto& r : P.jobs)
+      if (!r.done) {
+        wmin = std::min(wmin, r.win_at(k));
+        send = std::max(send, r.s);
+      }
+    const int nchunk = std::max(1, std::min({overlap_chunks, send - wmin, kMaxChunks}));
+    std::vector<int> cb(nchunk + 1);
+    for (int c = 0; c <= nchunk; ++c) cb[c] = wmin + (int)((int64_t)(send - wmin) * c / nchunk);
+    // fine solves: per chunk and group, every running job's active ICs x window
+    std::vector<std::vector<Seg>> fsegs(nchunk);
+    for (int c = 0; c < nchunk; ++c)
+      for (size_t gi = 0; gi < P.fine.size(); ++gi) {
+        const FineGroup& G = P.fine[gi];
+        std::vector<const JobRun*> mem;
+        for (auto& r : P.jobs)
+          if (!r.done && r.fine_grp[r.f32_at(k) ? 1 : 0] == (int)gi) mem.push_back(&r);
+        if (mem.empty()) continue;
+        auto q0 = [&](const JobRun* r) { return std::max(r->win_at(k), cb[c]); };
+        auto q1 = [&](const JobRun* r) { return std::min(r->s, cb[c + 1]); };
+        Seg sg{(int)gi, G.f32 ? 1 : 0, 0, {}, {}};
+        sg.i64[0] = T.v64.size();
+        for (auto* r : mem)
+          for (int64_t b = 0; b < r->B; ++b)
+            if (r->active[b])
+              for (int q = q0(r); q < q1(r); ++q) T.v64.push_back(offU(*r, b, q));
+        sg.i64[1] = T.v64.size();
+        sg.count = (int64_t)(sg.i64[1] - sg.i64[0]);
+        for (auto* r : mem)
+          for (int64_t b = 0; b < r->B; ++b)
+            if (r->active[b])
+              for (int q = q0(r); q < q1(r); ++q) T.v64.push_back(offF(*r, b, q, G.f32));
+        sg.i32[0] = T.v32.size();
+        for (auto* r : mem)
+          for (int64_t b = 0; b < r->B; ++b)
+            if (r->active[b])
+              for (int q = q0(r); q < q1(r); ++q) T.v32.push_back(r->pfine);
+        if (sg.count > 0) fsegs[c].push_back(sg);
+      }
     // sweep: step j applies G (per coarse group) and corrects (per N, F precision)
     std::vector<std::vector<Seg>> csteps(smax), ksteps(smax);
     for (int j = 0; j < smax; ++j) {
@@ -749,32 +799,48 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
     pr_status st = upload();
     if (st != PR_OK) return st;
     PR_HIP(launch_fill_u64(P.upd, P.total_ics, 0ull, hs));
-    PR_HIP(hipEventRecord(ev.e[0], hs));
-    for (auto& sg : fsegs) {
-      const FineGroup& G = P.fine[sg.grp];
-      StepJob fj{};
-      fj.n = G.N;
-      fj.f32 = G.f32;
-      fj.steps = G.steps;
-      fj.scheme = G.scheme;
-      fj.picard = G.picard;
-      fj.nfields = sg.count;
-      fj.ws = G.ws;
-      fj.resident = G.scheme == PR_SCHEME_SSI && effective_plan(G.N, G.f32) == PR_PLAN_RESIDENT;
-      fj.in_base = UB;
-      fj.in_offs = P.t64 + sg.i64[0];
-      fj.out_base = WB;
-      fj.out_offs = P.t64 + sg.i64[1];
-      fj.out_f32 = G.f32;
-      fj.params = P.params;
-      fj.pidx = P.t32 + sg.i32[0];
-      PR_HIP(launch_steps(fj, hs));
+    hipStream_t sf = hs;
+    if (nchunk > 1) {
+      sf = ovl.stream;
+      PR_HIP(hipEventRecord(ovl.ready, hs));
+      PR_HIP(hipStreamWaitEvent(sf, ovl.ready, 0));
+    }
+    for (int c = 0; c < nchunk; ++c) {
+      PR_HIP(hipEventRecord(ovl.start[c], sf));
+      for (auto& sg : fsegs[c]) {
+        const FineGroup& G = P.fine[sg.grp];
+        StepJob fj{};
+        fj.n = G.N;
+        fj.f32 = G.f32;
+        fj.steps = G.steps;
+        fj.scheme = G.scheme;
+        fj.picard = G.picard;
+        fj.nfields = sg.count;
+        fj.ws = G.ws;
+        fj.resident = G.scheme == PR_SCHEME_SSI && effective_plan(G.N, G.f32) == PR_PLAN_RESIDENT;
+        fj.in_base = UB;
+        fj.in_offs = P.t64 + sg.i64[0];
+        fj.out_base = WB;
+        fj.out_offs = P.t64 + sg.i64[1];
+        fj.out_f32 = G.f32;
+        fj.params = P.params;
+        fj.pidx = P.t32 + sg.i32[0];
+        PR_HIP(launch_steps(fj, sf));
+      }
+      PR_HIP(hipEventRecord(ovl.end[c], sf));
     }
     PR_HIP(hipEventRecord(ev.e[1], hs));
+    int waited = 0;  // chunks the sweep has waited for
     for (int j = 0; j < smax; ++j) {
       for (auto& sg : csteps[j])
         PR_HIP(run_coarse_group(P.coarse[sg.grp], P, sg.count, UB, P.t64 + sg.i64[0], WB,
                                 P.t64 + sg.i64[1], P.t32 + sg.i32[0], hs));
+      // the correction of step j reads F_j and overwrites U_{j+1}, an input
+      // of the chunk holding slice j + 1
+      while (waited < nchunk && cb[waited] <= j + 1) {
+        if (nchunk > 1) PR_HIP(hipStreamWaitEvent(hs, ovl.end[waited], 0));
+        ++waited;
+      }
       for (auto& sg : ksteps[j]) {
         CorrectJob cj{};
         cj.nfields = sg.count;
@@ -794,10 +860,15 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
         PR_HIP(launch_correct(cj, hs));
       }
     }
+    for (; waited < nchunk; ++waited)
+      if (nchunk > 1) PR_HIP(hipStreamWaitEvent(hs, ovl.end[waited], 0));
     PR_HIP(hipEventRecord(ev.e[2], hs));
     PR_HIP(hipMemcpyAsync(upd_h.data(), P.upd, P.total_ics * 8, hipMemcpyDeviceToHost, hs));
     PR_HIP(hipStreamSynchronize(hs));
-    const double fms = event_ms(ev.e[0], ev.e[1]), sms = event_ms(ev.e[1], ev.e[2]);
+    // fine time: the chunks' own spans; sweep time: from its first launch
+    double fms = 0.0;
+    for (int c = 0; c < nchunk; ++c) fms += event_ms(ovl.start[c], ovl.end[c]);
+    const double sms = event_ms(ev.e[1], ev.e[2]);
     for (int ji = 0; ji < n_jobs; ++ji) {
       JobRun& r = P.jobs[ji];
       if (r.done) continue;
@@ -1125,6 +1196,15 @@ pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nf
   if (chosen) *chosen = best;
   return PR_OK;
 }
+
+pr_status pr_set_overlap(int32_t chunks) {
+  if (chunks < 1 || chunks > kMaxChunks)
+    return fail(PR_ERR_INVALID_ARG, "overlap chunks must be in [1, %d]", kMaxChunks);
+  g_overlap_chunks.store(chunks);
+  return PR_OK;
+}
+
+int32_t pr_get_overlap(void) { return g_overlap_chunks.load(); }
 
 void pr_set_graphs(int32_t enabled) { set_graphs_enabled(enabled != 0); }
 

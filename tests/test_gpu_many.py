@@ -160,3 +160,35 @@ def test_schedule_converges_to_the_fp64_solution(api):
         U, st = api.pr_solve(dataclasses.replace(p, f32_iters=k32), g, dev(u0), 8, tol=1e-10)
         assert (st.ic_iterations > k32).all()
         assert rel(U.cpu().numpy(), ser) <= max(10 * e0, 1e-10)
+
+
+@pytest.mark.parametrize("chunks", [2, 3, 16])
+def test_overlapped_sweep_gives_the_same_bits(api, chunks):
+    """Fine chunks on a second stream overlapped with the sweep: the result
+    of pr_solve and pr_solve_many is the same bits as without overlap."""
+    from oracle import cnn
+    spec = cnn.CnnSpec(n_layers=3, channels=16)
+    ws, bs = cnn.init_weights(spec, seed=4, scale=0.1)
+    net = api.CnnCoarse(ws, bs, prec="bf16x2")
+    p = api.Problem(n=64, length=1.0, eps=0.02, conservative=True, stab=2.0, dt=1e-4, steps=20)
+    u0 = dev(synth.random_ic(64, [50, 51, 52]))
+    jobs = mixed_jobs(api)
+    try:
+        api.pr_set_overlap(1)
+        Ua, sta = api.pr_solve(p, net, u0, 11, tol=1e-9)
+        Ub, stb = api.pr_solve(p, api.Coarse(dt=2e-3), u0, 11, tol=0.0, max_iter=3,
+                               allow_not_converged=True)
+        ref_many = [U.clone() for U, _ in api.pr_solve_many(jobs)]
+        api.pr_set_overlap(chunks)
+        assert api.pr_get_overlap() == chunks
+        Ua2, sta2 = api.pr_solve(p, net, u0, 11, tol=1e-9)
+        Ub2, _ = api.pr_solve(p, api.Coarse(dt=2e-3), u0, 11, tol=0.0, max_iter=3,
+                              allow_not_converged=True)
+        jobs2 = mixed_jobs(api)
+        out2 = api.pr_solve_many(jobs2)
+    finally:
+        api.pr_set_overlap(1)
+    assert torch.equal(Ua, Ua2) and list(sta.ic_iterations) == list(sta2.ic_iterations)
+    assert torch.equal(Ub, Ub2)
+    for r, (U, _) in zip(ref_many, out2):
+        assert torch.equal(r, U)

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 6
+    assert lib.pr_abi_version() == 7
 
 
 def test_library_exports_match_nm(L):
@@ -169,3 +169,12 @@ def test_solve_many_validation(L):
     # a schedule needs no more workspace than FP64 fine solves
     arr = (L.Job * 1)(_job(L, 16 * G, 17 * G, f32_iters=3))
     assert lib.pr_solve_many_workspace_bytes(1, arr) > 0
+
+
+def test_overlap_setting(L):
+    lib = L.lib()
+    old = lib.pr_get_overlap()
+    assert lib.pr_set_overlap(0) == L.PR_ERR_INVALID_ARG
+    assert lib.pr_set_overlap(17) == L.PR_ERR_INVALID_ARG
+    assert lib.pr_set_overlap(3) == L.PR_OK and lib.pr_get_overlap() == 3
+    assert lib.pr_set_overlap(old) == L.PR_OK
