@@ -88,11 +88,12 @@ def measured_traffic(cfg_name, prec, n):
     per = d["per_dispatch"]
     t = "double" if prec == "f64" else "float"
 
-    def biggest(prefix):
-        cands = [(int(k.split("@")[1]), v) for k, v in per.items() if k.split("@")[0] == prefix]
+    def biggest(names):
+        cands = [(int(k.split("@")[1]), v) for k, v in per.items() if k.split("@")[0] in names]
         return max(cands)[1] if cands else None
-    row = biggest(f"pr::k_row<{n}, {t}, 1>")
-    col = biggest(f"pr::k_col<{n}, {t}>")
+    # the middle row pass, with or without its right-hand-side template argument
+    row = biggest({f"pr::k_row<{n}, {t}, 1>", f"pr::k_row<{n}, {t}, 1, 0>"})
+    col = biggest({f"pr::k_col<{n}, {t}>"})
     if row is None or col is None:
         return None
     return (row["fetch_MB"] + row["write_MB"] + col["fetch_MB"] + col["write_MB"]) * 1e6

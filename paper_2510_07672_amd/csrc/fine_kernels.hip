@@ -167,6 +167,16 @@ __device__ __forceinline__ void row_split_store(const cpx<T>* panel, cpx<T>* S, 
   }
 }
 
+// Line stride of the row-pass panel.  The rebuild and split loops put the
+// row pairs of one column in consecutive lanes; with four pairs per tile
+// a stride = 4 (mod 16) makes the 8 lanes served together (4 pairs x 2
+// columns, direct or mirrored) fall in distinct 16-byte bank quads.
+template <int N, typename T> struct RowLS {
+  static constexpr int value = (sizeof(T) == 8 && RowCfg<N, T>::PAIRS == 4 && N >= 128)
+                                   ? N + (N >> PR_PAD_SHIFT) + 4
+                                   : PadLS<N>::value;
+};
+
 // The step parameters of field f: the launch argument, or the field's entry
 // of the descriptor's parameter table.
 __device__ __forceinline__ StepParams field_params(const CallDesc* desc, int64_t f,
@@ -183,7 +193,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
-  constexpr int LS = PadLS<N>::value;
+  constexpr int LS = RowLS<N, T>::value;
   using Lay = LinePanel<LS>;
   __shared__ C panel[PAIRS * LS];
   __shared__ C tw[TwSize<N>::value];
@@ -217,7 +227,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
-  constexpr int LS = PadLS<N>::value;
+  constexpr int LS = RowLS<N, T>::value;
   using Lay = LinePanel<LS>;
   __shared__ C panel[PAIRS * LS];
   __shared__ C tw[TwSize<N>::value];
