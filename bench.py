@@ -287,7 +287,7 @@ def calib_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"calib_copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
-def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32):
+def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32, loss="mse"):
     """The workload's network, trained with Adam on fine-solver trajectories
     from seeds 1000.. (bf16 forward, FP32 gradients, 8-step rollouts
     checkpointed every 2), then evaluated in `prec`."""
@@ -295,7 +295,25 @@ def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32):
     L, C = cfg["cnn"]
     net = train.init_network(L, C, seed=0, prec="bf16")
     info = None
-    if steps > 0:
+    if steps > 0 and loss == "scheme":
+        # Algorithm 1: subsets of `batch` random ICs evolved by G itself, 4
+        # updates per state on the residual of one coarse step
+        import torch
+        from paper_2510_07672_amd import synth
+        dt_g = p.dt * p.steps
+        n_states = max(1, steps // (4 * max(1, n_traj // batch)))
+        u0 = torch.from_numpy(synth.random_ic(p.n, range(1000, 1000 + n_traj))).to("cuda")
+
+        def progress(step, lv, ms):
+            if step % 20 == 0:
+                note(f"scheme-loss update {step} loss {lv:.3e} ({ms:.0f} ms)")
+        log = train.train_scheme(net, p, u0, dt_g, n_steps=n_states, inner=4, subset=batch,
+                                 lr=1e-3, progress=progress)
+        info = {"loss": "scheme residual (eq. loss_ACN), one coarse step", "updates": len(log.loss),
+                "trajectories": n_traj, "states_per_subset": n_states, "batch": batch,
+                "loss_first": log.loss[0], "loss_last": log.loss[-1],
+                "step_ms_median": round(sorted(log.step_ms)[len(log.step_ms) // 2], 2)}
+    elif steps > 0:
         t0 = time.perf_counter()
         data = train.make_dataset(p, range(1000, 1000 + n_traj), n_slices)
         t_data = time.perf_counter() - t0
@@ -398,6 +416,9 @@ def main():
     ap.add_argument("--train-traj", type=int, default=512,
                     help="fine trajectories (16 slices each) the network is trained on")
     ap.add_argument("--train-batch", type=int, default=32)
+    ap.add_argument("--train-loss", default="mse", choices=["mse", "scheme"],
+                    help="mse against fine trajectories, or the scheme-residual loss of "
+                         "Algorithm 1 over one coarse step")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -430,7 +451,8 @@ def main():
     train_info = None
     if coarse == "cnn":
         g, train_info = trained_cnn(api, p, cfg, args.cnn_prec, args.train_steps,
-                                    n_traj=args.train_traj, batch=args.train_batch)
+                                    n_traj=args.train_traj, batch=args.train_batch,
+                                    loss=args.train_loss)
     else:
         g = g_num
     u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
@@ -491,8 +513,10 @@ def main():
     if coarse == "cnn":
         out["coarse_kernel"] = cnn_kernel_rate(api, p, g, u0)
         out["config"]["coarse"] = (f"u + CNN(u), {g.n_layers} conv layers x {g.channels} ch, GELU, "
-                                   f"{g.prec}; " + (f"trained {train_info['steps']} Adam steps on "
-                                   f"{train_info['trajectories']} fine trajectories"
+                                   f"{g.prec}; " + (("trained on the scheme residual"
+                                   if train_info.get("loss") else
+                                   f"trained {train_info['steps']} Adam steps on "
+                                   f"{train_info['trajectories']} fine trajectories")
                                    if train_info else "seed-0 weights, untrained"))
         if train_info:
             out["training"] = train_info

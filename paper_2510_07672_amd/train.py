@@ -1,6 +1,11 @@
-"""Training of the convolutional coarse propagator on trajectories of the
-fine propagator (Section 3.2, Algorithm 1, with the mean-squared loss
-against fine-solver states that the workloads fix).
+"""Training of the convolutional coarse propagator (Section 3.2).
+
+Two losses:
+  * `train`: the mean squared distance to fine-propagator trajectories
+    (the loss the workloads fix), over unrolled checkpointed rollouts;
+  * `train_scheme`: Algorithm 1 with the scheme-based loss eq. loss_ACN,
+    the residual of the Crank-Nicolson scheme (eq. fully-discrete) over one
+    coarse step, which needs no fine-solver data.
 
 Data: R initial conditions, each advanced slice by slice with the FP64
 fine propagator (pr_serial_fine), so targets are U_{t+1} = F(U_t).
@@ -85,6 +90,61 @@ def train(net: api.CnnCoarse, p: api.Problem, data: torch.Tensor, steps: int, ba
         log.loss.append(float(loss.item()))
         if progress is not None:
             progress(len(log.loss), log.loss[-1], log.step_ms[-1])
+    net.W.requires_grad_(False)
+    net.B.requires_grad_(False)
+    return log
+
+
+def scheme_residual(u_n: torch.Tensor, u_np1: torch.Tensor, p: api.Problem, dt: float) -> torch.Tensor:
+    """Pointwise residual of eq. fully-discrete for the pair (U_n, U_{n+1})
+    with step dt and the 5-point Laplacian, the quantity squared in
+    eq. loss_ACN; the nonlocal terms enter as dt/2 (g(U_{n+1}) + g(U_n)),
+    g = grid mean of f, in the conservative model."""
+    h = p.length / p.n
+
+    def lap(v):
+        return (torch.roll(v, 1, -2) + torch.roll(v, -1, -2) + torch.roll(v, 1, -1)
+                + torch.roll(v, -1, -1) - 4.0 * v) / (h * h)
+
+    f1, f0 = u_np1 - u_np1 ** 3, u_n - u_n ** 3
+    r = u_np1 - u_n - 0.5 * dt * (p.eps ** 2 * (lap(u_np1) + lap(u_n)) + f1 + f0)
+    if p.conservative:
+        r = r + 0.5 * dt * (f1.mean(dim=(-2, -1), keepdim=True) + f0.mean(dim=(-2, -1), keepdim=True))
+    return r
+
+
+def train_scheme(net: api.CnnCoarse, p: api.Problem, u0: torch.Tensor, dt: float, n_steps: int,
+                 inner: int = 4, subset: int = 16, lr: float = 1e-3, seed: int = 0,
+                 progress=None) -> TrainLog:
+    """Algorithm 1: the initial conditions u0 [R, N, N] are split at random
+    into subsets of `subset`; for each subset, for n = 0..n_steps-1, take
+    `inner` Adam updates on the mean squared scheme residual of
+    (U_n, G(U_n)) (eq. loss_ACN, step dt), then fix U_{n+1} = G(U_n) and go
+    on.  `progress(update, loss, ms)` is called after every update."""
+    net.W.requires_grad_(True)
+    net.B.requires_grad_(True)
+    opt = torch.optim.Adam([net.W, net.B], lr=lr)
+    gen = torch.Generator().manual_seed(seed)
+    order = torch.randperm(u0.shape[0], generator=gen)
+    log = TrainLog()
+    for s0 in range(0, u0.shape[0], subset):
+        U = u0[order[s0:s0 + subset].to(u0.device)].contiguous()
+        for _ in range(n_steps):
+            for _ in range(inner):
+                torch.cuda.synchronize()
+                tic = time.perf_counter()
+                out = autograd.cnn_apply(net, p, U)
+                loss = (scheme_residual(U, out, p, dt) ** 2).mean()
+                opt.zero_grad(set_to_none=True)
+                loss.backward()
+                opt.step()
+                torch.cuda.synchronize()
+                log.step_ms.append((time.perf_counter() - tic) * 1e3)
+                log.loss.append(float(loss.item()))
+                if progress is not None:
+                    progress(len(log.loss), log.loss[-1], log.step_ms[-1])
+            with torch.no_grad():
+                U = api.pr_coarse_apply(p, net, U)
     net.W.requires_grad_(False)
     net.B.requires_grad_(False)
     return log

@@ -161,3 +161,25 @@ def test_training_reduces_loss_and_coarse_error(mods):
     assert np.isfinite(log.loss).all()
     assert np.mean(log.loss[-5:]) < 0.3 * np.mean(log.loss[:5])
     assert after < 0.5 * before
+
+
+def test_scheme_loss_training_lowers_the_residual(mods):
+    """Algorithm 1 with the scheme-based loss (eq. loss_ACN): the residual
+    of G's step on unseen initial conditions falls."""
+    from paper_2510_07672_amd import train
+    api, _ = mods
+    n, dt = 64, 2e-3
+    p = api.Problem(n=n, length=1.0, eps=0.02, conservative=True, stab=2.0, dt=1e-4, steps=20)
+    net = train.init_network(3, 16, seed=0, prec="f32")
+    u_test = torch.from_numpy(synth.random_ic(n, [900, 901])).cuda()
+
+    def resid():
+        with torch.no_grad():
+            out = api.pr_coarse_apply(p, net, u_test)
+            return float((train.scheme_residual(u_test, out, p, dt) ** 2).mean())
+    before = resid()
+    u0 = torch.from_numpy(synth.random_ic(n, range(200, 232))).cuda()
+    log = train.train_scheme(net, p, u0, dt, n_steps=6, inner=4, subset=16, lr=2e-3)
+    after = resid()
+    assert np.isfinite(log.loss).all() and len(log.loss) == 2 * 6 * 4
+    assert after < 0.3 * before

@@ -150,3 +150,21 @@ def test_pins_catch_sign_of_f(monkeypatch):
     monkeypatch.setattr(ac, "f_double_well", lambda u: -(u - u ** 3))
     with pytest.raises(AssertionError):
         test_small_mode_cn_factor(False, "fd")
+
+
+@pytest.mark.parametrize("cons", [False, True])
+def test_training_scheme_residual_matches_the_cn_scheme(cons):
+    """The training loss of eq. loss_ACN vanishes on the oracle's converged
+    Crank-Nicolson step and equals the oracle's residual on any pair."""
+    import torch
+    from paper_2510_07672_amd import api, train
+    n, dt = 32, 4e-3
+    po = prob(n=n, cons=cons, dt=dt, eps=0.03)
+    pa = api.Problem(n=n, length=1.0, eps=0.03, conservative=cons, stab=0.0, dt=dt, steps=1)
+    u = synth.random_ic(n, [11, 12])
+    v = ac.cn_picard_step(u, po, dt, iters=30)
+    r = train.scheme_residual(torch.from_numpy(u), torch.from_numpy(v), pa, dt).numpy()
+    assert np.abs(r).max() <= 2e-13
+    w = synth.random_ic(n, [13, 14])
+    r2 = train.scheme_residual(torch.from_numpy(u), torch.from_numpy(w), pa, dt).numpy()
+    assert np.abs(r2 - ac.cn_residual(u, w, po, dt)).max() <= 1e-12
