@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 7
+#define PR_ABI_VERSION 8
 
 typedef enum {
   PR_OK = 0,
@@ -356,6 +356,19 @@ int32_t pr_get_coarse_plan(const pr_coarse* g, int32_t n);
 pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nfields,
                              const double* u_in, double* g_out, void* ws, size_t ws_bytes,
                              void* stream, int32_t* chosen);
+
+/* Working-set budget of streaming fine propagation, process-wide: a call
+ * with more fields than fit runs them in consecutive chunks whose spectra
+ * (N*N words per field, twice for PR_SCHEME_CN) total at most `bytes`,
+ * each chunk through all of its steps, so that the data of the two passes
+ * of a step stays in the GPU's last-level cache (MI355X: 256 MB).  The
+ * results do not depend on it.  0 turns chunking off; the default is
+ * 256 MiB.  pr_autotune_fine also times {off, 256 MiB, 128 MiB} on its
+ * batch and keeps the fastest for that (N, precision).
+ * pr_get_fine_working_set returns the budget in effect for (n, prec), or
+ * -1 for an unsupported pair. */
+pr_status pr_set_fine_working_set(int64_t bytes);
+int64_t pr_get_fine_working_set(int32_t n, pr_dtype prec);
 
 /* Overlap of the fine solves with the sequential sweep in pr_solve and
  * pr_solve_many, process-wide.  With chunks > 1 each iteration's fine batch

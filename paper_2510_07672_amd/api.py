@@ -347,6 +347,15 @@ def pr_autotune_coarse(p: Problem, g: "CnnCoarse", u_in: torch.Tensor) -> str:
     return _CPLAN_NAME[ch.value]
 
 
+def pr_set_fine_working_set(nbytes: int) -> None:
+    """Budget (bytes of spectra in flight) of chunked streaming F calls; 0 = off."""
+    L.check(L.lib().pr_set_fine_working_set(int(nbytes)), "pr_set_fine_working_set")
+
+
+def pr_get_fine_working_set(n: int, prec: str) -> int:
+    return int(L.lib().pr_get_fine_working_set(n, _PREC[prec]))
+
+
 def pr_set_overlap(chunks: int) -> None:
     """Fine-batch chunks overlapped with the sequential sweep (1 = no overlap)."""
     L.check(L.lib().pr_set_overlap(int(chunks)), "pr_set_overlap")

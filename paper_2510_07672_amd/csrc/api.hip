@@ -1197,6 +1197,17 @@ pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nf
   return PR_OK;
 }
 
+pr_status pr_set_fine_working_set(int64_t bytes) {
+  if (bytes < 0) return fail(PR_ERR_INVALID_ARG, "working-set budget must be >= 0");
+  set_working_set(bytes);
+  return PR_OK;
+}
+
+int64_t pr_get_fine_working_set(int32_t n, pr_dtype prec) {
+  if (!is_pow2(n) || n < 16 || n > 1024 || (prec != PR_F64 && prec != PR_F32)) return -1;
+  return working_set(n, prec == PR_F32);
+}
+
 pr_status pr_set_overlap(int32_t chunks) {
   if (chunks < 1 || chunks > kMaxChunks)
     return fail(PR_ERR_INVALID_ARG, "overlap chunks must be in [1, %d]", kMaxChunks);
@@ -1251,6 +1262,35 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
     best = ms[PR_PLAN_RESIDENT] <= ms[PR_PLAN_STREAM] ? PR_PLAN_RESIDENT : PR_PLAN_STREAM;
   }
   if (!is_cn(p)) g_tuned[l][f32 ? 1 : 0].store(best);
+  // working-set budget of the streaming plan: all fields at once, or
+  // chunks whose spectra fit 256 / 128 MiB, timed on this batch
+  if (best == PR_PLAN_STREAM || is_cn(p)) {
+    Events ev;
+    if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
+    PR_HIP(launch_tables(p->n, p->laplacian, w, s));
+    const int64_t budgets[3] = {0, 256ll << 20, 128ll << 20};
+    float bms = 0.f;
+    int64_t bbest = -1;
+    for (int64_t b : budgets) {
+      StepJob j = make_job(p, p->dt, p->steps, f32, nfields, w);
+      j.resident = false;
+      j.ws_override = b;
+      j.in_base = u_in;
+      j.out_base = u_out;
+      j.out_f32 = 0;
+      PR_HIP(launch_steps(j, s));  // warm-up
+      PR_HIP(hipEventRecord(ev.e[0], s));
+      PR_HIP(launch_steps(j, s));
+      PR_HIP(hipEventRecord(ev.e[1], s));
+      PR_HIP(hipEventSynchronize(ev.e[1]));
+      const float t = event_ms(ev.e[0], ev.e[1]);
+      if (bbest < 0 || t < bms) {
+        bms = t;
+        bbest = b;
+      }
+    }
+    record_working_set(p->n, f32, bbest);
+  }
   if (chosen) *chosen = best;
   return PR_OK;
 }

@@ -904,9 +904,68 @@ hipError_t launch_tables(int n, int laplacian, const FineWs& ws, hipStream_t st)
   return hipGetLastError();
 }
 
+// ---- working-set chunking
+//
+// A streaming F call moves every field's spectrum through two passes per
+// step.  While the spectra of the fields in flight fit in the GPU's last-
+// level cache (the 256 MB MALL of an MI355X), much of each pass's input is
+// still cached from the previous pass; measured at 512^2 in FP64, 128
+// fields per call (268 MB of spectra) run at 5.5 TB/s and 512 at 4.4.  So
+// a call with more fields runs them in consecutive chunks whose spectra
+// fit the working-set budget, each chunk through all of its steps.  The
+// fields' arithmetic does not depend on the chunking.
+
+static std::atomic<int64_t> g_ws_budget{256ll << 20};   // bytes; 0 = no chunking
+static std::atomic<int64_t> g_ws_tuned[11][2];           // per (log2 N, f32): -1 none
+
+static int log2n(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+void set_working_set(int64_t bytes) { g_ws_budget.store(bytes); }
+
+int64_t working_set(int n, bool f32) {
+  const int l = log2n(n);
+  if (l >= 0 && l <= 10) {
+    const int64_t t = g_ws_tuned[l][f32 ? 1 : 0].load();
+    if (t > 0) return t == 1 ? 0 : t;   // 1 records "no chunking"
+  }
+  return g_ws_budget.load();
+}
+
+void record_working_set(int n, bool f32, int64_t bytes) {
+  const int l = log2n(n);
+  if (l >= 0 && l <= 10) g_ws_tuned[l][f32 ? 1 : 0].store(bytes == 0 ? 1 : bytes);
+}
+
+int64_t chunk_fields(const StepJob& job) {
+  if (job.resident && job.scheme == SCHEME_SSI) return job.nfields;   // nothing streams
+  const int64_t budget = job.ws_override >= 0 ? job.ws_override : working_set(job.n, job.f32);
+  if (budget <= 0) return job.nfields;
+  const int64_t per = (int64_t)job.n * job.n * (job.f32 ? 4 : 8) * (job.scheme == SCHEME_CN ? 2 : 1);
+  return std::max<int64_t>(1, std::min<int64_t>(job.nfields, budget / per));
+}
+
 hipError_t launch_steps(const StepJob& job, hipStream_t st) {
   if (job.nfields <= 0 || job.steps <= 0) return hipSuccess;
-  return job.f32 ? launch_steps_t<float>(job, st) : launch_steps_t<double>(job, st);
+  const int64_t chunk = chunk_fields(job);
+  const int64_t n2 = (int64_t)job.n * job.n;
+  for (int64_t c0 = 0; c0 < job.nfields; c0 += chunk) {
+    StepJob sub = job;
+    sub.nfields = std::min(chunk, job.nfields - c0);
+    if (c0 > 0) {
+      if (job.in_offs) sub.in_offs = job.in_offs + c0;
+      else sub.in_base = job.in_base + c0 * n2;
+      if (job.out_offs) sub.out_offs = job.out_offs + c0;
+      else sub.out_base = (char*)job.out_base + c0 * n2 * (job.out_f32 ? 4 : 8);
+      if (job.pidx) sub.pidx = job.pidx + c0;
+    }
+    const hipError_t e = job.f32 ? launch_steps_t<float>(sub, st) : launch_steps_t<double>(sub, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 int row_tiles(int n, bool f32) {

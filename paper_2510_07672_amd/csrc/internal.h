@@ -110,6 +110,7 @@ struct StepJob {
   const StepParams* params;  // device or null: per-field parameters (see CallDesc)
   const int32_t* pidx;       // device or null
   bool resident;             // one block per field, all steps in LDS (N <= 128)
+  int64_t ws_override = -1;  // working-set budget in bytes for this call (-1: the setting)
   FineWs ws;
 };
 
@@ -179,6 +180,13 @@ hipError_t launch_tables(int n, int laplacian, const FineWs& ws, hipStream_t st)
 void set_graphs_enabled(bool on);
 bool graphs_enabled();
 hipError_t launch_steps(const StepJob& job, hipStream_t st);
+// Working-set budget of streaming F calls (bytes of spectra in flight; 0 =
+// all fields at once): the process-wide setting, the effective value for
+// (N, precision) and the autotuner's record.
+void set_working_set(int64_t bytes);
+int64_t working_set(int n, bool f32);
+void record_working_set(int n, bool f32, int64_t bytes);
+int64_t chunk_fields(const StepJob& job);
 hipError_t launch_correct(const CorrectJob& job, hipStream_t st);
 hipError_t launch_copy(int64_t nfields, int n, const double* src, const int64_t* s_offs,
                        double* dst, const int64_t* d_offs, hipStream_t st);

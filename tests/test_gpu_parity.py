@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def api():
     from paper_2510_07672_amd import api as A
-    assert A.pr_abi_version() == 7
+    assert A.pr_abi_version() == 8
     return A
 
 
@@ -388,3 +388,28 @@ def test_graph_solve_matches_eager_solve(graphs):
     Se = api.pr_serial_fine(p, u0, 5)
     api.pr_set_graphs(True)
     assert torch.equal(api.pr_serial_fine(p, u0, 5), Se)
+
+
+@pytest.mark.parametrize("budget_fields", [0, 1, 3, 7])
+def test_working_set_chunking_gives_the_same_bits(api, budget_fields):
+    """Streaming F in chunks sized by the working-set budget (here a few
+    fields of 256^2 per chunk, or off) gives the same bits as one call."""
+    n = 256
+    p = api.Problem(n=n, length=1.0, eps=0.01, conservative=True, stab=2.0, dt=2e-5, steps=4)
+    pc = api.Problem(n=n, length=1.0, eps=0.01, conservative=True, stab=0.0, dt=2e-5, steps=3,
+                     scheme="cn", picard=2)
+    u0 = dev(synth.random_ic(n, range(10)))
+    try:
+        api.pr_set_fine_working_set(0)
+        ref = api.pr_fine_propagate(p, u0)
+        refc = api.pr_fine_propagate(pc, u0)
+        refs, _ = api.pr_solve(p, api.Coarse(dt=8e-5), u0[:4].contiguous(), 5, tol=0.0, max_iter=2,
+                               allow_not_converged=True)
+        api.pr_set_fine_working_set(budget_fields * n * n * 8)
+        assert torch.equal(api.pr_fine_propagate(p, u0), ref)
+        assert torch.equal(api.pr_fine_propagate(pc, u0), refc)
+        U, _ = api.pr_solve(p, api.Coarse(dt=8e-5), u0[:4].contiguous(), 5, tol=0.0, max_iter=2,
+                            allow_not_converged=True)
+        assert torch.equal(U, refs)
+    finally:
+        api.pr_set_fine_working_set(256 << 20)

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 7
+    assert lib.pr_abi_version() == 8
 
 
 def test_library_exports_match_nm(L):
@@ -178,3 +178,14 @@ def test_overlap_setting(L):
     assert lib.pr_set_overlap(17) == L.PR_ERR_INVALID_ARG
     assert lib.pr_set_overlap(3) == L.PR_OK and lib.pr_get_overlap() == 3
     assert lib.pr_set_overlap(old) == L.PR_OK
+
+
+def test_working_set_setting(L):
+    import ctypes as C
+    lib = L.lib()
+    assert lib.pr_get_fine_working_set(512, L.PR_F64) == 256 << 20
+    assert lib.pr_get_fine_working_set(500, L.PR_F64) == -1
+    assert lib.pr_set_fine_working_set(-1) == L.PR_ERR_INVALID_ARG
+    assert lib.pr_set_fine_working_set(0) == L.PR_OK
+    assert lib.pr_get_fine_working_set(256, L.PR_F32) == 0
+    assert lib.pr_set_fine_working_set(256 << 20) == L.PR_OK
