@@ -383,6 +383,7 @@ struct SolvePlan {
   std::vector<FineGroup> fine;
   std::vector<CoarseGroup> coarse;
   StepParams* params = nullptr;         // [2 n_jobs]
+  std::vector<StepParams> hparams;      // host copy
   unsigned long long* upd = nullptr;    // [sum B]
   int64_t* t64 = nullptr;               // index tables
   int32_t* t32 = nullptr;
@@ -497,11 +498,28 @@ struct Seg {
   int64_t count;
   size_t i64[6];    // table starts (element index into t64)
   size_t i32[2];
+  int uni = -1;     // step launches: the parameter entry all fields share, or -1
 };
+
+bool same_params(const StepParams& a, const StepParams& b) {
+  return a.a == b.a && a.dt == b.dt && a.lam == b.lam && a.inv_n2 == b.inv_n2 &&
+         a.conservative == b.conservative;
+}
+
+// The parameter entry shared by every field of a launch, or -1: a shared
+// one goes in as the launch argument, so that the blocks need not load
+// their own before the first transform.
+template <class Idx>
+int shared_entry(const std::vector<StepParams>& hp, const std::vector<Idx>& idx) {
+  if (idx.empty()) return -1;
+  for (const Idx& i : idx)
+    if (!same_params(hp[i], hp[idx[0]])) return -1;
+  return (int)idx[0];
+}
 
 hipError_t run_coarse_group(const CoarseGroup& G, const SolvePlan& P, int64_t nfields,
                             const double* in_base, const int64_t* in_offs, double* out_base,
-                            const int64_t* out_offs, const int32_t* pidx, hipStream_t s) {
+                            const int64_t* out_offs, const int32_t* pidx, int uni, hipStream_t s) {
   if (G.g->kind == PR_G_CNN) return coarse_run(G.p, G.g, G.ws, nfields, in_base, in_offs, out_base, out_offs, s);
   StepJob j = make_job(G.p, G.g->dt, G.g->steps, G.g->prec == PR_F32, nfields, G.ws.fine);
   j.in_base = in_base;
@@ -509,8 +527,12 @@ hipError_t run_coarse_group(const CoarseGroup& G, const SolvePlan& P, int64_t nf
   j.out_base = out_base;
   j.out_offs = out_offs;
   j.out_f32 = 0;
-  j.params = P.params;
-  j.pidx = pidx;
+  if (uni >= 0) {
+    j.sp = P.hparams[uni];
+  } else {
+    j.params = P.params;
+    j.pidx = pidx;
+  }
   return launch_steps(j, s);
 }
 
@@ -592,7 +614,8 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
 
   // set-up: parameter table, twiddles, packed weights
   {
-    std::vector<StepParams> prm(2 * n_jobs);
+    std::vector<StepParams>& prm = P.hparams;
+    prm.assign(2 * n_jobs, StepParams{});
     for (int i = 0; i < n_jobs; ++i) {
       prm[2 * i] = step_params(&jobs[i].problem, jobs[i].problem.dt);
       prm[2 * i + 1] = step_params(&jobs[i].problem, jobs[i].coarse.kind == PR_G_SCHEME ? jobs[i].coarse.dt : jobs[i].problem.dt);
@@ -670,6 +693,11 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
         for (auto& m : mem) T.v64.push_back(offGC(*m.first, m.second, j));
         sg.i32[0] = T.v32.size();
         for (auto& m : mem) T.v32.push_back(m.first->pcoarse);
+        {
+          std::vector<int> idx;
+          for (auto& m : mem) idx.push_back(m.first->pcoarse);
+          sg.uni = shared_entry(P.hparams, idx);
+        }
         csteps[j].push_back(sg);
         Seg cp{P.coarse[gi].p->n, 0, sg.count, {}, {}};
         cp.i64[0] = sg.i64[1];
@@ -683,7 +711,7 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
     for (int j = 0; j < smax; ++j) {
       for (auto& sg : csteps[j])
         PR_HIP(run_coarse_group(P.coarse[sg.grp], P, sg.count, UB, P.t64 + sg.i64[0], WB,
-                                P.t64 + sg.i64[1], P.t32 + sg.i32[0], hs));
+                                P.t64 + sg.i64[1], P.t32 + sg.i32[0], sg.uni, hs));
       for (auto& cp : ksteps[j])
         PR_HIP(launch_copy(cp.count, cp.grp, WB, P.t64 + cp.i64[0], UB, P.t64 + cp.i64[1], hs));
     }
@@ -745,6 +773,11 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
           for (int64_t b = 0; b < r->B; ++b)
             if (r->active[b])
               for (int q = q0(r); q < q1(r); ++q) T.v32.push_back(r->pfine);
+        {
+          std::vector<int> idx;
+          for (auto* r : mem) idx.push_back(r->pfine);
+          sg.uni = shared_entry(P.hparams, idx);
+        }
         if (sg.count > 0) fsegs[c].push_back(sg);
       }
     // sweep: step j applies G (per coarse group) and corrects (per N, F precision)
@@ -769,6 +802,11 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
         }
         sg.i32[0] = T.v32.size();
         for (auto& m : mem) T.v32.push_back(m.first->pcoarse);
+        {
+          std::vector<int> idx;
+          for (auto& m : mem) idx.push_back(m.first->pcoarse);
+          sg.uni = shared_entry(P.hparams, idx);
+        }
         csteps[j].push_back(sg);
       }
       // corrections grouped by (N, F precision)
@@ -823,8 +861,12 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
         fj.out_base = WB;
         fj.out_offs = P.t64 + sg.i64[1];
         fj.out_f32 = G.f32;
-        fj.params = P.params;
-        fj.pidx = P.t32 + sg.i32[0];
+        if (sg.uni >= 0) {
+          fj.sp = P.hparams[sg.uni];
+        } else {
+          fj.params = P.params;
+          fj.pidx = P.t32 + sg.i32[0];
+        }
         PR_HIP(launch_steps(fj, sf));
       }
       PR_HIP(hipEventRecord(ovl.end[c], sf));
@@ -834,7 +876,7 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
     for (int j = 0; j < smax; ++j) {
       for (auto& sg : csteps[j])
         PR_HIP(run_coarse_group(P.coarse[sg.grp], P, sg.count, UB, P.t64 + sg.i64[0], WB,
-                                P.t64 + sg.i64[1], P.t32 + sg.i32[0], hs));
+                                P.t64 + sg.i64[1], P.t32 + sg.i32[0], sg.uni, hs));
       // the correction of step j reads F_j and overwrites U_{j+1}, an input
       // of the chunk holding slice j + 1
       while (waited < nchunk && cb[waited] <= j + 1) {
