@@ -40,7 +40,7 @@
 // Whether the column passes stage the symbol table in LDS (1) or read it
 // from global memory through the cache (0).
 #ifndef PR_S2_LDS
-#define PR_S2_LDS 1
+#define PR_S2_LDS 0
 #endif
 
 namespace pr {

@@ -24,6 +24,9 @@ enum { RHS_SSI = 0, RHS_F = 1, RHS_U = 2 };
 #ifndef PR_ROW_RUN_BYTES
 #define PR_ROW_RUN_BYTES 128   // contiguous bytes per spectral column in a row tile
 #endif
+#ifndef PR_ROW_PANEL_BYTES
+#define PR_ROW_PANEL_BYTES 40960   // cap on the row tile's LDS panel (bytes)
+#endif
 #ifndef PR_COL_THREADS
 #define PR_COL_THREADS 256     // threads of a column-pass block (N <= 2048 / CT)
 #endif
@@ -38,7 +41,7 @@ template <int N, typename T> struct RowCfg {
   static constexpr int kThreads = 4096 / N;                                   // >= 256 threads
   static constexpr int kCoalesce = PR_ROW_RUN_BYTES / (2 * (int)sizeof(T));  // run length
   static constexpr int kMaxThreads = 16384 / N;                               // <= 1024 threads
-  static constexpr int kMaxLds = 2 * (120 * 1024 / ((N + N / 8 + 1) * 2 * (int)sizeof(T)));
+  static constexpr int kMaxLds = 2 * (PR_ROW_PANEL_BYTES / ((N + N / 8 + 1) * 2 * (int)sizeof(T)));
   static constexpr int kT0 = kThreads > kCoalesce ? kThreads : kCoalesce;
   static constexpr int kT1 = kT0 < kMaxThreads ? kT0 : kMaxThreads;
   static constexpr int kT2 = pow2_floor(kT1 < kMaxLds ? kT1 : kMaxLds);
