@@ -192,3 +192,32 @@ def test_overlapped_sweep_gives_the_same_bits(api, chunks):
     assert torch.equal(Ub, Ub2)
     for r, (U, _) in zip(ref_many, out2):
         assert torch.equal(r, U)
+
+
+def test_many_combined_features_bitwise(api):
+    """A batch mixing both schemes, both Laplacians, numerical and network
+    coarse propagators, a precision schedule and a small working-set budget
+    (so fine calls run in several chunks) gives each job its own bits."""
+    from oracle import cnn
+    spec = cnn.CnnSpec(n_layers=3, channels=16)
+    ws, bs = cnn.init_weights(spec, seed=6, scale=0.1)
+    net = api.CnnCoarse(ws, bs, prec="bf16x2")
+    n = 64
+    ps = [api.Problem(n=n, length=1.0, eps=0.02, conservative=True, stab=2.0, dt=1e-4, steps=10,
+                      f32_iters=1),
+          api.Problem(n=n, length=1.0, eps=0.03, conservative=False, stab=0.0, dt=1e-4, steps=10,
+                      scheme="cn", picard=2, laplacian="spectral"),
+          api.Problem(n=128, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4, steps=10)]
+    gs = [net, api.Coarse(dt=1e-3), net]
+    seeds = [[60, 61], [62], [63, 64]]
+    try:
+        api.pr_set_fine_working_set(3 * n * n * 8)
+        jobs = [api.Job(p, g, dev(synth.random_ic(p.n, sd)), 6, 1e-9)
+                for p, g, sd in zip(ps, gs, seeds)]
+        out = api.pr_solve_many(jobs)
+        for j, (U, st) in zip(jobs, out):
+            U1, st1 = api.pr_solve(j.problem, j.coarse, j.u0, j.n_slices, tol=j.tol)
+            assert torch.equal(U, U1)
+            assert list(st.ic_iterations) == list(st1.ic_iterations)
+    finally:
+        api.pr_set_fine_working_set(256 << 20)
