@@ -17,8 +17,10 @@
 //                 twice (hi W + lo W), which keeps ~16 mantissa bits.
 //   k_cnn_hidden_f32  the same layer on the vector ALU in FP32 (reference
 //                 precision).
-//   k_cnn_last    C -> 1 on the vector ALU, plus the residual, written in
-//                 FP64, with per-tile FP64 sums of (G(u) - u).
+//   k_cnn_last_mma  C -> 1 on the matrix cores with the nine taps as the N
+//                 dimension, then a 3x3 gather of the per-tap products;
+//                 plus the residual, written in FP64, with per-tile FP64
+//                 sums of (G(u) - u).
 //   k_cnn_fix     the uniform mass fix and the limiter.
 #include <hip/hip_runtime.h>
 
@@ -274,6 +276,136 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
   }
 }
 
+// ------------------------------------------------------ last layer on MFMA
+//
+// C -> 1 as a GEMM whose N dimension is the nine taps:
+//   Y[q][t] = sum_c a[q][c] W[c][t]   on the (16 + 2)^2 input pixels q,
+//   out[p] = b + sum_t Y[p + (t / 3, t % 3)][t],
+// on the 16x16x32 bf16 MFMA (A = activations, B = weights in columns 0..8).
+// The FP32 weights enter as bfloat16 hi + lo (16 significant bits); split
+// activations add their lo part, so a term costs 2 or 3 products instead
+// of 9 C vector FMAs per pixel.
+
+template <int C> struct LastCfg {
+  static constexpr int T = 16, WI = T + 2, PX = WI * WI;
+  static constexpr int KB = (C + 31) / 32;   // 32-channel steps
+};
+
+// Lane (g, r) holds W[c = 32 kb + 8 g + j][tap r], j < 8, as hi and lo
+// (zero beyond C channels or nine taps).
+template <int C>
+__device__ __forceinline__ void last_weights(const float* __restrict__ W, int lane,
+                                             bf16x8* hi, bf16x8* lo) {
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int kb = 0; kb < LastCfg<C>::KB; ++kb) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = kb * 32 + 8 * g + j;
+      const float v = (c < C && r < 9) ? W[c * 9 + r] : 0.f;
+      const __bf16 h = (__bf16)v;
+      hi[kb][j] = h;
+      lo[kb][j] = (__bf16)(v - (float)h);
+    }
+  }
+}
+
+// Y for the input region in LDS (pixel stride CS; lo plane at a + plane
+// with SPLIT), then the sum over taps for output pixel tid (< 256),
+// without the bias.  Four waves of 64 lanes.  Y is LDS scratch of PX * 9
+// floats and may alias the region: the products stay in registers until
+// every wave has read its operands.  The region must be complete on
+// entry; the function synchronises between its phases.
+template <int C, bool SPLIT, int CS>
+__device__ __forceinline__ float last_layer_mfma(const __bf16* a, int plane, float* Y,
+                                                 const bf16x8* whi, const bf16x8* wlo, int tid) {
+  using L = LastCfg<C>;
+  constexpr int NBLK = (L::PX + 15) / 16, NW = 4, PER = (NBLK + NW - 1) / NW;
+  const int lane = tid & 63, wave = tid >> 6, r = lane & 15, g = lane >> 4;
+  f32x4 acc[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int mb = wave + NW * i;
+    if (mb < NBLK) {
+      const int p = mb * 16 + r, pc = p < L::PX ? p : L::PX - 1;
+#pragma unroll
+      for (int kb = 0; kb < L::KB; ++kb) {
+        const int c0 = kb * 32 + 8 * g;
+        const bf16x8 x = c0 < C ? *(const bf16x8*)&a[pc * CS + c0] : bf16x8{};
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, whi[kb], acc[i], 0, 0, 0);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, wlo[kb], acc[i], 0, 0, 0);
+        if constexpr (SPLIT) {
+          const bf16x8 xl = c0 < C ? *(const bf16x8*)&a[plane + pc * CS + c0] : bf16x8{};
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, whi[kb], acc[i], 0, 0, 0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // lane (g, r) holds Y for pixels 16 mb + 4 g + i, tap r
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int mb = wave + NW * i;
+    if (mb < NBLK && r < 9) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int q = mb * 16 + 4 * g + e;
+        if (q < L::PX) Y[q * 9 + r] = acc[i][e];
+      }
+    }
+  }
+  __syncthreads();
+  const int py = tid / L::T, px = tid % L::T;
+  float s = 0.f;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) s += Y[((py + t / 3) * L::WI + px + t % 3) * 9 + t];
+  return s;
+}
+
+template <int C, bool SPLIT>
+__global__ __launch_bounds__(256) void k_cnn_last_mma(
+    const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n,
+    const float* __restrict__ W, const float* __restrict__ b, const double* __restrict__ u_base,
+    const int64_t* __restrict__ u_offs, double* __restrict__ g_base,
+    const int64_t* __restrict__ g_offs, int residual, double* __restrict__ partials) {
+  using L = LastCfg<C>;
+  constexpr int CS = C + 8, C8 = C / 8;
+  constexpr size_t TB = (size_t)(SPLIT ? 2 : 1) * L::PX * CS * 2, YB = (size_t)L::PX * 9 * 4;
+  __shared__ __align__(16) unsigned char lds[TB > YB ? TB : YB];   // tile, then Y
+  __shared__ double red[4];
+  __bf16* tile = (__bf16*)lds;
+  const int tid = threadIdx.x;
+  const int tpr = n / L::T, m = n - 1;
+  const int64_t f = blockIdx.x / (tpr * tpr);
+  const int t = (int)(blockIdx.x % (tpr * tpr));
+  const int y0 = (t / tpr) * L::T, x0 = (t % tpr) * L::T;
+  bf16x8 whi[L::KB], wlo[L::KB];
+  last_weights<C>(W, tid & 63, whi, wlo);
+  for (int i = tid; i < L::PX * C8; i += 256) {
+    const int p = i / C8, c8 = i % C8;
+    const int ty = p / L::WI, tx = p % L::WI;
+    const int64_t gi = ((f * n + ((y0 + ty - 1) & m)) * (int64_t)n + ((x0 + tx - 1) & m)) * C + c8 * 8;
+    *(bf16x8*)&tile[p * CS + c8 * 8] = *(const bf16x8*)&in[gi];
+    if constexpr (SPLIT) *(bf16x8*)&tile[L::PX * CS + p * CS + c8 * 8] = *(const bf16x8*)&in_lo[gi];
+  }
+  __syncthreads();
+  const float s = b[0] + last_layer_mfma<C, SPLIT, CS>(tile, L::PX * CS, (float*)lds, whi, wlo, tid);
+  const int py = tid / L::T, px = tid % L::T;
+  const int64_t gi = (int64_t)(y0 + py) * n + x0 + px;
+  const double u = u_base[(u_offs ? u_offs[f] : f * (int64_t)n * n) + gi];
+  const double out = residual ? u + (double)s : (double)s;
+  g_base[(g_offs ? g_offs[f] : f * (int64_t)n * n) + gi] = out;
+  if (partials) {
+    double d = out - u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = d;
+    __syncthreads();
+    if (tid == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
+}
+
 // ---------------------------------------------------------- fused network
 //
 // Inference with every layer of a network with NH hidden layers in one
@@ -299,6 +431,9 @@ template <int C, int NH, bool SPLIT> struct FusedCfg {
   static constexpr int P = SPLIT ? 2 : 1;
   static constexpr size_t LDS = (size_t)P * (PLANE_A + PLANE_B) * 2 + (size_t)WU * WU * 4 +
                                 (size_t)C * 10 * 4 + 4 * 8;
+  // the last layer's scratch aliases its input region
+  static_assert((size_t)(T + 2) * (T + 2) * 9 * 4 <= (size_t)(T + 2) * (T + 2) * CS * 2,
+                "last-layer scratch exceeds its input region");
   static constexpr bool kFits = LDS <= 160 * 1024;
 };
 
@@ -338,6 +473,8 @@ __global__ __launch_bounds__(256) void k_cnn_fused(
     }
   for (int i = tid; i < C * 9; i += F::NT) sw0[i] = W0g[i];
   for (int i = tid; i < C; i += F::NT) sb0[i] = b0g[i];
+  bf16x8 wlh[LastCfg<C>::KB], wll[LastCfg<C>::KB];
+  last_weights<C>(WL, lane, wlh, wll);
 
   for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     const int64_t f = t / (tpr * tpr);
@@ -428,30 +565,13 @@ __global__ __launch_bounds__(256) void k_cnn_fused(
       }
       __syncthreads();
     }
-    // last layer: C -> 1 on the tile, residual and mass partials in FP64
+    // last layer: C -> 1 on the tile (MFMA over the taps), residual and
+    // mass partials in FP64
     {
-      const __bf16* in = (NH & 1) ? bufB : bufA;
+      __bf16* in = (NH & 1) ? bufB : bufA;
       const int plane = (NH & 1) ? F::PLANE_B : F::PLANE_A;
-      constexpr int Wi = F::T + 2;
       const int py = tid / F::T, px = tid % F::T;
-      float s = bL[0];
-      for (int tp = 0; tp < 9; ++tp) {
-        const int q = (py + tp / 3) * Wi + px + tp % 3;
-#pragma unroll
-        for (int c8 = 0; c8 < C / 8; ++c8) {
-          float x[8];
-          const bf16x8 hv = *(const bf16x8*)&in[q * F::CS + c8 * 8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) x[j] = (float)hv[j];
-          if constexpr (SPLIT) {
-            const bf16x8 lv = *(const bf16x8*)&in[plane + q * F::CS + c8 * 8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) x[j] += (float)lv[j];
-          }
-#pragma unroll
-          for (int j = 0; j < 8; ++j) s += WL[(c8 * 8 + j) * 9 + tp] * x[j];
-        }
-      }
+      const float s = bL[0] + last_layer_mfma<C, SPLIT, F::CS>(in, plane, (float*)in, wlh, wll, tid);
       const int64_t gi = (int64_t)(y0 + py) * n + x0 + px;
       const double uc = u[gi];
       const double o = residual ? uc + (double)s : (double)s;
@@ -569,80 +689,6 @@ __global__ __launch_bounds__(256) void k_cnn_last_ref(
     const int p = (py + tp / 3) * (kTile + 2) + px + tp % 3;
 #pragma unroll 8
     for (int ci = 0; ci < C; ++ci) s += W[ci * 9 + tp] * tile[p * (C + 1) + ci];
-  }
-  const int64_t gi = (int64_t)(y0 + py) * n + x0 + px;
-  const double u = u_base[(u_offs ? u_offs[f] : f * (int64_t)n * n) + gi];
-  const double out = residual ? u + (double)s : (double)s;
-  g_base[(g_offs ? g_offs[f] : f * (int64_t)n * n) + gi] = out;
-  if (partials) {
-    double d = out - u;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = d;
-    __syncthreads();
-    if (tid == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
-  }
-}
-
-// ------------------------------------------------------------- last layer
-
-// One pixel per thread.  The input tile is loaded with 16-byte vectors
-// (8 channels) and kept in the input precision; the weights are read with
-// wave-uniform addresses (scalar loads).
-template <int C, typename TI>
-__global__ __launch_bounds__(256) void k_cnn_last(
-    const TI* __restrict__ in, const TI* __restrict__ in_lo, int n, const float* __restrict__ W,
-    const float* __restrict__ b, const double* __restrict__ u_base,
-    const int64_t* __restrict__ u_offs, double* __restrict__ g_base,
-    const int64_t* __restrict__ g_offs, int residual, double* __restrict__ partials) {
-  constexpr int C8 = C / 8;
-  constexpr int PS = C + (sizeof(TI) == 2 ? 8 : 4);  // LDS pixel stride (elements)
-  constexpr int TP = (kTile + 2) * (kTile + 2);
-  __shared__ __align__(16) TI tile[TP * PS];
-  __shared__ __align__(16) TI tile_lo[(sizeof(TI) == 2 ? TP * PS : 1)];
-  __shared__ double red[4];
-  const int tid = threadIdx.x;
-  const int tpr = n / kTile, m = n - 1;
-  const int64_t f = blockIdx.x / (tpr * tpr);
-  const int t = (int)(blockIdx.x % (tpr * tpr));
-  const int y0 = (t / tpr) * kTile, x0 = (t % tpr) * kTile;
-  const bool split = sizeof(TI) == 2 && in_lo != nullptr;
-  for (int i = tid; i < TP * C8; i += 256) {
-    const int p = i / C8, c8 = i % C8;
-    const int ty = p / (kTile + 2), tx = p % (kTile + 2);
-    const int64_t gi = ((f * n + ((y0 + ty - 1) & m)) * (int64_t)n + ((x0 + tx - 1) & m)) * C + c8 * 8;
-    if constexpr (sizeof(TI) == 2) {
-      *(bf16x8*)&tile[p * PS + c8 * 8] = *(const bf16x8*)&in[gi];
-      if (split) *(bf16x8*)&tile_lo[p * PS + c8 * 8] = *(const bf16x8*)&in_lo[gi];
-    } else {
-      *(float4*)&tile[p * PS + c8 * 8] = *(const float4*)&in[gi];
-      *(float4*)&tile[p * PS + c8 * 8 + 4] = *(const float4*)&in[gi + 4];
-    }
-  }
-  __syncthreads();
-  const int py = tid / kTile, px = tid % kTile;
-  float s = b[0];
-  for (int tp = 0; tp < 9; ++tp) {
-    const int p = (py + tp / 3) * (kTile + 2) + px + tp % 3;
-#pragma unroll
-    for (int c8 = 0; c8 < C8; ++c8) {
-      float x[8];
-      if constexpr (sizeof(TI) == 2) {
-        const bf16x8 h = *(const bf16x8*)&tile[p * PS + c8 * 8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) x[j] = (float)h[j];
-        if (split) {
-          const bf16x8 l = *(const bf16x8*)&tile_lo[p * PS + c8 * 8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) x[j] += (float)l[j];
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) x[j] = tile[p * PS + c8 * 8 + j];
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) s += W[(c8 * 8 + j) * 9 + tp] * x[j];
-    }
   }
   const int64_t gi = (int64_t)(y0 + py) * n + x0 + px;
   const double u = u_base[(u_offs ? u_offs[f] : f * (int64_t)n * n) + gi];
@@ -1050,10 +1096,16 @@ static void cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t
                                                     (float*)z_buf(j, l, train));
     }
   }
-  k_cnn_last<C, __bf16><<<g16, b256, 0, st>>>(hi(L - 2), lo(L - 2), n, W + cnn_woff(L - 1, L, C),
-                                              B + cnn_boff(L - 1, C), j.in_base, j.in_offs, g_out,
-                                              train ? nullptr : j.out_offs, j.residual,
-                                              j.ws.partials);
+  if (split)
+    k_cnn_last_mma<C, true><<<g16, b256, 0, st>>>(hi(L - 2), lo(L - 2), n, W + cnn_woff(L - 1, L, C),
+                                                  B + cnn_boff(L - 1, C), j.in_base, j.in_offs,
+                                                  g_out, train ? nullptr : j.out_offs, j.residual,
+                                                  j.ws.partials);
+  else
+    k_cnn_last_mma<C, false><<<g16, b256, 0, st>>>(hi(L - 2), nullptr, n, W + cnn_woff(L - 1, L, C),
+                                                   B + cnn_boff(L - 1, C), j.in_base, j.in_offs,
+                                                   g_out, train ? nullptr : j.out_offs, j.residual,
+                                                   j.ws.partials);
 }
 
 // Forward of G; in training mode every layer's activation and pre-activation
