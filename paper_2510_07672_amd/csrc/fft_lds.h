@@ -98,17 +98,30 @@ __device__ __forceinline__ void dft_r(C* v) {
 #define PR_PAD_SHIFT 3
 #endif
 
-// Padded line stride for lines of N elements: N + N/2^PR_PAD_SHIFT pad
-// slots, made odd.
-template <int N> struct PadLS {
-  static constexpr int value = N + (N >> PR_PAD_SHIFT) + 1;
+// Padded line stride for lines of N elements: N + N/2^SH pad slots, made
+// odd.
+template <int N, int SH = PR_PAD_SHIFT> struct PadLS {
+  static constexpr int value = N + (N >> SH) + 1;
 };
 
-// Panel layout: element e of line l at l * LS + e + (e >> PR_PAD_SHIFT).
-template <int LS> struct LinePanel {
+// Panel layout: element e of line l at l * LS + e + (e >> SH).
+template <int LS, int SH = PR_PAD_SHIFT> struct LinePanel {
   __device__ __forceinline__ int operator()(int line, int e) const {
-    return line * LS + e + (e >> PR_PAD_SHIFT);
+    return line * LS + e + (e >> SH);
   }
+};
+
+// Pad shift of a block's panel of LINES lines of N elements of type T,
+// next to EXTRA further bytes of LDS: one pad slot per 8 elements, or one
+// per 16 where that lets one more work-group share a CU's 160 KB of LDS.
+// Only for 16-byte elements: a wave's accesses are served 8 lanes at a
+// time from 16 bank quads, and the first stage's stride-8 writes, whose
+// lane-to-lane slot distances alternate 8 and 9, still hit distinct quads.
+template <int N, int LINES, int EXTRA, int ESIZE> struct PanelShift {
+  static constexpr int kLds = 160 * 1024;
+  static constexpr int bytes(int sh) { return LINES * (N + (N >> sh) + 1) * ESIZE + EXTRA; }
+  static constexpr int value =
+      (ESIZE == 16 && PR_PAD_SHIFT == 3 && kLds / bytes(4) > kLds / bytes(3)) ? 4 : PR_PAD_SHIFT;
 };
 
 // Twiddles.  Stage (Ns, R) needs w^(r k) = exp(-2 pi i r k / (Ns R)) for

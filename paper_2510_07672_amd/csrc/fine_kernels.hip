@@ -172,9 +172,22 @@ __device__ __forceinline__ void row_split_store(const cpx<T>* panel, cpx<T>* S, 
 // a stride = 4 (mod 16) makes the 8 lanes served together (4 pairs x 2
 // columns, direct or mirrored) fall in distinct 16-byte bank quads.
 template <int N, typename T> struct RowLS {
+  static constexpr int SH =
+      PanelShift<N, RowCfg<N, T>::PAIRS,
+                 TwSize<N>::value * (int)sizeof(cpx<T>) + (RowCfg<N, T>::NT / 64 + 1) * 8 + 64,
+                 (int)sizeof(cpx<T>)>::value;
   static constexpr int value = (sizeof(T) == 8 && RowCfg<N, T>::PAIRS == 4 && N >= 128)
-                                   ? N + (N >> PR_PAD_SHIFT) + 4
-                                   : PadLS<N>::value;
+                                   ? N + (N >> SH) + 4
+                                   : PadLS<N, SH>::value;
+};
+
+// Column-pass panel: CT whole columns next to the twiddles (and, for the
+// Picard pass, the symbol table).
+template <int N, typename T, int EXTRA = 0> struct ColLS {
+  static constexpr int SH =
+      PanelShift<N, ColCfg<N>::CT, TwSize<N>::value * (int)sizeof(cpx<T>) + EXTRA + 64,
+                 (int)sizeof(cpx<T>)>::value;
+  static constexpr int value = PadLS<N, SH>::value;
 };
 
 // The step parameters of field f: the launch argument, or the field's entry
@@ -194,7 +207,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
   constexpr int LS = RowLS<N, T>::value;
-  using Lay = LinePanel<LS>;
+  using Lay = LinePanel<LS, RowLS<N, T>::SH>;
   __shared__ C panel[PAIRS * LS];
   __shared__ C tw[TwSize<N>::value];
   __shared__ double red[NT / 64 + 1];
@@ -228,7 +241,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
   constexpr int LS = RowLS<N, T>::value;
-  using Lay = LinePanel<LS>;
+  using Lay = LinePanel<LS, RowLS<N, T>::SH>;
   __shared__ C panel[PAIRS * LS];
   __shared__ C tw[TwSize<N>::value];
   __shared__ double red[NT / 64 + 1];
@@ -317,9 +330,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   using C = cpx<T>;
   constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
   constexpr int TILES = RowCfg<N, T>::TILES;
-  constexpr int LS = PadLS<N>::value;
+  using CL = ColLS<N, T, PR_S2_LDS ? N * 8 : 0>;
+  constexpr int LS = CL::value;
   constexpr int E0 = (N + NT - 1) / NT;  // packed-column elements per thread
-  using Lay = LinePanel<LS>;
+  using Lay = LinePanel<LS, CL::SH>;
   __shared__ C panel[CT * LS];
   __shared__ C tw[TwSize<N>::value];
 #if PR_S2_LDS
@@ -410,8 +424,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ xspec, const cpx<T>* __restrict__ tw_g) {
   using C = cpx<T>;
   constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
-  constexpr int LS = PadLS<N>::value;
-  using Lay = LinePanel<LS>;
+  using CL = ColLS<N, T>;
+  constexpr int LS = CL::value;
+  using Lay = LinePanel<LS, CL::SH>;
   __shared__ C panel[CT * LS];
   __shared__ C tw[TwSize<N>::value];
   const int tid = threadIdx.x;
@@ -468,9 +483,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
     const cpx<T>* __restrict__ tw_g, const double* __restrict__ s2_g, StepParams sp_arg) {
   using C = cpx<T>;
   constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
-  constexpr int LS = PadLS<N>::value;
+  using CL = ColLS<N, T, N * 8>;
+  constexpr int LS = CL::value;
   constexpr int E0 = (N + NT - 1) / NT;
-  using Lay = LinePanel<LS>;
+  using Lay = LinePanel<LS, CL::SH>;
   __shared__ C panel[CT * LS];
   __shared__ C tw[TwSize<N>::value];
   __shared__ double s2[N];
