@@ -166,7 +166,15 @@ template <int C> struct HidCfg {
   static constexpr int KB = KP / 32;                 // K steps
   static constexpr int TPIX = (TH + 2) * (TW + 2);
   static constexpr int OS = C + 8;                   // LDS stride of the output staging rows
+  static constexpr int TCH = TPIX * (C / 8);         // 16-byte chunks of an input tile
+  static constexpr int LPT = (TCH + NT - 1) / NT;    // per thread
 };
+
+// Whether the hidden layer prefetches the next tile into registers while
+// it computes the current one.  Split layers hold one or two work-groups
+// per CU (LDS), so the extra registers cost no occupancy; unsplit ones
+// would lose work-groups to them (measured slower at C = 32).
+template <int C, bool SPLIT> constexpr bool hidden_prefetch() { return SPLIT && C <= 48; }
 
 // Persistent over tiles: each wave keeps the whole layer's weight fragments
 // (KB x NB bfloat16x8 B operands) in registers, the block stages one input
@@ -201,21 +209,59 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
   }
   __bf16* st = stage + wave * (SPLIT ? 2 : 1) * 16 * H::OS;
 
+  // input tile t: chunk i (pixel i / (C/8) of the (TH+2) x (TW+2) region,
+  // channels 8 (i % (C/8)) ..) at element gidx(t, i) of `in`
+  auto gidx = [&](int64_t t, int i) -> int64_t {
+    const int64_t f = t / (tpy * tpx);
+    const int tt = (int)(t % (tpy * tpx));
+    const int y0 = (tt / tpx) * H::TH, x0 = (tt % tpx) * H::TW;
+    const int p = i / (C / 8), c8 = i % (C / 8);
+    const int ty = p / (H::TW + 2), tx = p % (H::TW + 2);
+    const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (n - 1);
+    return ((f * n + gy) * (int64_t)n + gx) * C + c8 * 8;
+  };
+  auto lidx = [&](int i) { return (i / (C / 8)) * H::CS + (i % (C / 8)) * 8; };
+  constexpr bool PF = hidden_prefetch<C, SPLIT>();
+  bf16x8 pre[PF ? H::LPT : 1], pre_lo[PF && SPLIT ? H::LPT : 1];
+  auto fetch = [&](int64_t t) {
+#pragma unroll
+    for (int q = 0; q < H::LPT; ++q) {
+      const int i = tid + q * H::NT;
+      if (i < H::TCH) {
+        const int64_t gi = gidx(t, i);
+        pre[q] = *(const bf16x8*)&in[gi];
+        if constexpr (SPLIT) pre_lo[q] = *(const bf16x8*)&in_lo[gi];
+      }
+    }
+  };
+  if constexpr (PF)
+    if ((int64_t)blockIdx.x < tiles) fetch(blockIdx.x);
+
   for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     const int64_t f = t / (tpy * tpx);
     const int tt = (int)(t % (tpy * tpx));
     const int y0 = (tt / tpx) * H::TH, x0 = (tt % tpx) * H::TW;
     __syncthreads();  // the previous tile is no longer read
-    constexpr int TCH = H::TPIX * (C / 8);
-    for (int i = tid; i < TCH; i += H::NT) {
-      const int p = i / (C / 8), c8 = i % (C / 8);
-      const int ty = p / (H::TW + 2), tx = p % (H::TW + 2);
-      const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (n - 1);
-      const int64_t gi = ((f * n + gy) * (int64_t)n + gx) * C + c8 * 8;
-      *(bf16x8*)&tile[p * H::CS + c8 * 8] = *(const bf16x8*)&in[gi];
-      if constexpr (SPLIT) *(bf16x8*)&tile_lo[p * H::CS + c8 * 8] = *(const bf16x8*)&in_lo[gi];
+    if constexpr (PF) {
+#pragma unroll
+      for (int q = 0; q < H::LPT; ++q) {
+        const int i = tid + q * H::NT;
+        if (i < H::TCH) {
+          *(bf16x8*)&tile[lidx(i)] = pre[q];
+          if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(i)] = pre_lo[q];
+        }
+      }
+    } else {
+      for (int i = tid; i < H::TCH; i += H::NT) {
+        const int64_t gi = gidx(t, i);
+        *(bf16x8*)&tile[lidx(i)] = *(const bf16x8*)&in[gi];
+        if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(i)] = *(const bf16x8*)&in_lo[gi];
+      }
     }
     __syncthreads();
+    // the next tile's loads run under this tile's matrix work
+    if constexpr (PF)
+      if (t + gridDim.x < tiles) fetch(t + gridDim.x);
 
     for (int m = 0; m < H::MBW; ++m) {
       const int mb = wave * H::MBW + m;
