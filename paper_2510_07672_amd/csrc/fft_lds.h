@@ -111,19 +111,6 @@ template <int LS, int SH = PR_PAD_SHIFT> struct LinePanel {
   }
 };
 
-// Pad shift of a block's panel of LINES lines of N elements of type T,
-// next to EXTRA further bytes of LDS: one pad slot per 8 elements, or one
-// per 16 where that lets one more work-group share a CU's 160 KB of LDS.
-// Only for 16-byte elements: a wave's accesses are served 8 lanes at a
-// time from 16 bank quads, and the first stage's stride-8 writes, whose
-// lane-to-lane slot distances alternate 8 and 9, still hit distinct quads.
-template <int N, int LINES, int EXTRA, int ESIZE> struct PanelShift {
-  static constexpr int kLds = 160 * 1024;
-  static constexpr int bytes(int sh) { return LINES * (N + (N >> sh) + 1) * ESIZE + EXTRA; }
-  static constexpr int value =
-      (ESIZE == 16 && PR_PAD_SHIFT == 3 && kLds / bytes(4) > kLds / bytes(3)) ? 4 : PR_PAD_SHIFT;
-};
-
 // Twiddles.  Stage (Ns, R) needs w^(r k) = exp(-2 pi i r k / (Ns R)) for
 // r = 1..R-1, k = 0..Ns-1.  They are kept per stage as [r-1][k], so the
 // lanes of a wave (consecutive k) read consecutive entries.
@@ -154,6 +141,24 @@ __device__ __forceinline__ void load_stage_twiddles(C* tw, const C* g, int tid) 
     }
   }
 }
+
+// Pad shift of a transform block's panel of LINES lines of N elements of
+// ESIZE bytes (line stride N + N/2^sh + PLUS), next to OTHER further bytes
+// of LDS, for THREADS threads: one pad slot per 8 elements, or one per 16
+// where that lets more blocks share a CU (160 KB of LDS, 2048 threads).
+// Only for 16-byte elements: a wave's 16-byte accesses are served 8 lanes
+// at a time from 16 bank quads, and the first stage's stride-8 writes,
+// whose lane-to-lane slot distances then alternate 8 and 9, still hit
+// distinct quads.
+template <int N, int LINES, int ESIZE, int OTHER, int PLUS, int THREADS> struct LdsPlan {
+  static constexpr int fit(int sh) {
+    const int b = LINES * (N + (N >> sh) + PLUS) * ESIZE + OTHER;
+    const int by_lds = 160 * 1024 / b, by_threads = 2048 / THREADS;
+    return by_lds < by_threads ? by_lds : by_threads;
+  }
+  static constexpr bool k16 = ESIZE == 16 && PR_PAD_SHIFT == 3;
+  static constexpr int SH = k16 && fit(4) > fit(PR_PAD_SHIFT) ? 4 : PR_PAD_SHIFT;
+};
 
 // Hooks.  A prologue provides `C load(int i, int line, int e)` for the
 // first stage's i-th input of this thread (line `line`, element `e`) and

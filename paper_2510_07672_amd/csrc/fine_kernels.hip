@@ -172,22 +172,21 @@ __device__ __forceinline__ void row_split_store(const cpx<T>* panel, cpx<T>* S, 
 // a stride = 4 (mod 16) makes the 8 lanes served together (4 pairs x 2
 // columns, direct or mirrored) fall in distinct 16-byte bank quads.
 template <int N, typename T> struct RowLS {
+  static constexpr bool kQuad = sizeof(T) == 8 && RowCfg<N, T>::PAIRS == 4 && N >= 128;
   static constexpr int SH =
-      PanelShift<N, RowCfg<N, T>::PAIRS,
-                 TwSize<N>::value * (int)sizeof(cpx<T>) + (RowCfg<N, T>::NT / 64 + 1) * 8 + 64,
-                 (int)sizeof(cpx<T>)>::value;
-  static constexpr int value = (sizeof(T) == 8 && RowCfg<N, T>::PAIRS == 4 && N >= 128)
-                                   ? N + (N >> SH) + 4
-                                   : PadLS<N, SH>::value;
+      LdsPlan<N, RowCfg<N, T>::PAIRS, (int)sizeof(cpx<T>),
+              TwSize<N>::value * (int)sizeof(cpx<T>) + (RowCfg<N, T>::NT / 64 + 1) * 8 + 64,
+              kQuad ? 4 : 1, RowCfg<N, T>::NT>::SH;
+  static constexpr int value = N + (N >> SH) + (kQuad ? 4 : 1);
 };
 
 // Column-pass panel: CT whole columns next to the twiddles (and, for the
 // Picard pass, the symbol table).
 template <int N, typename T, int EXTRA = 0> struct ColLS {
   static constexpr int SH =
-      PanelShift<N, ColCfg<N>::CT, TwSize<N>::value * (int)sizeof(cpx<T>) + EXTRA + 64,
-                 (int)sizeof(cpx<T>)>::value;
-  static constexpr int value = PadLS<N, SH>::value;
+      LdsPlan<N, ColCfg<N>::CT, (int)sizeof(cpx<T>), TwSize<N>::value * (int)sizeof(cpx<T>) + EXTRA + 64,
+              1, ColCfg<N>::NT>::SH;
+  static constexpr int value = N + (N >> SH) + 1;
 };
 
 // The step parameters of field f: the launch argument, or the field's entry
@@ -196,6 +195,43 @@ __device__ __forceinline__ StepParams field_params(const CallDesc* desc, int64_t
                                                    const StepParams& arg) {
   if (!desc->params) return arg;
   return desc->params[desc->pidx ? desc->pidx[f] : 0];
+}
+
+// Rebuild of pair p's spectrum Z_p[kx] = R_2p[kx] + i R_2p+1[kx] at kx = c
+// and N - c from the two rows' half-spectrum values A and B of column c
+// (c = 0 carries kx = 0 and kx = N/2 as its real and imaginary parts).
+template <int N, typename T, class Lay>
+__device__ __forceinline__ void row_rebuild_entry(cpx<T>* panel, Lay lay, int p, int c, cpx<T> A,
+                                                  cpx<T> B) {
+  using C = cpx<T>;
+  if (c == 0) {
+    panel[lay(p, 0)] = C{A.x, B.x};
+    panel[lay(p, N / 2)] = C{A.y, B.y};
+  } else {
+    panel[lay(p, c)] = C{A.x - B.y, A.y + B.x};
+    panel[lay(p, N - c)] = C{A.x + B.y, B.x - A.y};
+  }
+}
+
+// Middle row pass of one tile whose pair spectra are in the panel: inverse
+// transforms, the right-hand side (with the tile's FP64 sum of f for the
+// mass multiplier), forward transforms, split and store to S.
+template <int N, typename T, int RHS>
+__device__ __forceinline__ void row_mid_tile(cpx<T>* panel, const cpx<T>* tw, double* red,
+                                             double* __restrict__ partials, cpx<T>* S, int64_t f,
+                                             int tile, T a, T dt, int conservative, int tid) {
+  using Cfg = RowCfg<N, T>;
+  constexpr int PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
+  using Lay = LinePanel<RowLS<N, T>::value, RowLS<N, T>::SH>;
+  const Lay lay{};
+  double fsum = 0.0;
+  fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, RhsEpi<T, RHS>{a, dt, &fsum});
+  fft_lines<N, -1, NT, T>(panel, tw, lay, tid);
+  if (RHS == RHS_SSI && conservative) {
+    const double s = block_sum<NT>(fsum, red, tid);
+    if (tid == 0) partials[f * TILES + tile] = s;
+  }
+  row_split_store<N, T, PAIRS, NT>(panel, S, tile * Cfg::TR, tid, lay);
 }
 
 // First row pass of a call: the real FP64 state in, half spectra out.
@@ -259,15 +295,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   // rebuild Z_j[kx] = R_2j[kx] + i R_2j+1[kx] for kx = 0..N-1
   for (int e = tid; e < PAIRS * (N / 2); e += NT) {
     const int p = e % PAIRS, c = e / PAIRS;
-    const C A = S[(int64_t)c * N + r0 + 2 * p];
-    const C B = S[(int64_t)c * N + r0 + 2 * p + 1];
-    if (c == 0) {
-      panel[lay(p, 0)] = C{A.x, B.x};
-      panel[lay(p, N / 2)] = C{A.y, B.y};
-    } else {
-      panel[lay(p, c)] = C{A.x - B.y, A.y + B.x};
-      panel[lay(p, N - c)] = C{A.x + B.y, B.x - A.y};
-    }
+    row_rebuild_entry<N, T>(panel, lay, p, c, S[(int64_t)c * N + r0 + 2 * p],
+                            S[(int64_t)c * N + r0 + 2 * p + 1]);
   }
   __syncthreads();
   if constexpr (MODE == ROW_LAST) {
@@ -275,14 +304,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
     fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{},
                             RealRowsStore<N, T>{desc->out_base, ob, r0, desc->out_f32});
   } else {
-    double fsum = 0.0;
-    fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, RhsEpi<T, RHS>{a, dt, &fsum});
-    fft_lines<N, -1, NT, T>(panel, tw, lay, tid);
-    if (RHS == RHS_SSI && sp.conservative) {
-      const double s = block_sum<NT>(fsum, red, tid);
-      if (tid == 0) partials[f * TILES + tile] = s;
-    }
-    row_split_store<N, T, PAIRS, NT>(panel, S, r0, tid, lay);
+    row_mid_tile<N, T, RHS>(panel, tw, red, partials, S, f, tile, a, dt, sp.conservative, tid);
   }
 }
 
@@ -322,38 +344,25 @@ template <typename T> struct DivideEpi {
   }
 };
 
-template <int N, typename T>
-__global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col(
-    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec,
-    const double* __restrict__ partials, const cpx<T>* __restrict__ tw_g,
-    const double* __restrict__ s2_g, StepParams sp_arg) {
-  using C = cpx<T>;
-  constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
-  constexpr int TILES = RowCfg<N, T>::TILES;
-  using CL = ColLS<N, T, PR_S2_LDS ? N * 8 : 0>;
-  constexpr int LS = CL::value;
-  constexpr int E0 = (N + NT - 1) / NT;  // packed-column elements per thread
-  using Lay = LinePanel<LS, CL::SH>;
-  __shared__ C panel[CT * LS];
-  __shared__ C tw[TwSize<N>::value];
-#if PR_S2_LDS
-  __shared__ double s2[N];
-#else
-  const double* s2 = s2_g;
-#endif
-  __shared__ double corr_sh;
+// Column panel of CT columns next to the twiddles (and the symbol table
+// when it is kept in LDS).
+template <int N, typename T> using ColPanel = ColLS<N, T, PR_S2_LDS ? N * 8 : 0>;
 
-  const int tid = threadIdx.x;
-  const int64_t f = blockIdx.x / BLK;
-  if (f >= desc->nfields) return;
-  const StepParams sp = field_params(desc, f, sp_arg);
-  const int c0 = (blockIdx.x % BLK) * CT;
+// One column tile: CT columns of field f from c0, at P.  Forward transform
+// (inputs from `pro`), division by the symbol (the packed column c = 0 with
+// the mass correction), inverse transform straight to P.  corr_sh must not
+// be read by any thread of the block from a previous tile any more.
+template <int N, typename T, class Pro>
+__device__ __forceinline__ void col_tile(cpx<T>* panel, const cpx<T>* tw, double* corr_sh,
+                                         const double* s2, const double* __restrict__ partials,
+                                         cpx<T>* P, int64_t f, int c0, const StepParams& sp,
+                                         int tid, Pro pro) {
+  using C = cpx<T>;
+  constexpr int NT = ColCfg<N>::NT;
+  constexpr int TILES = RowCfg<N, T>::TILES;
+  constexpr int E0 = (N + NT - 1) / NT;  // packed-column elements per thread
+  using Lay = LinePanel<ColPanel<N, T>::value, ColPanel<N, T>::SH>;
   const Lay lay{};
-  C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
-  load_stage_twiddles<N, NT>(tw, tw_g, tid);
-#if PR_S2_LDS
-  for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
-#endif
   if (tid == 0) {
     double corr = 0.0;
     if (c0 == 0 && sp.conservative) {
@@ -361,14 +370,15 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
       for (int i = 0; i < TILES; ++i) sum += partials[f * TILES + i];
       corr = sp.dt * sum;  // dt * N^2 * mean f
     }
-    corr_sh = corr;
+    *corr_sh = corr;
   }
-  __syncthreads();
-  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, ColLoad<T>{P, N}, DivideEpi<T>{s2, sp, c0});
+  // the forward transform's last stage ends with a block barrier, which
+  // also publishes corr_sh
+  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, pro, DivideEpi<T>{s2, sp, c0});
   if (c0 == 0) {
     // packed column: z = A + iB with A the kx = 0 and B the kx = N/2
     // column spectra (both Hermitian in ky); scale A and B separately
-    const double corr = corr_sh;
+    const double corr = *corr_sh;
     C vals[E0];
 #pragma unroll
     for (int q = 0; q < E0; ++q) {
@@ -392,6 +402,37 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
     __syncthreads();
   }
   fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, ColStore<T>{P, N});
+}
+
+// One block per column tile.
+template <int N, typename T>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col(
+    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec,
+    const double* __restrict__ partials, const cpx<T>* __restrict__ tw_g,
+    const double* __restrict__ s2_g, StepParams sp_arg) {
+  using C = cpx<T>;
+  constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
+  __shared__ C panel[CT * ColPanel<N, T>::value];
+  __shared__ C tw[TwSize<N>::value];
+#if PR_S2_LDS
+  __shared__ double s2[N];
+#else
+  const double* s2 = s2_g;
+#endif
+  __shared__ double corr_sh;
+
+  const int tid = threadIdx.x;
+  const int64_t f = blockIdx.x / BLK;
+  if (f >= desc->nfields) return;
+  const StepParams sp = field_params(desc, f, sp_arg);
+  const int c0 = (blockIdx.x % BLK) * CT;
+  C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
+  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+#if PR_S2_LDS
+  for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
+#endif
+  __syncthreads();
+  col_tile<N, T>(panel, tw, &corr_sh, s2, partials, P, f, c0, sp, tid, ColLoad<T>{P, N});
 }
 
 // ------------------------------------------------ Crank-Nicolson + Picard
