@@ -1037,6 +1037,9 @@ int row_tiles(int n, bool f32) {
 
 // ------------------------------------------------- correction and norm
 
+// Block b of field fld takes points b * 1024 + k * 256 + threadIdx.x,
+// k < 4 (coalesced, four independent loads of each operand in flight);
+// the block's maximum goes to upd with one atomic.
 template <typename TF>
 __global__ __launch_bounds__(256) void k_correct(
     int64_t n2, const TF* __restrict__ fb, const int64_t* __restrict__ f_offs,
@@ -1045,6 +1048,8 @@ __global__ __launch_bounds__(256) void k_correct(
     double* __restrict__ ub, const int64_t* __restrict__ u_offs,
     unsigned long long* __restrict__ upd, const int32_t* __restrict__ upd_idx,
     int update_cache, int blocks_per_field) {
+  constexpr int PPT = 4;
+  __shared__ unsigned long long red[4];
   const int64_t fld = blockIdx.x / blocks_per_field;
   const int64_t part = blockIdx.x % blocks_per_field;
   const TF* fp = fb + (f_offs ? f_offs[fld] : fld * n2);
@@ -1052,32 +1057,52 @@ __global__ __launch_bounds__(256) void k_correct(
   double* go = gob + (go_offs ? go_offs[fld] : fld * n2);
   double* u = ub + (u_offs ? u_offs[fld] : fld * n2);
   unsigned long long m = 0;
-  const int64_t stride = (int64_t)blocks_per_field * blockDim.x;
-  for (int64_t i = part * blockDim.x + threadIdx.x; i < n2; i += stride) {
-    const double g1 = gn[i];
-    // U^k_{j+1} = F(U^{k-1}_j) + (G(U^k_j) - G(U^{k-1}_j)), in this order
-    const double un = (double)fp[i] + (g1 - go[i]);
-    const double d = fabs(un - u[i]);
-    u[i] = un;
-    if (update_cache) go[i] = g1;
-    // |d| >= 0, so its bit pattern orders like its value; NaN (sign
-    // cleared) sorts above +Inf and therefore survives the max
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(d);
-    m = bits > m ? bits : m;
+  const int64_t i0 = part * (256 * PPT) + threadIdx.x;
+  double g1[PPT], f[PPT], g0[PPT], u0[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int64_t i = i0 + k * 256;
+    if (i < n2) {
+      g1[k] = gn[i];
+      f[k] = (double)fp[i];
+      g0[k] = go[i];
+      u0[k] = u[i];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int64_t i = i0 + k * 256;
+    if (i < n2) {
+      // U^k_{j+1} = F(U^{k-1}_j) + (G(U^k_j) - G(U^{k-1}_j)), in this order
+      const double un = f[k] + (g1[k] - g0[k]);
+      const double d = fabs(un - u0[k]);
+      u[i] = un;
+      if (update_cache) go[i] = g1[k];
+      // |d| >= 0, so its bit pattern orders like its value; NaN (sign
+      // cleared) sorts above +Inf and therefore survives the max
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(d);
+      m = bits > m ? bits : m;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned long long t = __shfl_xor(m, o, 64);
     m = t > m ? t : m;
   }
-  if ((threadIdx.x & 63) == 0) atomicMax(&upd[upd_idx ? upd_idx[fld] : fld], m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long r = red[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) r = red[w] > r ? red[w] : r;
+    atomicMax(&upd[upd_idx ? upd_idx[fld] : fld], r);
+  }
 }
 
 hipError_t launch_correct(const CorrectJob& j, hipStream_t st) {
   if (j.nfields <= 0) return hipSuccess;
   const int64_t n2 = (int64_t)j.n * j.n;
-  int bpf = (int)((n2 + 256 * 8 - 1) / (256 * 8));
-  if (bpf < 1) bpf = 1;
+  const int bpf = (int)((n2 + 1023) / 1024);  // 256 threads x 4 points
   const dim3 grid((unsigned)(j.nfields * bpf)), block(256);
   if (j.f_f32)
     k_correct<float><<<grid, block, 0, st>>>(n2, (const float*)j.f, j.f_offs, j.g_new, j.gn_offs,
@@ -1101,16 +1126,22 @@ __global__ __launch_bounds__(256) void k_copy_fields(int64_t n2, const double* _
   const int64_t part = blockIdx.x % blocks_per_field;
   const double* s = src + (s_offs ? s_offs[fld] : fld * n2);
   double* d = dst + (d_offs ? d_offs[fld] : fld * n2);
-  const int64_t stride = (int64_t)blocks_per_field * blockDim.x;
-  for (int64_t i = part * blockDim.x + threadIdx.x; i < n2; i += stride) d[i] = s[i];
+  // points part * 1024 + k * 256 + threadIdx.x, k < 4: loads issued together
+  const int64_t i0 = part * 1024 + threadIdx.x;
+  double v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (i0 + k * 256 < n2) v[k] = s[i0 + k * 256];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (i0 + k * 256 < n2) d[i0 + k * 256] = v[k];
 }
 
 hipError_t launch_copy(int64_t nfields, int n, const double* src, const int64_t* s_offs,
                        double* dst, const int64_t* d_offs, hipStream_t st) {
   if (nfields <= 0) return hipSuccess;
   const int64_t n2 = (int64_t)n * n;
-  int bpf = (int)((n2 + 256 * 8 - 1) / (256 * 8));
-  if (bpf < 1) bpf = 1;
+  const int bpf = (int)((n2 + 1023) / 1024);  // 256 threads x 4 points
   k_copy_fields<<<dim3((unsigned)(nfields * bpf)), dim3(256), 0, st>>>(n2, src, s_offs, dst,
                                                                        d_offs, bpf);
   return hipGetLastError();
