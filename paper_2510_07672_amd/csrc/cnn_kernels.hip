@@ -8,11 +8,11 @@
 //   k_cnn_first   1 -> C on the vector ALU (K = 9), reading the FP64 state
 //                 unrounded, FP32 arithmetic.
 //   k_cnn_hidden  C -> C as an implicit GEMM on the matrix cores: M = output
-//                 pixels (16 per block of a 16x16x32 bf16 MFMA), N = output
-//                 channels (16 per block), K = 9 C ordered (tap, channel)
+//                 channels (16 per block of a 16x16x32 bf16 MFMA), N = output
+//                 pixels (16 per block), K = 9 C ordered (tap, channel)
 //                 and padded to a multiple of 32; FP32 accumulation.  A
-//                 work-group stages a (TH+2) x (TW+2) input tile and the
-//                 layer's packed weights in LDS.  With SPLIT the activation
+//                 work-group stages a (TH+2) x (TW+2) input tile in LDS;
+//                 the weights stay in registers.  With SPLIT the activation
 //                 is carried as hi + lo bfloat16 and every product is done
 //                 twice (hi W + lo W), which keeps ~16 mantissa bits.
 //   k_cnn_hidden_f32  the same layer on the vector ALU in FP32 (reference
@@ -33,6 +33,7 @@
 namespace pr {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
 __device__ __forceinline__ float act_fn(float x, int act) {
@@ -165,7 +166,6 @@ template <int C> struct HidCfg {
   static constexpr int NB = C / 16;                  // 16-channel blocks
   static constexpr int KB = KP / 32;                 // K steps
   static constexpr int TPIX = (TH + 2) * (TW + 2);
-  static constexpr int OS = C + 8;                   // LDS stride of the output staging rows
   static constexpr int TCH = TPIX * (C / 8);         // 16-byte chunks of an input tile
   static constexpr int LPT = (TCH + NT - 1) / NT;    // per thread
 };
@@ -177,9 +177,11 @@ template <int C> struct HidCfg {
 template <int C, bool SPLIT> constexpr bool hidden_prefetch() { return SPLIT && C <= 48; }
 
 // Persistent over tiles: each wave keeps the whole layer's weight fragments
-// (KB x NB bfloat16x8 B operands) in registers, the block stages one input
-// tile at a time in LDS, and each 16-pixel output block is staged in LDS
-// (per wave) so that it leaves as 16-byte coalesced stores.
+// (KB x NB bfloat16x8 A operands: rows = output channels) in registers and
+// the block stages one input tile at a time in LDS (the B operands: columns
+// = pixels).  Each lane then ends with 4 consecutive output channels of
+// one pixel, which it activates, rounds (hi / lo) and stores from
+// registers as 8-byte pieces of the channels-last output.
 template <int C, bool SPLIT>
 __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
     const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
@@ -190,7 +192,6 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
   extern __shared__ __align__(16) unsigned char smem[];
   __bf16* tile = (__bf16*)smem;                               // [TPIX][CS]
   __bf16* tile_lo = tile + H::TPIX * H::CS;                   // SPLIT only
-  __bf16* stage = tile + (SPLIT ? 2 : 1) * H::TPIX * H::CS;   // [NW][(SPLIT?2:1)*16][OS]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
@@ -199,15 +200,15 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
 
   // this lane's weight fragments and biases, for the whole kernel
   bf16x8 bfr[H::KB][H::NB];
-  float bias[H::NB];
+  float bias[H::NB][4];  // channels nb 16 + 4 g + i
 #pragma unroll
   for (int nb = 0; nb < H::NB; ++nb) {
-    bias[nb] = b[nb * 16 + r];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bias[nb][i] = b[nb * 16 + 4 * g + i];
 #pragma unroll
     for (int kb = 0; kb < H::KB; ++kb)
       bfr[kb][nb] = *(const bf16x8*)&Wp[(int64_t)(nb * 16 + r) * H::KP + kb * 32 + 8 * g];
   }
-  __bf16* st = stage + wave * (SPLIT ? 2 : 1) * 16 * H::OS;
 
   // input tile t: chunk i (pixel i / (C/8) of the (TH+2) x (TW+2) region,
   // channels 8 (i % (C/8)) ..) at element gidx(t, i) of `in`
@@ -279,45 +280,37 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
         if (!live) afr = bf16x8{};
 #pragma unroll
         for (int nb = 0; nb < H::NB; ++nb)
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[kb][nb], acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb][nb], afr, acc[nb], 0, 0, 0);
         if constexpr (SPLIT) {
           bf16x8 alo = *(const bf16x8*)&tile_lo[a_off];
           if (!live) alo = bf16x8{};
 #pragma unroll
           for (int nb = 0; nb < H::NB; ++nb)
-            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bfr[kb][nb], acc[nb], 0, 0, 0);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb][nb], alo, acc[nb], 0, 0, 0);
         }
       }
-      // bias + activation into the wave's staging rows: pixel 4 g + i, channel nb 16 + r
-      if (zout) {
-        const int64_t zb = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0 + 4 * g) * C + r;
+      // lane (r, g) holds channels nb 16 + 4 g + i of pixel ox0 + r: bias,
+      // activation and hi / lo rounding in registers, 8-byte stores (4
+      // consecutive channels) straight to the channels-last output
+      {
+        const int64_t pb = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0 + r) * C + 4 * g;
 #pragma unroll
-        for (int nb = 0; nb < H::NB; ++nb)
+        for (int nb = 0; nb < H::NB; ++nb) {
+          float z[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) zout[zb + (int64_t)i * C + nb * 16] = acc[nb][i] + bias[nb];
-      }
+          for (int i = 0; i < 4; ++i) z[i] = acc[nb][i] + bias[nb][i];
+          if (zout) *(float4*)&zout[pb + nb * 16] = float4{z[0], z[1], z[2], z[3]};
+          bf16x4 h, l;
 #pragma unroll
-      for (int nb = 0; nb < H::NB; ++nb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float v = act_fn(acc[nb][i] + bias[nb], act);
-          const __bf16 h = (__bf16)v;
-          st[(4 * g + i) * H::OS + nb * 16 + r] = h;
-          if constexpr (SPLIT) st[(16 + 4 * g + i) * H::OS + nb * 16 + r] = (__bf16)(v - (float)h);
+          for (int i = 0; i < 4; ++i) {
+            const float v = act_fn(z[i], act);
+            h[i] = (__bf16)v;
+            l[i] = (__bf16)(v - (float)h[i]);
+          }
+          *(bf16x4*)&out[pb + nb * 16] = h;
+          if constexpr (SPLIT) *(bf16x4*)&out_lo[pb + nb * 16] = l;
         }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): staged values visible to the wave
-      __builtin_amdgcn_wave_barrier();
-      // 16 pixels x C channels are contiguous in the output: 16-byte stores
-      const int64_t ob = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0) * C;
-      constexpr int CH = 16 * C / 8;
-      for (int i = lane; i < CH; i += 64) {
-        const int px = i / (C / 8), c8 = i % (C / 8);
-        *(bf16x8*)&out[ob + px * C + c8 * 8] = *(const bf16x8*)&st[px * H::OS + c8 * 8];
-        if constexpr (SPLIT)
-          *(bf16x8*)&out_lo[ob + px * C + c8 * 8] = *(const bf16x8*)&st[(16 + px) * H::OS + c8 * 8];
       }
-      __builtin_amdgcn_wave_barrier();
     }
   }
 }
@@ -1290,8 +1283,7 @@ size_t cnn_lds_bytes(int C, bool split) {
   switch (C) {
 #define PR_L(CC)                                                                               \
   case CC:                                                                                     \
-    return ((split ? 2 : 1) * (HidCfg<CC>::TPIX * HidCfg<CC>::CS +                             \
-                               HidCfg<CC>::NW * 16 * HidCfg<CC>::OS)) * 2;
+    return (size_t)(split ? 2 : 1) * HidCfg<CC>::TPIX * HidCfg<CC>::CS * 2;
     PR_L(16) PR_L(32) PR_L(48) PR_L(64)
 #undef PR_L
     default: return 0;
