@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_cnn_first(const double* __restrict__ u_
 template <int C> struct HidCfg {
   static constexpr int TH = 8, TW = 32;              // output tile (rows, columns)
   static constexpr int NW = 4, NT = 64 * NW;         // waves, threads
-  static constexpr int CS = C + 8;                   // LDS pixel stride (elements)
+  static constexpr int CS = C + 8;                   // LDS pixel stride (elements), one plane
   static constexpr int KP = (9 * C + 31) / 32 * 32;  // K padded to the MFMA depth
   static constexpr int MB = TH * TW / 16;            // 16-pixel blocks per tile
   static constexpr int MBW = MB / NW;                // per wave
@@ -167,21 +167,20 @@ template <int C> struct HidCfg {
   static constexpr int KB = KP / 32;                 // K steps
   static constexpr int TPIX = (TH + 2) * (TW + 2);
   static constexpr int TCH = TPIX * (C / 8);         // 16-byte chunks of an input tile
-  static constexpr int LPT = (TCH + NT - 1) / NT;    // per thread
 };
 
-// Whether the hidden layer prefetches the next tile into registers while
-// it computes the current one.  Split layers hold one or two work-groups
-// per CU (LDS), so the extra registers cost no occupancy; unsplit ones
-// would lose work-groups to them (measured slower at C = 32).
-template <int C, bool SPLIT> constexpr bool hidden_prefetch() { return SPLIT && C <= 48; }
+// LDS layout of the hidden layer's input tile: pixel p at p * PS; with
+// SPLIT a pixel holds its C hi values then its C lo values, with one
+// 8-element pad after both.  The 16 lanes of a fragment read then stride
+// an odd number of 16-byte bank quads, as one plane of stride C + 8 would,
+// while the pair costs 8 pad elements per pixel instead of 16 (at C = 32
+// that lets 3 work-groups share a CU instead of 2).
+template <int C, bool SPLIT> struct HidTile {
+  static constexpr int PS = SPLIT ? 2 * C + 8 : C + 8;
+  static constexpr int LO = SPLIT ? C : 0;   // offset of the lo values
+  static constexpr size_t BYTES = (size_t)HidCfg<C>::TPIX * PS * 2;
+};
 
-// Persistent over tiles: each wave keeps the whole layer's weight fragments
-// (KB x NB bfloat16x8 A operands: rows = output channels) in registers and
-// the block stages one input tile at a time in LDS (the B operands: columns
-// = pixels).  Each lane then ends with 4 consecutive output channels of
-// one pixel, which it activates, rounds (hi / lo) and stores from
-// registers as 8-byte pieces of the channels-last output.
 template <int C, bool SPLIT>
 __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
     const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
@@ -190,8 +189,9 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
   using H = HidCfg<C>;
   static_assert(C % 16 == 0, "hidden width must be a multiple of 16");
   extern __shared__ __align__(16) unsigned char smem[];
-  __bf16* tile = (__bf16*)smem;                               // [TPIX][CS]
-  __bf16* tile_lo = tile + H::TPIX * H::CS;                   // SPLIT only
+  using HT = HidTile<C, SPLIT>;
+  __bf16* tile = (__bf16*)smem;                               // [TPIX][PS]
+  __bf16* tile_lo = tile + HT::LO;                            // SPLIT only
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
@@ -221,48 +221,18 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
     const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (n - 1);
     return ((f * n + gy) * (int64_t)n + gx) * C + c8 * 8;
   };
-  auto lidx = [&](int i) { return (i / (C / 8)) * H::CS + (i % (C / 8)) * 8; };
-  constexpr bool PF = hidden_prefetch<C, SPLIT>();
-  bf16x8 pre[PF ? H::LPT : 1], pre_lo[PF && SPLIT ? H::LPT : 1];
-  auto fetch = [&](int64_t t) {
-#pragma unroll
-    for (int q = 0; q < H::LPT; ++q) {
-      const int i = tid + q * H::NT;
-      if (i < H::TCH) {
-        const int64_t gi = gidx(t, i);
-        pre[q] = *(const bf16x8*)&in[gi];
-        if constexpr (SPLIT) pre_lo[q] = *(const bf16x8*)&in_lo[gi];
-      }
-    }
-  };
-  if constexpr (PF)
-    if ((int64_t)blockIdx.x < tiles) fetch(blockIdx.x);
-
+  auto lidx = [&](int i) { return (i / (C / 8)) * HT::PS + (i % (C / 8)) * 8; };
   for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     const int64_t f = t / (tpy * tpx);
     const int tt = (int)(t % (tpy * tpx));
     const int y0 = (tt / tpx) * H::TH, x0 = (tt % tpx) * H::TW;
     __syncthreads();  // the previous tile is no longer read
-    if constexpr (PF) {
-#pragma unroll
-      for (int q = 0; q < H::LPT; ++q) {
-        const int i = tid + q * H::NT;
-        if (i < H::TCH) {
-          *(bf16x8*)&tile[lidx(i)] = pre[q];
-          if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(i)] = pre_lo[q];
-        }
-      }
-    } else {
-      for (int i = tid; i < H::TCH; i += H::NT) {
-        const int64_t gi = gidx(t, i);
-        *(bf16x8*)&tile[lidx(i)] = *(const bf16x8*)&in[gi];
-        if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(i)] = *(const bf16x8*)&in_lo[gi];
-      }
+    for (int i = tid; i < H::TCH; i += H::NT) {
+      const int64_t gi = gidx(t, i);
+      *(bf16x8*)&tile[lidx(i)] = *(const bf16x8*)&in[gi];
+      if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(i)] = *(const bf16x8*)&in_lo[gi];
     }
     __syncthreads();
-    // the next tile's loads run under this tile's matrix work
-    if constexpr (PF)
-      if (t + gridDim.x < tiles) fetch(t + gridDim.x);
 
     for (int m = 0; m < H::MBW; ++m) {
       const int mb = wave * H::MBW + m;
@@ -275,7 +245,7 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
         const int k0 = kb * 32 + 8 * g;
         const bool live = k0 < 9 * C;
         const int tap = live ? k0 / C : 0, ci0 = live ? k0 % C : 0;
-        const int a_off = ((oy + tap / 3) * (H::TW + 2) + ox0 + r + tap % 3) * H::CS + ci0;
+        const int a_off = ((oy + tap / 3) * (H::TW + 2) + ox0 + r + tap % 3) * HT::PS + ci0;
         bf16x8 afr = *(const bf16x8*)&tile[a_off];
         if (!live) afr = bf16x8{};
 #pragma unroll
@@ -1283,7 +1253,7 @@ size_t cnn_lds_bytes(int C, bool split) {
   switch (C) {
 #define PR_L(CC)                                                                               \
   case CC:                                                                                     \
-    return (size_t)(split ? 2 : 1) * HidCfg<CC>::TPIX * HidCfg<CC>::CS * 2;
+    return split ? HidTile<CC, true>::BYTES : HidTile<CC, false>::BYTES;
     PR_L(16) PR_L(32) PR_L(48) PR_L(64)
 #undef PR_L
     default: return 0;
