@@ -181,6 +181,13 @@ template <int C, bool SPLIT> struct HidTile {
   static constexpr size_t BYTES = (size_t)HidCfg<C>::TPIX * PS * 2;
 };
 
+// Whether a hidden layer overlaps one 16-pixel block's epilogue with the
+// next block's matrix work (two sets of accumulators live).  Measured: at
+// C = 32 split (3 work-groups per CU by LDS) the extra registers cost no
+// occupancy and the layer gains ~6%; unsplit C = 32 (4 -> 2 waves per
+// SIMD) and C = 48 (2 -> 1) lose more than they gain.
+template <int C, bool SPLIT> constexpr bool hidden_pipelined() { return SPLIT && C == 32; }
+
 template <int C, bool SPLIT>
 __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
     const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
@@ -234,10 +241,10 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
     }
     __syncthreads();
 
-    for (int m = 0; m < H::MBW; ++m) {
+    // block m's products
+    auto mma_block = [&](int m, f32x4* acc) {
       const int mb = wave * H::MBW + m;
       const int oy = mb / (H::TW / 16), ox0 = (mb % (H::TW / 16)) * 16;
-      f32x4 acc[H::NB];
 #pragma unroll
       for (int nb = 0; nb < H::NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -259,27 +266,49 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
             acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb][nb], alo, acc[nb], 0, 0, 0);
         }
       }
-      // lane (r, g) holds channels nb 16 + 4 g + i of pixel ox0 + r: bias,
-      // activation and hi / lo rounding in registers, 8-byte stores (4
-      // consecutive channels) straight to the channels-last output
-      {
-        const int64_t pb = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0 + r) * C + 4 * g;
+    };
+    // lane (r, g) holds channels nb 16 + 4 g + i of pixel ox0 + r: bias,
+    // activation and hi / lo rounding in registers, 8-byte stores (4
+    // consecutive channels) straight to the channels-last output
+    auto epilogue = [&](int m, const f32x4* acc) {
+      const int mb = wave * H::MBW + m;
+      const int oy = mb / (H::TW / 16), ox0 = (mb % (H::TW / 16)) * 16;
+      const int64_t pb = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0 + r) * C + 4 * g;
 #pragma unroll
-        for (int nb = 0; nb < H::NB; ++nb) {
-          float z[4];
+      for (int nb = 0; nb < H::NB; ++nb) {
+        float z[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) z[i] = acc[nb][i] + bias[nb][i];
-          if (zout) *(float4*)&zout[pb + nb * 16] = float4{z[0], z[1], z[2], z[3]};
-          bf16x4 h, l;
+        for (int i = 0; i < 4; ++i) z[i] = acc[nb][i] + bias[nb][i];
+        if (zout) *(float4*)&zout[pb + nb * 16] = float4{z[0], z[1], z[2], z[3]};
+        bf16x4 h, l;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float v = act_fn(z[i], act);
-            h[i] = (__bf16)v;
-            l[i] = (__bf16)(v - (float)h[i]);
-          }
-          *(bf16x4*)&out[pb + nb * 16] = h;
-          if constexpr (SPLIT) *(bf16x4*)&out_lo[pb + nb * 16] = l;
+        for (int i = 0; i < 4; ++i) {
+          const float v = act_fn(z[i], act);
+          h[i] = (__bf16)v;
+          l[i] = (__bf16)(v - (float)h[i]);
         }
+        *(bf16x4*)&out[pb + nb * 16] = h;
+        if constexpr (SPLIT) *(bf16x4*)&out_lo[pb + nb * 16] = l;
+      }
+    };
+    if constexpr (hidden_pipelined<C, SPLIT>()) {
+      // software pipeline: block m's matrix work is issued before block
+      // m - 1's epilogue, so the two overlap within the wave
+      f32x4 prev[H::NB];
+#pragma unroll
+      for (int m = 0; m < H::MBW; ++m) {
+        f32x4 acc[H::NB];
+        mma_block(m, acc);
+        if (m > 0) epilogue(m - 1, prev);
+#pragma unroll
+        for (int nb = 0; nb < H::NB; ++nb) prev[nb] = acc[nb];
+      }
+      epilogue(H::MBW - 1, prev);
+    } else {
+      for (int m = 0; m < H::MBW; ++m) {
+        f32x4 acc[H::NB];
+        mma_block(m, acc);
+        epilogue(m, acc);
       }
     }
   }
