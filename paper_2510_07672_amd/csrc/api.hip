@@ -195,6 +195,7 @@ CnnWs carve_cnn(Carver& c, int n, const pr_coarse* g, int64_t nfields, bool trai
   w.zs = c.take((size_t)(L - 1) * grad);
   w.o1 = (double*)c.take((size_t)nfields * n * n * 8);
   w.wpart = (double*)c.take(tiles * (size_t)(C * C * 9 + C) * 8);
+  w.wpart2 = (double*)c.take((size_t)kWGradGroups * (C * C * 9 + C) * 8);
   w.d[0] = c.take(grad);
   w.d[1] = c.take(grad);
   w.fpart = (double*)c.take((size_t)nfields * std::max<int64_t>(1, (int64_t)n * n / 2048) * 8);

@@ -860,6 +860,84 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const T* __restrict__ d
   }
 }
 
+// The same partial sums for wide layers (CI, CO >= 32), register-blocked:
+// a task is 4 output channels x 9 taps of one input channel, so that per
+// pixel a thread reads 4 values of dY and 9 of X for 36 products (instead
+// of 2 reads per product).  Each task accumulates its tile's 256 pixels in
+// T, in pixel order, and stores the sums as doubles; biases as above.
+template <int CI, int CO, typename T, typename TX>
+__global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict__ dY,
+                                                            const TX* __restrict__ X,
+                                                            const TX* __restrict__ X_lo, int n,
+                                                            double* __restrict__ partial) {
+  static_assert(CO % 4 == 0, "output channels in blocks of 4");
+  constexpr int NP = CO * CI * 9 + CO, TASKS = (CO / 4) * CI;
+  __shared__ T xt[(kTile + 2) * (kTile + 2) * (CI + 1)];
+  __shared__ T yt[kTile * kTile * (CO + 1)];
+  const int tid = threadIdx.x;
+  const int tpr = n / kTile, m = n - 1;
+  const int64_t f = blockIdx.x / (tpr * tpr);
+  const int t = (int)(blockIdx.x % (tpr * tpr));
+  const int y0 = (t / tpr) * kTile, x0 = (t % tpr) * kTile;
+  for (int i = tid; i < (kTile + 2) * (kTile + 2) * CI; i += 256) {
+    const int p = i / CI, c = i % CI;
+    const int ty = p / (kTile + 2), tx = p % (kTile + 2);
+    const int64_t gi = ((f * n + ((y0 + ty - 1) & m)) * (int64_t)n + ((x0 + tx - 1) & m)) * CI + c;
+    T v = (T)X[gi];
+    if (X_lo) v += (T)X_lo[gi];
+    xt[p * (CI + 1) + c] = v;
+  }
+  for (int i = tid; i < kTile * kTile * CO; i += 256) {
+    const int p = i / CO, c = i % CO;
+    yt[p * (CO + 1) + c] = dY[((f * n + y0 + p / kTile) * (int64_t)n + x0 + p % kTile) * CO + c];
+  }
+  __syncthreads();
+  double* out = partial + (int64_t)blockIdx.x * NP;
+  for (int task = tid; task < TASKS; task += 256) {
+    const int co0 = (task % (CO / 4)) * 4, ci = task / (CO / 4);
+    T acc[4][9];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp) acc[k][tp] = (T)0;
+    for (int p = 0; p < kTile * kTile; ++p) {
+      const int py = p / kTile, px = p % kTile;
+      T y[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) y[k] = yt[p * (CO + 1) + co0 + k];
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp) {
+        const T x = xt[((py + tp / 3) * (kTile + 2) + px + tp % 3) * (CI + 1) + ci];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k][tp] += y[k] * x;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp) out[((co0 + k) * CI + ci) * 9 + tp] = (double)acc[k][tp];
+  }
+  for (int co = tid; co < CO; co += 256) {
+    double s = 0.0;
+    for (int p = 0; p < kTile * kTile; ++p) s += (double)yt[p * (CO + 1) + co];
+    out[CO * CI * 9 + co] = s;
+  }
+}
+
+// First stage of the deterministic weight-gradient reduction: group g
+// (blockIdx.y) sums rows [g per, (g + 1) per) of partial, in row order, into
+// part2[g][q].  Many groups keep the whole GPU reading the partial sums.
+__global__ void k_reduce_groups(const double* __restrict__ partial, int64_t blocks, int np,
+                                int64_t per, double* __restrict__ part2) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= np) return;
+  const int64_t b0 = (int64_t)blockIdx.y * per;
+  const int64_t b1 = b0 + per < blocks ? b0 + per : blocks;
+  double s = 0.0;
+  for (int64_t b = b0; b < b1; ++b) s += partial[b * np + q];
+  part2[(int64_t)blockIdx.y * np + q] = s;
+}
+
 // out[q] = sum over blocks of partial[block][q], in block order
 template <typename T>
 __global__ void k_reduce_partials(const double* __restrict__ partial, int64_t blocks, int np,
@@ -1179,8 +1257,15 @@ static void conv_bwd(const CnnJob& j, const TG* dY, const TX* X, const TX* X_lo,
   const int64_t tiles16 = j.nfields * (int64_t)(n / kTile) * (n / kTile);
   const dim3 g16((unsigned)tiles16), b256(256);
   constexpr int NP = CO * CI * 9 + CO;
-  k_conv_bwd_weight<CI, CO, TG, TX><<<g16, b256, 0, st>>>(dY, X, X_lo, n, j.ws.wpart);
-  k_reduce_partials<TW><<<dim3((NP + 255) / 256), b256, 0, st>>>(j.ws.wpart, tiles16, NP, dW,
+  if constexpr (CI >= 32 && CO >= 32)
+    k_conv_bwd_weight_rb<CI, CO, TG, TX><<<g16, b256, 0, st>>>(dY, X, X_lo, n, j.ws.wpart);
+  else
+    k_conv_bwd_weight<CI, CO, TG, TX><<<g16, b256, 0, st>>>(dY, X, X_lo, n, j.ws.wpart);
+  // tiles -> kWGradGroups group sums -> dW, each stage in a fixed order
+  const int64_t per = (tiles16 + kWGradGroups - 1) / kWGradGroups;
+  k_reduce_groups<<<dim3((NP + 255) / 256, kWGradGroups), b256, 0, st>>>(j.ws.wpart, tiles16, NP,
+                                                                         per, j.ws.wpart2);
+  k_reduce_partials<TW><<<dim3((NP + 255) / 256), b256, 0, st>>>(j.ws.wpart2, kWGradGroups, NP, dW,
                                                                  CO * CI * 9, db);
   if (dX) k_conv_bwd_data<CI, CO, TG, TW><<<g16, b256, 0, st>>>(dY, n, W, dX);
 }

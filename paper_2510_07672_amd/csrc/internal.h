@@ -134,6 +134,9 @@ enum { kActGelu = 0, kActTanh = 1 };
 enum { kCnnF64 = 0, kCnnF32 = 1, kCnnBf16 = 2, kCnnBf16x2 = 3 };   // same values as pr_dtype
 constexpr int kCnnF64MaxC = 32;   // widest FP64 network whose tiles fit in LDS
 
+// Tile groups of the first stage of the weight-gradient reduction.
+constexpr int kWGradGroups = 64;
+
 struct CnnWs {
   void* wpack;       // bfloat16 [L-2][C][KP] packed hidden-layer weights
   void* act[2];      // ping-pong activations [nfields][N][N][C] (x2 for hi+lo)
@@ -143,6 +146,7 @@ struct CnnWs {
   void* zs;          // [L-1] pre-activations
   double* o1;        // [nfields][N][N] forward output before the limiter
   double* wpart;     // [tiles][params] weight-gradient partial sums
+  double* wpart2;    // [kWGradGroups][params] their sums over groups of tiles
   void* d[2];        // gradient buffers [nfields][N][N][C]
   double* fpart;     // per-field partial sums of the output-stage gradient
 };
