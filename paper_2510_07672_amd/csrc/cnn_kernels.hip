@@ -779,9 +779,19 @@ __global__ __launch_bounds__(256) void k_cnn_fix(double* __restrict__ g_base,
 // Weight and bias gradients are summed per 16 x 16 tile into FP64 partials
 // and then over tiles in a fixed order, so results are deterministic.
 
+// Wt[tap][co][ci] = W[co][ci][tap]: the data gradient's weights, laid out so
+// that one (tap, co) step reads CI consecutive values.
+template <int CI, int CO, typename TW>
+__global__ void k_w_transpose(const TW* __restrict__ W, TW* __restrict__ Wt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= CO * CI * 9) return;
+  const int tp = i % 9, ci = (i / 9) % CI, co = i / (9 * CI);
+  Wt[(tp * CO + co) * CI + ci] = W[i];
+}
+
 template <int CI, int CO, typename T, typename TW>
 __global__ __launch_bounds__(256) void k_conv_bwd_data(const T* __restrict__ dY, int n,
-                                                       const TW* __restrict__ W,
+                                                       const TW* __restrict__ Wt,
                                                        T* __restrict__ dX) {
   __shared__ T tile[(kTile + 2) * (kTile + 2) * (CO + 1)];
   const int tid = threadIdx.x;
@@ -806,8 +816,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const T* __restrict__ dY,
     const int p = (py + 2 - ky) * (kTile + 2) + px + 2 - kx;
     for (int co = 0; co < CO; ++co) {
       const T d = tile[p * (CO + 1) + co];
+      const TW* w = Wt + (tp * CO + co) * CI;  // contiguous in ci: wide scalar loads
 #pragma unroll
-      for (int ci = 0; ci < CI; ++ci) acc[ci] += (T)W[(co * CI + ci) * 9 + tp] * d;
+      for (int ci = 0; ci < CI; ++ci) acc[ci] += (T)w[ci] * d;
     }
   }
   const int64_t o = ((f * n + y0 + py) * (int64_t)n + x0 + px) * CI;
@@ -900,6 +911,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict_
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int tp = 0; tp < 9; ++tp) acc[k][tp] = (T)0;
+#pragma unroll 2
     for (int p = 0; p < kTile * kTile; ++p) {
       const int py = p / kTile, px = p % kTile;
       T y[4];
@@ -1267,7 +1279,13 @@ static void conv_bwd(const CnnJob& j, const TG* dY, const TX* X, const TX* X_lo,
                                                                          per, j.ws.wpart2);
   k_reduce_partials<TW><<<dim3((NP + 255) / 256), b256, 0, st>>>(j.ws.wpart2, kWGradGroups, NP, dW,
                                                                  CO * CI * 9, db);
-  if (dX) k_conv_bwd_data<CI, CO, TG, TW><<<g16, b256, 0, st>>>(dY, n, W, dX);
+  if (dX) {
+    // the weight partials are reduced by now: their buffer holds the
+    // transposed weights
+    TW* Wt = (TW*)j.ws.wpart;
+    k_w_transpose<CI, CO, TW><<<dim3((CO * CI * 9 + 255) / 256), b256, 0, st>>>(W, Wt);
+    k_conv_bwd_data<CI, CO, TG, TW><<<g16, b256, 0, st>>>(dY, n, Wt, dX);
+  }
 }
 
 template <int C, typename TG, typename TA, typename TZ, typename TW>
