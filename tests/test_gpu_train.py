@@ -72,7 +72,7 @@ def oracle_grads(spec, ws, bs, u, r, emulate=False):
 
 
 @pytest.mark.parametrize("prec,C,L,n", [("f32", 32, 4, 64), ("f32", 16, 3, 128), ("bf16", 32, 4, 64),
-                                        ("bf16", 48, 3, 64)])
+                                        ("bf16", 48, 3, 64), ("f64", 32, 3, 32)])
 def test_backward_matches_oracle_autograd(mods, prec, C, L, n):
     api, _ = mods
     spec = cnn.CnnSpec(n_layers=L, channels=C)
@@ -83,7 +83,7 @@ def test_backward_matches_oracle_autograd(mods, prec, C, L, n):
     du, dW, dB = api.pr_cnn_backward(problem(api, n), net, torch.from_numpy(u).cuda(),
                                      torch.from_numpy(r).cuda())
     gu, gW, gB = oracle_grads(spec, ws, bs, u, r, emulate=(prec == "bf16"))
-    tol_u, tol_p = (1e-5, 1e-4) if prec == "f32" else (2e-2, 2e-2)
+    tol_u, tol_p = {"f64": (1e-11, 1e-11), "f32": (1e-5, 1e-4)}.get(prec, (2e-2, 2e-2))
     assert rel(du, gu) <= tol_u
     assert rel(dW, gW) <= tol_p
     assert rel(dB, gB) <= tol_p
