@@ -114,6 +114,10 @@ template <int LS, int SH = PR_PAD_SHIFT> struct LinePanel {
 // Twiddles.  Stage (Ns, R) needs w^(r k) = exp(-2 pi i r k / (Ns R)) for
 // r = 1..R-1, k = 0..Ns-1.  They are kept per stage as [r-1][k], so the
 // lanes of a wave (consecutive k) read consecutive entries.
+// Radix of the stage that follows Ns: 8 while it fits, the leftover 2 or 4
+// last.  (The leftover first measured 1.2-1.6x slower per step: a radix-2
+// or -4 first stage gives each thread two or four butterflies of strided
+// global loads.)
 template <int N> constexpr int stage_radix(int ns) { return (N / ns) >= 8 ? 8 : N / ns; }
 
 template <int N> constexpr int tw_offset(int ns_target) {
@@ -225,7 +229,7 @@ template <int N, int NS, int SIGN, int NT, int G, typename T, class Lay, class P
 __device__ __forceinline__ void fft_from(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid, Pro& pro,
                                          Epi& epi) {
   if constexpr (NS < N) {
-    constexpr int R = (N / NS) >= 8 ? 8 : (N / NS);
+    constexpr int R = stage_radix<N>(NS);
     fft_stage<N, R, NS, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
     fft_from<N, NS * R, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
   }
