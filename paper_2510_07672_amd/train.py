@@ -62,15 +62,19 @@ class TrainLog:
 
 def train(net: api.CnnCoarse, p: api.Problem, data: torch.Tensor, steps: int, batch: int = 32,
           rollout: int = 8, ckpt: int = 2, lr: float = 1e-3, seed: int = 0,
-          progress=None) -> TrainLog:
+          progress=None, lr_final: float = None) -> TrainLog:
     """`steps` Adam updates on random (trajectory, start) pairs; `progress`,
-    if given, is called as progress(step, loss, ms) after every update."""
+    if given, is called as progress(step, loss, ms) after every update.
+    With `lr_final` the learning rate follows a cosine from `lr` down to it
+    over the run; otherwise it stays at `lr`."""
     R, T1 = data.shape[0], data.shape[1]
     if T1 - 1 < rollout:
         raise ValueError("trajectories shorter than the rollout")
     net.W.requires_grad_(True)
     net.B.requires_grad_(True)
     opt = torch.optim.Adam([net.W, net.B], lr=lr)
+    sched = (torch.optim.lr_scheduler.CosineAnnealingLR(opt, T_max=max(1, steps), eta_min=lr_final)
+             if lr_final is not None else None)
     gen = torch.Generator().manual_seed(seed)
     log = TrainLog()
     for _ in range(steps):
@@ -85,6 +89,8 @@ def train(net: api.CnnCoarse, p: api.Problem, data: torch.Tensor, steps: int, ba
         opt.zero_grad(set_to_none=True)
         loss.backward()
         opt.step()
+        if sched is not None:
+            sched.step()
         torch.cuda.synchronize()
         log.step_ms.append((time.perf_counter() - tic) * 1e3)
         log.loss.append(float(loss.item()))
