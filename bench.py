@@ -431,9 +431,9 @@ def main():
         calib_copy()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the fine solves would shard by slice with no communication; see DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (its fine "
+              "solves would shard by slice with no communication, the correction sweep passing "
+              "one state per GPU boundary)", file=sys.stderr)
         sys.exit(2)
 
     import torch
