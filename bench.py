@@ -193,7 +193,7 @@ def schedule_compare(api, p, g, u0, s, kmax, schedules=(1, 2)):
     return out
 
 
-# Config 5: 48 concurrent solves, the recipe fixed here (seeded, synthetic)
+# The uneven batch (--config c5): 48 concurrent solves, the recipe fixed here (seeded, synthetic)
 def c5_jobs(api, torch, synth, f32_iters, fine_prec="f64", g_prec="f64"):
     """Job i: N = (128, 256, 1024)[i % 3], slices = (16, 32, 64, 128, 256)[i % 5],
     eps = 0.01 + 0.02 i / 47, classic for even i and mass-conservative for
@@ -212,7 +212,7 @@ def c5_jobs(api, torch, synth, f32_iters, fine_prec="f64", g_prec="f64"):
 
 
 def uneven_bench(args):
-    """Config 5: the 48-solve uneven batch through pr_solve_many, FP64 plain
+    """The 48-solve uneven batch (c5) through pr_solve_many, FP64 plain
     form against the mixed form (FP32-then-FP64 fine schedule), each run
     until every job's sup-norm update is <= 5e-7, then checked against each
     job's FP64 serial fine solve (rel-L2 <= 1e-6 per job)."""
@@ -338,7 +338,7 @@ def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32, los
 
 
 def training_bench(args):
-    """Config 4: one training step = an 8-step rollout of the network on a
+    """Training (c4): one step = an 8-step rollout of the network on a
     batch of 32 trajectories at 256^2 (bf16 forward, FP32 gradients,
     checkpoints every 2 steps), the MSE against fine-solver states, the
     backward through the hand-written kernels and an Adam update."""
@@ -411,11 +411,11 @@ def main():
     ap.add_argument("--kmax", type=int, default=16)
     ap.add_argument("--coarse", default=None, choices=["num", "cnn"],
                     help="numerical coarse step, or the workload's convolutional network "
-                         "(default: the network for configs 2 and 3, the scheme for config 1)")
+                         "(default: the network for c2 and c3, the scheme for c1)")
     ap.add_argument("--cnn-prec", default="bf16x2", choices=["bf16", "bf16x2", "f32"])
     ap.add_argument("--train-steps", type=int, default=2000,
                     help="Adam steps on fine trajectories before timing (network only); "
-                         "2000 (about two minutes) bring config 2 to rel-L2 <= 1e-6 at k = 2")
+                         "2000 (about two minutes) bring c2 to rel-L2 <= 1e-6 at k = 2")
     ap.add_argument("--train-traj", type=int, default=512,
                     help="fine trajectories (16 slices each) the network is trained on")
     ap.add_argument("--train-batch", type=int, default=32)

@@ -107,7 +107,7 @@ def test_cn_mass_and_fixed_points_on_gpu(api):
 
 
 def test_parareal_with_cn_fine_matches_oracle(api):
-    # config-1 shape with the paper's scheme as F and as the numerical G
+    # 64^2, 8 slices of 100 steps, with the paper's scheme as F and as the numerical G
     p = api.Problem(n=64, length=1.0, eps=0.02, conservative=False, stab=0.0, dt=1e-4, steps=100,
                     scheme="cn", picard=2)
     g = api.Coarse(dt=1e-2)

@@ -1,14 +1,14 @@
 """Parity at the workloads' full sizes, in the launch configuration the
 benchmark times, on outputs the FP64 oracle can compute one by one.
 
-  * config 2: F (200 semi-implicit steps) on all 512 fields of 256^2 in one
+  * F (200 semi-implicit steps) on all 512 fields of 256^2 in one
     call, two sampled fields against the oracle, rel-L2 <= 1e-12;
-  * config 3: F (100 steps, conservative) on all 2048 fields of 512^2,
+  * F (100 steps, conservative) on all 2048 fields of 512^2,
     sampled fields against the oracle, plus the mass of every field;
-  * the config-2 network (4 x 32, GELU) on the 8-field batch, sampled
+  * the 4 x 32 GELU network on a batch of 8 fields of 256^2, sampled
     fields against the oracle (FP32 <= 1e-5; split bf16 <= 2e-4 against
     the oracle with bf16 hidden weights);
-  * Parareal at config-2 size: after k iterations the first k slices equal
+  * Parareal on 8 ICs x 64 slices of 256^2: after k iterations the first k slices equal
     the GPU's serial fine solve bit for bit (Section 3.3), for k = 1, 2;
   * degenerate cases: one slice, no iterations, and a tolerance every
     first update meets.

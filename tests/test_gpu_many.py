@@ -148,7 +148,7 @@ def test_schedule_never_freezes_in_fp32_iterations(api):
 
 
 def test_schedule_converges_to_the_fp64_solution(api):
-    # config-1 sizes: 64^2, eps 0.02, dt 1e-4, 100 steps/slice, 8 slices
+    # 64^2, eps 0.02, dt 1e-4, 100 steps/slice, 8 slices
     import dataclasses
     p = api.Problem(n=64, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4, steps=100)
     g = api.Coarse(dt=1e-2)
