@@ -73,11 +73,14 @@ def kernel_src_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cfg_name, prec, n):
-    """HBM bytes of one fine step (middle row pass + column pass of the
-    fine sweep) from the committed FETCH_SIZE / WRITE_SIZE counter summary,
-    already scaled by the plain-copy calibration; None if the kernels
-    changed since the counters were taken."""
+def measured_traffic(cfg_name, prec, n, nfields):
+    """HBM bytes of one fine step over `nfields` fields (middle row pass +
+    column pass of the fine sweep) from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, already scaled by the plain-copy
+    calibration; None if the kernels changed since the counters were
+    taken.  A streaming call may run its fields in working-set chunks: the
+    largest dispatch covers grid / (N^2 / 16) fields (256-thread column
+    blocks of 2048 / N columns), and the step is scaled from it."""
     path = os.path.join(ROOT, "profiles", f"fine_step_{cfg_name}_{prec}.json")
     if not os.path.exists(path):
         return None
@@ -90,13 +93,16 @@ def measured_traffic(cfg_name, prec, n):
 
     def biggest(names):
         cands = [(int(k.split("@")[1]), v) for k, v in per.items() if k.split("@")[0] in names]
-        return max(cands)[1] if cands else None
+        return max(cands, key=lambda c: c[0]) if cands else None
     # the middle row pass, with or without its right-hand-side template argument
     row = biggest({f"pr::k_row<{n}, {t}, 1>", f"pr::k_row<{n}, {t}, 1, 0>"})
     col = biggest({f"pr::k_col<{n}, {t}>"})
     if row is None or col is None:
         return None
-    return (row["fetch_MB"] + row["write_MB"] + col["fetch_MB"] + col["write_MB"]) * 1e6
+    fields_per_dispatch = col[0] * 16 // (n * n)
+    row, col = row[1], col[1]
+    per_step = (row["fetch_MB"] + row["write_MB"] + col["fetch_MB"] + col["write_MB"]) * 1e6
+    return per_step * nfields / max(1, fields_per_dispatch)
 
 
 def cpu_baseline(cfg, prec, budget_s=12.0):
@@ -491,7 +497,7 @@ def main():
     fine_ms_avg = float(np.mean(fine_ms))
     bpp = bytes_per_point_step(args.prec, args.scheme, args.picard)
     achieved = pts * bpp / (fine_ms_avg * 1e-3) / 1e9
-    traffic = measured_traffic(args.config, args.prec, n) if args.scheme == "ssi" else None
+    traffic = measured_traffic(args.config, args.prec, n, B * s) if args.scheme == "ssi" else None
     step_alg_bytes = B * s * n * n * bpp
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
