@@ -131,6 +131,23 @@ template <int N> struct TwSize {
   static constexpr int value = tw_offset<N>(N) > 0 ? tw_offset<N>(N) : 1;
 };
 
+// Compact table: per stage only the r = 1 row, w^k for k < Ns; the other
+// powers are formed by repeated multiplication in the butterfly (R - 2
+// complex products, a few ulps of extra rounding).  Passed to the
+// transforms wrapped in TwPow, so that the stage code selects the form.
+template <int N> constexpr int tw_offset_pow(int ns_target) {
+  int off = 0;
+  for (int ns = 1; ns < ns_target; ns *= stage_radix<N>(ns))
+    if (ns > 1) off += ns;
+  return off;
+}
+template <int N> struct TwSizePow {
+  static constexpr int value = tw_offset_pow<N>(N) > 0 ? tw_offset_pow<N>(N) : 1;
+};
+template <typename C> struct TwPow {
+  const C* p;
+};
+
 // Fill the per-stage table from g[t] = exp(-2 pi i t / N).  The caller
 // synchronises the block before the first transform.
 template <int N, int NT, typename C>
@@ -162,7 +179,27 @@ template <int N, int LINES, int ESIZE, int OTHER, int PLUS, int THREADS> struct 
   }
   static constexpr bool k16 = ESIZE == 16 && PR_PAD_SHIFT == 3;
   static constexpr int SH = k16 && fit(4) > fit(PR_PAD_SHIFT) ? 4 : PR_PAD_SHIFT;
+  static constexpr int FIT = fit(SH);  // blocks per CU
 };
+
+// Fill the compact table: stage (Ns, R) gets w^k = g[k N / (Ns R)], k < Ns.
+template <int N, int NT, typename C>
+__device__ __forceinline__ void load_stage_twiddles_pow(C* tw, const C* g, int tid) {
+  for (int ns = 1; ns < N; ns *= stage_radix<N>(ns)) {
+    const int R = stage_radix<N>(ns);
+    if (ns == 1) continue;
+    const int off = tw_offset_pow<N>(ns);
+    for (int k = tid; k < ns; k += NT) tw[off + k] = g[k * (N / (ns * R))];
+  }
+}
+
+// The twiddle source of a block: the full per-stage table, or the compact
+// one wrapped in TwPow.
+template <bool POW, typename C>
+__device__ __forceinline__ auto twiddle_source(const C* tw) {
+  if constexpr (POW) return TwPow<C>{tw};
+  else return tw;
+}
 
 // Hooks.  A prologue provides `C load(int i, int line, int e)` for the
 // first stage's i-th input of this thread (line `line`, element `e`) and
@@ -175,13 +212,15 @@ struct NoEpi {
   static constexpr bool kWritesLds = true;
 };
 
-// One Stockham stage over the panel.  tw holds the forward twiddles (laid
-// out per stage by load_stage_twiddles); SIGN = -1 forward,
+// One Stockham stage over the panel.  tw gives the forward twiddles (the
+// per-stage table of load_stage_twiddles, or TwPow over the compact one);
+// SIGN = -1 forward,
 // +1 inverse.  Each of the NT threads owns
 // G groups of eight elements.
-template <int N, int R, int NS, int SIGN, int NT, int G, typename T, class Lay, class Pro, class Epi>
-__device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid,
-                                          Pro& pro, Epi& epi) {
+template <int N, int R, int NS, int SIGN, int NT, int G, typename T, class TW, class Lay, class Pro,
+          class Epi>
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, TW tw, Lay lay, int tid, Pro& pro,
+                                          Epi& epi) {
   constexpr int NB = N / R;        // butterflies per line
   constexpr int BPT = G * 8 / R;   // butterflies per thread
   constexpr bool kFirst = NS == 1;
@@ -207,11 +246,22 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay
   for (int q = 0; q < BPT; ++q) {
     const int k = jj[q] % NS;
     if constexpr (NS > 1) {
+      if constexpr (std::is_same<TW, TwPow<cpx<T>>>::value) {
+        cpx<T> w1 = tw.p[tw_offset_pow<N>(NS) + k];
+        if constexpr (SIGN > 0) w1.y = -w1.y;
+        cpx<T> w = w1;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cpx<T> w = tw[tw_offset<N>(NS) + (r - 1) * NS + k];
-        if constexpr (SIGN > 0) w.y = -w.y;
-        v[q * R + r] = cmul(v[q * R + r], w);
+        for (int r = 1; r < R; ++r) {
+          v[q * R + r] = cmul(v[q * R + r], w);
+          if (r + 1 < R) w = cmul(w, w1);
+        }
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[tw_offset<N>(NS) + (r - 1) * NS + k];
+          if constexpr (SIGN > 0) w.y = -w.y;
+          v[q * R + r] = cmul(v[q * R + r], w);
+        }
       }
     }
     dft_r<R, SIGN>(&v[q * R]);
@@ -225,9 +275,8 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* tw, Lay lay
   if constexpr (kToLds) __syncthreads();
 }
 
-template <int N, int NS, int SIGN, int NT, int G, typename T, class Lay, class Pro, class Epi>
-__device__ __forceinline__ void fft_from(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid, Pro& pro,
-                                         Epi& epi) {
+template <int N, int NS, int SIGN, int NT, int G, typename T, class TW, class Lay, class Pro, class Epi>
+__device__ __forceinline__ void fft_from(cpx<T>* buf, TW tw, Lay lay, int tid, Pro& pro, Epi& epi) {
   if constexpr (NS < N) {
     constexpr int R = stage_radix<N>(NS);
     fft_stage<N, R, NS, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
@@ -239,10 +288,10 @@ __device__ __forceinline__ void fft_from(cpx<T>* buf, const cpx<T>* tw, Lay lay,
 // Requires NT * 8 * G == (number of lines) * N.  Unless a prologue
 // supplies the inputs, `buf` must be complete (synchronised) on entry.  On
 // exit the block is synchronised if the last stage wrote LDS.
-template <int N, int SIGN, int NT, typename T, int G = 1, class Lay, class Pro = NoPro,
+template <int N, int SIGN, int NT, typename T, int G = 1, class TW, class Lay, class Pro = NoPro,
           class Epi = NoEpi>
-__device__ __forceinline__ void fft_lines(cpx<T>* buf, const cpx<T>* tw, Lay lay, int tid,
-                                          Pro pro = Pro{}, Epi epi = Epi{}) {
+__device__ __forceinline__ void fft_lines(cpx<T>* buf, TW tw, Lay lay, int tid, Pro pro = Pro{},
+                                          Epi epi = Epi{}) {
   fft_from<N, 1, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
 }
 

@@ -171,23 +171,41 @@ __device__ __forceinline__ void row_split_store(const cpx<T>* panel, cpx<T>* S, 
 // row pairs of one column in consecutive lanes; with four pairs per tile
 // a stride = 4 (mod 16) makes the 8 lanes served together (4 pairs x 2
 // columns, direct or mirrored) fall in distinct 16-byte bank quads.
+// The plan also picks the twiddle table: the full per-stage one, or (for
+// 16-byte elements, where it lets one more work-group share a CU) the
+// compact one of r = 1 rows, whose other powers the butterflies multiply
+// out.  TWN is the table's length in elements.
 template <int N, typename T> struct RowLS {
   static constexpr bool kQuad = sizeof(T) == 8 && RowCfg<N, T>::PAIRS == 4 && N >= 128;
-  static constexpr int SH =
-      LdsPlan<N, RowCfg<N, T>::PAIRS, (int)sizeof(cpx<T>),
-              TwSize<N>::value * (int)sizeof(cpx<T>) + (RowCfg<N, T>::NT / 64 + 1) * 8 + 64,
-              kQuad ? 4 : 1, RowCfg<N, T>::NT>::SH;
+  static constexpr int E = (int)sizeof(cpx<T>), kOther = (RowCfg<N, T>::NT / 64 + 1) * 8 + 64;
+  using PF = LdsPlan<N, RowCfg<N, T>::PAIRS, E, TwSize<N>::value * E + kOther, kQuad ? 4 : 1,
+                     RowCfg<N, T>::NT>;
+  using PP = LdsPlan<N, RowCfg<N, T>::PAIRS, E, TwSizePow<N>::value * E + kOther, kQuad ? 4 : 1,
+                     RowCfg<N, T>::NT>;
+  static constexpr bool TWP = E == 16 && PP::FIT > PF::FIT;
+  static constexpr int TWN = TWP ? TwSizePow<N>::value : TwSize<N>::value;
+  static constexpr int SH = TWP ? PP::SH : PF::SH;
   static constexpr int value = N + (N >> SH) + (kQuad ? 4 : 1);
 };
 
 // Column-pass panel: CT whole columns next to the twiddles (and, for the
 // Picard pass, the symbol table).
 template <int N, typename T, int EXTRA = 0> struct ColLS {
-  static constexpr int SH =
-      LdsPlan<N, ColCfg<N>::CT, (int)sizeof(cpx<T>), TwSize<N>::value * (int)sizeof(cpx<T>) + EXTRA + 64,
-              1, ColCfg<N>::NT>::SH;
+  static constexpr int E = (int)sizeof(cpx<T>);
+  using PF = LdsPlan<N, ColCfg<N>::CT, E, TwSize<N>::value * E + EXTRA + 64, 1, ColCfg<N>::NT>;
+  using PP = LdsPlan<N, ColCfg<N>::CT, E, TwSizePow<N>::value * E + EXTRA + 64, 1, ColCfg<N>::NT>;
+  static constexpr bool TWP = E == 16 && PP::FIT > PF::FIT;
+  static constexpr int TWN = TWP ? TwSizePow<N>::value : TwSize<N>::value;
+  static constexpr int SH = TWP ? PP::SH : PF::SH;
   static constexpr int value = N + (N >> SH) + 1;
 };
+
+// Stage the block's twiddle table in LDS in the plan's form.
+template <int N, int NT, bool TWP, typename C>
+__device__ __forceinline__ void load_twiddles(C* tw, const C* g, int tid) {
+  if constexpr (TWP) load_stage_twiddles_pow<N, NT>(tw, g, tid);
+  else load_stage_twiddles<N, NT>(tw, g, tid);
+}
 
 // The step parameters of field f: the launch argument, or the field's entry
 // of the descriptor's parameter table.
@@ -216,8 +234,8 @@ __device__ __forceinline__ void row_rebuild_entry(cpx<T>* panel, Lay lay, int p,
 // Middle row pass of one tile whose pair spectra are in the panel: inverse
 // transforms, the right-hand side (with the tile's FP64 sum of f for the
 // mass multiplier), forward transforms, split and store to S.
-template <int N, typename T, int RHS>
-__device__ __forceinline__ void row_mid_tile(cpx<T>* panel, const cpx<T>* tw, double* red,
+template <int N, typename T, int RHS, class TW>
+__device__ __forceinline__ void row_mid_tile(cpx<T>* panel, TW tw, double* red,
                                              double* __restrict__ partials, cpx<T>* S, int64_t f,
                                              int tile, T a, T dt, int conservative, int tid) {
   using Cfg = RowCfg<N, T>;
@@ -245,8 +263,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   constexpr int LS = RowLS<N, T>::value;
   using Lay = LinePanel<LS, RowLS<N, T>::SH>;
   __shared__ C panel[PAIRS * LS];
-  __shared__ C tw[TwSize<N>::value];
+  __shared__ C tw_s[RowLS<N, T>::TWN];
   __shared__ double red[NT / 64 + 1];
+  const auto tw = twiddle_source<RowLS<N, T>::TWP>((const C*)tw_s);
 
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / TILES;
@@ -255,7 +274,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   const int tile = blockIdx.x % TILES;
   const int r0 = tile * TR;
   const Lay lay{};
-  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  load_twiddles<N, NT, RowLS<N, T>::TWP>(tw_s, tw_g, tid);
   const T a = (T)sp.a, dt = (T)sp.dt;
   double fsum = 0.0;
   const double* u = desc->in_base + (desc->in_offs ? desc->in_offs[f] : f * (int64_t)N * N);
@@ -279,8 +298,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   constexpr int LS = RowLS<N, T>::value;
   using Lay = LinePanel<LS, RowLS<N, T>::SH>;
   __shared__ C panel[PAIRS * LS];
-  __shared__ C tw[TwSize<N>::value];
+  __shared__ C tw_s[RowLS<N, T>::TWN];
   __shared__ double red[NT / 64 + 1];
+  const auto tw = twiddle_source<RowLS<N, T>::TWP>((const C*)tw_s);
 
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / TILES;
@@ -289,7 +309,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   const int tile = blockIdx.x % TILES;
   const int r0 = tile * TR;
   const Lay lay{};
-  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  load_twiddles<N, NT, RowLS<N, T>::TWP>(tw_s, tw_g, tid);
   C* S = spec + f * (int64_t)(N / 2) * N;
   const T a = (T)sp.a, dt = (T)sp.dt;
   // rebuild Z_j[kx] = R_2j[kx] + i R_2j+1[kx] for kx = 0..N-1
@@ -352,8 +372,8 @@ template <int N, typename T> using ColPanel = ColLS<N, T, PR_S2_LDS ? N * 8 : 0>
 // (inputs from `pro`), division by the symbol (the packed column c = 0 with
 // the mass correction), inverse transform straight to P.  corr_sh must not
 // be read by any thread of the block from a previous tile any more.
-template <int N, typename T, class Pro>
-__device__ __forceinline__ void col_tile(cpx<T>* panel, const cpx<T>* tw, double* corr_sh,
+template <int N, typename T, class TW, class Pro>
+__device__ __forceinline__ void col_tile(cpx<T>* panel, TW tw, double* corr_sh,
                                          const double* s2, const double* __restrict__ partials,
                                          cpx<T>* P, int64_t f, int c0, const StepParams& sp,
                                          int tid, Pro pro) {
@@ -413,7 +433,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   using C = cpx<T>;
   constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
   __shared__ C panel[CT * ColPanel<N, T>::value];
-  __shared__ C tw[TwSize<N>::value];
+  __shared__ C tw_s[ColPanel<N, T>::TWN];
+  const auto tw = twiddle_source<ColPanel<N, T>::TWP>((const C*)tw_s);
 #if PR_S2_LDS
   __shared__ double s2[N];
 #else
@@ -427,7 +448,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   const StepParams sp = field_params(desc, f, sp_arg);
   const int c0 = (blockIdx.x % BLK) * CT;
   C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
-  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  load_twiddles<N, NT, ColPanel<N, T>::TWP>(tw_s, tw_g, tid);
 #if PR_S2_LDS
   for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
 #endif
@@ -469,13 +490,14 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   constexpr int LS = CL::value;
   using Lay = LinePanel<LS, CL::SH>;
   __shared__ C panel[CT * LS];
-  __shared__ C tw[TwSize<N>::value];
+  __shared__ C tw_s[CL::TWN];
+  const auto tw = twiddle_source<CL::TWP>((const C*)tw_s);
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / BLK;
   if (f >= desc->nfields) return;
   const int c0 = (blockIdx.x % BLK) * CT;
   C* P = xspec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
-  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  load_twiddles<N, NT, CL::TWP>(tw_s, tw_g, tid);
   __syncthreads();
   fft_lines<N, -1, NT, T>(panel, tw, Lay{}, tid, ColLoad<T>{P, N}, ColStore<T>{P, N});
 }
@@ -529,8 +551,9 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   constexpr int E0 = (N + NT - 1) / NT;
   using Lay = LinePanel<LS, CL::SH>;
   __shared__ C panel[CT * LS];
-  __shared__ C tw[TwSize<N>::value];
+  __shared__ C tw_s[CL::TWN];
   __shared__ double s2[N];
+  const auto tw = twiddle_source<CL::TWP>((const C*)tw_s);
 
   const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / BLK;
@@ -540,7 +563,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   const Lay lay{};
   C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
   C* X = xspec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
-  load_stage_twiddles<N, NT>(tw, tw_g, tid);
+  load_twiddles<N, NT, CL::TWP>(tw_s, tw_g, tid);
   for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
   __syncthreads();
   fft_lines<N, -1, NT, T>(panel, tw, lay, tid, ColLoad<T>{P, N}, CnEpi<N, T, MODE>{X, s2, sp, c0});
