@@ -133,12 +133,15 @@ template <int N> struct TwSize {
 
 // Compact table: per stage only the r = 1 row, w^k for k < Ns; the other
 // powers are formed by repeated multiplication in the butterfly (R - 2
-// complex products, a few ulps of extra rounding).  Passed to the
-// transforms wrapped in TwPow, so that the stage code selects the form.
+// complex products, a few ulps of extra rounding).  Stages with Ns > 64
+// store that row factored, w^k = w^(8 (k / 8)) w^(k % 8): Ns / 8 + 8
+// entries and one more product.  Passed to the transforms wrapped in
+// TwPow, so that the stage code selects the form.
+constexpr int tw_pow_rows(int ns) { return ns > 64 ? ns / 8 + 8 : ns; }
 template <int N> constexpr int tw_offset_pow(int ns_target) {
   int off = 0;
   for (int ns = 1; ns < ns_target; ns *= stage_radix<N>(ns))
-    if (ns > 1) off += ns;
+    if (ns > 1) off += tw_pow_rows(ns);
   return off;
 }
 template <int N> struct TwSizePow {
@@ -182,14 +185,20 @@ template <int N, int LINES, int ESIZE, int OTHER, int PLUS, int THREADS> struct 
   static constexpr int FIT = fit(SH);  // blocks per CU
 };
 
-// Fill the compact table: stage (Ns, R) gets w^k = g[k N / (Ns R)], k < Ns.
+// Fill the compact table: stage (Ns, R) gets w^k = g[k N / (Ns R)], k < Ns
+// (factored into w^(8a), a < Ns / 8, and w^b, b < 8, when Ns > 64).
 template <int N, int NT, typename C>
 __device__ __forceinline__ void load_stage_twiddles_pow(C* tw, const C* g, int tid) {
   for (int ns = 1; ns < N; ns *= stage_radix<N>(ns)) {
     const int R = stage_radix<N>(ns);
     if (ns == 1) continue;
-    const int off = tw_offset_pow<N>(ns);
-    for (int k = tid; k < ns; k += NT) tw[off + k] = g[k * (N / (ns * R))];
+    const int off = tw_offset_pow<N>(ns), stride = N / (ns * R);
+    if (ns > 64) {
+      for (int a = tid; a < ns / 8; a += NT) tw[off + a] = g[8 * a * stride];
+      for (int b = tid; b < 8; b += NT) tw[off + ns / 8 + b] = g[b * stride];
+    } else {
+      for (int k = tid; k < ns; k += NT) tw[off + k] = g[k * stride];
+    }
   }
 }
 
@@ -247,7 +256,10 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, TW tw, Lay lay, int tid, 
     const int k = jj[q] % NS;
     if constexpr (NS > 1) {
       if constexpr (std::is_same<TW, TwPow<cpx<T>>>::value) {
-        cpx<T> w1 = tw.p[tw_offset_pow<N>(NS) + k];
+        constexpr int off = tw_offset_pow<N>(NS);
+        cpx<T> w1;
+        if constexpr (NS > 64) w1 = cmul(tw.p[off + k / 8], tw.p[off + NS / 8 + k % 8]);
+        else w1 = tw.p[off + k];
         if constexpr (SIGN > 0) w1.y = -w1.y;
         cpx<T> w = w1;
 #pragma unroll
