@@ -226,12 +226,13 @@ struct NoEpi {
 // SIGN = -1 forward,
 // +1 inverse.  Each of the NT threads owns
 // G groups of eight elements.
-template <int N, int R, int NS, int SIGN, int NT, int G, typename T, class TW, class Lay, class Pro,
-          class Epi>
+template <int N, int R, int NS, int SIGN, int NT, int G, bool LF, typename T, class TW, class Lay,
+          class Pro, class Epi>
 __device__ __forceinline__ void fft_stage(cpx<T>* buf, TW tw, Lay lay, int tid, Pro& pro,
                                           Epi& epi) {
   constexpr int NB = N / R;        // butterflies per line
   constexpr int BPT = G * 8 / R;   // butterflies per thread
+  constexpr int LINES = NT * G * 8 / N;
   constexpr bool kFirst = NS == 1;
   constexpr bool kLast = NS * R == N;
   constexpr bool kFromPro = kFirst && !std::is_same<Pro, NoPro>::value;
@@ -241,8 +242,8 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, TW tw, Lay lay, int tid, 
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
     const int b = tid + q * NT;
-    line[q] = b / NB;
-    jj[q] = b % NB;
+    line[q] = LF ? b % LINES : b / NB;
+    jj[q] = LF ? b / LINES : b % NB;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if constexpr (kFromPro) v[q * R + r] = pro.load(q * R + r, line[q], jj[q] + r * NB);
@@ -287,24 +288,28 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, TW tw, Lay lay, int tid, 
   if constexpr (kToLds) __syncthreads();
 }
 
-template <int N, int NS, int SIGN, int NT, int G, typename T, class TW, class Lay, class Pro, class Epi>
+template <int N, int NS, int SIGN, int NT, int G, bool LF, typename T, class TW, class Lay, class Pro,
+          class Epi>
 __device__ __forceinline__ void fft_from(cpx<T>* buf, TW tw, Lay lay, int tid, Pro& pro, Epi& epi) {
   if constexpr (NS < N) {
     constexpr int R = stage_radix<N>(NS);
-    fft_stage<N, R, NS, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
-    fft_from<N, NS * R, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
+    fft_stage<N, R, NS, SIGN, NT, G, LF, T>(buf, tw, lay, tid, pro, epi);
+    fft_from<N, NS * R, SIGN, NT, G, LF, T>(buf, tw, lay, tid, pro, epi);
   }
 }
 
 // Unnormalised length-N DFT of every line in the panel, in place.
 // Requires NT * 8 * G == (number of lines) * N.  Unless a prologue
 // supplies the inputs, `buf` must be complete (synchronised) on entry.  On
-// exit the block is synchronised if the last stage wrote LDS.
-template <int N, int SIGN, int NT, typename T, int G = 1, class TW, class Lay, class Pro = NoPro,
-          class Epi = NoEpi>
+// exit the block is synchronised if the last stage wrote LDS.  Butterfly b
+// of a stage belongs to line b / (N/R), position b % (N/R) (a line's
+// elements in consecutive lanes) or, with LF, to line b % lines, position
+// b / lines (the lines in consecutive lanes).
+template <int N, int SIGN, int NT, typename T, int G = 1, bool LF = false, class TW, class Lay,
+          class Pro = NoPro, class Epi = NoEpi>
 __device__ __forceinline__ void fft_lines(cpx<T>* buf, TW tw, Lay lay, int tid, Pro pro = Pro{},
                                           Epi epi = Epi{}) {
-  fft_from<N, 1, SIGN, NT, G, T>(buf, tw, lay, tid, pro, epi);
+  fft_from<N, 1, SIGN, NT, G, LF, T>(buf, tw, lay, tid, pro, epi);
 }
 
 // Deterministic block sum of one double per thread (fixed tree order).

@@ -78,6 +78,38 @@ __device__ __forceinline__ int opaque_tid(int tid) {
   return tid;
 }
 
+// ------------------------------------------------------- spectral layout
+//
+// A field's half spectrum (N/2 columns kx of N rows ky, complex) is stored
+// in blocks of W columns, row-major inside a block: (c, r) at
+// (c / W) N W + r W + c % W.  W = 1 is plain column-major.  At N >= 1024,
+// W = ColCfg<N>::CT: a column tile is then one contiguous block and a row
+// tile reads TR W consecutive values per block instead of TR (measured
+// faster there; at N <= 512 the column pass lost more than the row pass
+// gained).  The column transforms then put a tile's lines in consecutive
+// lanes (fft_lines' LF), so that their global loads and stores run along
+// the block.
+template <int N> struct SpecLayout {
+  static constexpr int W = N >= 1024 ? ColCfg<N>::CT : 1;
+  static constexpr bool LF = W > 1;
+};
+template <int N> __device__ __forceinline__ int64_t spec_at(int c, int r) {
+  constexpr int W = SpecLayout<N>::W;
+  return (int64_t)(c / W) * N * W + (int64_t)r * W + (c % W);
+}
+// Offset of (line, e) from the start of a column tile (W divides CT).
+template <int N> __device__ __forceinline__ int64_t col_at(int line, int e) {
+  constexpr int W = SpecLayout<N>::W;
+  return (int64_t)(line / W) * N * W + (int64_t)e * W + (line % W);
+}
+// Entry e of a row tile's (pair, column) loops: W consecutive columns in
+// consecutive lanes, then the pairs, then the column blocks.
+template <int N, int PAIRS> __device__ __forceinline__ void row_entry(int e, int& p, int& c) {
+  constexpr int W = SpecLayout<N>::W;
+  p = (e / W) % PAIRS;
+  c = (e / (W * PAIRS)) * W + e % W;
+}
+
 // --------------------------------------------------------------- row pass
 
 // What the row pass transforms, on the two rows carried by one complex
@@ -150,7 +182,8 @@ __device__ __forceinline__ void row_split_store(const cpx<T>* panel, cpx<T>* S, 
                                                 Lay lay) {
   using C = cpx<T>;
   for (int e = tid; e < PAIRS * (N / 2); e += NT) {
-    const int p = e % PAIRS, c = e / PAIRS;
+    int p, c;
+    row_entry<N, PAIRS>(e, p, c);
     C A, B;
     if (c == 0) {
       const C z0 = panel[lay(p, 0)], zn = panel[lay(p, N / 2)];
@@ -162,8 +195,8 @@ __device__ __forceinline__ void row_split_store(const cpx<T>* panel, cpx<T>* S, 
       A = C{h * (z.x + w.x), h * (z.y - w.y)};
       B = C{h * (z.y + w.y), h * (w.x - z.x)};
     }
-    S[(int64_t)c * N + r0 + 2 * p] = A;
-    S[(int64_t)c * N + r0 + 2 * p + 1] = B;
+    S[spec_at<N>(c, r0 + 2 * p)] = A;
+    S[spec_at<N>(c, r0 + 2 * p + 1)] = B;
   }
 }
 
@@ -314,9 +347,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   const T a = (T)sp.a, dt = (T)sp.dt;
   // rebuild Z_j[kx] = R_2j[kx] + i R_2j+1[kx] for kx = 0..N-1
   for (int e = tid; e < PAIRS * (N / 2); e += NT) {
-    const int p = e % PAIRS, c = e / PAIRS;
-    row_rebuild_entry<N, T>(panel, lay, p, c, S[(int64_t)c * N + r0 + 2 * p],
-                            S[(int64_t)c * N + r0 + 2 * p + 1]);
+    int p, c;
+    row_entry<N, PAIRS>(e, p, c);
+    row_rebuild_entry<N, T>(panel, lay, p, c, S[spec_at<N>(c, r0 + 2 * p)],
+                            S[spec_at<N>(c, r0 + 2 * p + 1)]);
   }
   __syncthreads();
   if constexpr (MODE == ROW_LAST) {
@@ -330,18 +364,17 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
 
 // ------------------------------------------------------------ column pass
 
-template <typename T> struct ColLoad {
+// Element e of line (column) `line` of the column tile starting at P.
+template <int N, typename T> struct ColLoad {
   const cpx<T>* P;
-  int n;
-  __device__ __forceinline__ cpx<T> load(int, int line, int e) const { return P[line * n + e]; }
+  __device__ __forceinline__ cpx<T> load(int, int line, int e) const { return P[col_at<N>(line, e)]; }
   __device__ __forceinline__ void after_reads() const {}
 };
 
-template <typename T> struct ColStore {
+template <int N, typename T> struct ColStore {
   static constexpr bool kWritesLds = false;
   cpx<T>* P;
-  int n;
-  __device__ __forceinline__ void apply(int line, int e, cpx<T>& v) const { P[line * n + e] = v; }
+  __device__ __forceinline__ void apply(int line, int e, cpx<T>& v) const { P[col_at<N>(line, e)] = v; }
 };
 
 // 1 / (N^2 ((1 + S dt) + dt eps^2 mu_k)) for bin (ky, kx)
@@ -394,7 +427,7 @@ __device__ __forceinline__ void col_tile(cpx<T>* panel, TW tw, double* corr_sh,
   }
   // the forward transform's last stage ends with a block barrier, which
   // also publishes corr_sh
-  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, pro, DivideEpi<T>{s2, sp, c0});
+  fft_lines<N, -1, NT, T, 1, SpecLayout<N>::LF>(panel, tw, lay, tid, pro, DivideEpi<T>{s2, sp, c0});
   if (c0 == 0) {
     // packed column: z = A + iB with A the kx = 0 and B the kx = N/2
     // column spectra (both Hermitian in ky); scale A and B separately
@@ -421,7 +454,7 @@ __device__ __forceinline__ void col_tile(cpx<T>* panel, TW tw, double* corr_sh,
     }
     __syncthreads();
   }
-  fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, ColStore<T>{P, N});
+  fft_lines<N, +1, NT, T, 1, SpecLayout<N>::LF>(panel, tw, lay, tid, NoPro{}, ColStore<N, T>{P});
 }
 
 // One block per column tile.
@@ -453,7 +486,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
 #endif
   __syncthreads();
-  col_tile<N, T>(panel, tw, &corr_sh, s2, partials, P, f, c0, sp, tid, ColLoad<T>{P, N});
+  col_tile<N, T>(panel, tw, &corr_sh, s2, partials, P, f, c0, sp, tid, ColLoad<N, T>{P});
 }
 
 // ------------------------------------------------ Crank-Nicolson + Picard
@@ -499,7 +532,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   C* P = xspec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
   load_twiddles<N, NT, CL::TWP>(tw_s, tw_g, tid);
   __syncthreads();
-  fft_lines<N, -1, NT, T>(panel, tw, Lay{}, tid, ColLoad<T>{P, N}, ColStore<T>{P, N});
+  fft_lines<N, -1, NT, T, 1, SpecLayout<N>::LF>(panel, tw, Lay{}, tid, ColLoad<N, T>{P},
+                                                  ColStore<N, T>{P});
 }
 
 // Last forward stage of a Picard column pass, for every column but the
@@ -515,7 +549,7 @@ template <int N, typename T, int MODE> struct CnEpi {
     if (col == 0) return;  // the packed column is done after the transform
     const double q = 0.5 * sp.lam * (s2[col] + s2[ky]);
     const T h = (T)(0.5 * sp.dt);
-    cpx<T>* xp = X + (int64_t)line * N + ky;
+    cpx<T>* xp = X + col_at<N>(line, ky);
     const cpx<T> x = *xp;
     cpx<T> K = x;
     if constexpr ((MODE & CN_FIRST) != 0) {
@@ -566,7 +600,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   load_twiddles<N, NT, CL::TWP>(tw_s, tw_g, tid);
   for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
   __syncthreads();
-  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, ColLoad<T>{P, N}, CnEpi<N, T, MODE>{X, s2, sp, c0});
+  fft_lines<N, -1, NT, T, 1, SpecLayout<N>::LF>(panel, tw, lay, tid, ColLoad<N, T>{P},
+                                                  CnEpi<N, T, MODE>{X, s2, sp, c0});
   if (c0 == 0) {
     const double h = 0.5 * sp.dt;
     C vals[E0], xnew[E0];
@@ -580,7 +615,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
           if (ky == 0) z.x = (T)0;
           if (kr == 0) w.x = (T)0;
         }
-        const C x = X[ky], xr = X[kr];
+        const C x = X[col_at<N>(0, ky)], xr = X[col_at<N>(0, kr)];
         const double q0 = 0.5 * sp.lam * (s2[0] + s2[ky]), qn = 0.5 * sp.lam * (s2[N / 2] + s2[ky]);
         C K = x, Kr = xr;
         if constexpr ((MODE & CN_FIRST) != 0) {
@@ -602,12 +637,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
       const int ky = tid + q * NT;
       if (ky < N) {
         panel[lay(0, ky)] = vals[q];
-        if constexpr (MODE != 0) X[ky] = xnew[q];
+        if constexpr (MODE != 0) X[col_at<N>(0, ky)] = xnew[q];
       }
     }
     __syncthreads();
   }
-  fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, ColStore<T>{P, N});
+  fft_lines<N, +1, NT, T, 1, SpecLayout<N>::LF>(panel, tw, lay, tid, NoPro{}, ColStore<N, T>{P});
 }
 
 // ---------------------------------------------------- on-chip resident step
