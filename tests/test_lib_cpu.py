@@ -189,3 +189,15 @@ def test_working_set_setting(L):
     assert lib.pr_set_fine_working_set(0) == L.PR_OK
     assert lib.pr_get_fine_working_set(256, L.PR_F32) == 0
     assert lib.pr_set_fine_working_set(256 << 20) == L.PR_OK
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark runs on one GPU: asked for more it exits with status 2
+    and says so, before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
