@@ -339,20 +339,36 @@ typedef enum { PR_PLAN_AUTO = 0, PR_PLAN_STREAM = 1, PR_PLAN_RESIDENT = 2 } pr_p
  *                        C = 16 (1..4 hidden layers), C = 32 (1..2) and
  *                        C = 48 (1, PR_BF16 only); other shapes fall back
  *                        to LAYERED;
+ *   PR_CNN_PLAN_FOLDED   one launch per hidden layer: the first convolution
+ *                        (1 -> C) runs inside the first hidden layer's
+ *                        launch, on that layer's input tile in LDS; at
+ *                        C = 32 the last convolution's per-tap products are
+ *                        formed in the last hidden layer's epilogue, and a
+ *                        small kernel sums them over the 3 x 3 taps; the
+ *                        first layer's output and the last hidden layer's
+ *                        never go through HBM.  Bitwise the same result as
+ *                        LAYERED; networks with at least one hidden layer,
+ *                        other shapes fall back to LAYERED;
  *   PR_CNN_PLAN_AUTO     the autotuner's measured choice for the shape if
- *                        pr_autotune_coarse ran, else LAYERED.
+ *                        pr_autotune_coarse ran, else FOLDED for PR_BF16X2
+ *                        networks with a hidden layer, else LAYERED.
  * Training (pr_cnn_backward) always runs layer by layer. */
-typedef enum { PR_CNN_PLAN_AUTO = 0, PR_CNN_PLAN_LAYERED = 1, PR_CNN_PLAN_FUSED = 2 } pr_cnn_plan;
+typedef enum {
+  PR_CNN_PLAN_AUTO = 0,
+  PR_CNN_PLAN_LAYERED = 1,
+  PR_CNN_PLAN_FUSED = 2,
+  PR_CNN_PLAN_FOLDED = 3
+} pr_cnn_plan;
 
 pr_status pr_set_coarse_plan(int32_t plan);
 
-/* The plan pr_coarse_apply will use for g on N x N fields (LAYERED or FUSED),
- * or -1 if g is not a valid network. */
+/* The plan pr_coarse_apply will use for g on N x N fields (LAYERED, FUSED
+ * or HEAD), or -1 if g is not a valid network. */
 int32_t pr_get_coarse_plan(const pr_coarse* g, int32_t n);
 
-/* Times both plans for g on the caller's batch (u_in -> g_out, workspace
- * as for pr_coarse_apply) and records the faster as the AUTO choice for
- * the shape (channels, n_layers, prec).  *chosen receives it. */
+/* Times every plan available for g on the caller's batch (u_in -> g_out,
+ * workspace as for pr_coarse_apply) and records the fastest as the AUTO
+ * choice for the shape (channels, n_layers, prec).  *chosen receives it. */
 pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nfields,
                              const double* u_in, double* g_out, void* ws, size_t ws_bytes,
                              void* stream, int32_t* chosen);

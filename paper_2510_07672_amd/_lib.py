@@ -33,7 +33,7 @@ EXPORTED = [
     "pr_status_string", "pr_last_error", "pr_abi_version",
 ]
 PR_PLAN_AUTO, PR_PLAN_STREAM, PR_PLAN_RESIDENT = 0, 1, 2
-PR_CNN_PLAN_AUTO, PR_CNN_PLAN_LAYERED, PR_CNN_PLAN_FUSED = 0, 1, 2
+PR_CNN_PLAN_AUTO, PR_CNN_PLAN_LAYERED, PR_CNN_PLAN_FUSED, PR_CNN_PLAN_FOLDED = 0, 1, 2, 3
 
 
 class Problem(C.Structure):

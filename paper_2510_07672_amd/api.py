@@ -321,12 +321,15 @@ def pr_autotune_fine(p: Problem, u_in: torch.Tensor) -> str:
     return _PLAN_NAME[ch.value]
 
 
-_CPLAN = {"auto": L.PR_CNN_PLAN_AUTO, "layered": L.PR_CNN_PLAN_LAYERED, "fused": L.PR_CNN_PLAN_FUSED}
+_CPLAN = {"auto": L.PR_CNN_PLAN_AUTO, "layered": L.PR_CNN_PLAN_LAYERED, "fused": L.PR_CNN_PLAN_FUSED,
+          "folded": L.PR_CNN_PLAN_FOLDED}
 _CPLAN_NAME = {v: k for k, v in _CPLAN.items()}
 
 
 def pr_set_coarse_plan(plan: str) -> None:
-    """Network inference plan, process-wide: 'auto', 'layered' or 'fused'."""
+    """Network inference plan, process-wide: 'auto', 'layered', 'fused' or
+    'folded' (one launch per hidden layer, with the first convolution and,
+    at 32 channels, the last one's per-tap products folded into them)."""
     L.check(L.lib().pr_set_coarse_plan(_CPLAN[plan]), "pr_set_coarse_plan")
 
 
@@ -335,7 +338,8 @@ def pr_get_coarse_plan(g: "CnnCoarse", n: int) -> str:
 
 
 def pr_autotune_coarse(p: Problem, g: "CnnCoarse", u_in: torch.Tensor) -> str:
-    """Time both network plans on u_in and keep the faster as the 'auto' choice."""
+    """Time the network plans available for g on u_in and keep the fastest
+    as the 'auto' choice."""
     B = _fields(u_in, p.n, "u_in")
     pc, gc = p.c(), g.c()
     out = torch.empty_like(u_in)

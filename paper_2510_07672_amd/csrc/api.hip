@@ -1185,7 +1185,8 @@ pr_status pr_set_fine_plan(int32_t n, pr_dtype prec, int32_t plan) {
 }
 
 pr_status pr_set_coarse_plan(int32_t plan) {
-  if (plan != PR_CNN_PLAN_AUTO && plan != PR_CNN_PLAN_LAYERED && plan != PR_CNN_PLAN_FUSED)
+  if (plan != PR_CNN_PLAN_AUTO && plan != PR_CNN_PLAN_LAYERED && plan != PR_CNN_PLAN_FUSED &&
+      plan != PR_CNN_PLAN_FOLDED)
     return fail(PR_ERR_INVALID_ARG, "coarse plan %d unknown", plan);
   cnn_set_plan(plan);
   return PR_OK;
@@ -1211,14 +1212,17 @@ pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nf
     return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, c.used);
   if ((st = cnn_lds_once()) != PR_OK) return st;
   int best = PR_CNN_PLAN_LAYERED;
-  if (cnn_fused_available(g->channels, g->n_layers, g->prec)) {
+  const bool fused = cnn_fused_available(g->channels, g->n_layers, g->prec) && g->n_layers <= 10;
+  const bool folded = cnn_folded_available(g->channels, g->n_layers, g->prec);
+  if (fused || folded) {
     hipStream_t s = (hipStream_t)stream;
     Events ev;
     if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
     const int saved = cnn_get_plan();
     PR_HIP(coarse_setup(p, g, w, s));
-    float ms[3] = {0, 0, 0};
-    for (int plan = PR_CNN_PLAN_LAYERED; plan <= PR_CNN_PLAN_FUSED; ++plan) {
+    float ms[4] = {0, 0, 0, 0};
+    for (int plan = PR_CNN_PLAN_LAYERED; plan <= PR_CNN_PLAN_FOLDED; ++plan) {
+      if ((plan == PR_CNN_PLAN_FUSED && !fused) || (plan == PR_CNN_PLAN_FOLDED && !folded)) continue;
       cnn_set_plan(plan);
       hipError_t e = coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s);  // warm-up
       if (e == hipSuccess) e = hipEventRecord(ev.e[0], s);
@@ -1233,7 +1237,8 @@ pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nf
       ms[plan] = event_ms(ev.e[0], ev.e[1]);
     }
     cnn_set_plan(saved);
-    best = ms[PR_CNN_PLAN_FUSED] <= ms[PR_CNN_PLAN_LAYERED] ? PR_CNN_PLAN_FUSED : PR_CNN_PLAN_LAYERED;
+    for (int plan = PR_CNN_PLAN_FUSED; plan <= PR_CNN_PLAN_FOLDED; ++plan)
+      if (ms[plan] > 0 && ms[plan] <= ms[best]) best = plan;
   }
   cnn_record_tuned(g->channels, g->n_layers, g->prec, best);
   if (chosen) *chosen = best;

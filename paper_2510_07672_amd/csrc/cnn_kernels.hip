@@ -21,6 +21,10 @@
 //                 dimension, then a 3x3 gather of the per-tap products;
 //                 plus the residual, written in FP64, with per-tile FP64
 //                 sums of (G(u) - u).
+//   Folded inference plan: k_cnn_hidden computes the first layer on its own
+//                 input tile (FIRST) and, at C = 32, the last layer's
+//                 per-tap products in its epilogue (TAIL);
+//                 k_cnn_last_gather then sums the products over the taps.
 //   k_cnn_fix     the uniform mass fix and the limiter.
 #include <hip/hip_runtime.h>
 
@@ -179,6 +183,43 @@ template <int C, bool SPLIT> struct HidTile {
   static constexpr int PS = SPLIT ? 2 * C + 8 : C + 8;
   static constexpr int LO = SPLIT ? C : 0;   // offset of the lo values
   static constexpr size_t BYTES = (size_t)HidCfg<C>::TPIX * PS * 2;
+  // With the first layer computed in the same launch: after the tile, the
+  // (TH+4) x (TW+4) patch of the state that the tile's first-layer outputs
+  // read, then the first layer's C x 9 weights and C biases (FP32).
+  static constexpr int UH = HidCfg<C>::TH + 4, UW = HidCfg<C>::TW + 4;
+  static constexpr size_t FIRST_BYTES = BYTES + (size_t)(UH * UW + 10 * C) * 4;
+};
+
+template <int C> struct LastCfg {
+  static constexpr int T = 16, WI = T + 2, PX = WI * WI;
+  static constexpr int KB = (C + 31) / 32;   // 32-channel steps
+};
+
+// Lane (g, r) holds W[c = 32 kb + 8 g + j][tap r], j < 8, as hi and lo
+// (zero beyond C channels or nine taps).
+template <int C>
+__device__ __forceinline__ void last_weights(const float* __restrict__ W, int lane,
+                                             bf16x8* hi, bf16x8* lo) {
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int kb = 0; kb < LastCfg<C>::KB; ++kb) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = kb * 32 + 8 * g + j;
+      const float v = (c < C && r < 9) ? W[c * 9 + r] : 0.f;
+      const __bf16 h = (__bf16)v;
+      hi[kb][j] = h;
+      lo[kb][j] = (__bf16)(v - (float)h);
+    }
+  }
+}
+
+// The first layer's inputs, for a hidden-layer launch that also computes it.
+struct FirstIn {
+  const double* u_base;   // field f at u_base + (u_offs ? u_offs[f] : f N^2)
+  const int64_t* u_offs;
+  const float* W;         // [C][9] FP32, torch order
+  const float* b;         // [C]
 };
 
 // Whether a hidden layer overlaps one 16-pixel block's epilogue with the
@@ -188,17 +229,39 @@ template <int C, bool SPLIT> struct HidTile {
 // SIMD) and C = 48 (2 -> 1) lose more than they gain.
 template <int C, bool SPLIT> constexpr bool hidden_pipelined() { return SPLIT && C == 32; }
 
-template <int C, bool SPLIT>
+// A hidden layer C -> C, persistent over (TH x TW) output tiles.
+//
+// With FIRST the layer's input tile is not read from HBM: the work-group
+// computes it, the first layer 1 -> C on the (TH+2) x (TW+2) tile pixels
+// from the FP64 state, with the arithmetic of k_cnn_first (the same FP32
+// multiply-add chain, activation and hi / lo rounding), so the result is
+// bitwise that of the two launches.  Inference only: the first layer's
+// activations and pre-activations are not kept.
+//
+// With TAIL (C = 32) the layer's activations are not stored: the epilogue
+// multiplies them at once by the last layer's weights, as k_cnn_last_mma
+// does after reloading them, and stores the nine per-tap products
+// Y[t][pixel] (tap planes of nfields N^2 floats) for k_cnn_last_gather.
+// For that the weight rows are permuted so that lane group g receives
+// output channels 8 g .. 8 g + 7 of its pixel: those registers are then
+// the 16x16x32 A fragment that k_cnn_last_mma loads for the pixel, and the
+// same three products in the same order give Y bit for bit.
+template <int C, bool SPLIT, bool FIRST = false, bool TAIL = false>
 __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
     const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
     const __bf16* __restrict__ Wp, const float* __restrict__ b, int act,
-    __bf16* __restrict__ out, __bf16* __restrict__ out_lo, float* __restrict__ zout) {
+    __bf16* __restrict__ out, __bf16* __restrict__ out_lo, float* __restrict__ zout,
+    FirstIn fi, const float* __restrict__ WL, float* __restrict__ Yp) {
   using H = HidCfg<C>;
   static_assert(C % 16 == 0, "hidden width must be a multiple of 16");
+  static_assert(!TAIL || C == 32, "the last layer folds into a hidden layer of 32 channels");
   extern __shared__ __align__(16) unsigned char smem[];
   using HT = HidTile<C, SPLIT>;
   __bf16* tile = (__bf16*)smem;                               // [TPIX][PS]
   __bf16* tile_lo = tile + HT::LO;                            // SPLIT only
+  float* su = (float*)(smem + HT::BYTES);                     // FIRST: [UH][UW]
+  float* sw0 = su + HT::UH * HT::UW;                          // FIRST: [C][9]
+  float* sb0 = sw0 + 9 * C;                                   // FIRST: [C]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
@@ -206,16 +269,21 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
   const int64_t tiles = nfields * tpy * tpx;
 
   // this lane's weight fragments and biases, for the whole kernel
+  // output channel of row m of channel block nb
+  auto och = [](int nb, int m) { return TAIL ? 8 * (m / 4) + 4 * nb + m % 4 : nb * 16 + m; };
   bf16x8 bfr[H::KB][H::NB];
-  float bias[H::NB][4];  // channels nb 16 + 4 g + i
+  float bias[H::NB][4];  // channels och(nb, 4 g + i)
 #pragma unroll
   for (int nb = 0; nb < H::NB; ++nb) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bias[nb][i] = b[nb * 16 + 4 * g + i];
+    for (int i = 0; i < 4; ++i) bias[nb][i] = b[och(nb, 4 * g + i)];
 #pragma unroll
     for (int kb = 0; kb < H::KB; ++kb)
-      bfr[kb][nb] = *(const bf16x8*)&Wp[(int64_t)(nb * 16 + r) * H::KP + kb * 32 + 8 * g];
+      bfr[kb][nb] = *(const bf16x8*)&Wp[(int64_t)och(nb, r) * H::KP + kb * 32 + 8 * g];
   }
+  bf16x8 lwhi[1], lwlo[1];  // TAIL: the last layer's weights, as in k_cnn_last_mma
+  if constexpr (TAIL) last_weights<C>(WL, lane, lwhi, lwlo);
+  const int64_t yplane = nfields * (int64_t)n * n;
 
   // input tile t: chunk i (pixel i / (C/8) of the (TH+2) x (TW+2) region,
   // channels 8 (i % (C/8)) ..) at element gidx(t, i) of `in`
@@ -229,15 +297,52 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
     return ((f * n + gy) * (int64_t)n + gx) * C + c8 * 8;
   };
   auto lidx = [&](int i) { return (i / (C / 8)) * HT::PS + (i % (C / 8)) * 8; };
+  if constexpr (FIRST) {
+    for (int i = tid; i < 9 * C; i += H::NT) sw0[i] = fi.W[i];
+    for (int i = tid; i < C; i += H::NT) sb0[i] = fi.b[i];
+  }
   for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     const int64_t f = t / (tpy * tpx);
     const int tt = (int)(t % (tpy * tpx));
     const int y0 = (tt / tpx) * H::TH, x0 = (tt % tpx) * H::TW;
     __syncthreads();  // the previous tile is no longer read
-    for (int i = tid; i < H::TCH; i += H::NT) {
-      const int64_t gi = gidx(t, i);
-      *(bf16x8*)&tile[lidx(i)] = *(const bf16x8*)&in[gi];
-      if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(i)] = *(const bf16x8*)&in_lo[gi];
+    if constexpr (FIRST) {
+      // state patch: su[sy][sx] = u[y0 + sy - 2][x0 + sx - 2], periodic
+      const double* u = fi.u_base + (fi.u_offs ? fi.u_offs[f] : f * (int64_t)n * n);
+      for (int i = tid; i < HT::UH * HT::UW; i += H::NT) {
+        const int sy = i / HT::UW, sx = i % HT::UW;
+        su[i] = (float)u[(int64_t)((y0 + sy - 2) & (n - 1)) * n + ((x0 + sx - 2) & (n - 1))];
+      }
+      __syncthreads();
+      // tile pixel (ty, tx) is state point (y0 + ty - 1, x0 + tx - 1); its
+      // tap tp reads su[ty + tp / 3][tx + tp % 3].  Item = 8 channels of
+      // one pixel, as in k_cnn_first.
+      for (int item = tid; item < H::TCH; item += H::NT) {
+        const int c8 = item % (C / 8), px = item / (C / 8);
+        const int ty = px / (H::TW + 2), tx = px % (H::TW + 2);
+        float v[9];
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp) v[tp] = su[(ty + tp / 3) * HT::UW + tx + tp % 3];
+        bf16x8 h, l;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int co = c8 * 8 + j;
+          float s = sb0[co];
+#pragma unroll
+          for (int tp = 0; tp < 9; ++tp) s += sw0[co * 9 + tp] * v[tp];
+          const float r = act_fn(s, act);
+          h[j] = (__bf16)r;
+          l[j] = (__bf16)(r - (float)h[j]);
+        }
+        *(bf16x8*)&tile[lidx(item)] = h;
+        if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(item)] = l;
+      }
+    } else {
+      for (int i = tid; i < H::TCH; i += H::NT) {
+        const int64_t gi = gidx(t, i);
+        *(bf16x8*)&tile[lidx(i)] = *(const bf16x8*)&in[gi];
+        if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(i)] = *(const bf16x8*)&in_lo[gi];
+      }
     }
     __syncthreads();
 
@@ -274,6 +379,7 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
       const int mb = wave * H::MBW + m;
       const int oy = mb / (H::TW / 16), ox0 = (mb % (H::TW / 16)) * 16;
       const int64_t pb = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0 + r) * C + 4 * g;
+      bf16x8 xh, xl;  // TAIL: channels 8 g .. 8 g + 7 of pixel ox0 + r
 #pragma unroll
       for (int nb = 0; nb < H::NB; ++nb) {
         float z[4];
@@ -287,11 +393,31 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
           h[i] = (__bf16)v;
           l[i] = (__bf16)(v - (float)h[i]);
         }
-        *(bf16x4*)&out[pb + nb * 16] = h;
-        if constexpr (SPLIT) *(bf16x4*)&out_lo[pb + nb * 16] = l;
+        if constexpr (TAIL) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            xh[4 * nb + i] = h[i];
+            xl[4 * nb + i] = l[i];
+          }
+        } else {
+          *(bf16x4*)&out[pb + nb * 16] = h;
+          if constexpr (SPLIT) *(bf16x4*)&out_lo[pb + nb * 16] = l;
+        }
+      }
+      if constexpr (TAIL) {
+        // lane (g, r) receives Y[pixel ox0 + 4 g + e][tap r]
+        f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, lwhi[0], y, 0, 0, 0);
+        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, lwlo[0], y, 0, 0, 0);
+        if constexpr (SPLIT) y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, lwhi[0], y, 0, 0, 0);
+        if (r < 9)
+          *(f32x4*)&Yp[r * yplane + (f * n + y0 + oy) * (int64_t)n + x0 + ox0 + 4 * g] = y;
       }
     };
-    if constexpr (hidden_pipelined<C, SPLIT>()) {
+    // (not with TAIL: the folded last layer's operands and the second set
+    // of accumulators exceed the registers of 3 waves per SIMD; bounded to
+    // 3 it spills, and measured 5% slower than unpipelined)
+    if constexpr (hidden_pipelined<C, SPLIT>() && !TAIL) {
       // software pipeline: block m's matrix work is issued before block
       // m - 1's epilogue, so the two overlap within the wave
       f32x4 prev[H::NB];
@@ -323,30 +449,6 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
 // The FP32 weights enter as bfloat16 hi + lo (16 significant bits); split
 // activations add their lo part, so a term costs 2 or 3 products instead
 // of 9 C vector FMAs per pixel.
-
-template <int C> struct LastCfg {
-  static constexpr int T = 16, WI = T + 2, PX = WI * WI;
-  static constexpr int KB = (C + 31) / 32;   // 32-channel steps
-};
-
-// Lane (g, r) holds W[c = 32 kb + 8 g + j][tap r], j < 8, as hi and lo
-// (zero beyond C channels or nine taps).
-template <int C>
-__device__ __forceinline__ void last_weights(const float* __restrict__ W, int lane,
-                                             bf16x8* hi, bf16x8* lo) {
-  const int r = lane & 15, g = lane >> 4;
-#pragma unroll
-  for (int kb = 0; kb < LastCfg<C>::KB; ++kb) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int c = kb * 32 + 8 * g + j;
-      const float v = (c < C && r < 9) ? W[c * 9 + r] : 0.f;
-      const __bf16 h = (__bf16)v;
-      hi[kb][j] = h;
-      lo[kb][j] = (__bf16)(v - (float)h);
-    }
-  }
-}
 
 // Y for the input region in LDS (pixel stride CS; lo plane at a + plane
 // with SPLIT), then the sum over taps for output pixel tid (< 256),
@@ -430,6 +532,44 @@ __global__ __launch_bounds__(256) void k_cnn_last_mma(
   __syncthreads();
   const float s = b[0] + last_layer_mfma<C, SPLIT, CS>(tile, L::PX * CS, (float*)lds, whi, wlo, tid);
   const int py = tid / L::T, px = tid % L::T;
+  const int64_t gi = (int64_t)(y0 + py) * n + x0 + px;
+  const double u = u_base[(u_offs ? u_offs[f] : f * (int64_t)n * n) + gi];
+  const double out = residual ? u + (double)s : (double)s;
+  g_base[(g_offs ? g_offs[f] : f * (int64_t)n * n) + gi] = out;
+  if (partials) {
+    double d = out - u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = d;
+    __syncthreads();
+    if (tid == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
+}
+
+// The last layer from per-tap products that a TAIL hidden layer stored:
+// out[p] = b + sum_t Y[t][p + (t / 3 - 1, t % 3 - 1)], then the residual
+// and the per-tile mass partials, each as k_cnn_last_mma forms them (same
+// 16 x 16 tiles, same order of sums), so the output is bitwise the same.
+__global__ __launch_bounds__(256) void k_cnn_last_gather(
+    const float* __restrict__ Yp, int n, int64_t nfields, const float* __restrict__ b,
+    const double* __restrict__ u_base, const int64_t* __restrict__ u_offs,
+    double* __restrict__ g_base, const int64_t* __restrict__ g_offs, int residual,
+    double* __restrict__ partials) {
+  constexpr int T = 16;
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int tpr = n / T, m = n - 1;
+  const int64_t f = blockIdx.x / (tpr * tpr);
+  const int t = (int)(blockIdx.x % (tpr * tpr));
+  const int y0 = (t / tpr) * T, x0 = (t % tpr) * T;
+  const int py = tid / T, px = tid % T;
+  const int64_t plane = nfields * (int64_t)n * n;
+  const float* Yf = Yp + f * (int64_t)n * n;
+  float sum = 0.f;
+#pragma unroll
+  for (int tp = 0; tp < 9; ++tp)
+    sum += Yf[tp * plane + (int64_t)((y0 + py + tp / 3 - 1) & m) * n + ((x0 + px + tp % 3 - 1) & m)];
+  const float s = b[0] + sum;
   const int64_t gi = (int64_t)(y0 + py) * n + x0 + px;
   const double u = u_base[(u_offs ? u_offs[f] : f * (int64_t)n * n) + gi];
   const double out = residual ? u + (double)s : (double)s;
@@ -1031,16 +1171,17 @@ __global__ void k_add_into(double* __restrict__ du, const T* __restrict__ d, int
 
 // --------------------------------------------------------------- launch
 
-size_t cnn_lds_bytes(int C, bool split);
+size_t cnn_lds_bytes(int C, bool split, bool first);
 
 // Blocks of the persistent hidden-layer kernel that fill the GPU once.
-template <int C, bool SPLIT>
+template <int C, bool SPLIT, bool FIRST = false, bool TAIL = false>
 static int hidden_cap() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 512;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cnn_hidden<C, SPLIT>,
-                                                   HidCfg<C>::NT, cnn_lds_bytes(C, SPLIT)) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cnn_hidden<C, SPLIT, FIRST, TAIL>,
+                                                   HidCfg<C>::NT,
+                                                   cnn_lds_bytes(C, SPLIT, FIRST)) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   return cus * per_cu;
@@ -1172,14 +1313,25 @@ bool cnn_fused_available(int C, int L, int prec) {
   }
 }
 
+bool cnn_folded_available(int C, int L, int prec) {
+  return (prec == kCnnBf16 || prec == kCnnBf16x2) && C % 16 == 0 && C <= 64 && L >= 3;
+}
+
 int cnn_effective_plan(int C, int L, int prec) {
-  if (!cnn_fused_available(C, L, prec) || L < 3 || L > 10) return CNN_PLAN_LAYERED;
+  const bool fused = cnn_fused_available(C, L, prec) && L >= 3 && L <= 10;
+  const bool folded = cnn_folded_available(C, L, prec);
   int pl = g_cnn_plan.load();
-  if (pl == CNN_PLAN_AUTO) pl = g_cnn_tuned[c_index(C)][L - 3][prec == kCnnBf16x2 ? 1 : 0].load();
-  // untuned default: layer by layer (measured faster for the 4 x 32 network
-  // at 256^2, where the halo recomputation adds more activation work than
-  // the saved HBM traffic is worth)
-  return pl == CNN_PLAN_FUSED ? CNN_PLAN_FUSED : CNN_PLAN_LAYERED;
+  if (pl == CNN_PLAN_AUTO && L >= 3 && L <= 10)
+    pl = g_cnn_tuned[c_index(C)][L - 3][prec == kCnnBf16x2 ? 1 : 0].load();
+  // untuned default: FOLDED for split networks, measured faster than
+  // LAYERED there; unsplit, its first hidden layer needs more registers
+  // than 4 waves per SIMD allow and LAYERED wins.  (The whole-network fused
+  // kernel measured slower for the 4 x 32 network at 256^2, where the halo
+  // recomputation adds more activation work than the saved HBM traffic is
+  // worth.)
+  if (pl == CNN_PLAN_AUTO) pl = folded && prec == kCnnBf16x2 ? CNN_PLAN_FOLDED : CNN_PLAN_LAYERED;
+  if ((pl == CNN_PLAN_FUSED && !fused) || (pl == CNN_PLAN_FOLDED && !folded)) pl = CNN_PLAN_LAYERED;
+  return pl;
 }
 
 void cnn_set_plan(int plan) { g_cnn_plan.store(plan); }
@@ -1204,27 +1356,70 @@ static void cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t
   const float* B = (const float*)j.B;
   auto hi = [&](int l) { return (__bf16*)act_buf(j, l, train); };
   auto lo = [&](int l) { return split ? hi(l) + act_elems : (__bf16*)nullptr; };
-  k_cnn_first<C, __bf16><<<g16, b256, 0, st>>>(j.in_base, j.in_offs, n, W, B, j.act, hi(0), lo(0),
-                                               (float*)z_buf(j, 0, train));
+  // PR_CNN_PLAN_FOLDED (inference only; training keeps every layer's
+  // activations): the first layer runs inside the first hidden layer's
+  // launch, and at C = 32 the last layer's per-tap products inside the
+  // last hidden layer's, summed over the taps by k_cnn_last_gather
+  const bool folded = !train && cnn_effective_plan(C, L, j.prec) == CNN_PLAN_FOLDED;
+  const bool tail = folded && C == 32;
+  float* Yp = nullptr;
+  if (!folded)
+    k_cnn_first<C, __bf16><<<g16, b256, 0, st>>>(j.in_base, j.in_offs, n, W, B, j.act, hi(0), lo(0),
+                                                 (float*)z_buf(j, 0, train));
   for (int l = 1; l < L - 1; ++l) {
     if constexpr (C % 16 == 0) {
       using H = HidCfg<C>;
       const __bf16* wp = (const __bf16*)j.ws.wpack + (int64_t)(l - 1) * C * H::KP;
-      const size_t lds = cnn_lds_bytes(C, split);
+      const bool first = folded && l == 1, last = tail && l == L - 2;
+      const size_t lds = cnn_lds_bytes(C, split, first);
       const int64_t tiles = j.nfields * (n / H::TH) * (n / H::TW);
-      static const int cap0 = hidden_cap<C, false>(), cap1 = hidden_cap<C, true>();
-      const dim3 gh((unsigned)std::min<int64_t>(tiles, split ? cap1 : cap0)), bh(H::NT);
-      if (split)
-        k_cnn_hidden<C, true><<<gh, bh, lds, st>>>(hi(l - 1), lo(l - 1), n, j.nfields, wp,
-                                                   B + cnn_boff(l, C), j.act, hi(l), lo(l),
-                                                   (float*)z_buf(j, l, train));
-      else
-        k_cnn_hidden<C, false><<<gh, bh, lds, st>>>(hi(l - 1), nullptr, n, j.nfields, wp,
-                                                    B + cnn_boff(l, C), j.act, hi(l), nullptr,
-                                                    (float*)z_buf(j, l, train));
+      const dim3 bh(H::NT);
+      const FirstIn fi{j.in_base, j.in_offs, W, B};
+      const float* WL = W + cnn_woff(L - 1, L, C);
+      // the tap planes (9 floats per pixel) take the place of the layer's
+      // output activations (2 C or 4 C bytes per pixel)
+      if (last) Yp = (float*)hi(l);
+      float* zo = (float*)z_buf(j, l, train);
+      const __bf16* ih = first ? nullptr : hi(l - 1);
+      const __bf16* il = first ? nullptr : lo(l - 1);
+      __bf16* oh = last ? nullptr : hi(l);
+      __bf16* ol = last ? nullptr : lo(l);
+#define PR_HID(SP, FI, TA)                                                                       \
+  {                                                                                              \
+    static const int cap = hidden_cap<C, SP, FI, TA>();                                          \
+    const dim3 gh((unsigned)std::min<int64_t>(tiles, cap));                                      \
+    k_cnn_hidden<C, SP, FI, TA><<<gh, bh, lds, st>>>(ih, il, n, j.nfields, wp, B + cnn_boff(l, C), \
+                                                     j.act, oh, ol, zo, fi, WL, Yp);             \
+  }
+      if constexpr (C == 32) {
+        if (split) {
+          if (first && last) PR_HID(true, true, true)
+          else if (first) PR_HID(true, true, false)
+          else if (last) PR_HID(true, false, true)
+          else PR_HID(true, false, false)
+        } else {
+          if (first && last) PR_HID(false, true, true)
+          else if (first) PR_HID(false, true, false)
+          else if (last) PR_HID(false, false, true)
+          else PR_HID(false, false, false)
+        }
+      } else {
+        if (split) {
+          if (first) PR_HID(true, true, false)
+          else PR_HID(true, false, false)
+        } else {
+          if (first) PR_HID(false, true, false)
+          else PR_HID(false, false, false)
+        }
+      }
+#undef PR_HID
     }
   }
-  if (split)
+  if (Yp)
+    k_cnn_last_gather<<<g16, b256, 0, st>>>(Yp, n, j.nfields, B + cnn_boff(L - 1, C), j.in_base,
+                                            j.in_offs, g_out, train ? nullptr : j.out_offs,
+                                            j.residual, j.ws.partials);
+  else if (split)
     k_cnn_last_mma<C, true><<<g16, b256, 0, st>>>(hi(L - 2), lo(L - 2), n, W + cnn_woff(L - 1, L, C),
                                                   B + cnn_boff(L - 1, C), j.in_base, j.in_offs,
                                                   g_out, train ? nullptr : j.out_offs, j.residual,
@@ -1381,11 +1576,12 @@ hipError_t launch_cnn_backward(const CnnJob& j, const double* dG, double* du, vo
   }
 }
 
-size_t cnn_lds_bytes(int C, bool split) {
+size_t cnn_lds_bytes(int C, bool split, bool first) {
   switch (C) {
 #define PR_L(CC)                                                                               \
   case CC:                                                                                     \
-    return split ? HidTile<CC, true>::BYTES : HidTile<CC, false>::BYTES;
+    return split ? (first ? HidTile<CC, true>::FIRST_BYTES : HidTile<CC, true>::BYTES)         \
+                 : (first ? HidTile<CC, false>::FIRST_BYTES : HidTile<CC, false>::BYTES);
     PR_L(16) PR_L(32) PR_L(48) PR_L(64)
 #undef PR_L
     default: return 0;
@@ -1414,14 +1610,22 @@ hipError_t cnn_set_lds_limits() {
   PR_F(16, 1) PR_F(16, 2) PR_F(16, 3) PR_F(16, 4) PR_F(32, 1) PR_F(32, 2)
 #undef PR_F
   if (e == hipSuccess) e = fused_lds_limit<48, 1, false>();
-#define PR_A(CC, SP)                                                                         \
-  if (e == hipSuccess && cnn_lds_bytes(CC, SP) <= kMaxLds)                                   \
-    e = hipFuncSetAttribute((const void*)k_cnn_hidden<CC, SP>,                               \
+#define PR_A(CC, SP, FI)                                                                     \
+  if (e == hipSuccess && cnn_lds_bytes(CC, SP, FI) <= kMaxLds)                               \
+    e = hipFuncSetAttribute((const void*)k_cnn_hidden<CC, SP, FI>,                           \
                             hipFuncAttributeMaxDynamicSharedMemorySize,                      \
-                            (int)cnn_lds_bytes(CC, SP));
-  PR_A(16, false) PR_A(16, true) PR_A(32, false) PR_A(32, true)
-  PR_A(48, false) PR_A(48, true) PR_A(64, false) PR_A(64, true)
+                            (int)cnn_lds_bytes(CC, SP, FI));
+#define PR_B(CC) PR_A(CC, false, false) PR_A(CC, true, false) PR_A(CC, false, true) PR_A(CC, true, true)
+  PR_B(16) PR_B(32) PR_B(48) PR_B(64)
+#undef PR_B
 #undef PR_A
+#define PR_T(SP, FI)                                                                         \
+  if (e == hipSuccess)                                                                       \
+    e = hipFuncSetAttribute((const void*)k_cnn_hidden<32, SP, FI, true>,                     \
+                            hipFuncAttributeMaxDynamicSharedMemorySize,                      \
+                            (int)cnn_lds_bytes(32, SP, FI));
+  PR_T(false, false) PR_T(true, false) PR_T(false, true) PR_T(true, true)
+#undef PR_T
   return e;
 }
 

@@ -164,10 +164,13 @@ struct CnnJob {
   CnnWs ws;
 };
 
-// Inference plan of the network: one layer per launch, or all layers in
-// one fused kernel (bf16 kinds, shapes with a fused instantiation).
-enum { CNN_PLAN_AUTO = 0, CNN_PLAN_LAYERED = 1, CNN_PLAN_FUSED = 2 };
+// Inference plan of the network: one layer per launch, all layers in one
+// fused kernel (bf16 kinds, shapes with a fused instantiation), or one
+// layer per launch with the first layer inside the first hidden layer's
+// launch (bf16 kinds with at least one hidden layer).
+enum { CNN_PLAN_AUTO = 0, CNN_PLAN_LAYERED = 1, CNN_PLAN_FUSED = 2, CNN_PLAN_FOLDED = 3 };
 bool cnn_fused_available(int C, int L, int prec);
+bool cnn_folded_available(int C, int L, int prec);
 int cnn_effective_plan(int C, int L, int prec);
 void cnn_set_plan(int plan);
 int cnn_get_plan();
@@ -179,7 +182,7 @@ hipError_t launch_cnn_backward(const CnnJob& j, const double* dG, double* du, vo
                                hipStream_t st);
 int cnn_act_bytes(int prec);
 int cnn_grad_bytes(int prec);
-size_t cnn_lds_bytes(int C, bool split);
+size_t cnn_lds_bytes(int C, bool split, bool first = false);
 hipError_t cnn_set_lds_limits();
 
 hipError_t launch_tables(int n, int laplacian, const FineWs& ws, hipStream_t st);

@@ -176,6 +176,61 @@ def test_fused_plan_matches_layered_and_oracle(api, L, C, prec, n):
     assert net_rel(fused, emu, u0) <= (2e-3 if prec == "bf16" else 2e-4)
 
 
+@pytest.mark.parametrize("L,C,prec,n,nf,act,mass", [(4, 32, "bf16x2", 256, 3, "gelu", False),
+                                                    (4, 32, "bf16", 32, 1, "gelu", False),
+                                                    (3, 32, "bf16x2", 64, 3, "gelu", True),
+                                                    (3, 32, "bf16", 32, 2, "tanh", False),
+                                                    (5, 32, "bf16x2", 128, 2, "gelu", True),
+                                                    (3, 16, "bf16x2", 64, 5, "tanh", False),
+                                                    (6, 48, "bf16x2", 64, 2, "gelu", False),
+                                                    (3, 64, "bf16", 128, 2, "gelu", False)])
+def test_folded_plan_is_bitwise_layered(api, L, C, prec, n, nf, act, mass):
+    """The first convolution computed inside the first hidden layer's launch,
+    and at 32 channels the last one's per-tap products in the last hidden
+    layer's epilogue, give the layer-by-layer result bit for bit, within the
+    bf16 tolerances of the oracle.  L = 3 at 32 channels folds both into
+    the one hidden layer; the mass fix reads the gather's tile sums."""
+    print(f"case folded L={L} C={C} {prec} n={n} fields={nf} {act} mass_fix={mass}", flush=True)
+    spec = cnn.CnnSpec(n_layers=L, channels=C, act=act, mass_fix=mass)
+    ws, bs, g = make(api, spec, seed=7 * L + C, prec=prec)
+    u0 = synth.random_ic(n, range(40, 40 + nf))
+    p = problem(api, n)
+    try:
+        api.pr_set_coarse_plan("folded")
+        assert api.pr_get_coarse_plan(g, n) == "folded"
+        folded = api.pr_coarse_apply(p, g, dev(u0))
+        api.pr_set_coarse_plan("layered")
+        layered = api.pr_coarse_apply(p, g, dev(u0))
+    finally:
+        api.pr_set_coarse_plan("auto")
+    assert torch.equal(folded, layered)
+    if mass:
+        f = folded.cpu().numpy()
+        assert np.abs(f.mean(axis=(1, 2)) - u0.mean(axis=(1, 2))).max() <= 1e-14
+    emu = cnn.forward(u0, ws, bs, spec, emulate_bf16=True if prec == "bf16" else "weights")
+    assert net_rel(folded.cpu().numpy(), emu, u0) <= (2e-3 if prec == "bf16" else 2e-4)
+
+
+def test_folded_plan_in_parareal_is_bitwise_layered(api):
+    """Through pr_solve the network reads its fields from the window by
+    offset tables; the folded plan must not change a bit of the solution."""
+    print("case folded plan in pr_solve, 4 x 32 bf16x2, 64^2", flush=True)
+    n, s = 64, 6
+    p = api.Problem(n=n, length=1.0, eps=0.02, conservative=True, stab=2.0, dt=1e-4, steps=10)
+    spec = cnn.CnnSpec(n_layers=4, channels=32)
+    _, _, g = make(api, spec, seed=3, prec="bf16x2", scale=0.1)
+    u0 = dev(synth.random_ic(n, [50, 51, 52]))
+    try:
+        api.pr_set_coarse_plan("folded")
+        Uh, sth = api.pr_solve(p, g, u0, s, tol=0.0, max_iter=3, allow_not_converged=True)
+        api.pr_set_coarse_plan("layered")
+        Ul, stl = api.pr_solve(p, g, u0, s, tol=0.0, max_iter=3, allow_not_converged=True)
+    finally:
+        api.pr_set_coarse_plan("auto")
+    assert torch.equal(Uh, Ul)
+    assert sth.iterations == stl.iterations
+
+
 def test_fused_plan_mass_fix_limiter_and_autotune(api):
     spec = cnn.CnnSpec(n_layers=4, channels=32, mass_fix=True, limiter=(-0.95, 0.95))
     ws, bs, g = make(api, spec, seed=31, prec="bf16x2")
@@ -191,8 +246,22 @@ def test_fused_plan_mass_fix_limiter_and_autotune(api):
     o2 = api.pr_coarse_apply(p, g2, dev(u0)).cpu().numpy()
     assert np.abs(o2.mean(axis=(1, 2)) - u0.mean(axis=(1, 2))).max() <= 1e-14
     choice = api.pr_autotune_coarse(p, g2, dev(u0))
-    assert choice in ("fused", "layered")
+    assert choice in ("fused", "layered", "folded")
     assert api.pr_get_coarse_plan(g2, n) == choice
-    # shapes without a fused kernel stay layered
+    # shapes without a fused kernel fall back to layered; untuned, a split
+    # network with a hidden layer takes the folded plan, an unsplit one or
+    # one without a hidden layer takes layered
     _, _, g64 = make(api, cnn.CnnSpec(n_layers=4, channels=64), seed=1, prec="bf16")
+    _, _, g2l = make(api, cnn.CnnSpec(n_layers=2, channels=32), seed=1, prec="bf16x2")
+    _, _, g5 = make(api, cnn.CnnSpec(n_layers=5, channels=16), seed=1, prec="bf16x2")
+    try:
+        api.pr_set_coarse_plan("fused")
+        assert api.pr_get_coarse_plan(g64, n) == "layered"
+        api.pr_set_coarse_plan("folded")
+        assert api.pr_get_coarse_plan(g64, n) == "folded"
+        assert api.pr_get_coarse_plan(g2l, n) == "layered"
+    finally:
+        api.pr_set_coarse_plan("auto")
     assert api.pr_get_coarse_plan(g64, n) == "layered"
+    assert api.pr_get_coarse_plan(g2l, n) == "layered"
+    assert api.pr_get_coarse_plan(g5, n) == "folded"
