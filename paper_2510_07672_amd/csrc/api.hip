@@ -247,10 +247,13 @@ hipError_t coarse_setup(const pr_problem* p, const pr_coarse* g, const CoarseWs&
   return launch_tables(p->n, p->laplacian, w.fine, s);
 }
 
-// G on `nfields` fields addressed through optional offset tables.
+// G on `nfields` fields addressed through optional offset tables; with
+// corr, followed by that Parareal correction of the same fields (whose
+// g_new addresses the output); with out2_base, the output also goes there.
 hipError_t coarse_run(const pr_problem* p, const pr_coarse* g, const CoarseWs& w, int64_t nfields,
                       const double* in_base, const int64_t* in_offs, double* out_base,
-                      const int64_t* out_offs, hipStream_t s);
+                      const int64_t* out_offs, hipStream_t s, const CorrectJob* corr = nullptr,
+                      double* out2_base = nullptr, const int64_t* out2_offs = nullptr);
 
 float event_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
@@ -273,7 +276,8 @@ struct Events {
 
 hipError_t coarse_run(const pr_problem* p, const pr_coarse* g, const CoarseWs& w, int64_t nfields,
                       const double* in_base, const int64_t* in_offs, double* out_base,
-                      const int64_t* out_offs, hipStream_t s) {
+                      const int64_t* out_offs, hipStream_t s, const CorrectJob* corr,
+                      double* out2_base, const int64_t* out2_offs) {
   if (g->kind == PR_G_CNN) {
     CnnJob j = make_cnn_job(p, g, w.cnn);
     j.nfields = nfields;
@@ -281,6 +285,9 @@ hipError_t coarse_run(const pr_problem* p, const pr_coarse* g, const CoarseWs& w
     j.in_offs = in_offs;
     j.out_base = out_base;
     j.out_offs = out_offs;
+    j.corr = corr;
+    j.out2_base = out2_base;
+    j.out2_offs = out2_offs;
     return launch_cnn(j, s);
   }
   StepJob j = make_job(p, g->dt, g->steps, g->prec == PR_F32, nfields, w.fine);
@@ -289,7 +296,10 @@ hipError_t coarse_run(const pr_problem* p, const pr_coarse* g, const CoarseWs& w
   j.out_base = out_base;
   j.out_offs = out_offs;
   j.out_f32 = 0;
-  return launch_steps(j, s);
+  hipError_t e = launch_steps(j, s);
+  if (e == hipSuccess && corr) e = launch_correct(*corr, s);
+  if (e == hipSuccess && out2_base) e = launch_copy(nfields, p->n, out_base, out_offs, out2_base, out2_offs, s);
+  return e;
 }
 
 // ------------------------------------------------------ Parareal driver
@@ -520,8 +530,12 @@ int shared_entry(const std::vector<StepParams>& hp, const std::vector<Idx>& idx)
 
 hipError_t run_coarse_group(const CoarseGroup& G, const SolvePlan& P, int64_t nfields,
                             const double* in_base, const int64_t* in_offs, double* out_base,
-                            const int64_t* out_offs, const int32_t* pidx, int uni, hipStream_t s) {
-  if (G.g->kind == PR_G_CNN) return coarse_run(G.p, G.g, G.ws, nfields, in_base, in_offs, out_base, out_offs, s);
+                            const int64_t* out_offs, const int32_t* pidx, int uni, hipStream_t s,
+                            const CorrectJob* corr = nullptr, double* out2_base = nullptr,
+                            const int64_t* out2_offs = nullptr) {
+  if (G.g->kind == PR_G_CNN)
+    return coarse_run(G.p, G.g, G.ws, nfields, in_base, in_offs, out_base, out_offs, s, corr,
+                      out2_base, out2_offs);
   StepJob j = make_job(G.p, G.g->dt, G.g->steps, G.g->prec == PR_F32, nfields, G.ws.fine);
   j.in_base = in_base;
   j.in_offs = in_offs;
@@ -534,7 +548,10 @@ hipError_t run_coarse_group(const CoarseGroup& G, const SolvePlan& P, int64_t nf
     j.params = P.params;
     j.pidx = pidx;
   }
-  return launch_steps(j, s);
+  hipError_t e = launch_steps(j, s);
+  if (e == hipSuccess && corr) e = launch_correct(*corr, s);
+  if (e == hipSuccess && out2_base) e = launch_copy(nfields, G.p->n, out_base, out_offs, out2_base, out2_offs, s);
+  return e;
 }
 
 pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hipStream_t hs) {
@@ -709,13 +726,16 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
     }
     st = upload();
     if (st != PR_OK) return st;
-    for (int j = 0; j < smax; ++j) {
-      for (auto& sg : csteps[j])
+    // G(U_j) goes to the coarse cache and to U_{j+1} (cp lists the same
+    // fields as sg, in the same order)
+    for (int j = 0; j < smax; ++j)
+      for (size_t c = 0; c < csteps[j].size(); ++c) {
+        const Seg& sg = csteps[j][c];
+        const Seg& cp = ksteps[j][c];
         PR_HIP(run_coarse_group(P.coarse[sg.grp], P, sg.count, UB, P.t64 + sg.i64[0], WB,
-                                P.t64 + sg.i64[1], P.t32 + sg.i32[0], sg.uni, hs));
-      for (auto& cp : ksteps[j])
-        PR_HIP(launch_copy(cp.count, cp.grp, WB, P.t64 + cp.i64[0], UB, P.t64 + cp.i64[1], hs));
-    }
+                                P.t64 + sg.i64[1], P.t32 + sg.i32[0], sg.uni, hs, nullptr, UB,
+                                P.t64 + cp.i64[1]));
+      }
     PR_HIP(hipStreamSynchronize(hs));
   }
 
@@ -874,34 +894,55 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
     }
     PR_HIP(hipEventRecord(ev.e[1], hs));
     int waited = 0;  // chunks the sweep has waited for
+    auto correction = [&](const Seg& sg) {
+      CorrectJob cj{};
+      cj.nfields = sg.count;
+      cj.n = sg.grp;
+      cj.f = WB;
+      cj.f_offs = P.t64 + sg.i64[0];
+      cj.f_f32 = sg.f32;
+      cj.g_new = WB;
+      cj.gn_offs = P.t64 + sg.i64[1];
+      cj.g_old = WB;
+      cj.go_offs = P.t64 + sg.i64[2];
+      cj.u = UB;
+      cj.u_offs = P.t64 + sg.i64[3];
+      cj.upd = P.upd;
+      cj.upd_idx = P.t32 + sg.i32[0];
+      cj.update_cache = 1;
+      return cj;
+    };
     for (int j = 0; j < smax; ++j) {
+      // the correction of step j reads F_j and overwrites U_{j+1}, an input
+      // of the chunk holding slice j + 1
+      auto wait_chunks = [&]() -> hipError_t {
+        while (waited < nchunk && cb[waited] <= j + 1) {
+          if (nchunk > 1) {
+            const hipError_t e = hipStreamWaitEvent(hs, ovl.end[waited], 0);
+            if (e != hipSuccess) return e;
+          }
+          ++waited;
+        }
+        return hipSuccess;
+      };
+      // One coarse group and one correction group: the correction's fields
+      // are the coarse call's, in the same order (both follow the group's
+      // member list), so G hands its output straight to the correction
+      // (the network's last kernel applies it where it can).
+      if (csteps[j].size() == 1 && ksteps[j].size() == 1 &&
+          csteps[j][0].count == ksteps[j][0].count) {
+        const Seg& sg = csteps[j][0];
+        const CorrectJob cj = correction(ksteps[j][0]);
+        PR_HIP(wait_chunks());
+        PR_HIP(run_coarse_group(P.coarse[sg.grp], P, sg.count, UB, P.t64 + sg.i64[0], WB,
+                                P.t64 + sg.i64[1], P.t32 + sg.i32[0], sg.uni, hs, &cj));
+        continue;
+      }
       for (auto& sg : csteps[j])
         PR_HIP(run_coarse_group(P.coarse[sg.grp], P, sg.count, UB, P.t64 + sg.i64[0], WB,
                                 P.t64 + sg.i64[1], P.t32 + sg.i32[0], sg.uni, hs));
-      // the correction of step j reads F_j and overwrites U_{j+1}, an input
-      // of the chunk holding slice j + 1
-      while (waited < nchunk && cb[waited] <= j + 1) {
-        if (nchunk > 1) PR_HIP(hipStreamWaitEvent(hs, ovl.end[waited], 0));
-        ++waited;
-      }
-      for (auto& sg : ksteps[j]) {
-        CorrectJob cj{};
-        cj.nfields = sg.count;
-        cj.n = sg.grp;
-        cj.f = WB;
-        cj.f_offs = P.t64 + sg.i64[0];
-        cj.f_f32 = sg.f32;
-        cj.g_new = WB;
-        cj.gn_offs = P.t64 + sg.i64[1];
-        cj.g_old = WB;
-        cj.go_offs = P.t64 + sg.i64[2];
-        cj.u = UB;
-        cj.u_offs = P.t64 + sg.i64[3];
-        cj.upd = P.upd;
-        cj.upd_idx = P.t32 + sg.i32[0];
-        cj.update_cache = 1;
-        PR_HIP(launch_correct(cj, hs));
-      }
+      PR_HIP(wait_chunks());
+      for (auto& sg : ksteps[j]) PR_HIP(launch_correct(correction(sg), hs));
     }
     for (; waited < nchunk; ++waited)
       if (nchunk > 1) PR_HIP(hipStreamWaitEvent(hs, ovl.end[waited], 0));

@@ -550,11 +550,13 @@ __global__ __launch_bounds__(256) void k_cnn_last_mma(
 // out[p] = b + sum_t Y[t][p + (t / 3 - 1, t % 3 - 1)], then the residual
 // and the per-tile mass partials, each as k_cnn_last_mma forms them (same
 // 16 x 16 tiles, same order of sums), so the output is bitwise the same.
+// With g2_base the output also goes to a second destination.
 __global__ __launch_bounds__(256) void k_cnn_last_gather(
     const float* __restrict__ Yp, int n, int64_t nfields, const float* __restrict__ b,
     const double* __restrict__ u_base, const int64_t* __restrict__ u_offs,
     double* __restrict__ g_base, const int64_t* __restrict__ g_offs, int residual,
-    double* __restrict__ partials) {
+    double* __restrict__ partials, double* __restrict__ g2_base,
+    const int64_t* __restrict__ g2_offs) {
   constexpr int T = 16;
   __shared__ double red[4];
   const int tid = threadIdx.x;
@@ -574,6 +576,7 @@ __global__ __launch_bounds__(256) void k_cnn_last_gather(
   const double u = u_base[(u_offs ? u_offs[f] : f * (int64_t)n * n) + gi];
   const double out = residual ? u + (double)s : (double)s;
   g_base[(g_offs ? g_offs[f] : f * (int64_t)n * n) + gi] = out;
+  if (g2_base) g2_base[(g2_offs ? g2_offs[f] : f * (int64_t)n * n) + gi] = out;
   if (partials) {
     double d = out - u;
 #pragma unroll
@@ -581,6 +584,80 @@ __global__ __launch_bounds__(256) void k_cnn_last_gather(
     if ((tid & 63) == 0) red[tid >> 6] = d;
     __syncthreads();
     if (tid == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
+}
+
+// The same sum over the taps with the Parareal correction of the sweep
+// applied at once (no mass fix or limiter): g1 = G(u) as k_cnn_last_gather
+// forms it, then u <- f + (g1 - g_old), g_old <- g1 and the running sup
+// norm of the update, each as k_correct does them, so G(u) itself is not
+// stored.  Four points per thread at k_correct's positions and one atomic
+// per block of 1024 points.
+template <typename TF>
+__global__ __launch_bounds__(256) void k_cnn_gather_correct(
+    const float* __restrict__ Yp, int n, int64_t nfields, const float* __restrict__ b,
+    const double* __restrict__ in_base, const int64_t* __restrict__ in_offs, int residual,
+    const TF* __restrict__ fb, const int64_t* __restrict__ f_offs,
+    double* __restrict__ gob, const int64_t* __restrict__ go_offs,
+    double* __restrict__ ub, const int64_t* __restrict__ u_offs,
+    unsigned long long* __restrict__ upd, const int32_t* __restrict__ upd_idx, int update_cache,
+    int blocks_per_field) {
+  constexpr int PPT = 4;
+  __shared__ unsigned long long red[4];
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t fld = blockIdx.x / blocks_per_field;
+  const int64_t part = blockIdx.x % blocks_per_field;
+  const int m = n - 1;
+  const int64_t plane = nfields * n2;
+  const float* Yf = Yp + fld * n2;
+  const double* uin = in_base + (in_offs ? in_offs[fld] : fld * n2);
+  const TF* fp = fb + (f_offs ? f_offs[fld] : fld * n2);
+  double* go = gob + (go_offs ? go_offs[fld] : fld * n2);
+  double* u = ub + (u_offs ? u_offs[fld] : fld * n2);
+  const int64_t i0 = part * (256 * PPT) + threadIdx.x;
+  double g1[PPT], f[PPT], g0[PPT], u0[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int64_t i = i0 + k * 256;
+    if (i < n2) {
+      const int y = (int)(i / n), x = (int)(i % n);
+      float sum = 0.f;
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp)
+        sum += Yf[tp * plane + (int64_t)((y + tp / 3 - 1) & m) * n + ((x + tp % 3 - 1) & m)];
+      const float s = b[0] + sum;
+      const double v = uin[i];
+      g1[k] = residual ? v + (double)s : (double)s;
+      f[k] = (double)fp[i];
+      g0[k] = go[i];
+      u0[k] = u[i];
+    }
+  }
+  unsigned long long mx = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int64_t i = i0 + k * 256;
+    if (i < n2) {
+      const double un = f[k] + (g1[k] - g0[k]);
+      const double d = fabs(un - u0[k]);
+      u[i] = un;
+      if (update_cache) go[i] = g1[k];
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(d);
+      mx = bits > mx ? bits : mx;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long t = __shfl_xor(mx, o, 64);
+    mx = t > mx ? t : mx;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long r = red[0];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) r = red[w] > r ? red[w] : r;
+    atomicMax(&upd[upd_idx ? upd_idx[fld] : fld], r);
   }
 }
 
@@ -1198,6 +1275,10 @@ static int64_t cnn_boff(int l, int C) { return (int64_t)l * C; }
 int cnn_act_bytes(int prec) { return prec == kCnnF64 ? 8 : prec == kCnnF32 ? 4 : prec == kCnnBf16x2 ? 4 : 2; }
 int cnn_grad_bytes(int prec) { return prec == kCnnF64 ? 8 : 4; }
 
+// per-tile sums of G(u) - u for the mass fix, or nullptr (the last layer
+// then skips the reduction)
+static double* mass_partials(const CnnJob& j) { return j.mass_fix ? j.ws.partials : nullptr; }
+
 // activation (and pre-activation) buffer of layer l's output
 static void* act_buf(const CnnJob& j, int l, bool train) {
   const size_t bytes = (size_t)j.nfields * j.n * j.n * j.channels * cnn_act_bytes(j.prec);
@@ -1224,7 +1305,7 @@ static void cnn_fwd_ref(const CnnJob& j, bool train, double* g_out, hipStream_t 
   k_cnn_last_ref<C, T><<<g16, b256, 0, st>>>((const T*)act_buf(j, L - 2, train), n,
                                              W + cnn_woff(L - 1, L, C), B + cnn_boff(L - 1, C),
                                              j.in_base, j.in_offs, g_out, train ? nullptr : j.out_offs,
-                                             j.residual, j.ws.partials);
+                                             j.residual, mass_partials(j));
 }
 
 std::atomic<int> g_cnn_plan{0};          // pr_cnn_plan, process-wide setting
@@ -1261,7 +1342,7 @@ static bool launch_fused_nh(const CnnJob& j, double* g_out, hipStream_t st) {
     k_cnn_fused<C, NH, SPLIT><<<grid, block, F::LDS, st>>>(
         j.in_base, j.in_offs, j.n, j.nfields, W, B, (const __bf16*)j.ws.wpack, B + C,
         W + cnn_woff(L - 1, L, C), B + cnn_boff(L - 1, C), j.act, j.residual, g_out, j.out_offs,
-        j.ws.partials);
+        mass_partials(j));
     return true;
   }
 }
@@ -1340,13 +1421,17 @@ void cnn_record_tuned(int C, int L, int prec, int plan) {
   if (L >= 3 && L <= 10) g_cnn_tuned[c_index(C)][L - 3][prec == kCnnBf16x2 ? 1 : 0].store(plan);
 }
 
+// What the last kernel of a forward pass took over from the caller.
+enum { kDidCorr = 1, kDidOut2 = 2 };
+
+// Returns the kDid* flags of what the last kernel did.
 template <int C>
-static void cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t st) {
+static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t st) {
   const int n = j.n, L = j.n_layers;
   if (!train && cnn_effective_plan(C, L, j.prec) == CNN_PLAN_FUSED) {
     const bool done = j.prec == kCnnBf16x2 ? launch_fused_c<C, true>(j, g_out, st)
                                            : launch_fused_c<C, false>(j, g_out, st);
-    if (done) return;
+    if (done) return 0;
   }
   const int64_t tiles16 = (int64_t)(n / kTile) * (n / kTile);
   const dim3 g16((unsigned)(j.nfields * tiles16)), b256(256);
@@ -1415,20 +1500,40 @@ static void cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t
 #undef PR_HID
     }
   }
-  if (Yp)
+  const bool fold_corr = Yp && j.corr && !j.mass_fix && !j.limiter;
+  if (fold_corr) {
+    const CorrectJob& c = *j.corr;
+    const int bpf = (int)((int64_t)n * n / 1024);  // 256 threads x 4 points; N >= 32
+    const dim3 gc((unsigned)(j.nfields * bpf));
+    if (c.f_f32)
+      k_cnn_gather_correct<float><<<gc, b256, 0, st>>>(
+          Yp, n, j.nfields, B + cnn_boff(L - 1, C), j.in_base, j.in_offs, j.residual,
+          (const float*)c.f, c.f_offs, c.g_old, c.go_offs, c.u, c.u_offs, c.upd, c.upd_idx,
+          c.update_cache, bpf);
+    else
+      k_cnn_gather_correct<double><<<gc, b256, 0, st>>>(
+          Yp, n, j.nfields, B + cnn_boff(L - 1, C), j.in_base, j.in_offs, j.residual,
+          (const double*)c.f, c.f_offs, c.g_old, c.go_offs, c.u, c.u_offs, c.upd, c.upd_idx,
+          c.update_cache, bpf);
+  } else if (Yp) {
+    // the second destination only where nothing changes the output later
+    double* o2 = j.mass_fix || j.limiter ? nullptr : j.out2_base;
     k_cnn_last_gather<<<g16, b256, 0, st>>>(Yp, n, j.nfields, B + cnn_boff(L - 1, C), j.in_base,
                                             j.in_offs, g_out, train ? nullptr : j.out_offs,
-                                            j.residual, j.ws.partials);
+                                            j.residual, mass_partials(j), o2, j.out2_offs);
+    return o2 ? kDidOut2 : 0;
+  }
   else if (split)
     k_cnn_last_mma<C, true><<<g16, b256, 0, st>>>(hi(L - 2), lo(L - 2), n, W + cnn_woff(L - 1, L, C),
                                                   B + cnn_boff(L - 1, C), j.in_base, j.in_offs,
                                                   g_out, train ? nullptr : j.out_offs, j.residual,
-                                                  j.ws.partials);
+                                                  mass_partials(j));
   else
     k_cnn_last_mma<C, false><<<g16, b256, 0, st>>>(hi(L - 2), nullptr, n, W + cnn_woff(L - 1, L, C),
                                                    B + cnn_boff(L - 1, C), j.in_base, j.in_offs,
                                                    g_out, train ? nullptr : j.out_offs, j.residual,
-                                                   j.ws.partials);
+                                                   mass_partials(j));
+  return fold_corr ? kDidCorr : 0;
 }
 
 // Forward of G; in training mode every layer's activation and pre-activation
@@ -1437,6 +1542,8 @@ template <int C>
 static hipError_t launch_cnn_fwd_c(const CnnJob& j, bool train, hipStream_t st) {
   const int n = j.n;
   double* g_out = train ? j.ws.o1 : j.out_base;
+  if (train && (j.corr || j.out2_base)) return hipErrorInvalidValue;
+  int did = 0;
   if (j.prec == kCnnF64) {
     if constexpr (C <= kCnnF64MaxC) cnn_fwd_ref<C, double>(j, train, g_out, st);
     else return hipErrorInvalidValue;
@@ -1444,15 +1551,27 @@ static hipError_t launch_cnn_fwd_c(const CnnJob& j, bool train, hipStream_t st) 
     cnn_fwd_ref<C, float>(j, train, g_out, st);
   } else {
     if (j.n_layers > 2 && C % 16 != 0) return hipErrorInvalidValue;
-    cnn_fwd_bf16<C>(j, train, g_out, st);
+    did = cnn_fwd_bf16<C>(j, train, g_out, st);
   }
   const int limiter = train ? 0 : j.limiter;
-  if (j.mass_fix || limiter) {
+  if (!(did & kDidCorr) && (j.mass_fix || limiter)) {
     const int bpf = (int)std::max<int64_t>(1, (int64_t)n * n / 2048);
     const int64_t tiles16 = (int64_t)(n / kTile) * (n / kTile);
     k_cnn_fix<<<dim3((unsigned)(j.nfields * bpf)), dim3(256), 0, st>>>(
         g_out, train ? nullptr : j.out_offs, n, j.ws.partials, (int)tiles16, j.mass_fix, limiter,
         j.lim_lo, j.lim_hi, bpf);
+  }
+  // a correction the network's last kernel did not apply: on the stored
+  // output (its g_new must address g_out as written above)
+  if (j.corr && !(did & kDidCorr)) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_correct(*j.corr, st);
+  }
+  if (j.out2_base && !(did & kDidOut2)) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_copy(j.nfields, n, g_out, j.out_offs, j.out2_base, j.out2_offs, st);
   }
   return hipGetLastError();
 }

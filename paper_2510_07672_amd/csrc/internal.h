@@ -162,6 +162,17 @@ struct CnnJob {
   double* out_base;
   const int64_t* out_offs;
   CnnWs ws;
+  // Parareal correction to apply after the forward pass (inference), field
+  // i of this job being field i of the correction, whose g_new addresses
+  // the output; the folded plan's last kernel applies it without storing
+  // the output (at C = 32, without mass fix or limiter), else launch_cnn
+  // runs it on the stored output.  nullptr: none.
+  const CorrectJob* corr;
+  // a second destination of the output (field i at out2_base +
+  // out2_offs[i]), written by the last kernel where it can, else copied
+  // after the forward pass; nullptr: none.  Inference, without corr.
+  double* out2_base;
+  const int64_t* out2_offs;
 };
 
 // Inference plan of the network: one layer per launch, all layers in one

@@ -211,13 +211,20 @@ def test_folded_plan_is_bitwise_layered(api, L, C, prec, n, nf, act, mass):
     assert net_rel(folded.cpu().numpy(), emu, u0) <= (2e-3 if prec == "bf16" else 2e-4)
 
 
-def test_folded_plan_in_parareal_is_bitwise_layered(api):
+@pytest.mark.parametrize("conservative,f32_iters,mass_fix", [(False, 0, False), (True, 1, False),
+                                                          (False, 0, True)])
+def test_folded_plan_in_parareal_is_bitwise_layered(api, conservative, f32_iters, mass_fix):
     """Through pr_solve the network reads its fields from the window by
-    offset tables; the folded plan must not change a bit of the solution."""
-    print("case folded plan in pr_solve, 4 x 32 bf16x2, 64^2", flush=True)
+    offset tables, and under the folded plan its last kernel also applies the
+    Parareal correction (FP32 fine values in the first iteration with
+    f32_iters = 1); with a mass fix the correction runs after the fix.  The
+    solution and the per-iteration update norms must not change by a bit."""
+    print(f"case folded plan in pr_solve, 4 x 32 bf16x2, 64^2, conservative={conservative} "
+          f"f32_iters={f32_iters} mass_fix={mass_fix}", flush=True)
     n, s = 64, 6
-    p = api.Problem(n=n, length=1.0, eps=0.02, conservative=True, stab=2.0, dt=1e-4, steps=10)
-    spec = cnn.CnnSpec(n_layers=4, channels=32)
+    p = api.Problem(n=n, length=1.0, eps=0.02, conservative=conservative, stab=2.0, dt=1e-4,
+                    steps=10, f32_iters=f32_iters)
+    spec = cnn.CnnSpec(n_layers=4, channels=32, mass_fix=mass_fix)
     _, _, g = make(api, spec, seed=3, prec="bf16x2", scale=0.1)
     u0 = dev(synth.random_ic(n, [50, 51, 52]))
     try:
@@ -229,6 +236,11 @@ def test_folded_plan_in_parareal_is_bitwise_layered(api):
         api.pr_set_coarse_plan("auto")
     assert torch.equal(Uh, Ul)
     assert sth.iterations == stl.iterations
+    assert np.array_equal(sth.history, stl.history)
+    # the last iteration's update is that of the solution against the previous one
+    Up, _ = api.pr_solve(p, g, u0, s, tol=0.0, max_iter=2, allow_not_converged=True)
+    d = (Uh - Up).abs().amax(dim=(1, 2, 3)).cpu().numpy()
+    assert np.array_equal(sth.history[-1], d)
 
 
 def test_fused_plan_mass_fix_limiter_and_autotune(api):
