@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 8
+#define PR_ABI_VERSION 9
 
 typedef enum {
   PR_OK = 0,

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 8
+    assert lib.pr_abi_version() == 9
 
 
 def test_library_exports_match_nm(L):
@@ -178,6 +178,18 @@ def test_overlap_setting(L):
     assert lib.pr_set_overlap(17) == L.PR_ERR_INVALID_ARG
     assert lib.pr_set_overlap(3) == L.PR_OK and lib.pr_get_overlap() == 3
     assert lib.pr_set_overlap(old) == L.PR_OK
+
+
+def test_coarse_plan_setting(L):
+    """The network plans are AUTO, LAYERED, FUSED and FOLDED; anything else
+    is rejected and leaves the setting alone."""
+    lib = L.lib()
+    assert (L.PR_CNN_PLAN_AUTO, L.PR_CNN_PLAN_LAYERED, L.PR_CNN_PLAN_FUSED,
+            L.PR_CNN_PLAN_FOLDED) == (0, 1, 2, 3)
+    for bad in (-1, 4, 99):
+        assert lib.pr_set_coarse_plan(bad) == L.PR_ERR_INVALID_ARG
+    for ok in (3, 2, 1, 0):
+        assert lib.pr_set_coarse_plan(ok) == L.PR_OK
 
 
 def test_working_set_setting(L):
