@@ -268,8 +268,8 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
   const int tpy = n / H::TH, tpx = n / H::TW;
   const int64_t tiles = nfields * tpy * tpx;
 
-  // this lane's weight fragments and biases, for the whole kernel
-  // output channel of row m of channel block nb
+  // this lane's weight fragments and biases, for the whole kernel; och is
+  // the output channel of row m of channel block nb
   auto och = [](int nb, int m) { return TAIL ? 8 * (m / 4) + 4 * nb + m % 4 : nb * 16 + m; };
   bf16x8 bfr[H::KB][H::NB];
   float bias[H::NB][4];  // channels och(nb, 4 g + i)
