@@ -170,17 +170,23 @@ def test_overlapped_sweep_gives_the_same_bits(api, chunks):
     spec = cnn.CnnSpec(n_layers=3, channels=16)
     ws, bs = cnn.init_weights(spec, seed=4, scale=0.1)
     net = api.CnnCoarse(ws, bs, prec="bf16x2")
+    # 32 channels: the folded plan applies the correction in the network's
+    # last kernel, after the sweep has waited for the fine chunk
+    w32, b32 = cnn.init_weights(cnn.CnnSpec(n_layers=3, channels=32), seed=6, scale=0.1)
+    net32 = api.CnnCoarse(w32, b32, prec="bf16x2")
     p = api.Problem(n=64, length=1.0, eps=0.02, conservative=True, stab=2.0, dt=1e-4, steps=20)
     u0 = dev(synth.random_ic(64, [50, 51, 52]))
     jobs = mixed_jobs(api)
     try:
         api.pr_set_overlap(1)
+        Uc, stc = api.pr_solve(p, net32, u0, 11, tol=0.0, max_iter=4, allow_not_converged=True)
         Ua, sta = api.pr_solve(p, net, u0, 11, tol=1e-9)
         Ub, stb = api.pr_solve(p, api.Coarse(dt=2e-3), u0, 11, tol=0.0, max_iter=3,
                                allow_not_converged=True)
         ref_many = [U.clone() for U, _ in api.pr_solve_many(jobs)]
         api.pr_set_overlap(chunks)
         assert api.pr_get_overlap() == chunks
+        Uc2, stc2 = api.pr_solve(p, net32, u0, 11, tol=0.0, max_iter=4, allow_not_converged=True)
         Ua2, sta2 = api.pr_solve(p, net, u0, 11, tol=1e-9)
         Ub2, _ = api.pr_solve(p, api.Coarse(dt=2e-3), u0, 11, tol=0.0, max_iter=3,
                               allow_not_converged=True)
@@ -190,6 +196,7 @@ def test_overlapped_sweep_gives_the_same_bits(api, chunks):
         api.pr_set_overlap(1)
     assert torch.equal(Ua, Ua2) and list(sta.ic_iterations) == list(sta2.ic_iterations)
     assert torch.equal(Ub, Ub2)
+    assert torch.equal(Uc, Uc2) and np.array_equal(stc.history, stc2.history)
     for r, (U, _) in zip(ref_many, out2):
         assert torch.equal(r, U)
 
@@ -221,3 +228,39 @@ def test_many_combined_features_bitwise(api):
             assert list(st.ic_iterations) == list(st1.ic_iterations)
     finally:
         api.pr_set_fine_working_set(256 << 20)
+
+
+def test_many_folded_network_plan_gives_the_same_bits(api):
+    """Jobs sharing one 32-channel split network form one coarse group: under
+    the folded plan the network's last kernel applies their corrections
+    through the shared offset tables (a job in FP32 iterations splits the
+    corrections into two groups, and those steps run them separately).  The
+    solutions, iteration counts and update norms match the layered plan's
+    bit for bit."""
+    from oracle import cnn
+    print("case pr_solve_many, folded vs layered network plan", flush=True)
+    n = 64
+    spec = cnn.CnnSpec(n_layers=4, channels=32)
+    ws, bs = cnn.init_weights(spec, seed=4, scale=0.1)
+    net = api.CnnCoarse(ws, bs, prec="bf16x2")
+    pa = api.Problem(n=n, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4, steps=10)
+    pb = api.Problem(n=n, length=1.0, eps=0.03, conservative=True, stab=2.0, dt=1e-4, steps=10)
+    pc = api.Problem(n=n, length=1.0, eps=0.02, conservative=True, stab=2.0, dt=1e-4, steps=10,
+                     f32_iters=1)
+
+    def jobs():
+        return [api.Job(pa, net, dev(synth.random_ic(n, [61, 62])), 6, 1e-9),
+                api.Job(pb, net, dev(synth.random_ic(n, [63])), 4, 1e-9),
+                api.Job(pc, net, dev(synth.random_ic(n, [64, 65])), 5, 1e-9)]
+
+    try:
+        api.pr_set_coarse_plan("folded")
+        out_f = api.pr_solve_many(jobs(), allow_not_converged=True)
+        api.pr_set_coarse_plan("layered")
+        out_l = api.pr_solve_many(jobs(), allow_not_converged=True)
+    finally:
+        api.pr_set_coarse_plan("auto")
+    for (Uf, sf), (Ul, sl) in zip(out_f, out_l):
+        assert torch.equal(Uf, Ul)
+        assert list(sf.ic_iterations) == list(sl.ic_iterations)
+        assert np.array_equal(sf.history, sl.history)
