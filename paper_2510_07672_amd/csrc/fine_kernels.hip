@@ -1097,7 +1097,7 @@ int row_tiles(int n, bool f32) {
 
 // Block b of field fld takes points b * 1024 + k * 256 + threadIdx.x,
 // k < 4 (coalesced, four independent loads of each operand in flight);
-// the block's maximum goes to upd with one atomic.
+// the block's maximum goes to upd with at most one atomic.
 template <typename TF>
 __global__ __launch_bounds__(256) void k_correct(
     int64_t n2, const TF* __restrict__ fb, const int64_t* __restrict__ f_offs,
@@ -1153,7 +1153,10 @@ __global__ __launch_bounds__(256) void k_correct(
     unsigned long long r = red[0];
 #pragma unroll
     for (int w = 1; w < 4; ++w) r = red[w] > r ? red[w] : r;
-    atomicMax(&upd[upd_idx ? upd_idx[fld] : fld], r);
+    // the norm only grows: a maximum not above the stored value cannot
+    // change it, and skipping its atomic spares the contended address
+    unsigned long long* dst = &upd[upd_idx ? upd_idx[fld] : fld];
+    if (r > __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMax(dst, r);
   }
 }
 
