@@ -587,6 +587,43 @@ __global__ __launch_bounds__(256) void k_cnn_last_gather(
   }
 }
 
+// k_cnn_last_gather without the tile sums (no mass fix): points in the
+// linear order of k_cnn_gather_correct, two per thread, so more blocks and
+// fewer dependent loads per block; each point's sum is formed as there.
+__global__ __launch_bounds__(256) void k_cnn_last_gather_lin(
+    const float* __restrict__ Yp, int n, int64_t nfields, const float* __restrict__ b,
+    const double* __restrict__ u_base, const int64_t* __restrict__ u_offs,
+    double* __restrict__ g_base, const int64_t* __restrict__ g_offs, int residual,
+    double* __restrict__ g2_base, const int64_t* __restrict__ g2_offs, int blocks_per_field) {
+  constexpr int PPT = 2;
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t fld = blockIdx.x / blocks_per_field;
+  const int64_t part = blockIdx.x % blocks_per_field;
+  const int m = n - 1;
+  const int64_t plane = nfields * n2;
+  const float* Yf = Yp + fld * n2;
+  const double* u = u_base + (u_offs ? u_offs[fld] : fld * n2);
+  double* g = g_base + (g_offs ? g_offs[fld] : fld * n2);
+  double* g2 = g2_base ? g2_base + (g2_offs ? g2_offs[fld] : fld * n2) : nullptr;
+  const int64_t i0 = part * (256 * PPT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int64_t i = i0 + k * 256;
+    if (i < n2) {
+      const int y = (int)(i / n), x = (int)(i % n);
+      float sum = 0.f;
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp)
+        sum += Yf[tp * plane + (int64_t)((y + tp / 3 - 1) & m) * n + ((x + tp % 3 - 1) & m)];
+      const float s = b[0] + sum;
+      const double v = u[i];
+      const double out = residual ? v + (double)s : (double)s;
+      g[i] = out;
+      if (g2) g2[i] = out;
+    }
+  }
+}
+
 // The same sum over the taps with the Parareal correction of the sweep
 // applied at once (no mass fix or limiter): g1 = G(u) as k_cnn_last_gather
 // forms it, then u <- f + (g1 - g_old), g_old <- g1 and the running sup
@@ -1522,9 +1559,14 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
   } else if (Yp) {
     // the second destination only where nothing changes the output later
     double* o2 = j.mass_fix || j.limiter ? nullptr : j.out2_base;
-    k_cnn_last_gather<<<g16, b256, 0, st>>>(Yp, n, j.nfields, B + cnn_boff(L - 1, C), j.in_base,
-                                            j.in_offs, g_out, train ? nullptr : j.out_offs,
-                                            j.residual, mass_partials(j), o2, j.out2_offs);
+    if (j.mass_fix)
+      k_cnn_last_gather<<<g16, b256, 0, st>>>(Yp, n, j.nfields, B + cnn_boff(L - 1, C), j.in_base,
+                                              j.in_offs, g_out, train ? nullptr : j.out_offs,
+                                              j.residual, mass_partials(j), o2, j.out2_offs);
+    else
+      k_cnn_last_gather_lin<<<dim3((unsigned)(j.nfields * (n * n / 512))), b256, 0, st>>>(
+          Yp, n, j.nfields, B + cnn_boff(L - 1, C), j.in_base, j.in_offs, g_out,
+          train ? nullptr : j.out_offs, j.residual, o2, j.out2_offs, n * n / 512);
     return o2 ? kDidOut2 : 0;
   }
   else if (split)
