@@ -36,11 +36,11 @@ CONFIGS = {
     "c2": dict(workload="classic AC 256x256 eps=0.01, 8 ICs x 64 slices x 200 steps dt=2e-5 "
                         "(512 fine solves per launch), G = u + CNN(u) 4 conv x 32 ch",
                n=256, eps=0.01, dt=2e-5, steps=200, slices=64, ics=8, conservative=False,
-               seed0=0, g_steps=1, cnn=(4, 32)),
+               seed0=0, g_steps=1, cnn=(4, 32), train_steps=2000, train_traj=512),
     "c3": dict(workload="mass-conservative AC 512x512 eps=0.01, 16 ICs x 128 slices x 100 steps "
                         "dt=1e-5 (2048 fine solves per launch), G = u + CNN(u) 6 conv x 48 ch",
                n=512, eps=0.01, dt=1e-5, steps=100, slices=128, ics=16, conservative=True,
-               seed0=0, g_steps=1, cnn=(6, 48)),
+               seed0=0, g_steps=1, cnn=(6, 48), train_steps=60, train_traj=128),
 }
 
 
@@ -419,11 +419,13 @@ def main():
                     help="numerical coarse step, or the workload's convolutional network "
                          "(default: the network for c2 and c3, the scheme for c1)")
     ap.add_argument("--cnn-prec", default="bf16x2", choices=["bf16", "bf16x2", "f32"])
-    ap.add_argument("--train-steps", type=int, default=2000,
+    ap.add_argument("--train-steps", type=int, default=None,
                     help="Adam steps on fine trajectories before timing (network only); "
-                         "2000 (about two minutes) bring c2 to rel-L2 <= 1e-6 at k = 2")
-    ap.add_argument("--train-traj", type=int, default=512,
-                    help="fine trajectories (16 slices each) the network is trained on")
+                         "default 2000 for c2 (about two minutes; they bring it to rel-L2 "
+                         "<= 1e-6 at k = 2) and 60 for c3 (1.2 s per step there)")
+    ap.add_argument("--train-traj", type=int, default=None,
+                    help="fine trajectories (16 slices each) the network is trained on "
+                         "(default 512 for c2, 128 for c3)")
     ap.add_argument("--train-batch", type=int, default=32)
     ap.add_argument("--train-lr-final", type=float, default=None,
                     help="cosine learning-rate decay from 1e-3 to this value over the run")
@@ -461,8 +463,10 @@ def main():
     g_num = api.Coarse(dt=cfg["dt"] * c / cfg["g_steps"], steps=cfg["g_steps"], prec="f64")
     train_info = None
     if coarse == "cnn":
-        g, train_info = trained_cnn(api, p, cfg, args.cnn_prec, args.train_steps,
-                                    n_traj=args.train_traj, batch=args.train_batch,
+        steps = cfg.get("train_steps", 0) if args.train_steps is None else args.train_steps
+        n_traj = cfg.get("train_traj", 128) if args.train_traj is None else args.train_traj
+        g, train_info = trained_cnn(api, p, cfg, args.cnn_prec, steps,
+                                    n_traj=n_traj, batch=args.train_batch,
                                     loss=args.train_loss, lr_final=args.train_lr_final)
     else:
         g = g_num
