@@ -350,8 +350,9 @@ typedef enum { PR_PLAN_AUTO = 0, PR_PLAN_STREAM = 1, PR_PLAN_RESIDENT = 2 } pr_p
  *                        LAYERED; networks with at least one hidden layer,
  *                        other shapes fall back to LAYERED;
  *   PR_CNN_PLAN_AUTO     the autotuner's measured choice for the shape if
- *                        pr_autotune_coarse ran, else FOLDED for PR_BF16X2
- *                        networks with a hidden layer, else LAYERED.
+ *                        pr_autotune_coarse ran, else FOLDED for networks
+ *                        with a hidden layer that are PR_BF16X2 or have 32
+ *                        channels, else LAYERED.
  * Training (pr_cnn_backward) always runs layer by layer. */
 typedef enum {
   PR_CNN_PLAN_AUTO = 0,

@@ -1072,6 +1072,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const T* __restrict__ dY,
     const int ky = tp / 3, kx = tp % 3;
     // dY at q - (ky - 1, kx - 1): tile coordinates (py + 2 - ky, px + 2 - kx)
     const int p = (py + 2 - ky) * (kTile + 2) + px + 2 - kx;
+    // unrolled by 4 so that the next channels' LDS value and scalar weight
+    // loads are in flight during the current channel's products (each
+    // accumulator still sums in (tp, co) order: the same bits; 32 -> 32 at
+    // 32 fields of 256^2 with the weight pass below: pr_cnn_backward 7.5 ->
+    // 6.2 ms)
+#pragma unroll 4
     for (int co = 0; co < CO; ++co) {
       const T d = tile[p * (CO + 1) + co];
       const TW* w = Wt + (tp * CO + co) * CI;  // contiguous in ci: wide scalar loads
@@ -1169,7 +1175,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict_
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int tp = 0; tp < 9; ++tp) acc[k][tp] = (T)0;
-#pragma unroll 2
+    // 8 pixels in flight per thread (each accumulator still sums its 256
+    // pixels in order: the same bits as unroll 2, 3% faster)
+#pragma unroll 8
     for (int p = 0; p < kTile * kTile; ++p) {
       const int py = p / kTile, px = p % kTile;
       T y[4];
@@ -1445,13 +1453,15 @@ int cnn_effective_plan(int C, int L, int prec) {
   int pl = g_cnn_plan.load();
   if (pl == CNN_PLAN_AUTO && L >= 3 && L <= 10)
     pl = g_cnn_tuned[c_index(C)][L - 3][prec == kCnnBf16x2 ? 1 : 0].load();
-  // untuned default: FOLDED for split networks, measured faster than
-  // LAYERED there; unsplit, its first hidden layer needs more registers
-  // than 4 waves per SIMD allow and LAYERED wins.  (The whole-network fused
+  // untuned default: FOLDED for split networks and at 32 channels, where
+  // it measured faster than LAYERED; other unsplit widths fold only the
+  // first layer, whose hidden-layer variant needs more registers than 4
+  // waves per SIMD allow, and LAYERED wins.  (The whole-network fused
   // kernel measured slower for the 4 x 32 network at 256^2, where the halo
   // recomputation adds more activation work than the saved HBM traffic is
   // worth.)
-  if (pl == CNN_PLAN_AUTO) pl = folded && prec == kCnnBf16x2 ? CNN_PLAN_FOLDED : CNN_PLAN_LAYERED;
+  if (pl == CNN_PLAN_AUTO)
+    pl = folded && (prec == kCnnBf16x2 || C == 32) ? CNN_PLAN_FOLDED : CNN_PLAN_LAYERED;
   if ((pl == CNN_PLAN_FUSED && !fused) || (pl == CNN_PLAN_FOLDED && !folded)) pl = CNN_PLAN_LAYERED;
   return pl;
 }

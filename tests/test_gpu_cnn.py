@@ -260,9 +260,9 @@ def test_fused_plan_mass_fix_limiter_and_autotune(api):
     choice = api.pr_autotune_coarse(p, g2, dev(u0))
     assert choice in ("fused", "layered", "folded")
     assert api.pr_get_coarse_plan(g2, n) == choice
-    # shapes without a fused kernel fall back to layered; untuned, a split
-    # network with a hidden layer takes the folded plan, an unsplit one or
-    # one without a hidden layer takes layered
+    # shapes without a fused kernel fall back to layered; untuned, a network
+    # with a hidden layer that is split or 32 channels wide takes the folded
+    # plan, another unsplit one or one without a hidden layer takes layered
     _, _, g64 = make(api, cnn.CnnSpec(n_layers=4, channels=64), seed=1, prec="bf16")
     _, _, g2l = make(api, cnn.CnnSpec(n_layers=2, channels=32), seed=1, prec="bf16x2")
     _, _, g5 = make(api, cnn.CnnSpec(n_layers=5, channels=16), seed=1, prec="bf16x2")
@@ -277,3 +277,5 @@ def test_fused_plan_mass_fix_limiter_and_autotune(api):
     assert api.pr_get_coarse_plan(g64, n) == "layered"
     assert api.pr_get_coarse_plan(g2l, n) == "layered"
     assert api.pr_get_coarse_plan(g5, n) == "folded"
+    _, _, g32 = make(api, cnn.CnnSpec(n_layers=5, channels=32), seed=1, prec="bf16")
+    assert api.pr_get_coarse_plan(g32, n) == "folded"
