@@ -1123,6 +1123,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const T* __restrict__ d
     if (q < CO * CI * 9) {
       const int co = q / (CI * 9), ci = (q / 9) % CI, tp = q % 9;
       const int ky = tp / 3, kx = tp % 3;
+      // 8 pixels in flight; the sum still runs in pixel order (the same
+      // bits; pr_cnn_backward at 32 fields of 256^2: 6.5 -> 6.2 ms)
+#pragma unroll 8
       for (int p = 0; p < kTile * kTile; ++p) {
         const int py = p / kTile, px = p % kTile;
         s += (double)(yt[p * (CO + 1) + co] * xt[((py + ky) * (kTile + 2) + px + kx) * (CI + 1) + ci]);
