@@ -1150,8 +1150,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict_
                                                             double* __restrict__ partial) {
   static_assert(CO % 4 == 0, "output channels in blocks of 4");
   constexpr int NP = CO * CI * 9 + CO, TASKS = (CO / 4) * CI;
-  __shared__ T xt[(kTile + 2) * (kTile + 2) * (CI + 1)];
-  __shared__ T yt[kTile * kTile * (CO + 1)];
+  // Unpadded tiles: in the product loop every lane of a wave reads the same
+  // pixel (its lanes differ in channels only), so there are no bank
+  // conflicts to avoid, and dY's 4 channels come in one 16-byte read
+  // (pr_cnn_backward at 32 fields of 256^2: 6.21 -> 6.10 ms, same bits).
+  constexpr int XS = CI, YS = CO;
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  __shared__ __align__(32) T xt[(kTile + 2) * (kTile + 2) * XS];
+  __shared__ __align__(32) T yt[kTile * kTile * YS];
   const int tid = threadIdx.x;
   const int tpr = n / kTile, m = n - 1;
   const int64_t f = blockIdx.x / (tpr * tpr);
@@ -1163,11 +1169,11 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict_
     const int64_t gi = ((f * n + ((y0 + ty - 1) & m)) * (int64_t)n + ((x0 + tx - 1) & m)) * CI + c;
     T v = (T)X[gi];
     if (X_lo) v += (T)X_lo[gi];
-    xt[p * (CI + 1) + c] = v;
+    xt[p * XS + c] = v;
   }
   for (int i = tid; i < kTile * kTile * CO; i += 256) {
     const int p = i / CO, c = i % CO;
-    yt[p * (CO + 1) + c] = dY[((f * n + y0 + p / kTile) * (int64_t)n + x0 + p % kTile) * CO + c];
+    yt[p * YS + c] = dY[((f * n + y0 + p / kTile) * (int64_t)n + x0 + p % kTile) * CO + c];
   }
   __syncthreads();
   double* out = partial + (int64_t)blockIdx.x * NP;
@@ -1184,11 +1190,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict_
     for (int p = 0; p < kTile * kTile; ++p) {
       const int py = p / kTile, px = p % kTile;
       T y[4];
+      const T4 yv = *(const T4*)&yt[p * YS + co0];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) y[k] = yt[p * (CO + 1) + co0 + k];
+      for (int k = 0; k < 4; ++k) y[k] = yv[k];
 #pragma unroll
       for (int tp = 0; tp < 9; ++tp) {
-        const T x = xt[((py + tp / 3) * (kTile + 2) + px + tp % 3) * (CI + 1) + ci];
+        const T x = xt[((py + tp / 3) * (kTile + 2) + px + tp % 3) * XS + ci];
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[k][tp] += y[k] * x;
       }
@@ -1200,7 +1207,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict_
   }
   for (int co = tid; co < CO; co += 256) {
     double s = 0.0;
-    for (int p = 0; p < kTile * kTile; ++p) s += (double)yt[p * (CO + 1) + co];
+    for (int p = 0; p < kTile * kTile; ++p) s += (double)yt[p * YS + co];
     out[CO * CI * 9 + co] = s;
   }
 }
