@@ -1238,11 +1238,21 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int64_t bl
   else out_b[q - nw] = (T)s;
 }
 
-// dZ = dA * act'(z), in place on dA
+// dZ = dA * act'(z), in place on dA; four consecutive elements per thread
+// (count is a multiple of 4: channels come in multiples of 8), so each
+// lane moves 16-byte or wider words
 template <typename T, typename TZ>
-__global__ void k_act_bwd(T* __restrict__ dA, const TZ* __restrict__ z, int64_t count, int act) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) dA[i] = dA[i] * (T)act_grad<T>((T)z[i], act);
+__global__ __launch_bounds__(256) void k_act_bwd(T* __restrict__ dA, const TZ* __restrict__ z,
+                                                 int64_t count, int act) {
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  typedef TZ Z4 __attribute__((ext_vector_type(4)));
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i >= count) return;
+  T4 d = *(const T4*)&dA[i];
+  const Z4 zz = *(const Z4*)&z[i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) d[k] = d[k] * (T)act_grad<T>((T)zz[k], act);
+  *(T4*)&dA[i] = d;
 }
 
 // Backward of the output stage.  Forward: o0 = [residual] u + net; o1 = o0 -
@@ -1691,7 +1701,7 @@ static hipError_t cnn_bwd_layers(const CnnJob& j, const double* dG, double* du, 
   // last layer: C -> 1
   conv_bwd<C, 1, TG, TA, TW>(j, d0, A(L - 2), Alo(L - 2), W + cnn_woff(L - 1, L, C),
                              gW + cnn_woff(L - 1, L, C), gB + cnn_boff(L - 1, C), d1, st);
-  const dim3 ge((unsigned)((act_elems + 255) / 256)), b256(256);
+  const dim3 ge((unsigned)((act_elems / 4 + 255) / 256)), b256(256);  // act_elems % 8 == 0
   k_act_bwd<TG, TZ><<<ge, b256, 0, st>>>(d1, Z(L - 2), act_elems, j.act);
   std::swap(d0, d1);  // d0 = dZ of layer L-2
   for (int l = L - 2; l >= 1; --l) {
