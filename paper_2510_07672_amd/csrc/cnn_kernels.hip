@@ -1138,6 +1138,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const T* __restrict__ d
   }
 }
 
+// Byte offset of the bias sums in k_conv_bwd_weight_rb's partials, after
+// the weight sums of all blocks (256-byte aligned).
+__host__ __device__ constexpr size_t rb_bias_offset(int64_t blocks, int nw, size_t elem) {
+  return ((size_t)blocks * nw * elem + 255) / 256 * 256;
+}
+
 // The same partial sums for wide layers (CI, CO >= 32), register-blocked:
 // a task is 4 output channels x 9 taps of one input channel, so that per
 // pixel a thread reads 4 values of dY and 9 of X for 36 products (instead
@@ -1147,9 +1153,9 @@ template <int CI, int CO, typename T, typename TX>
 __global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict__ dY,
                                                             const TX* __restrict__ X,
                                                             const TX* __restrict__ X_lo, int n,
-                                                            double* __restrict__ partial) {
+                                                            void* __restrict__ partial) {
   static_assert(CO % 4 == 0, "output channels in blocks of 4");
-  constexpr int NP = CO * CI * 9 + CO, TASKS = (CO / 4) * CI;
+  constexpr int NW = CO * CI * 9, TASKS = (CO / 4) * CI;
   // Unpadded tiles: in the product loop every lane of a wave reads the same
   // pixel (its lanes differ in channels only), so there are no bank
   // conflicts to avoid, and dY's 4 channels come in one 16-byte read
@@ -1176,7 +1182,11 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict_
     yt[p * YS + c] = dY[((f * n + y0 + p / kTile) * (int64_t)n + x0 + p % kTile) * CO + c];
   }
   __syncthreads();
-  double* out = partial + (int64_t)blockIdx.x * NP;
+  // the weight sums in T (the accumulators' own type, widened only when
+  // reduced), the bias sums in FP64 after them
+  T* out = (T*)partial + (int64_t)blockIdx.x * NW;
+  double* outb = (double*)((char*)partial + rb_bias_offset(gridDim.x, NW, sizeof(T))) +
+                 (int64_t)blockIdx.x * CO;
   for (int task = tid; task < TASKS; task += 256) {
     const int co0 = (task % (CO / 4)) * 4, ci = task / (CO / 4);
     T acc[4][9];
@@ -1203,26 +1213,33 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_rb(const T* __restrict_
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int tp = 0; tp < 9; ++tp) out[((co0 + k) * CI + ci) * 9 + tp] = (double)acc[k][tp];
+      for (int tp = 0; tp < 9; ++tp) out[((co0 + k) * CI + ci) * 9 + tp] = acc[k][tp];
   }
   for (int co = tid; co < CO; co += 256) {
     double s = 0.0;
     for (int p = 0; p < kTile * kTile; ++p) s += (double)yt[p * YS + co];
-    out[CO * CI * 9 + co] = s;
+    outb[co] = s;
   }
 }
 
 // First stage of the deterministic weight-gradient reduction: group g
 // (blockIdx.y) sums rows [g per, (g + 1) per) of partial, in row order, into
 // part2[g][q].  Many groups keep the whole GPU reading the partial sums.
-__global__ void k_reduce_groups(const double* __restrict__ partial, int64_t blocks, int np,
-                                int64_t per, double* __restrict__ part2) {
+// Entries q < nw of block b at wp[b nw + q] (PW, widened exactly to
+// double), the others at bp[b (np - nw) + q - nw]; nw = np for one array.
+template <typename PW>
+__global__ void k_reduce_groups(const PW* __restrict__ wp, const double* __restrict__ bp,
+                                int64_t blocks, int nw, int np, int64_t per,
+                                double* __restrict__ part2) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= np) return;
   const int64_t b0 = (int64_t)blockIdx.y * per;
   const int64_t b1 = b0 + per < blocks ? b0 + per : blocks;
   double s = 0.0;
-  for (int64_t b = b0; b < b1; ++b) s += partial[b * np + q];
+  if (q < nw)
+    for (int64_t b = b0; b < b1; ++b) s += (double)wp[b * nw + q];
+  else
+    for (int64_t b = b0; b < b1; ++b) s += bp[b * (np - nw) + q - nw];
   part2[(int64_t)blockIdx.y * np + q] = s;
 }
 
@@ -1659,14 +1676,22 @@ static void conv_bwd(const CnnJob& j, const TG* dY, const TX* X, const TX* X_lo,
   const int64_t tiles16 = j.nfields * (int64_t)(n / kTile) * (n / kTile);
   const dim3 g16((unsigned)tiles16), b256(256);
   constexpr int NP = CO * CI * 9 + CO;
-  if constexpr (CI >= 32 && CO >= 32)
-    k_conv_bwd_weight_rb<CI, CO, TG, TX><<<g16, b256, 0, st>>>(dY, X, X_lo, n, j.ws.wpart);
-  else
-    k_conv_bwd_weight<CI, CO, TG, TX><<<g16, b256, 0, st>>>(dY, X, X_lo, n, j.ws.wpart);
   // tiles -> kWGradGroups group sums -> dW, each stage in a fixed order
   const int64_t per = (tiles16 + kWGradGroups - 1) / kWGradGroups;
-  k_reduce_groups<<<dim3((NP + 255) / 256, kWGradGroups), b256, 0, st>>>(j.ws.wpart, tiles16, NP,
-                                                                         per, j.ws.wpart2);
+  const dim3 gr((NP + 255) / 256, kWGradGroups);
+  if constexpr (CI >= 32 && CO >= 32) {
+    // weight sums stored in TG (half the bytes in FP32), biases in FP64
+    constexpr int NW = CO * CI * 9;
+    k_conv_bwd_weight_rb<CI, CO, TG, TX><<<g16, b256, 0, st>>>(dY, X, X_lo, n, j.ws.wpart);
+    const double* bp = (const double*)((const char*)j.ws.wpart +
+                                       rb_bias_offset(tiles16, NW, sizeof(TG)));
+    k_reduce_groups<TG><<<gr, b256, 0, st>>>((const TG*)j.ws.wpart, bp, tiles16, NW, NP, per,
+                                             j.ws.wpart2);
+  } else {
+    k_conv_bwd_weight<CI, CO, TG, TX><<<g16, b256, 0, st>>>(dY, X, X_lo, n, j.ws.wpart);
+    k_reduce_groups<double><<<gr, b256, 0, st>>>(j.ws.wpart, nullptr, tiles16, NP, NP, per,
+                                                 j.ws.wpart2);
+  }
   k_reduce_partials<TW><<<dim3((NP + 255) / 256), b256, 0, st>>>(j.ws.wpart2, kWGradGroups, NP, dW,
                                                                  CO * CI * 9, db);
   if (dX) {
