@@ -1235,11 +1235,16 @@ __global__ void k_reduce_groups(const PW* __restrict__ wp, const double* __restr
   if (q >= np) return;
   const int64_t b0 = (int64_t)blockIdx.y * per;
   const int64_t b1 = b0 + per < blocks ? b0 + per : blocks;
+  // unrolled so that several blocks' loads are in flight; the sum still
+  // runs in block order
   double s = 0.0;
-  if (q < nw)
+  if (q < nw) {
+#pragma unroll 8
     for (int64_t b = b0; b < b1; ++b) s += (double)wp[b * nw + q];
-  else
+  } else {
+#pragma unroll 8
     for (int64_t b = b0; b < b1; ++b) s += bp[b * (np - nw) + q - nw];
+  }
   part2[(int64_t)blockIdx.y * np + q] = s;
 }
 
