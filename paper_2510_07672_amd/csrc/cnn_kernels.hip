@@ -1255,6 +1255,7 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int64_t bl
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= np) return;
   double s = 0.0;
+#pragma unroll 8
   for (int64_t b = 0; b < blocks; ++b) s += partial[b * np + q];
   if (q < nw) out_w[q] = (T)s;
   else out_b[q - nw] = (T)s;
