@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 9
+#define PR_ABI_VERSION 10
 
 typedef enum {
   PR_OK = 0,
@@ -213,6 +213,28 @@ pr_status pr_cnn_backward(const pr_problem* p, const pr_coarse* g, int64_t nfiel
                           void* grad_w, void* grad_b, void* ws, size_t ws_bytes,
                           void* stream);
 
+/* The scheme-residual training loss of Algorithm 1 (eq. loss_ACN): for
+ * `nfields` pairs (U_n, U_{n+1}) = (u_n, u_np1), device
+ * double[nfields][N][N], the residual of the Crank-Nicolson scheme
+ * (Section 3.1, eq. fully-discrete) over one step dt with the 5-point
+ * Laplacian and the mass-keeping placement of the nonlocal term,
+ *   r = U1 - U0 - dt/2 (eps^2 (Lap_h U1 + Lap_h U0) + f(U1) + f(U0))
+ *       + dt/2 (mean f(U1) + mean f(U0))   (conservative model only),
+ * and the loss mean(r^2) over every point of every pair, written to
+ * *loss (device, one double).  Optional outputs (NULL to skip):
+ *   grad   device double[nfields][N][N]: dloss/du_np1 (the coarse
+ *          propagator's output is u_np1 in training);
+ *   resid  device double[nfields][N][N]: r.
+ * eps, the model and N come from p (p->laplacian must be PR_LAP_FD5,
+ * PR_ERR_UNSUPPORTED otherwise; p->dt, steps and scheme are not used).
+ * FP64 throughout; every sum is per-block partials added in a fixed
+ * order.  The output arrays must not alias the inputs or each other. */
+size_t pr_scheme_loss_workspace_bytes(const pr_problem* p, int64_t nfields);
+pr_status pr_scheme_loss(const pr_problem* p, double dt, int64_t nfields,
+                         const double* u_n, const double* u_np1, double* loss,
+                         double* grad, double* resid, void* ws, size_t ws_bytes,
+                         void* stream);
+
 /* ------------------------------------------------------- correction --- */
 
 /* The Parareal correction of Section 3.3 / Algorithm 2, for `nfields`
@@ -364,7 +386,7 @@ typedef enum {
 pr_status pr_set_coarse_plan(int32_t plan);
 
 /* The plan pr_coarse_apply will use for g on N x N fields (LAYERED, FUSED
- * or HEAD), or -1 if g is not a valid network. */
+ * or FOLDED), or -1 if g is not a valid network. */
 int32_t pr_get_coarse_plan(const pr_coarse* g, int32_t n);
 
 /* Times every plan available for g on the caller's batch (u_in -> g_out,

@@ -221,6 +221,24 @@ def cn_residual(u: np.ndarray, v: np.ndarray, p: "Problem", dt: float) -> np.nda
                                 + fu + fv) + dt * cn_nonlocal(fu, fv, p.conservative))
 
 
+def cn_residual_loss(u: np.ndarray, v: np.ndarray, p: "Problem", dt: float):
+    """The scheme-based training loss of Algorithm 1 (eq. loss_ACN) for the
+    pairs (U_n, U_{n+1}) = (u, v): L = mean of cn_residual^2 over every
+    point of every pair, and dL/dv.
+
+    The residual is linear in the stencil and pointwise in f, so with
+    J = dr/dv = I - dt/2 (eps^2 Lap_h + diag f'(v)) + dt/2 (1/N^2) 1 f'(v)^T
+    (the last term in the conservative model only, f' = 1 - 3 v^2) the
+    gradient is (2/M) J^T r; Lap_h is symmetric.  M = number of points."""
+    r = cn_residual(u, v, p, dt)
+    m = r.size
+    fp = 1.0 - 3.0 * v * v
+    g = r - 0.5 * dt * (p.eps * p.eps * apply_laplacian(r, p) + fp * r)
+    if p.conservative:
+        g = g + 0.5 * dt * fp * r.mean(axis=(-2, -1), keepdims=True)
+    return float((r * r).mean()), (2.0 / m) * g
+
+
 def step(u: np.ndarray, p: "Problem", dt: float) -> np.ndarray:
     """One step of the problem's fine scheme with step size dt."""
     if p.scheme == "cn":

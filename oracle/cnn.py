@@ -77,34 +77,69 @@ def conv3x3_periodic(x: torch.Tensor, W: torch.Tensor, b: torch.Tensor) -> torch
 
 
 def bf16(x: torch.Tensor) -> torch.Tensor:
-    """Round to bfloat16 (round to nearest even) and back to float64."""
-    return x.to(torch.bfloat16).to(torch.float64)
+    """Each value rounded to the nearest bfloat16 number (8 significant
+    bits), ties to the one with an even last bit, in a single rounding from
+    float64; returned as float64.  Normal-range values only (weights and
+    activations of the network).  Gradients pass straight through."""
+    xd = x.detach().to(torch.float64)
+    m, e = torch.frexp(xd)                  # xd = m 2^e, 1/2 <= |m| < 1
+    r = torch.ldexp(torch.round(m * 256.0), (e - 8).to(torch.float64))
+    return x + (r - xd)
+
+
+PRECISIONS = ("exact", "bf16", "bf16x2")
+
+
+def rounding_plan(prec: str, n_layers: int):
+    """Which numbers a network of the given number format rounds to bfloat16.
+
+    Section 3.2's network is a chain of 3x3 convolutions; the workloads run
+    it on the bfloat16 matrix cores with FP32 accumulation.  The dense
+    contractions are the hidden convolutions C -> C, and those are what
+    take bfloat16 operands:
+
+      "exact"   nothing is rounded (float64 throughout);
+      "bf16"    the weights of every hidden layer (0 < l < L-1) and every
+                activation a layer hands on (the output of layers
+                0 .. L-2, after the activation function) are rounded to
+                bfloat16; the first layer (1 -> C, nine taps per output)
+                keeps its weights and reads the state unrounded, and the
+                last layer (C -> 1) keeps its weights;
+      "bf16x2"  the split form: the same bfloat16 hidden weights, with each
+                activation carried as a pair hi + lo of bfloat16 numbers
+                (16 significant bits or more), taken here as unrounded.
+
+    Returns (round_weights[l], round_activation[l]) for l = 0 .. L-1.
+    All sums stay float64; the GPU's FP32 accumulation and its hi + lo
+    pairs differ from this by FP32-level roundings, well inside the test
+    tolerances derived from them."""
+    if prec not in PRECISIONS:
+        raise ValueError(f"unknown network precision {prec!r}")
+    L = n_layers
+    rw = [prec != "exact" and 0 < l < L - 1 for l in range(L)]
+    ra = [prec == "bf16" and l < L - 1 for l in range(L)]
+    return rw, ra
 
 
 def forward(u, weights: Sequence[torch.Tensor], biases: Sequence[torch.Tensor],
-            spec: CnnSpec, emulate_bf16=False) -> np.ndarray:
+            spec: CnnSpec, prec: str = "exact") -> np.ndarray:
     """G(u) for u [B, N, N] (numpy or torch); returns float64 numpy.
 
-    emulate_bf16 = True (or "all"): the activations after every layer but
-    the last, and the weights of the hidden (C -> C) layers, are rounded to
-    bfloat16 where a bfloat16 kernel stores them (the first and last layers
-    keep their weights and the first reads the state unrounded);
-    "weights": only those weights are rounded.
-    All sums stay float64."""
-    round_w = emulate_bf16 in (True, "all", "weights")
-    round_a = emulate_bf16 in (True, "all")
+    `prec` is the network's number format, as `rounding_plan` defines it;
+    "exact" is the network itself in float64."""
+    rw, ra = rounding_plan(prec, spec.n_layers)
     ut = torch.as_tensor(np.asarray(u, dtype=np.float64))
     x = ut[:, None]
     L = spec.n_layers
     for l in range(L):
         W, b = weights[l].to(torch.float64), biases[l].to(torch.float64)
-        if round_w and 0 < l < L - 1:
+        if rw[l]:
             W = bf16(W)
         x = conv3x3_periodic(x, W, b)
         if l < L - 1:
             x = _act(x, spec.act)
-            if round_a:
-                x = bf16(x)
+        if ra[l]:
+            x = bf16(x)
     net = x[:, 0]
     out = ut + net if spec.residual else net
     if spec.mass_fix:

@@ -23,6 +23,7 @@ EXPORTED = [
     "pr_fine_workspace_bytes", "pr_fine_propagate",
     "pr_coarse_workspace_bytes", "pr_coarse_apply",
     "pr_cnn_backward_workspace_bytes", "pr_cnn_backward",
+    "pr_scheme_loss_workspace_bytes", "pr_scheme_loss",
     "pr_correct",
     "pr_solve_workspace_bytes", "pr_solve",
     "pr_solve_many_workspace_bytes", "pr_solve_many",
@@ -86,6 +87,8 @@ def lib() -> C.CDLL:
             "pr_coarse_apply": (C.c_int, [P, G, i64, vp, vp, vp, sz, vp]),
             "pr_cnn_backward_workspace_bytes": (sz, [P, G, i64]),
             "pr_cnn_backward": (C.c_int, [P, G, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
+            "pr_scheme_loss_workspace_bytes": (sz, [P, i64]),
+            "pr_scheme_loss": (C.c_int, [P, C.c_double, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
             "pr_correct": (C.c_int, [i64, i32, vp, C.c_int, vp, vp, vp, vp, i32, vp]),
             "pr_solve_workspace_bytes": (sz, [P, G, i64, i32]),
             "pr_solve": (C.c_int, [P, G, i64, i32, vp, vp, C.c_double, i32, S, vp, sz, vp]),

@@ -186,6 +186,27 @@ def pr_cnn_backward(p: Problem, g: "CnnCoarse", u_in: torch.Tensor, grad_out: to
     return du, dW, dB
 
 
+def pr_scheme_loss(p: Problem, dt: float, u_n: torch.Tensor, u_np1: torch.Tensor,
+                   grad: bool = True, resid: bool = False, ws: Optional[torch.Tensor] = None):
+    """Mean squared Crank-Nicolson residual of the pairs (u_n, u_np1) over one
+    step dt (eq. loss_ACN), as a 0-d device tensor, with dloss/du_np1 and
+    the residual when asked for: returns (loss, grad or None, resid or None)."""
+    B = _fields(u_n, p.n, "u_n")
+    if _fields(u_np1, p.n, "u_np1") != B:
+        raise ValueError("u_n and u_np1 must hold the same number of fields")
+    pc = p.c()
+    loss = torch.empty((), dtype=torch.float64, device=u_n.device)
+    g = torch.empty_like(u_n) if grad else None
+    r = torch.empty_like(u_n) if resid else None
+    need = L.lib().pr_scheme_loss_workspace_bytes(C.byref(pc), B)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, u_n.device)
+    L.check(L.lib().pr_scheme_loss(C.byref(pc), float(dt), B, _ptr(u_n), _ptr(u_np1), _ptr(loss),
+                                   _ptr(g), _ptr(r), _ptr(ws), ws.numel(), _stream(u_n.device)),
+            "pr_scheme_loss")
+    return loss, g, r
+
+
 def pr_correct(f: torch.Tensor, g_new: torch.Tensor, g_old: torch.Tensor, u: torch.Tensor,
                upd_max: torch.Tensor, update_cache: bool = True):
     """u <- f + (g_new - g_old); upd_max <- max(upd_max, |change|); g_old <- g_new."""

@@ -4,6 +4,8 @@ Algorithm 1).  Argument marshalling only: forward and backward both run in
 libpr's kernels (pr_coarse_apply, pr_cnn_backward).
 
 CnnApply    one application G(u; W, b).
+SchemeLoss  the scheme-residual loss of eq. loss_ACN of a pair (U_n, U_{n+1})
+            with its gradient with respect to U_{n+1} (pr_scheme_loss).
 CnnRollout  s successive applications u_{t+1} = G(u_t), returning every
             u_t (t = 1..s).  Only every `ckpt`-th state is kept; backward
             recomputes each segment of `ckpt` steps from its first state
@@ -80,3 +82,23 @@ class CnnRollout(torch.autograd.Function):
 
 def cnn_rollout(net, problem, u0, steps, ckpt=2):
     return CnnRollout.apply(u0, net.W, net.B, net, problem, steps, ckpt)
+
+
+class SchemeLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u_n, u_np1, problem, dt):
+        loss, grad, _ = api.pr_scheme_loss(problem, dt, u_n.detach().contiguous(),
+                                           u_np1.detach().contiguous(), grad=True)
+        ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        return None, grad * gout, None, None
+
+
+def scheme_loss(problem, u_n, u_np1, dt):
+    """mean(r^2) of the Crank-Nicolson residual of (u_n, u_np1); differentiable
+    in u_np1 (u_n is data)."""
+    return SchemeLoss.apply(u_n, u_np1, problem, dt)

@@ -16,6 +16,7 @@
 
 #include "../../include/pr.h"
 #include "internal.h"
+#include "loss_kernels.h"
 
 using namespace pr;
 
@@ -1105,6 +1106,45 @@ pr_status pr_coarse_apply(const pr_problem* p, const pr_coarse* g, int64_t nfiel
   hipStream_t s = (hipStream_t)stream;
   PR_HIP(coarse_setup(p, g, w, s));
   PR_HIP(coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s));
+  return PR_OK;
+}
+
+size_t pr_scheme_loss_workspace_bytes(const pr_problem* p, int64_t nfields) {
+  if (check_problem(p) != PR_OK || nfields < 0) return 0;
+  return scheme_loss_ws_bytes(p->n, nfields, true);
+}
+
+pr_status pr_scheme_loss(const pr_problem* p, double dt, int64_t nfields, const double* u_n,
+                         const double* u_np1, double* loss, double* grad, double* resid,
+                         void* ws, size_t ws_bytes, void* stream) {
+  pr_status st = check_problem(p);
+  if (st != PR_OK) return st;
+  if (p->laplacian != PR_LAP_FD5)
+    return fail(PR_ERR_UNSUPPORTED, "the scheme loss uses the 5-point Laplacian (PR_LAP_FD5)");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(PR_ERR_INVALID_ARG, "dt must be finite and > 0");
+  if (nfields < 1) return fail(PR_ERR_INVALID_ARG, "nfields must be >= 1");
+  if (!u_n || !u_np1 || !loss) return fail(PR_ERR_INVALID_ARG, "u_n / u_np1 / loss is NULL");
+  const size_t fb = (size_t)nfields * p->n * p->n * sizeof(double);
+  auto overlaps = [](const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return a && b && x < y + nb && y < x + na;
+  };
+  const void* outs[3] = {loss, grad, resid};
+  const size_t osz[3] = {sizeof(double), fb, fb};
+  for (int i = 0; i < 3; ++i) {
+    if (overlaps(outs[i], osz[i], u_n, fb) || overlaps(outs[i], osz[i], u_np1, fb))
+      return fail(PR_ERR_INVALID_ARG, "an output aliases an input");
+    for (int k = i + 1; k < 3; ++k)
+      if (overlaps(outs[i], osz[i], outs[k], osz[k]))
+        return fail(PR_ERR_INVALID_ARG, "outputs alias each other");
+  }
+  const size_t need = scheme_loss_ws_bytes(p->n, nfields, resid == nullptr);
+  if (!ws || ws_bytes < need)
+    return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
+  const double h = p->length / p->n;
+  SchemeLossJob j{p->n, nfields, u_n, u_np1, dt, p->eps * p->eps, 1.0 / (h * h),
+                  p->conservative, loss, grad, resid, ws};
+  PR_HIP(launch_scheme_loss(j, (hipStream_t)stream));
   return PR_OK;
 }
 

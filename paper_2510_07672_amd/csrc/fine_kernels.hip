@@ -898,6 +898,7 @@ struct GraphEntry {
   int64_t grid_fields;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  hipEvent_t done;     // recorded after every launch of exec
   uint64_t last_use;
 };
 
@@ -911,6 +912,15 @@ constexpr size_t kMaxGraphs = 32;
 void set_graphs_enabled(bool on) { g_graphs_on.store(on); }
 bool graphs_enabled() { return g_graphs_on.load(); }
 
+// Replays an entry on st and marks the launch with the entry's event.
+// Called with g_graph_mu held.
+static hipError_t replay(GraphEntry& e, hipStream_t st) {
+  e.last_use = ++g_graph_clock;
+  hipError_t err = hipGraphLaunch(e.exec, st);
+  if (err != hipSuccess) return err;
+  return hipEventRecord(e.done, st);
+}
+
 template <int N, typename T>
 static hipError_t launch_stream_graph(const StepJob& job, hipStream_t st) {
   // with per-field parameters the launch argument is unused, and every
@@ -921,47 +931,65 @@ static hipError_t launch_stream_graph(const StepJob& job, hipStream_t st) {
                job.ws.desc, job.ws.spec, job.scheme == SCHEME_CN ? job.ws.xspec : nullptr,
                job.ws.partials, job.f32 ? (const void*)job.ws.tw32 : (const void*)job.ws.tw64,
                job.ws.s2};
-  std::lock_guard<std::mutex> lock(g_graph_mu);
-  GraphEntry* hit = nullptr;
-  for (auto& e : g_graphs)
-    if (e.key.same(key) && e.grid_fields >= job.nfields &&
-        (!hit || e.grid_fields < hit->grid_fields))
-      hit = &e;
-  if (!hit) {
-    hipError_t err;
-    if (!g_capture_stream) {
-      err = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking);
-      if (err != hipSuccess) return err;
-    }
+  auto find = [&]() -> GraphEntry* {
+    GraphEntry* hit = nullptr;
+    for (auto& e : g_graphs)
+      if (e.key.same(key) && e.grid_fields >= job.nfields &&
+          (!hit || e.grid_fields < hit->grid_fields))
+        hit = &e;
+    return hit;
+  };
+  GraphEntry victim{};
+  bool evict = false;
+  {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    if (GraphEntry* hit = find()) return replay(*hit, st);
     if (g_graphs.size() >= kMaxGraphs) {
-      // evict the least recently used entry once nothing can still run it
+      // take the least recently used entry out of the cache; it is
+      // destroyed below, once its last launch has finished
       size_t lru = 0;
       for (size_t i = 1; i < g_graphs.size(); ++i)
         if (g_graphs[i].last_use < g_graphs[lru].last_use) lru = i;
-      err = hipDeviceSynchronize();
-      if (err != hipSuccess) return err;
-      (void)hipGraphExecDestroy(g_graphs[lru].exec);
-      (void)hipGraphDestroy(g_graphs[lru].graph);
+      victim = g_graphs[lru];
       g_graphs.erase(g_graphs.begin() + lru);
+      evict = true;
     }
-    GraphEntry e{key, job.nfields, nullptr, nullptr, 0};
-    err = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
-    if (err != hipSuccess) return err;
-    enqueue_steps<N, T>(job, job.nfields, g_capture_stream);
-    hipError_t lerr = hipGetLastError();
-    err = hipStreamEndCapture(g_capture_stream, &e.graph);
-    if (lerr != hipSuccess) return lerr;
-    if (err != hipSuccess) return err;
-    err = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
-    if (err != hipSuccess) {
-      (void)hipGraphDestroy(e.graph);
-      return err;
-    }
-    g_graphs.push_back(e);
-    hit = &g_graphs.back();
   }
-  hit->last_use = ++g_graph_clock;
-  return hipGraphLaunch(hit->exec, st);
+  if (evict) {
+    // waits for that entry's work only (not the device), without the lock
+    hipError_t err = hipEventSynchronize(victim.done);
+    (void)hipGraphExecDestroy(victim.exec);
+    (void)hipGraphDestroy(victim.graph);
+    (void)hipEventDestroy(victim.done);
+    if (err != hipSuccess) return err;
+  }
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  if (GraphEntry* hit = find()) return replay(*hit, st);   // captured meanwhile
+  hipError_t err;
+  if (!g_capture_stream) {
+    err = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking);
+    if (err != hipSuccess) return err;
+  }
+  GraphEntry e{key, job.nfields, nullptr, nullptr, nullptr, 0};
+  err = hipEventCreateWithFlags(&e.done, hipEventDisableTiming);
+  if (err != hipSuccess) return err;
+  err = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
+  if (err != hipSuccess) {
+    (void)hipEventDestroy(e.done);
+    return err;
+  }
+  enqueue_steps<N, T>(job, job.nfields, g_capture_stream);
+  hipError_t lerr = hipGetLastError();
+  err = hipStreamEndCapture(g_capture_stream, &e.graph);
+  if (lerr == hipSuccess && err == hipSuccess)
+    err = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+  if (lerr != hipSuccess || err != hipSuccess) {
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    (void)hipEventDestroy(e.done);
+    return lerr != hipSuccess ? lerr : err;
+  }
+  g_graphs.push_back(e);
+  return replay(g_graphs.back(), st);
 }
 
 template <int N, typename T>

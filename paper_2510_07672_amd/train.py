@@ -5,7 +5,8 @@ Two losses:
     (the loss the workloads fix), over unrolled checkpointed rollouts;
   * `train_scheme`: Algorithm 1 with the scheme-based loss eq. loss_ACN,
     the residual of the Crank-Nicolson scheme (eq. fully-discrete) over one
-    coarse step, which needs no fine-solver data.
+    coarse step, which needs no fine-solver data; the residual, the loss
+    and its gradient run in libpr (pr_scheme_loss).
 
 Data: R initial conditions, each advanced slice by slice with the FP64
 fine propagator (pr_serial_fine), so targets are U_{t+1} = F(U_t).
@@ -62,11 +63,12 @@ class TrainLog:
 
 def train(net: api.CnnCoarse, p: api.Problem, data: torch.Tensor, steps: int, batch: int = 32,
           rollout: int = 8, ckpt: int = 2, lr: float = 1e-3, seed: int = 0,
-          progress=None, lr_final: float = None) -> TrainLog:
+          progress=None, lr_final: float = None, lr_drop: float = None) -> TrainLog:
     """`steps` Adam updates on random (trajectory, start) pairs; `progress`,
     if given, is called as progress(step, loss, ms) after every update.
     With `lr_final` the learning rate follows a cosine from `lr` down to it
-    over the run; otherwise it stays at `lr`."""
+    over the run; with `lr_drop` = q it drops to lr / 10 for the last
+    fraction q of the steps; otherwise it stays at `lr`."""
     R, T1 = data.shape[0], data.shape[1]
     if T1 - 1 < rollout:
         raise ValueError("trajectories shorter than the rollout")
@@ -77,7 +79,11 @@ def train(net: api.CnnCoarse, p: api.Problem, data: torch.Tensor, steps: int, ba
              if lr_final is not None else None)
     gen = torch.Generator().manual_seed(seed)
     log = TrainLog()
-    for _ in range(steps):
+    drop_at = steps - int(round(steps * lr_drop)) if lr_drop else None
+    for it in range(steps):
+        if drop_at is not None and it == drop_at:
+            for grp in opt.param_groups:
+                grp["lr"] = lr * 0.1
         idx = torch.randint(0, R, (batch,), generator=gen)
         t0 = torch.randint(0, T1 - rollout, (batch,), generator=gen)
         u0 = data[idx, t0].contiguous()
@@ -101,24 +107,6 @@ def train(net: api.CnnCoarse, p: api.Problem, data: torch.Tensor, steps: int, ba
     return log
 
 
-def scheme_residual(u_n: torch.Tensor, u_np1: torch.Tensor, p: api.Problem, dt: float) -> torch.Tensor:
-    """Pointwise residual of eq. fully-discrete for the pair (U_n, U_{n+1})
-    with step dt and the 5-point Laplacian, the quantity squared in
-    eq. loss_ACN; the nonlocal terms enter as dt/2 (g(U_{n+1}) + g(U_n)),
-    g = grid mean of f, in the conservative model."""
-    h = p.length / p.n
-
-    def lap(v):
-        return (torch.roll(v, 1, -2) + torch.roll(v, -1, -2) + torch.roll(v, 1, -1)
-                + torch.roll(v, -1, -1) - 4.0 * v) / (h * h)
-
-    f1, f0 = u_np1 - u_np1 ** 3, u_n - u_n ** 3
-    r = u_np1 - u_n - 0.5 * dt * (p.eps ** 2 * (lap(u_np1) + lap(u_n)) + f1 + f0)
-    if p.conservative:
-        r = r + 0.5 * dt * (f1.mean(dim=(-2, -1), keepdim=True) + f0.mean(dim=(-2, -1), keepdim=True))
-    return r
-
-
 def train_scheme(net: api.CnnCoarse, p: api.Problem, u0: torch.Tensor, dt: float, n_steps: int,
                  inner: int = 4, subset: int = 16, lr: float = 1e-3, seed: int = 0,
                  progress=None) -> TrainLog:
@@ -140,7 +128,7 @@ def train_scheme(net: api.CnnCoarse, p: api.Problem, u0: torch.Tensor, dt: float
                 torch.cuda.synchronize()
                 tic = time.perf_counter()
                 out = autograd.cnn_apply(net, p, U)
-                loss = (scheme_residual(U, out, p, dt) ** 2).mean()
+                loss = autograd.scheme_loss(p, U, out, dt)
                 opt.zero_grad(set_to_none=True)
                 loss.backward()
                 opt.step()

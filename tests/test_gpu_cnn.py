@@ -3,13 +3,22 @@ the FP64 oracle, through the C ABI.
 
 Tolerances (relative L2 of the network part net = G(u) - u):
   * FP32 path: 1e-5 (FP32 sums of 9 C terms per layer).
-  * bf16 path against the oracle that rounds weights and activations to
-    bfloat16 where the kernel stores them: 2e-3 -- the two differ only in
+  * bf16 path against the oracle's "bf16" network (hidden weights and
+    every activation rounded to bfloat16): 2e-3 -- the two differ only in
     FP32 vs FP64 summation and in the rare bfloat16 rounding decisions that
     sit within one FP32 rounding of a tie (each such flip moves one
     activation by one bfloat16 ulp, 2^-8 relative).
-  * bf16 path against the unrounded oracle: 3e-2 (8-bit activations).
-  * hi+lo bf16 path against the oracle with bfloat16 weights only: 2e-4.
+  * bf16 path against the exact network: 1e-2 (8-bit activations).
+  * hi+lo bf16 path against the oracle's "bf16x2" network (bfloat16 hidden
+    weights, activations unrounded): 2e-4.
+  * hi+lo bf16 path against the exact network: 5e-3 -- what is left is
+    the rounding of the hidden weights (measured on the oracle: <= 2.9e-3
+    over the shapes tested here).  With hidden weights that are bfloat16
+    numbers, i.e. the network the split kernels compute exactly up to
+    their activation pairs: 5e-5 -- a hi + lo pair keeps 16 significant
+    bits or more (relative error <= 2^-17 ~ 7.6e-6 per activation), and
+    the last layer's weights are hi + lo pairs too; the oracle's split
+    emulation of that network measures <= 7e-6.
 """
 
 import numpy as np
@@ -80,21 +89,74 @@ def test_cnn_bf16_matches_oracle(api, L, C, n):
     ws, bs, g = make(api, spec, seed=7 + C, prec="bf16")
     u0 = synth.random_ic(n, [4, 5])
     out = api.pr_coarse_apply(problem(api, n), g, dev(u0)).cpu().numpy()
-    emu = cnn.forward(u0, ws, bs, spec, emulate_bf16=True)
+    emu = cnn.forward(u0, ws, bs, spec, prec="bf16")
     exact = cnn.forward(u0, ws, bs, spec)
-    assert net_rel(out, emu, u0) <= 2e-3
-    assert net_rel(out, exact, u0) <= 3e-2
+    e_emu, e_exact = net_rel(out, emu, u0), net_rel(out, exact, u0)
+    print(f"bf16 vs bf16 oracle {e_emu:.2e}, vs exact {e_exact:.2e}", flush=True)
+    assert e_emu <= 2e-3
+    assert e_exact <= 1e-2
 
 
-@pytest.mark.parametrize("C", [32, 48])
-def test_cnn_bf16x2_matches_oracle(api, C):
-    spec = cnn.CnnSpec(n_layers=4, channels=C)
+@pytest.mark.parametrize("L,C", [(4, 32), (4, 48), (3, 16), (3, 32), (6, 48)])
+def test_cnn_bf16x2_matches_oracle(api, L, C):
+    print(f"case cnn bf16x2 L={L} C={C}", flush=True)
+    spec = cnn.CnnSpec(n_layers=L, channels=C)
     ws, bs, g = make(api, spec, seed=11, prec="bf16x2")
     n = 64
     u0 = synth.random_ic(n, [6, 7])
     out = api.pr_coarse_apply(problem(api, n), g, dev(u0)).cpu().numpy()
-    ref = cnn.forward(u0, ws, bs, spec, emulate_bf16="weights")
-    assert net_rel(out, ref, u0) <= 2e-4
+    ref = cnn.forward(u0, ws, bs, spec, prec="bf16x2")
+    e_emu, e_exact = net_rel(out, ref, u0), net_rel(out, cnn.forward(u0, ws, bs, spec), u0)
+    print(f"bf16x2 vs split oracle {e_emu:.2e}, vs exact {e_exact:.2e}", flush=True)
+    assert e_emu <= 2e-4
+    assert e_exact <= 5e-3
+
+
+def bf16_hidden(ws):
+    """The same weights with those of the hidden layers made bfloat16 numbers."""
+    return [w if l in (0, len(ws) - 1) else cnn.bf16(w) for l, w in enumerate(ws)]
+
+
+@pytest.mark.parametrize("L,C,n", [(4, 32, 64), (4, 48, 64), (3, 16, 32), (6, 48, 128),
+                                   (3, 32, 256)])
+def test_cnn_bf16x2_with_bf16_weights_matches_exact_oracle(api, L, C, n):
+    """With bfloat16 hidden weights the split network is the exact network up
+    to its activation pairs: compared with the oracle's exact FP64 network."""
+    print(f"case cnn bf16x2 bf16-weights L={L} C={C} n={n}", flush=True)
+    spec = cnn.CnnSpec(n_layers=L, channels=C)
+    ws, bs = cnn.init_weights(spec, seed=17 + C)
+    ws = bf16_hidden(ws)
+    g = api.CnnCoarse(ws, bs, prec="bf16x2")
+    u0 = synth.random_ic(n, [8, 9])
+    out = api.pr_coarse_apply(problem(api, n), g, dev(u0)).cpu().numpy()
+    e = net_rel(out, cnn.forward(u0, ws, bs, spec), u0)
+    print(f"bf16x2 with bf16 hidden weights vs exact {e:.2e}", flush=True)
+    assert e <= 5e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x2"])
+def test_cnn_config3_shape_matches_exact_oracle(api, prec):
+    """The 6 x 48 network on its whole 16-field batch of 512^2, in the plan the
+    benchmark runs (untuned default: folded for split networks), checked on
+    two sampled fields against the exact FP64 network."""
+    print(f"case cnn config-3 shape 6x48 512^2 x 16 {prec}", flush=True)
+    n, B = 512, 16
+    spec = cnn.CnnSpec(n_layers=6, channels=48)
+    ws, bs = cnn.init_weights(spec, seed=0, scale=0.1)
+    p = api.Problem(n=n, length=1.0, eps=0.01, conservative=True, stab=2.0, dt=1e-5, steps=100)
+    u0 = synth.random_ic(n, range(B))
+    samples = [0, 15]
+    for weights, tol in ((ws, 1e-2 if prec == "bf16" else 5e-3),
+                         (bf16_hidden(ws), 1e-2 if prec == "bf16" else 5e-5)):
+        g = api.CnnCoarse(weights, bs, prec=prec)
+        if prec == "bf16x2":
+            assert api.pr_get_coarse_plan(g, n) == "folded"
+        out = api.pr_coarse_apply(p, g, dev(u0)).cpu().numpy()
+        ref = cnn.forward(u0[samples], weights, bs, spec)
+        for k, i in enumerate(samples):
+            e = net_rel(out[i], ref[k], u0[i])
+            print(f"field {i}: {prec} vs exact {e:.2e} (bound {tol:g})", flush=True)
+            assert e <= tol
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
@@ -172,8 +234,9 @@ def test_fused_plan_matches_layered_and_oracle(api, L, C, prec, n):
     finally:
         api.pr_set_coarse_plan("auto")
     assert net_rel(fused, layered, u0) <= 1e-6
-    emu = cnn.forward(u0, ws, bs, spec, emulate_bf16=True if prec == "bf16" else "weights")
+    emu = cnn.forward(u0, ws, bs, spec, prec=prec)
     assert net_rel(fused, emu, u0) <= (2e-3 if prec == "bf16" else 2e-4)
+    assert net_rel(fused, cnn.forward(u0, ws, bs, spec), u0) <= (1e-2 if prec == "bf16" else 5e-3)
 
 
 @pytest.mark.parametrize("L,C,prec,n,nf,act,mass", [(4, 32, "bf16x2", 256, 3, "gelu", False),
@@ -207,8 +270,10 @@ def test_folded_plan_is_bitwise_layered(api, L, C, prec, n, nf, act, mass):
     if mass:
         f = folded.cpu().numpy()
         assert np.abs(f.mean(axis=(1, 2)) - u0.mean(axis=(1, 2))).max() <= 1e-14
-    emu = cnn.forward(u0, ws, bs, spec, emulate_bf16=True if prec == "bf16" else "weights")
+    emu = cnn.forward(u0, ws, bs, spec, prec=prec)
     assert net_rel(folded.cpu().numpy(), emu, u0) <= (2e-3 if prec == "bf16" else 2e-4)
+    assert net_rel(folded.cpu().numpy(), cnn.forward(u0, ws, bs, spec), u0) <= \
+        (1e-2 if prec == "bf16" else 5e-3)
 
 
 @pytest.mark.parametrize("conservative,f32_iters,mass_fix", [(False, 0, False), (True, 1, False),

@@ -73,11 +73,12 @@ def test_network_full_batch_sampled(api, prec):
     u0 = synth.random_ic(n, range(B))
     out = api.pr_coarse_apply(p, g, torch.from_numpy(u0).cuda()).cpu().numpy()
     samples = [0, 7]
-    ref = cnn.forward(u0[samples], ws, bs, spec,
-                      emulate_bf16=False if prec == "f32" else "weights")
+    ref = cnn.forward(u0[samples], ws, bs, spec, prec="exact" if prec == "f32" else prec)
     tol = 1e-5 if prec == "f32" else 2e-4
+    exact = cnn.forward(u0[samples], ws, bs, spec) if prec != "f32" else ref
     for k, i in enumerate(samples):
         assert rel(out[i] - u0[i], ref[k] - u0[i]) <= tol
+        assert rel(out[i] - u0[i], exact[k] - u0[i]) <= (1e-5 if prec == "f32" else 5e-3)
 
 
 def test_parareal_prefix_at_config2_size(api):

@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def api():
     from paper_2510_07672_amd import api as A
-    assert A.pr_abi_version() == 9
+    assert A.pr_abi_version() == 10
     return A
 
 
@@ -369,6 +369,35 @@ def test_graph_replays_match_eager(graphs, prec):
         _ = (x * x).sum().item()
         torch.cuda.synchronize()
         assert torch.equal(out, ref), f"replay {rep}"
+
+
+def test_graph_cache_eviction(graphs):
+    """More distinct launch sequences than the graph cache holds (32): each
+    new one evicts the least recently used graph after that graph's last
+    launch has finished (an event per entry, no device-wide wait); every
+    result equals the eager launch bit for bit, also for sequences whose
+    graphs were evicted and are captured again."""
+    print("case graph cache eviction: 40 step counts at 64^2", flush=True)
+    api = graphs
+    u0 = dev(synth.random_ic(64, range(3)))
+    api.pr_set_fine_plan(64, "f64", "stream")
+    try:
+        refs = {}
+        api.pr_set_graphs(False)
+        for c in range(1, 41):
+            p = api.Problem(n=64, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4,
+                            steps=c)
+            refs[c] = api.pr_fine_propagate(p, u0)
+        api.pr_set_graphs(True)
+        ws = api.workspace(1 << 24, "cuda")
+        for c in list(range(1, 41)) + [1, 2, 3]:
+            p = api.Problem(n=64, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4,
+                            steps=c)
+            out = api.pr_fine_propagate(p, u0, ws=ws)
+            assert torch.equal(out, refs[c]), f"steps {c}"
+    finally:
+        api.pr_set_fine_plan(64, "f64", "auto")
+        api.pr_set_graphs(True)
 
 
 def test_graph_solve_matches_eager_solve(graphs):

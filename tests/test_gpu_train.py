@@ -176,10 +176,55 @@ def test_scheme_loss_training_lowers_the_residual(mods):
     def resid():
         with torch.no_grad():
             out = api.pr_coarse_apply(p, net, u_test)
-            return float((train.scheme_residual(u_test, out, p, dt) ** 2).mean())
+            return float(api.pr_scheme_loss(p, dt, u_test, out, grad=False)[0])
     before = resid()
     u0 = torch.from_numpy(synth.random_ic(n, range(200, 232))).cuda()
     log = train.train_scheme(net, p, u0, dt, n_steps=6, inner=4, subset=16, lr=2e-3)
     after = resid()
     assert np.isfinite(log.loss).all() and len(log.loss) == 2 * 6 * 4
     assert after < 0.3 * before
+
+
+@pytest.mark.parametrize("cons,n,nf", [(False, 32, 2), (True, 32, 3), (True, 256, 2),
+                                       (False, 64, 1)])
+def test_scheme_loss_matches_oracle(mods, cons, n, nf):
+    """pr_scheme_loss (eq. loss_ACN): the residual, the loss and its gradient in
+    U_{n+1} against the oracle's, FP64 (rel. 1e-12); the loss vanishes on the
+    oracle's converged Crank-Nicolson step."""
+    print(f"case scheme loss cons={cons} n={n} fields={nf}", flush=True)
+    from oracle import allen_cahn as ac
+    api, _ = mods
+    dt = 4e-3
+    p = api.Problem(n=n, length=1.0, eps=0.03, conservative=cons, stab=2.0, dt=1e-4, steps=1)
+    po = ac.Problem(n=n, length=1.0, eps=0.03, conservative=cons, stab=2.0, dt=dt, steps=1,
+                    scheme="cn")
+    u = synth.random_ic(n, range(60, 60 + nf))
+    w = synth.random_ic(n, range(80, 80 + nf))
+    loss, grad, r = api.pr_scheme_loss(p, dt, torch.from_numpy(u).cuda(), torch.from_numpy(w).cuda(),
+                                       grad=True, resid=True)
+    l_ref, g_ref = ac.cn_residual_loss(u, w, po, dt)
+    r_ref = ac.cn_residual(u, w, po, dt)
+    assert np.linalg.norm(r.cpu().numpy() - r_ref) <= 1e-12 * np.linalg.norm(r_ref)
+    assert abs(float(loss) - l_ref) <= 1e-12 * l_ref
+    assert np.linalg.norm(grad.cpu().numpy() - g_ref) <= 1e-12 * np.linalg.norm(g_ref)
+    # without the residual output (kept in the workspace): the same bits
+    loss2, grad2, _ = api.pr_scheme_loss(p, dt, torch.from_numpy(u).cuda(),
+                                         torch.from_numpy(w).cuda())
+    assert float(loss2) == float(loss) and torch.equal(grad2, grad)
+    v = ac.cn_picard_step(u, po, dt, iters=30)
+    l0, _, _ = api.pr_scheme_loss(p, dt, torch.from_numpy(u).cuda(), torch.from_numpy(v).cuda(),
+                                  grad=False)
+    assert float(l0) <= 1e-26
+
+
+def test_scheme_loss_autograd(mods):
+    """autograd.scheme_loss backpropagates the library's gradient into U_{n+1}."""
+    from paper_2510_07672_amd import autograd
+    api, _ = mods
+    n, dt = 32, 2e-3
+    p = api.Problem(n=n, length=1.0, eps=0.02, conservative=True, stab=2.0, dt=1e-4, steps=1)
+    u = torch.from_numpy(synth.random_ic(n, [3, 4])).cuda()
+    w = torch.from_numpy(synth.random_ic(n, [5, 6])).cuda().requires_grad_(True)
+    (3.0 * autograd.scheme_loss(p, u, w, dt)).backward()
+    _, g, _ = api.pr_scheme_loss(p, dt, u, w.detach())
+    assert torch.equal(w.grad, 3.0 * g)

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 9
+    assert lib.pr_abi_version() == 10
 
 
 def test_library_exports_match_nm(L):
@@ -213,3 +213,30 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_scheme_loss_validation(L):
+    """pr_scheme_loss checks its arguments before any launch."""
+    lib = L.lib()
+    p = _prob(L)
+    big = 1 << 30
+    n2b = 16 * 16 * 8
+    u0, u1, loss, grad = (C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20),
+                          C.c_void_p(4 << 20))
+    ws = C.c_void_p(8 << 20)
+    need = lib.pr_scheme_loss_workspace_bytes(C.byref(p), 2)
+    assert need > 2 * n2b
+    f = lib.pr_scheme_loss
+    assert f(C.byref(_prob(L, laplacian=1)), 1e-3, 2, u0, u1, loss, grad, None, ws, big,
+             None) == L.PR_ERR_UNSUPPORTED
+    assert f(C.byref(p), 0.0, 2, u0, u1, loss, grad, None, ws, big, None) == L.PR_ERR_INVALID_ARG
+    assert f(C.byref(p), 1e-3, 0, u0, u1, loss, grad, None, ws, big, None) == L.PR_ERR_INVALID_ARG
+    assert f(C.byref(p), 1e-3, 2, None, u1, loss, grad, None, ws, big, None) == L.PR_ERR_INVALID_ARG
+    assert f(C.byref(p), 1e-3, 2, u0, u1, None, grad, None, ws, big, None) == L.PR_ERR_INVALID_ARG
+    # an output inside an input, or two outputs on one another
+    assert f(C.byref(p), 1e-3, 2, u0, u1, C.c_void_p((1 << 20) + 8), grad, None, ws, big,
+             None) == L.PR_ERR_INVALID_ARG
+    assert f(C.byref(p), 1e-3, 2, u0, u1, loss, grad, grad, ws, big, None) == L.PR_ERR_INVALID_ARG
+    assert f(C.byref(p), 1e-3, 2, u0, u1, loss, grad, None, ws, need - 1,
+             None) == L.PR_ERR_WORKSPACE
+    assert lib.pr_last_error()

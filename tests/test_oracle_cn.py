@@ -153,18 +153,48 @@ def test_pins_catch_sign_of_f(monkeypatch):
 
 
 @pytest.mark.parametrize("cons", [False, True])
-def test_training_scheme_residual_matches_the_cn_scheme(cons):
-    """The training loss of eq. loss_ACN vanishes on the oracle's converged
-    Crank-Nicolson step and equals the oracle's residual on any pair."""
-    import torch
-    from paper_2510_07672_amd import api, train
-    n, dt = 32, 4e-3
-    po = prob(n=n, cons=cons, dt=dt, eps=0.03)
-    pa = api.Problem(n=n, length=1.0, eps=0.03, conservative=cons, stab=0.0, dt=dt, steps=1)
-    u = synth.random_ic(n, [11, 12])
+def test_scheme_loss_gradient_by_finite_differences(cons):
+    """The scheme-residual loss of eq. loss_ACN and its gradient in U_{n+1}:
+    central differences of the loss in every point of a tiny pair, and the
+    loss vanishing on a converged Crank-Nicolson step."""
+    n, dt = 8, 4e-3
+    po = prob(n=n, cons=cons, dt=dt, eps=0.05)
+    u = synth.random_ic(n, [21, 22])
+    w = synth.random_ic(n, [23, 24])
+    loss, grad = ac.cn_residual_loss(u, w, po, dt)
+    assert abs(loss - float((ac.cn_residual(u, w, po, dt) ** 2).mean())) <= 1e-15 * loss
+    h = 1e-6
+    fd = np.zeros_like(w)
+    for idx in np.ndindex(*w.shape):
+        wp, wm = w.copy(), w.copy()
+        wp[idx] += h
+        wm[idx] -= h
+        fd[idx] = (ac.cn_residual_loss(u, wp, po, dt)[0] - ac.cn_residual_loss(u, wm, po, dt)[0]) / (2 * h)
+    assert np.abs(fd - grad).max() <= 1e-7 * np.abs(grad).max()
     v = ac.cn_picard_step(u, po, dt, iters=30)
-    r = train.scheme_residual(torch.from_numpy(u), torch.from_numpy(v), pa, dt).numpy()
-    assert np.abs(r).max() <= 2e-13
-    w = synth.random_ic(n, [13, 14])
-    r2 = train.scheme_residual(torch.from_numpy(u), torch.from_numpy(w), pa, dt).numpy()
-    assert np.abs(r2 - ac.cn_residual(u, w, po, dt)).max() <= 1e-12
+    l0, g0 = ac.cn_residual_loss(u, v, po, dt)
+    assert l0 <= 1e-26 and np.abs(g0).max() <= 1e-13
+
+
+def test_scheme_loss_pins_catch_a_dropped_mean_term(monkeypatch):
+    orig = ac.cn_residual_loss
+
+    def no_mean(u, v, p, dt):
+        import dataclasses
+        return orig(u, v, dataclasses.replace(p, conservative=False), dt)
+    monkeypatch.setattr(ac, "cn_residual_loss", no_mean)
+    with pytest.raises(AssertionError):
+        test_scheme_loss_gradient_by_finite_differences(True)
+
+
+def test_scheme_loss_pins_catch_a_gradient_without_its_mean_term(monkeypatch):
+    orig = ac.cn_residual_loss
+
+    def grad_without_mean(u, v, p, dt):
+        loss, g = orig(u, v, p, dt)
+        r = ac.cn_residual(u, v, p, dt)
+        fp = 1.0 - 3.0 * v * v
+        return loss, g - (2.0 / r.size) * 0.5 * dt * fp * r.mean(axis=(-2, -1), keepdims=True)
+    monkeypatch.setattr(ac, "cn_residual_loss", grad_without_mean)
+    with pytest.raises(AssertionError):
+        test_scheme_loss_gradient_by_finite_differences(True)

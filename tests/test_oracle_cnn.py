@@ -91,14 +91,112 @@ def test_zero_output_layer_gives_identity():
     assert np.array_equal(cnn.forward(u, ws, bs, spec), u)
 
 
-def test_bf16_emulation_is_close_and_not_equal():
-    spec = _spec(channels=16)
-    ws, bs = cnn.init_weights(spec, seed=9)
-    u = synth.random_ic(32, [1])
-    a = cnn.forward(u, ws, bs, spec)
-    b = cnn.forward(u, ws, bs, spec, emulate_bf16=True)
-    rel = np.linalg.norm(a - b) / np.linalg.norm(a)
-    assert 1e-6 < rel < 1e-2
+# ---------------------------------------------------------------- bfloat16
+# The network in bfloat16 (oracle.cnn.rounding_plan): hidden-layer weights
+# and every activation rounded ("bf16"), or the hidden-layer weights only,
+# activations carried as hi + lo pairs ("bf16x2").  Pinned against the
+# same network written out with the shift-definition convolution and an
+# integer-bit rounding, so that moving any one rounding fails.
+
+def _rne_bf16_bits(x):
+    """Round-to-nearest-even to 8 significant bits on the float64 bit
+    pattern: add half an ulp of the kept part (minus one, plus the kept
+    part's last bit) and clear the 45 dropped bits."""
+    b = np.ascontiguousarray(x, dtype=np.float64).view(np.uint64)
+    keep_lsb = (b >> np.uint64(45)) & np.uint64(1)
+    b = (b + np.uint64((1 << 44) - 1) + keep_lsb) & ~np.uint64((1 << 45) - 1)
+    return b.view(np.float64)
+
+
+def test_bf16_rounding_literals():
+    one = 1.0
+    cases = [
+        (one + 2.0 ** -8, 1.0),                       # tie -> even (1.0000000)
+        (one + 3 * 2.0 ** -8, one + 2.0 ** -6),       # tie -> even (1.0000010)
+        (one + 2.0 ** -8 + 2.0 ** -40, one + 2.0 ** -7),  # above the tie
+        (255.5, 256.0), (254.5, 254.0),               # ties at exponent 7
+        (-(one + 2.0 ** -8), -1.0),
+        (0.1, 0.10009765625),                         # 0x3DCD
+        (1.0 / 3.0, 0.333984375),                     # 0x3EAB
+        (0.0, 0.0),
+    ]
+    x = torch.tensor([c[0] for c in cases], dtype=torch.float64)
+    want = [c[1] for c in cases]
+    assert cnn.bf16(x).tolist() == want
+
+
+def test_bf16_rounding_matches_bits_and_library():
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(200000) * np.exp(rng.uniform(-20, 20, 200000))
+    got = cnn.bf16(torch.from_numpy(x)).numpy()
+    assert np.array_equal(got, _rne_bf16_bits(x))
+    # float32 inputs: torch's own float -> bfloat16 conversion rounds once
+    x32 = x.astype(np.float32)
+    lib = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(cnn.bf16(torch.from_numpy(x32.astype(np.float64))).numpy(), lib)
+
+
+def _gelu_np(x):
+    return 0.5 * x * (1.0 + np.vectorize(math.erf)(x / math.sqrt(2.0)))
+
+
+def _written_out(u, ws, bs, L, prec):
+    """The bfloat16 network by hand: shift-definition convolutions, GELU
+    from math.erf, integer-bit rounding of the hidden weights and (bf16)
+    of each activation a layer hands on."""
+    x = u[:, None]
+    for l in range(L):
+        W, b = ws[l].numpy(), bs[l].numpy()
+        if prec in ("bf16", "bf16x2") and 0 < l < L - 1:
+            W = _rne_bf16_bits(W)
+        x = cnn.conv3x3_periodic_loops(x, W, b)
+        if l < L - 1:
+            x = _gelu_np(x)
+            if prec == "bf16":
+                x = _rne_bf16_bits(x)
+    return u + x[:, 0]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x2", "exact"])
+@pytest.mark.parametrize("L", [3, 4])
+def test_bf16_network_is_the_written_out_chain(prec, L):
+    spec = _spec(n_layers=L, channels=8)
+    ws, bs = cnn.init_weights(spec, seed=13 + L)
+    u = synth.random_ic(12, [2, 3])
+    got = cnn.forward(u, ws, bs, spec, prec=prec)
+    ref = _written_out(u, ws, bs, L, prec)
+    assert np.linalg.norm((got - u) - (ref - u)) <= 1e-13 * np.linalg.norm(ref - u)
+    if prec != "exact":
+        ex = cnn.forward(u, ws, bs, spec)
+        d = np.linalg.norm((got - u) - (ex - u)) / np.linalg.norm(ex - u)
+        assert 1e-5 < d < 1e-2      # the roundings are there, and small
+
+
+@pytest.mark.parametrize("move", ["first_weights", "last_weights", "no_act_round_l0",
+                                  "round_last_output", "split_rounds_acts", "no_hidden_weights"])
+def test_pins_catch_a_moved_rounding(monkeypatch, move):
+    orig = cnn.rounding_plan
+
+    def moved(prec, L):
+        rw, ra = orig(prec, L)
+        rw, ra = list(rw), list(ra)
+        if move == "first_weights":
+            rw[0] = prec != "exact"
+        elif move == "last_weights":
+            rw[L - 1] = prec != "exact"
+        elif move == "no_act_round_l0":
+            ra[0] = False
+        elif move == "round_last_output":
+            ra[L - 1] = prec == "bf16"
+        elif move == "split_rounds_acts":
+            ra = [prec == "bf16x2" and l < L - 1 for l in range(L)] if prec == "bf16x2" else ra
+        elif move == "no_hidden_weights":
+            rw = [False] * L
+        return rw, ra
+    monkeypatch.setattr(cnn, "rounding_plan", moved)
+    prec = "bf16x2" if move == "split_rounds_acts" else "bf16"
+    with pytest.raises(AssertionError):
+        test_bf16_network_is_the_written_out_chain(prec, 4)
 
 
 def test_pins_catch_zero_padding(monkeypatch):
