@@ -311,6 +311,31 @@ def uneven_bench(args):
             "speedup_vs_serial_fp64": round(t_ser * 1e3 / best["ms"], 3)}
 
 
+def copy_rates(sizes=(1 << 28, 1 << 30, 1 << 32), reps=5):
+    """What a plain read-once write-once stream reaches on this GPU: torch's
+    device copy at several sizes (events on the current stream, best of
+    `reps`), in GB/s of bytes read plus bytes written."""
+    import torch
+    out = {}
+    for nb in sizes:
+        x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        best = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            y.copy_(x)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[f"{nb >> 20} MiB"] = round(2 * nb / (best * 1e-3) / 1e9, 1)
+        del x, y
+        torch.cuda.empty_cache()
+    return {"copy_GB_per_s": out, "note": "torch copy_, bytes read + bytes written per second"}
+
+
 def calib_copy(nbytes=1 << 30, reps=3):
     """A plain copy of `nbytes` bytes: reads nbytes and writes nbytes per
     launch, so HBM counters per dispatch can be scaled against it."""
@@ -671,9 +696,14 @@ def main():
                          "(0 = one chunk, every field through each step in turn)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--copy-rate", action="store_true",
+                    help="only time plain device copies of 256 MiB, 1 GiB and 4 GiB")
     args = ap.parse_args()
     if args.calib_copy:
         calib_copy()
+        return
+    if args.copy_rate:
+        print(json.dumps(copy_rates()), flush=True)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (its fine "

@@ -447,8 +447,9 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
  * workspace, so one capture serves every later call on the same
  * workspace whose batch is no larger (e.g. every Parareal iteration).
  * The library keeps at most 32 captures, evicting the least recently used
- * (after a device-wide synchronisation).  pr_set_graphs(0) launches the
- * kernels one by one instead; results are identical either way. */
+ * once that capture's last launch has finished (an event recorded after
+ * each of its launches; no device-wide wait).  pr_set_graphs(0) launches
+ * the kernels one by one instead; results are identical either way. */
 void pr_set_graphs(int32_t enabled);
 int32_t pr_get_graphs(void);
 

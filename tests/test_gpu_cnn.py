@@ -138,7 +138,22 @@ def test_cnn_bf16x2_with_bf16_weights_matches_exact_oracle(api, L, C, n):
 def test_cnn_config3_shape_matches_exact_oracle(api, prec):
     """The 6 x 48 network on its whole 16-field batch of 512^2, in the plan the
     benchmark runs (untuned default: folded for split networks), checked on
-    two sampled fields against the exact FP64 network."""
+    two sampled fields.
+
+    Split form against the exact FP64 network: net-relative <= 5e-3 (the
+    rounding of the hidden weights; 2.2e-3 on the oracle's split network)
+    and, with bfloat16 hidden weights, <= 5e-5.  Plain bf16: against the
+    oracle's bf16 network net-relative <= 5e-3, and against the exact
+    network G-relative (|G_bf16(u) - G(u)| / |G(u)|) <= 1e-2.  The
+    net-relative distance of the bf16 format itself from the exact network
+    is 1.3e-2 for these weights (the oracle's bf16 network measures it):
+    the seed-0 network's output is a small difference of O(1) activations
+    (RMS 1.2e-4 per point), which 8-bit activations resolve only to ~1%.
+    The same cancellation amplifies the bfloat16 rounding decisions that
+    FP32 and FP64 sums take differently: the same bf16 network evaluated
+    on the CPU with FP32 sums differs from the oracle's by 2.2e-3 on
+    field 0, as the GPU does (2.3e-3); hence 5e-3 here, where the 4-layer
+    networks above stay under 2e-3."""
     print(f"case cnn config-3 shape 6x48 512^2 x 16 {prec}", flush=True)
     n, B = 512, 16
     spec = cnn.CnnSpec(n_layers=6, channels=48)
@@ -146,17 +161,26 @@ def test_cnn_config3_shape_matches_exact_oracle(api, prec):
     p = api.Problem(n=n, length=1.0, eps=0.01, conservative=True, stab=2.0, dt=1e-5, steps=100)
     u0 = synth.random_ic(n, range(B))
     samples = [0, 15]
-    for weights, tol in ((ws, 1e-2 if prec == "bf16" else 5e-3),
-                         (bf16_hidden(ws), 1e-2 if prec == "bf16" else 5e-5)):
+    cases = ((ws, 5e-3), (bf16_hidden(ws), 5e-5)) if prec == "bf16x2" else ((ws, None),)
+    for weights, tol in cases:
         g = api.CnnCoarse(weights, bs, prec=prec)
         if prec == "bf16x2":
             assert api.pr_get_coarse_plan(g, n) == "folded"
         out = api.pr_coarse_apply(p, g, dev(u0)).cpu().numpy()
         ref = cnn.forward(u0[samples], weights, bs, spec)
+        emu = cnn.forward(u0[samples], weights, bs, spec, prec=prec) if prec == "bf16" else None
         for k, i in enumerate(samples):
             e = net_rel(out[i], ref[k], u0[i])
-            print(f"field {i}: {prec} vs exact {e:.2e} (bound {tol:g})", flush=True)
-            assert e <= tol
+            if prec == "bf16x2":
+                print(f"field {i}: bf16x2 vs exact {e:.2e} (bound {tol:g})", flush=True)
+                assert e <= tol
+            else:
+                e_emu = net_rel(out[i], emu[k], u0[i])
+                e_g = float(np.linalg.norm(out[i] - ref[k]) / np.linalg.norm(ref[k]))
+                print(f"field {i}: bf16 vs bf16 oracle {e_emu:.2e}, vs exact {e:.2e} net / "
+                      f"{e_g:.2e} G", flush=True)
+                assert e_emu <= 5e-3
+                assert e_g <= 1e-2
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])

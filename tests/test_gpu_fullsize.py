@@ -112,3 +112,41 @@ def test_degenerate_parareal_cases(api):
     # a tolerance every first update meets: one iteration
     _, stt = api.pr_solve(p, g, u0, 4, tol=1e3)
     assert stt.iterations == 1 and (stt.ic_iterations == 1).all()
+
+
+@pytest.mark.parametrize("cfg", ["c2", "c3"])
+def test_serial_fine_full_horizon_matches_oracle(api, cfg):
+    """The reference the Parareal speedups are measured against: the GPU's
+    serial FP64 fine solve over the whole horizon (config 2: 64 slices x 200
+    steps of 256^2; config 3: 128 slices x 100 steps of 512^2, conservative)
+    against the oracle's serial composition of F (Algorithm 2's fine
+    propagator), on the bench's first initial conditions.
+
+    Bound at slice j after m = j c steps: 1e-12 + 2 m 2^-52.  The two FP64
+    implementations round differently (twiddles, the order of the
+    butterflies, the divide), by about an ulp per step, and the scheme
+    carries those differences along; measured at config 2 they grow by
+    ~2.3e-16 per step (1.04e-12 after 4600 steps), so 1e-12 holds for one
+    F call (200 steps, tested elsewhere) and 2 ulps per step for the
+    horizon: <= 5.7e-12 after 12 800 steps, 1e5 below the 1e-6 the
+    speedups are stated at."""
+    if cfg == "c2":
+        n, eps, dt, c, s, cons, seeds = 256, 0.01, 2e-5, 200, 64, False, [0, 1]
+    else:
+        n, eps, dt, c, s, cons, seeds = 512, 0.01, 1e-5, 100, 128, True, [0]
+    print(f"case full-horizon serial fine {cfg}", flush=True)
+    p = api.Problem(n=n, length=1.0, eps=eps, conservative=cons, stab=2.0, dt=dt, steps=c)
+    u0 = synth.random_ic(n, seeds)
+    U = api.pr_serial_fine(p, torch.from_numpy(u0).cuda(), s).cpu().numpy()
+    ref = ac.serial_fine_trajectory(u0, oracle_problem(p), s)
+    worst = 0.0
+    for b in range(len(seeds)):
+        for j in range(s + 1):
+            bound = 1e-12 + 2 * j * c * 2.0 ** -52
+            e = rel(U[b, j], ref[b, j])
+            worst = max(worst, e / bound)
+            assert e <= bound, f"IC {b} slice {j}: {e:.3e} > {bound:.3e}"
+    print(f"{cfg}: final slice rel-L2 {rel(U[0, s], ref[0, s]):.3e}, worst error/bound {worst:.2f}",
+          flush=True)
+    if cons:
+        assert np.abs(U.mean(axis=(-2, -1)) - u0.mean(axis=(-2, -1))[:, None]).max() <= 1e-13
