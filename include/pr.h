@@ -179,6 +179,25 @@ pr_status pr_fine_propagate(const pr_problem* p, int64_t nfields,
                             const double* u_in, void* u_out, pr_dtype out_dtype,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* F as pr_fine_propagate, for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument and no allocation of any kind.  The
+ * workspace is a static device array of PR_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends; its address
+ * on the current device is looked up on the first call there.  A call
+ * whose pr_fine_workspace_bytes(p, nfields) exceeds that size is rejected
+ * with PR_ERR_WORKSPACE (64 MiB: e.g. 120 FP64 fields of 256^2, 30 of
+ * 512^2).  Every call on one GPU uses the same array, so calls that
+ * overlap in time on one GPU (other streams, other threads) race: order
+ * them on one stream.  Nothing in the array needs clearing between calls.
+ * The kernels are launched one by one on `stream` (no graph of the
+ * library's own), so a caller may capture the call into its own graph.
+ * Results are bit for bit those of pr_fine_propagate. */
+#define PR_NOALLOC_SCRATCH_BYTES (64u << 20)
+pr_status pr_fine_propagate_noalloc(const pr_problem* p, int64_t nfields,
+                                    const double* u_in, void* u_out,
+                                    pr_dtype out_dtype, void* stream);
+
 /* ---------------------------------------------------------------- G --- */
 
 size_t pr_coarse_workspace_bytes(const pr_problem* p, const pr_coarse* g,

@@ -20,7 +20,7 @@ PR_SCHEME_SSI, PR_SCHEME_CN = 0, 1
 PR_LAP_FD5, PR_LAP_SPECTRAL = 0, 1
 
 EXPORTED = [
-    "pr_fine_workspace_bytes", "pr_fine_propagate",
+    "pr_fine_workspace_bytes", "pr_fine_propagate", "pr_fine_propagate_noalloc",
     "pr_coarse_workspace_bytes", "pr_coarse_apply",
     "pr_cnn_backward_workspace_bytes", "pr_cnn_backward",
     "pr_scheme_loss_workspace_bytes", "pr_scheme_loss",
@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
         sig = {
             "pr_fine_workspace_bytes": (sz, [P, i64]),
             "pr_fine_propagate": (C.c_int, [P, i64, vp, vp, C.c_int, vp, sz, vp]),
+            "pr_fine_propagate_noalloc": (C.c_int, [P, i64, vp, vp, C.c_int, vp]),
             "pr_coarse_workspace_bytes": (sz, [P, G, i64]),
             "pr_coarse_apply": (C.c_int, [P, G, i64, vp, vp, vp, sz, vp]),
             "pr_cnn_backward_workspace_bytes": (sz, [P, G, i64]),

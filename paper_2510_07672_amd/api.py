@@ -151,6 +151,19 @@ def pr_fine_propagate(p: Problem, u_in: torch.Tensor, out_dtype=torch.float64,
     return out
 
 
+def pr_fine_propagate_noalloc(p: Problem, u_in: torch.Tensor, out: torch.Tensor):
+    """F(U) into the caller's `out` [B, N, N] (float64 or float32) with the
+    library's static scratch: no workspace, no allocation."""
+    B = _fields(u_in, p.n, "u_in")
+    if out.shape != u_in.shape or out.dtype not in _DT or not out.is_contiguous():
+        raise TypeError("out must be a contiguous float64/float32 tensor shaped like u_in")
+    pc = p.c()
+    L.check(L.lib().pr_fine_propagate_noalloc(C.byref(pc), B, _ptr(u_in), _ptr(out), _DT[out.dtype],
+                                              _stream(u_in.device)),
+            "pr_fine_propagate_noalloc")
+    return out
+
+
 def pr_coarse_apply(p: Problem, g: Coarse, u_in: torch.Tensor,
                     out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
     """G(U) with the numerical coarse step."""

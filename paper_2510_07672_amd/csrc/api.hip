@@ -1057,8 +1057,9 @@ size_t pr_fine_workspace_bytes(const pr_problem* p, int64_t nfields) {
   return c.used;
 }
 
-pr_status pr_fine_propagate(const pr_problem* p, int64_t nfields, const double* u_in, void* u_out,
-                            pr_dtype out_dtype, void* ws, size_t ws_bytes, void* stream) {
+static pr_status fine_propagate(const pr_problem* p, int64_t nfields, const double* u_in,
+                                void* u_out, pr_dtype out_dtype, void* ws, size_t ws_bytes,
+                                void* stream, bool eager) {
   pr_status st = check_problem(p);
   if (st != PR_OK) return st;
   if (nfields < 0) return fail(PR_ERR_INVALID_ARG, "nfields < 0");
@@ -1076,9 +1077,68 @@ pr_status pr_fine_propagate(const pr_problem* p, int64_t nfields, const double* 
   j.in_base = u_in;
   j.out_base = u_out;
   j.out_f32 = out_dtype == PR_F32;
+  j.eager = eager;
   PR_HIP(launch_tables(p->n, p->laplacian, w, s));
   PR_HIP(launch_steps(j, s));
   return PR_OK;
+}
+
+pr_status pr_fine_propagate(const pr_problem* p, int64_t nfields, const double* u_in, void* u_out,
+                            pr_dtype out_dtype, void* ws, size_t ws_bytes, void* stream) {
+  return fine_propagate(p, nfields, u_in, u_out, out_dtype, ws, ws_bytes, stream, false);
+}
+
+// ------------------------------------------------ F without allocation
+//
+// pr_fine_propagate_noalloc: the same launches as pr_fine_propagate, with
+// the workspace in a file-scope device array instead of a caller buffer.
+// Host code never passes the array's name to a kernel: each device's
+// address is looked up once (hipGetSymbolAddress, with that device
+// current) and kept.
+
+static __device__ __align__(256) unsigned char scratch[PR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device ordinal; null until looked up
+}  // namespace
+
+static pr_status scratch_address(void** out) {
+  int dev = 0;
+  PR_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(PR_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PR_OK;
+}
+
+pr_status pr_fine_propagate_noalloc(const pr_problem* p, int64_t nfields, const double* u_in,
+                                    void* u_out, pr_dtype out_dtype, void* stream) {
+  pr_status st = check_problem(p);
+  if (st != PR_OK) return st;
+  if (nfields < 0) return fail(PR_ERR_INVALID_ARG, "nfields < 0");
+  if (nfields == 0) return PR_OK;
+  const size_t need = pr_fine_workspace_bytes(p, nfields);
+  if (need > (size_t)PR_NOALLOC_SCRATCH_BYTES)
+    return fail(PR_ERR_WORKSPACE,
+                "pr_fine_propagate_noalloc: %lld fields of %d^2 need %zu bytes of scratch, more "
+                "than its %zu; call pr_fine_propagate with a workspace, or fewer fields",
+                (long long)nfields, p->n, need, (size_t)PR_NOALLOC_SCRATCH_BYTES);
+  if (!u_in || !u_out) return fail(PR_ERR_INVALID_ARG, "u_in / u_out is NULL");
+  void* ws = nullptr;
+  if ((st = scratch_address(&ws)) != PR_OK) return st;
+  // launched kernel by kernel: no graph of the library's own is captured or
+  // instantiated (a caller may be capturing this stream)
+  return fine_propagate(p, nfields, u_in, u_out, out_dtype, ws, PR_NOALLOC_SCRATCH_BYTES, stream,
+                        true);
 }
 
 size_t pr_coarse_workspace_bytes(const pr_problem* p, const pr_coarse* g, int64_t nfields) {

@@ -994,7 +994,7 @@ static hipError_t launch_stream_graph(const StepJob& job, hipStream_t st) {
 
 template <int N, typename T>
 static hipError_t launch_steps_n(const StepJob& job, hipStream_t st) {
-  if (graphs_enabled()) return launch_stream_graph<N, T>(job, st);
+  if (graphs_enabled() && !job.eager) return launch_stream_graph<N, T>(job, st);
   enqueue_steps<N, T>(job, job.nfields, st);
   return hipGetLastError();
 }

@@ -114,6 +114,7 @@ struct StepJob {
   const int32_t* pidx;       // device or null
   bool resident;             // one block per field, all steps in LDS (N <= 128)
   int64_t ws_override = -1;  // working-set budget in bytes for this call (-1: the setting)
+  bool eager = false;        // launch kernel by kernel even with graphs on
   FineWs ws;
 };
 
