@@ -349,13 +349,13 @@ def calib_copy(nbytes=1 << 30, reps=3):
 
 
 def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32, loss="mse",
-                lr_final=None, lr_drop=None):
+                lr_final=None, lr_drop=None, train_prec="bf16"):
     """The workload's network, trained with Adam on fine-solver trajectories
     from seeds 1000.. (bf16 forward, FP32 gradients, 8-step rollouts
     checkpointed every 2), then evaluated in `prec`."""
     from paper_2510_07672_amd import train
     L, C = cfg["cnn"]
-    net = train.init_network(L, C, seed=0, prec="bf16")
+    net = train.init_network(L, C, seed=0, prec=train_prec)
     info = None
     if steps > 0 and loss == "scheme":
         # Algorithm 1: subsets of `batch` random ICs evolved by G itself, 4
@@ -391,7 +391,7 @@ def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32, los
             lr_txt = f"cosine 1e-3 -> {lr_final:g}"
         elif lr_drop:
             lr_txt = f"1e-3, then 1e-4 for the last {lr_drop:g} of the steps"
-        info = {"steps": steps, "lr": lr_txt,
+        info = {"steps": steps, "lr": lr_txt, "forward_prec": train_prec,
                 "trajectories": n_traj, "slices_per_trajectory": n_slices,
                 "batch": batch,
                 "data_s": round(t_data, 2), "loss_first": log.loss[0], "loss_last": log.loss[-1],
@@ -531,7 +531,7 @@ def run_config(args, cname, api, torch, synth, full=True):
                                     n_traj=n_traj, batch=args.train_batch,
                                     loss=args.train_loss, lr_final=args.train_lr_final,
                                     lr_drop=cfg.get("train_lr_drop") if args.train_lr_drop is None
-                                    else args.train_lr_drop)
+                                    else args.train_lr_drop, train_prec=args.train_prec)
     else:
         g = g_num
     u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
@@ -688,6 +688,8 @@ def main():
     ap.add_argument("--train-lr-drop", type=float, default=None,
                     help="fraction of the training steps, at the end, run at a tenth of the "
                          "learning rate")
+    ap.add_argument("--train-prec", default="bf16", choices=["bf16", "bf16x2"],
+                    help="network precision of the training forward passes")
     ap.add_argument("--train-loss", default="mse", choices=["mse", "scheme"],
                     help="mse against fine trajectories, or the scheme-residual loss of "
                          "Algorithm 1 over one coarse step")

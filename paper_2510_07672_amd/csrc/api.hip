@@ -182,7 +182,9 @@ CnnWs carve_cnn(Carver& c, int n, const pr_coarse* g, int64_t nfields, bool trai
   const int C = g->channels, L = g->n_layers;
   const int kp = (9 * C + 31) / 32 * 32;
   const bool mfma = g->prec == PR_BF16 || g->prec == PR_BF16X2;
-  w.wpack = c.take(!mfma || L < 3 ? 16 : (size_t)(L - 2) * C * kp * 2);
+  // hidden layers, then the last layer's hi / lo A-fragments per lane
+  // (2 KB per 32-deep step)
+  w.wpack = c.take(!mfma || L < 3 ? 16 : (size_t)(L - 2) * C * kp * 2 + (size_t)((C + 31) / 32) * 2048);
   const size_t act = (size_t)nfields * n * n * C * cnn_act_bytes(g->prec);
   const size_t tiles = (size_t)nfields * (n / 16) * (n / 16);
   w.partials = (double*)c.take(tiles * 8);

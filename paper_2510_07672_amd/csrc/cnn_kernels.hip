@@ -22,7 +22,7 @@
 //                 plus the residual, written in FP64, with per-tile FP64
 //                 sums of (G(u) - u).
 //   Folded inference plan: k_cnn_hidden computes the first layer on its own
-//                 input tile (FIRST) and, at C = 32, the last layer's
+//                 input tile (FIRST) and, at C = 32 or 48, the last layer's
 //                 per-tap products in its epilogue (TAIL);
 //                 k_cnn_last_gather then sums the products over the taps.
 //   k_cnn_fix     the uniform mass fix and the limiter.
@@ -190,13 +190,51 @@ template <int C, bool SPLIT> struct HidTile {
   static constexpr size_t FIRST_BYTES = BYTES + (size_t)(UH * UW + 10 * C) * 4;
 };
 
+// Tuning knobs (compile time): whether the last layer folds into the last
+// hidden layer at 48 channels, and the waves per SIMD the 48-channel hidden
+// layer's registers are bounded to.
+#ifndef PR_TAIL48
+#define PR_TAIL48 1
+#endif
+#ifndef PR_HID48_WAVES
+#define PR_HID48_WAVES 2
+#endif
+
 template <int C> struct LastCfg {
   static constexpr int T = 16, WI = T + 2, PX = WI * WI;
   static constexpr int KB = (C + 31) / 32;   // 32-channel steps
 };
 
-// Lane (g, r) holds W[c = 32 kb + 8 g + j][tap r], j < 8, as hi and lo
-// (zero beyond C channels or nine taps).
+// The last layer's K order.  In each 32-deep step kb of the C -> 1
+// product, lane group g (lanes 16 g .. 16 g + 15) supplies K slots
+// 8 g .. 8 g + 7; last_chan gives the channel in slot j of that group, or
+// -1 for a zero slot.  At C = 48 group g holds channels 12 g .. 12 g + 11,
+// the first eight in step 0 and the last four in step 1 (its slots 4..7
+// zero): exactly the channels a TAIL hidden layer leaves in the lanes of
+// group g.  Other widths take channels 32 kb + 8 g + j in order.
+template <int C>
+__device__ __forceinline__ int last_chan(int kb, int g, int j) {
+  if constexpr (C == 48) return kb == 0 ? 12 * g + j : (j < 4 ? 12 * g + 8 + j : -1);
+  const int c = kb * 32 + 8 * g + j;
+  return c < C ? c : -1;
+}
+
+// The A fragment of step kb for lane group g: the channels last_chan
+// names, of the pixel whose channels start at a (8-byte aligned).
+template <int C>
+__device__ __forceinline__ bf16x8 last_frag(const __bf16* a, int kb, int g) {
+  if constexpr (C == 48) {
+    const bf16x4 x0 = *(const bf16x4*)&a[kb == 0 ? 12 * g : 12 * g + 8];
+    const bf16x4 x1 = kb == 0 ? *(const bf16x4*)&a[12 * g + 4] : bf16x4{};
+    return __builtin_shufflevector(x0, x1, 0, 1, 2, 3, 4, 5, 6, 7);
+  } else {
+    const int c0 = kb * 32 + 8 * g;
+    return c0 < C ? *(const bf16x8*)&a[c0] : bf16x8{};
+  }
+}
+
+// Lane (g, r) holds W[c = last_chan(kb, g, j)][tap r], j < 8, as hi and lo
+// (zero in zero slots or beyond nine taps).
 template <int C>
 __device__ __forceinline__ void last_weights(const float* __restrict__ W, int lane,
                                              bf16x8* hi, bf16x8* lo) {
@@ -205,12 +243,27 @@ __device__ __forceinline__ void last_weights(const float* __restrict__ W, int la
   for (int kb = 0; kb < LastCfg<C>::KB; ++kb) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int c = kb * 32 + 8 * g + j;
-      const float v = (c < C && r < 9) ? W[c * 9 + r] : 0.f;
+      const int c = last_chan<C>(kb, g, j);
+      const float v = (c >= 0 && r < 9) ? W[c * 9 + r] : 0.f;
       const __bf16 h = (__bf16)v;
       hi[kb][j] = h;
       lo[kb][j] = (__bf16)(v - (float)h);
     }
+  }
+}
+
+// The last layer's weights as the per-lane B fragments last_weights forms:
+// out[(2 kb + h) 64 + lane] = (h ? lo : hi)[kb] of that lane.
+template <int C>
+__global__ void k_cnn_pack_last(const float* __restrict__ W, bf16x8* __restrict__ out) {
+  const int lane = threadIdx.x;
+  if (lane >= 64) return;
+  bf16x8 hi[LastCfg<C>::KB], lo[LastCfg<C>::KB];
+  last_weights<C>(W, lane, hi, lo);
+#pragma unroll
+  for (int kb = 0; kb < LastCfg<C>::KB; ++kb) {
+    out[(2 * kb) * 64 + lane] = hi[kb];
+    out[(2 * kb + 1) * 64 + lane] = lo[kb];
   }
 }
 
@@ -238,7 +291,7 @@ template <int C, bool SPLIT> constexpr bool hidden_pipelined() { return SPLIT &&
 // bitwise that of the two launches.  Inference only: the first layer's
 // activations and pre-activations are not kept.
 //
-// With TAIL (C = 32) the layer's activations are not stored: the epilogue
+// With TAIL (C = 32 or 48) the layer's activations are not stored: the epilogue
 // multiplies them at once by the last layer's weights, as k_cnn_last_mma
 // does after reloading them, and stores the nine per-tap products
 // Y[t][pixel] (tap planes of nfields N^2 floats) for k_cnn_last_gather.
@@ -247,14 +300,16 @@ template <int C, bool SPLIT> constexpr bool hidden_pipelined() { return SPLIT &&
 // the 16x16x32 A fragment that k_cnn_last_mma loads for the pixel, and the
 // same three products in the same order give Y bit for bit.
 template <int C, bool SPLIT, bool FIRST = false, bool TAIL = false>
-__global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
+__global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C == 48 ? PR_HID48_WAVES : 1))) void k_cnn_hidden(
     const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
     const __bf16* __restrict__ Wp, const float* __restrict__ b, int act,
     __bf16* __restrict__ out, __bf16* __restrict__ out_lo, float* __restrict__ zout,
-    FirstIn fi, const float* __restrict__ WL, float* __restrict__ Yp) {
+    FirstIn fi, const float* __restrict__ WL, const bf16x8* __restrict__ WLp,
+    float* __restrict__ Yp) {
   using H = HidCfg<C>;
   static_assert(C % 16 == 0, "hidden width must be a multiple of 16");
-  static_assert(!TAIL || C == 32, "the last layer folds into a hidden layer of 32 channels");
+  static_assert(!TAIL || C == 32 || C == 48,
+                "the last layer folds into a hidden layer of 32 or 48 channels");
   extern __shared__ __align__(16) unsigned char smem[];
   using HT = HidTile<C, SPLIT>;
   __bf16* tile = (__bf16*)smem;                               // [TPIX][PS]
@@ -270,19 +325,30 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
 
   // this lane's weight fragments and biases, for the whole kernel; och is
   // the output channel of row m of channel block nb
-  auto och = [](int nb, int m) { return TAIL ? 8 * (m / 4) + 4 * nb + m % 4 : nb * 16 + m; };
+  auto och = [](int nb, int m) { return TAIL ? (C / 4) * (m / 4) + 4 * nb + m % 4 : nb * 16 + m; };
   bf16x8 bfr[H::KB][H::NB];
-  float bias[H::NB][4];  // channels och(nb, 4 g + i)
+  // biases of channels och(nb, 4 g + i), consecutive in i: in registers for
+  // the whole kernel, or at C = 48 read per 16-pixel block (16-byte loads),
+  // which leaves the registers the folded last layer needs at 2 waves per SIMD
+  constexpr bool kBiasRegs = C != 48;
+  float bias[H::NB][4];
 #pragma unroll
   for (int nb = 0; nb < H::NB; ++nb) {
+    if constexpr (kBiasRegs) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) bias[nb][i] = b[och(nb, 4 * g + i)];
+      for (int i = 0; i < 4; ++i) bias[nb][i] = b[och(nb, 4 * g + i)];
+    }
 #pragma unroll
     for (int kb = 0; kb < H::KB; ++kb)
       bfr[kb][nb] = *(const bf16x8*)&Wp[(int64_t)och(nb, r) * H::KP + kb * 32 + 8 * g];
   }
-  bf16x8 lwhi[1], lwlo[1];  // TAIL: the last layer's weights, as in k_cnn_last_mma
-  if constexpr (TAIL) last_weights<C>(WL, lane, lwhi, lwlo);
+  constexpr int LKB = LastCfg<C>::KB;
+  // TAIL: the last layer's weights, as in k_cnn_last_mma; held in registers
+  // at C = 32, loaded per 16-pixel block (packed by k_cnn_pack_last) at
+  // C = 48, where the registers would cost a wave per SIMD
+  constexpr bool kTailRegs = C == 32;
+  bf16x8 lwhi[LKB], lwlo[LKB];
+  if constexpr (TAIL && kTailRegs) last_weights<C>(WL, lane, lwhi, lwlo);
   const int64_t yplane = nfields * (int64_t)n * n;
 
   // input tile t: chunk i (pixel i / (C/8) of the (TH+2) x (TW+2) region,
@@ -379,12 +445,26 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
       const int mb = wave * H::MBW + m;
       const int oy = mb / (H::TW / 16), ox0 = (mb % (H::TW / 16)) * 16;
       const int64_t pb = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0 + r) * C + 4 * g;
-      bf16x8 xh, xl;  // TAIL: channels 8 g .. 8 g + 7 of pixel ox0 + r
+      // TAIL: the lane's channels (C/4) g + q of pixel ox0 + r, q = 4 nb + i,
+      // as the last layer's A fragments: slot j of step kb holds q = 8 kb + j.
+      // Step kb's products are issued as soon as its fragment is complete,
+      // so one fragment pair is live at a time; lane (g, r) receives
+      // Y[pixel ox0 + 4 g + e][tap r]
+      bf16x8 xh = bf16x8{}, xl = bf16x8{};
+      f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int nb = 0; nb < H::NB; ++nb) {
         float z[4];
+        if constexpr (kBiasRegs) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) z[i] = acc[nb][i] + bias[nb][i];
+          for (int i = 0; i < 4; ++i) z[i] = acc[nb][i] + bias[nb][i];
+        } else {
+          const float4 bv = *(const float4*)&b[och(nb, 4 * g)];
+          z[0] = acc[nb][0] + bv.x;
+          z[1] = acc[nb][1] + bv.y;
+          z[2] = acc[nb][2] + bv.z;
+          z[3] = acc[nb][3] + bv.w;
+        }
         if (zout) *(float4*)&zout[pb + nb * 16] = float4{z[0], z[1], z[2], z[3]};
         bf16x4 h, l;
 #pragma unroll
@@ -396,8 +476,24 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
         if constexpr (TAIL) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            xh[4 * nb + i] = h[i];
-            xl[4 * nb + i] = l[i];
+            xh[(4 * nb + i) % 8] = h[i];
+            xl[(4 * nb + i) % 8] = l[i];
+          }
+          if ((4 * nb + 4) % 8 == 0 || nb == H::NB - 1) {
+            const int kb = (4 * nb) / 8;
+            bf16x8 wh, wl;
+            if constexpr (kTailRegs) {
+              wh = lwhi[kb];
+              wl = lwlo[kb];
+            } else {
+              wh = WLp[(2 * kb) * 64 + lane];
+              wl = WLp[(2 * kb + 1) * 64 + lane];
+            }
+            y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, wh, y, 0, 0, 0);
+            y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, wl, y, 0, 0, 0);
+            if constexpr (SPLIT) y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, wh, y, 0, 0, 0);
+            xh = bf16x8{};
+            xl = bf16x8{};
           }
         } else {
           *(bf16x4*)&out[pb + nb * 16] = h;
@@ -405,11 +501,6 @@ __global__ __launch_bounds__(HidCfg<C>::NT) void k_cnn_hidden(
         }
       }
       if constexpr (TAIL) {
-        // lane (g, r) receives Y[pixel ox0 + 4 g + e][tap r]
-        f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, lwhi[0], y, 0, 0, 0);
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, lwlo[0], y, 0, 0, 0);
-        if constexpr (SPLIT) y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, lwhi[0], y, 0, 0, 0);
         if (r < 9)
           *(f32x4*)&Yp[r * yplane + (f * n + y0 + oy) * (int64_t)n + x0 + ox0 + 4 * g] = y;
       }
@@ -471,12 +562,11 @@ __device__ __forceinline__ float last_layer_mfma(const __bf16* a, int plane, flo
       const int p = mb * 16 + r, pc = p < L::PX ? p : L::PX - 1;
 #pragma unroll
       for (int kb = 0; kb < L::KB; ++kb) {
-        const int c0 = kb * 32 + 8 * g;
-        const bf16x8 x = c0 < C ? *(const bf16x8*)&a[pc * CS + c0] : bf16x8{};
+        const bf16x8 x = last_frag<C>(a + pc * CS, kb, g);
         acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, whi[kb], acc[i], 0, 0, 0);
         acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, wlo[kb], acc[i], 0, 0, 0);
         if constexpr (SPLIT) {
-          const bf16x8 xl = c0 < C ? *(const bf16x8*)&a[plane + pc * CS + c0] : bf16x8{};
+          const bf16x8 xl = last_frag<C>(a + plane + pc * CS, kb, g);
           acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, whi[kb], acc[i], 0, 0, 0);
         }
       }
@@ -1537,10 +1627,10 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
   auto lo = [&](int l) { return split ? hi(l) + act_elems : (__bf16*)nullptr; };
   // PR_CNN_PLAN_FOLDED (inference only; training keeps every layer's
   // activations): the first layer runs inside the first hidden layer's
-  // launch, and at C = 32 the last layer's per-tap products inside the
+  // launch, and at C = 32 or 48 the last layer's per-tap products inside the
   // last hidden layer's, summed over the taps by k_cnn_last_gather
   const bool folded = !train && cnn_effective_plan(C, L, j.prec) == CNN_PLAN_FOLDED;
-  const bool tail = folded && C == 32;
+  const bool tail = folded && (C == 32 || (C == 48 && PR_TAIL48));
   float* Yp = nullptr;
   if (!folded)
     k_cnn_first<C, __bf16><<<g16, b256, 0, st>>>(j.in_base, j.in_offs, n, W, B, j.act, hi(0), lo(0),
@@ -1555,6 +1645,7 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
       const dim3 bh(H::NT);
       const FirstIn fi{j.in_base, j.in_offs, W, B};
       const float* WL = W + cnn_woff(L - 1, L, C);
+      const bf16x8* WLp = (const bf16x8*)((const __bf16*)j.ws.wpack + (int64_t)(L - 2) * C * H::KP);
       // the tap planes (9 floats per pixel) take the place of the layer's
       // output activations (2 C or 4 C bytes per pixel)
       if (last) Yp = (float*)hi(l);
@@ -1568,9 +1659,9 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
     static const int cap = hidden_cap<C, SP, FI, TA>();                                          \
     const dim3 gh((unsigned)std::min<int64_t>(tiles, cap));                                      \
     k_cnn_hidden<C, SP, FI, TA><<<gh, bh, lds, st>>>(ih, il, n, j.nfields, wp, B + cnn_boff(l, C), \
-                                                     j.act, oh, ol, zo, fi, WL, Yp);             \
+                                                     j.act, oh, ol, zo, fi, WL, WLp, Yp);        \
   }
-      if constexpr (C == 32) {
+      if constexpr (C == 32 || C == 48) {
         if (split) {
           if (first && last) PR_HID(true, true, true)
           else if (first) PR_HID(true, true, false)
@@ -1774,6 +1865,15 @@ hipError_t launch_cnn_pack(const CnnJob& j, hipStream_t st) {
         (const float*)j.W + wo, C, C, kp, (__bf16*)j.ws.wpack + (int64_t)(l - 1) * C * kp);
     wo += (int64_t)C * C * 9;
   }
+  bf16x8* last = (bf16x8*)((__bf16*)j.ws.wpack + (int64_t)(L - 2) * C * kp);
+  switch (C) {
+    case 8: k_cnn_pack_last<8><<<1, 64, 0, st>>>((const float*)j.W + wo, last); break;
+    case 16: k_cnn_pack_last<16><<<1, 64, 0, st>>>((const float*)j.W + wo, last); break;
+    case 32: k_cnn_pack_last<32><<<1, 64, 0, st>>>((const float*)j.W + wo, last); break;
+    case 48: k_cnn_pack_last<48><<<1, 64, 0, st>>>((const float*)j.W + wo, last); break;
+    case 64: k_cnn_pack_last<64><<<1, 64, 0, st>>>((const float*)j.W + wo, last); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1845,12 +1945,13 @@ hipError_t cnn_set_lds_limits() {
   PR_B(16) PR_B(32) PR_B(48) PR_B(64)
 #undef PR_B
 #undef PR_A
-#define PR_T(SP, FI)                                                                         \
-  if (e == hipSuccess)                                                                       \
-    e = hipFuncSetAttribute((const void*)k_cnn_hidden<32, SP, FI, true>,                     \
+#define PR_T(CC, SP, FI)                                                                     \
+  if (e == hipSuccess && cnn_lds_bytes(CC, SP, FI) <= kMaxLds)                               \
+    e = hipFuncSetAttribute((const void*)k_cnn_hidden<CC, SP, FI, true>,                     \
                             hipFuncAttributeMaxDynamicSharedMemorySize,                      \
-                            (int)cnn_lds_bytes(32, SP, FI));
-  PR_T(false, false) PR_T(true, false) PR_T(false, true) PR_T(true, true)
+                            (int)cnn_lds_bytes(CC, SP, FI));
+  PR_T(32, false, false) PR_T(32, true, false) PR_T(32, false, true) PR_T(32, true, true)
+  PR_T(48, false, false) PR_T(48, true, false) PR_T(48, false, true) PR_T(48, true, true)
 #undef PR_T
   return e;
 }

@@ -139,7 +139,8 @@ constexpr int kCnnF64MaxC = 32;   // widest FP64 network whose tiles fit in LDS
 constexpr int kWGradGroups = 64;
 
 struct CnnWs {
-  void* wpack;       // bfloat16 [L-2][C][KP] packed hidden-layer weights
+  void* wpack;       // bfloat16 [L-2][C][KP] packed hidden-layer weights, then
+                     // the last layer's [KB][hi, lo][64 lanes][8] fragments
   void* act[2];      // ping-pong activations [nfields][N][N][C] (x2 for hi+lo)
   double* partials;  // [nfields][(N/16)^2] FP64 sums of G(u) - u
   // backward only
