@@ -594,10 +594,17 @@ def run_config(args, cname, api, torch, synth, full=True):
         uu = u0.repeat(s, 1, 1).contiguous()
         chunked = fine_rate(api, p, uu, 10)
         beyond = fine_rate(api, p, uu, 10, working_set=0)
-        del uu
         roof_fine["chunked_10_steps"] = chunked
         roof_fine["beyond_mall"] = dict(beyond, working_set="off (one chunk of all fields)")
         note(f"{cname}: fine step chunked {chunked['GB/s']} GB/s, unchunked {beyond['GB/s']} GB/s")
+        if args.prec == "f64":
+            # the FP32 fine step (16 B per point and step) on the same fields,
+            # the precision of the schedule's first iterations
+            import dataclasses
+            p32 = dataclasses.replace(p, fine_prec="f32")
+            roof_fine["f32_step"] = {"chunked_10_steps": fine_rate(api, p32, uu, 10),
+                                     "beyond_mall": fine_rate(api, p32, uu, 10, working_set=0)}
+        del uu
     out = {
         "value": round(value, 2), "unit": "Gpts/s", "ms_per_step": round(ms_per_step, 3),
         "steps": steps_t,
@@ -693,6 +700,9 @@ def main():
     ap.add_argument("--train-loss", default="mse", choices=["mse", "scheme"],
                     help="mse against fine trajectories, or the scheme-residual loss of "
                          "Algorithm 1 over one coarse step")
+    ap.add_argument("--fine-queue", action="store_true",
+                    help="run the fine solves as one persistent work-queue launch per size and "
+                         "precision class (pr_set_fine_queue)")
     ap.add_argument("--working-set", type=int, default=None,
                     help="working-set budget in bytes of chunked streaming fine calls "
                          "(0 = one chunk, every field through each step in turn)")
@@ -718,6 +728,8 @@ def main():
     api.pr_set_overlap(args.overlap)
     if args.working_set is not None:
         api.pr_set_fine_working_set(args.working_set)
+    if args.fine_queue:
+        api.pr_set_fine_queue(True)
 
     if args.config == "c4":
         print(json.dumps(training_bench(args)), flush=True)

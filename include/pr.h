@@ -459,6 +459,23 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
                            void* u_out, void* ws, size_t ws_bytes, void* stream,
                            int32_t* chosen);
 
+/* The work-queue fine sweep (Section 3.3's fine solves of all slices, as
+ * one persistent launch).  With it on, the semi-implicit fine solves of a
+ * pr_fine_propagate call, and those of every launch group of one Parareal
+ * iteration of pr_solve / pr_solve_many, run as one persistent launch per
+ * (N, fine precision) class instead of 2*steps + 1 launches per group: the
+ * blocks take the tiles of every pass of every field from a queue, and a
+ * tile waits only for the previous pass of its own field (per-field
+ * counters), so passes of different fields and groups overlap.  The
+ * results are bitwise those of the per-pass launches.  It covers N = 64 ..
+ * 1024 in PR_F64 and N = 64 .. 256 in PR_F32 (other sizes, FP32 at 512 and
+ * 1024, and Crank-Nicolson keep the per-pass launches).  Process-wide,
+ * default off: on MI355X it is slower than the per-pass launches at every
+ * size measured, because each work item ends with a device-scope release,
+ * which writes back the dirty lines of its XCD's L2. */
+pr_status pr_set_fine_queue(int32_t on);
+int32_t pr_get_fine_queue(void);
+
 /* A streaming F (or numerical G) call is 2*steps + 1 launches.  With
  * graphs on (the default), that sequence is captured once per (problem,
  * steps, workspace) into a hipGraph and replayed; the batch size and the

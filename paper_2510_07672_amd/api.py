@@ -394,6 +394,16 @@ def pr_get_fine_working_set(n: int, prec: str) -> int:
     return int(L.lib().pr_get_fine_working_set(n, _PREC[prec]))
 
 
+def pr_set_fine_queue(on: bool) -> None:
+    """Run the semi-implicit fine solves as one persistent work-queue launch
+    per (N, precision) class (True) or pass by pass (False, default)."""
+    L.check(L.lib().pr_set_fine_queue(int(bool(on))), "pr_set_fine_queue")
+
+
+def pr_get_fine_queue() -> bool:
+    return bool(L.lib().pr_get_fine_queue())
+
+
 def pr_set_overlap(chunks: int) -> None:
     """Fine-batch chunks overlapped with the sequential sweep (1 = no overlap)."""
     L.check(L.lib().pr_set_overlap(int(chunks)), "pr_set_overlap")

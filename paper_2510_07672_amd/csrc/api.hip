@@ -120,6 +120,7 @@ FineWs carve_fine(Carver& c, int n, bool f32, int64_t nfields, bool cn = false) 
   w.partials = (double*)c.take((size_t)nfields * row_tiles(n, f32) * sizeof(double));
   w.spec = c.take((size_t)nfields * n * (n / 2) * (f32 ? 8 : 16));
   if (cn) w.xspec = c.take((size_t)nfields * n * (n / 2) * (f32 ? 8 : 16));
+  w.queue = c.take(fine_queue_ws_bytes(nfields));
   return w;
 }
 
@@ -403,6 +404,7 @@ struct SolvePlan {
   int32_t* t32 = nullptr;
   int64_t n64 = 0, n32 = 0;
   int64_t total_ics = 0;
+  void* queue = nullptr;                // work-queue sweep over all fine groups
   size_t bytes = 0;
 };
 
@@ -484,7 +486,12 @@ pr_status plan_solve(int32_t n_jobs, pr_job* jobs, void* base, SolvePlan& P) {
     r.gcache = (double*)c.take((size_t)(r.B * r.s * r.n2) * 8);
     r.fbuf = c.take((size_t)(r.B * r.s * r.n2) * (r.f32_only ? 4 : 8));
   }
-  for (auto& g : P.fine) g.ws = carve_fine(c, g.N, g.f32, g.cap, g.scheme == PR_SCHEME_CN);
+  int64_t fine_fields = 0;
+  for (auto& g : P.fine) {
+    g.ws = carve_fine(c, g.N, g.f32, g.cap, g.scheme == PR_SCHEME_CN);
+    fine_fields += g.cap;
+  }
+  P.queue = c.take(fine_queue_ws_bytes(fine_fields));
   for (auto& g : P.coarse) {
     g.ws = carve_coarse(c, g.p, g.g, g.cap);
     g.gtmp = (double*)c.take((size_t)g.cap * g.p->n * g.p->n * 8);
@@ -869,6 +876,7 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
     }
     for (int c = 0; c < nchunk; ++c) {
       PR_HIP(hipEventRecord(ovl.start[c], sf));
+      std::vector<StepJob> queued;   // the work-queue sweep's jobs, if it is on
       for (auto& sg : fsegs[c]) {
         const FineGroup& G = P.fine[sg.grp];
         StepJob fj{};
@@ -891,8 +899,13 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
           fj.params = P.params;
           fj.pidx = P.t32 + sg.i32[0];
         }
-        PR_HIP(launch_steps(fj, sf));
+        if (fine_queue_enabled() && fine_queue_supports(fj))
+          queued.push_back(fj);
+        else
+          PR_HIP(launch_steps(fj, sf));
       }
+      if (!queued.empty())
+        PR_HIP(launch_fine_queue(queued.data(), (int)queued.size(), P.queue, sf));
       PR_HIP(hipEventRecord(ovl.end[c], sf));
     }
     PR_HIP(hipEventRecord(ev.e[1], hs));
@@ -1081,7 +1094,10 @@ static pr_status fine_propagate(const pr_problem* p, int64_t nfields, const doub
   j.out_f32 = out_dtype == PR_F32;
   j.eager = eager;
   PR_HIP(launch_tables(p->n, p->laplacian, w, s));
-  PR_HIP(launch_steps(j, s));
+  if (fine_queue_enabled() && fine_queue_supports(j))
+    PR_HIP(launch_fine_queue(&j, 1, w.queue, s));
+  else
+    PR_HIP(launch_steps(j, s));
   return PR_OK;
 }
 
@@ -1142,6 +1158,14 @@ pr_status pr_fine_propagate_noalloc(const pr_problem* p, int64_t nfields, const 
   return fine_propagate(p, nfields, u_in, u_out, out_dtype, ws, PR_NOALLOC_SCRATCH_BYTES, stream,
                         true);
 }
+
+pr_status pr_set_fine_queue(int32_t on) {
+  if (on != 0 && on != 1) return fail(PR_ERR_INVALID_ARG, "pr_set_fine_queue: on must be 0 or 1");
+  set_fine_queue(on != 0);
+  return PR_OK;
+}
+
+int32_t pr_get_fine_queue(void) { return fine_queue_enabled() ? 1 : 0; }
 
 size_t pr_coarse_workspace_bytes(const pr_problem* p, const pr_coarse* g, int64_t nfields) {
   if (check_problem(p) != PR_OK || check_coarse(g, p->n) != PR_OK || nfields < 0) return 0;

@@ -286,25 +286,22 @@ __device__ __forceinline__ void row_mid_tile(cpx<T>* panel, TW tw, double* red,
 }
 
 // First row pass of a call: the real FP64 state in, half spectra out.
+// Tile `tile` of field f; panel, tw_s and red are the block's LDS.
 template <int N, typename T, int RHS = RHS_SSI>
-__global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row_first(
-    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
-    const cpx<T>* __restrict__ tw_g, StepParams sp_arg) {
+__device__ __forceinline__ void row_first_body(cpx<T>* panel, cpx<T>* tw_s, double* red,
+                                               const CallDesc* __restrict__ desc,
+                                               cpx<T>* __restrict__ spec,
+                                               double* __restrict__ partials,
+                                               const cpx<T>* __restrict__ tw_g,
+                                               const StepParams& sp_arg, int64_t f, int tile,
+                                               int tid) {
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
   constexpr int LS = RowLS<N, T>::value;
   using Lay = LinePanel<LS, RowLS<N, T>::SH>;
-  __shared__ C panel[PAIRS * LS];
-  __shared__ C tw_s[RowLS<N, T>::TWN];
-  __shared__ double red[NT / 64 + 1];
   const auto tw = twiddle_source<RowLS<N, T>::TWP>((const C*)tw_s);
-
-  const int tid = threadIdx.x;
-  const int64_t f = blockIdx.x / TILES;
-  if (f >= desc->nfields) return;
   const StepParams sp = field_params(desc, f, sp_arg);
-  const int tile = blockIdx.x % TILES;
   const int r0 = tile * TR;
   const Lay lay{};
   load_twiddles<N, NT, RowLS<N, T>::TWP>(tw_s, tw_g, tid);
@@ -320,26 +317,35 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   row_split_store<N, T, PAIRS, NT>(panel, spec + f * (int64_t)(N / 2) * N, r0, tid, lay);
 }
 
-// Middle and last row passes: one block per tile of TR rows of one field.
-template <int N, typename T, int MODE, int RHS = RHS_SSI>
-__global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
+template <int N, typename T, int RHS = RHS_SSI>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row_first(
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
     const cpx<T>* __restrict__ tw_g, StepParams sp_arg) {
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
-  constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
+  __shared__ C panel[Cfg::PAIRS * RowLS<N, T>::value];
+  __shared__ C tw_s[RowLS<N, T>::TWN];
+  __shared__ double red[Cfg::NT / 64 + 1];
+  const int64_t f = blockIdx.x / Cfg::TILES;
+  if (f >= desc->nfields) return;
+  row_first_body<N, T, RHS>(panel, tw_s, red, desc, spec, partials, tw_g, sp_arg, f,
+                            (int)(blockIdx.x % Cfg::TILES), threadIdx.x);
+}
+
+// Middle and last row passes: tile `tile` (TR rows) of field f.
+template <int N, typename T, int MODE, int RHS = RHS_SSI>
+__device__ __forceinline__ void row_body(cpx<T>* panel, cpx<T>* tw_s, double* red,
+                                         const CallDesc* __restrict__ desc,
+                                         cpx<T>* __restrict__ spec, double* __restrict__ partials,
+                                         const cpx<T>* __restrict__ tw_g, const StepParams& sp_arg,
+                                         int64_t f, int tile, int tid) {
+  using C = cpx<T>;
+  using Cfg = RowCfg<N, T>;
+  constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT;
   constexpr int LS = RowLS<N, T>::value;
   using Lay = LinePanel<LS, RowLS<N, T>::SH>;
-  __shared__ C panel[PAIRS * LS];
-  __shared__ C tw_s[RowLS<N, T>::TWN];
-  __shared__ double red[NT / 64 + 1];
   const auto tw = twiddle_source<RowLS<N, T>::TWP>((const C*)tw_s);
-
-  const int tid = threadIdx.x;
-  const int64_t f = blockIdx.x / TILES;
-  if (f >= desc->nfields) return;
   const StepParams sp = field_params(desc, f, sp_arg);
-  const int tile = blockIdx.x % TILES;
   const int r0 = tile * TR;
   const Lay lay{};
   load_twiddles<N, NT, RowLS<N, T>::TWP>(tw_s, tw_g, tid);
@@ -360,6 +366,22 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) voi
   } else {
     row_mid_tile<N, T, RHS>(panel, tw, red, partials, S, f, tile, a, dt, sp.conservative, tid);
   }
+}
+
+// One block per tile of TR rows of one field.
+template <int N, typename T, int MODE, int RHS = RHS_SSI>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
+    const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
+    const cpx<T>* __restrict__ tw_g, StepParams sp_arg) {
+  using C = cpx<T>;
+  using Cfg = RowCfg<N, T>;
+  __shared__ C panel[Cfg::PAIRS * RowLS<N, T>::value];
+  __shared__ C tw_s[RowLS<N, T>::TWN];
+  __shared__ double red[Cfg::NT / 64 + 1];
+  const int64_t f = blockIdx.x / Cfg::TILES;
+  if (f >= desc->nfields) return;
+  row_body<N, T, MODE, RHS>(panel, tw_s, red, desc, spec, partials, tw_g, sp_arg, f,
+                            (int)(blockIdx.x % Cfg::TILES), threadIdx.x);
 }
 
 // ------------------------------------------------------------ column pass
@@ -457,6 +479,36 @@ __device__ __forceinline__ void col_tile(cpx<T>* panel, TW tw, double* corr_sh,
   fft_lines<N, +1, NT, T, 1, SpecLayout<N>::LF>(panel, tw, lay, tid, NoPro{}, ColStore<N, T>{P});
 }
 
+// Column tile `blk` (CT columns) of field f; panel, tw_s, s2_s (PR_S2_LDS
+// only) and corr_sh are the block's LDS.
+template <int N, typename T>
+__device__ __forceinline__ void col_body(cpx<T>* panel, cpx<T>* tw_s, double* s2_s,
+                                         double* corr_sh, const CallDesc* __restrict__ desc,
+                                         cpx<T>* __restrict__ spec,
+                                         const double* __restrict__ partials,
+                                         const cpx<T>* __restrict__ tw_g,
+                                         const double* __restrict__ s2_g, const StepParams& sp_arg,
+                                         int64_t f, int blk, int tid) {
+  using C = cpx<T>;
+  constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT;
+  const auto tw = twiddle_source<ColPanel<N, T>::TWP>((const C*)tw_s);
+#if PR_S2_LDS
+  const double* s2 = s2_s;
+#else
+  const double* s2 = s2_g;
+  (void)s2_s;
+#endif
+  const StepParams sp = field_params(desc, f, sp_arg);
+  const int c0 = blk * CT;
+  C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
+  load_twiddles<N, NT, ColPanel<N, T>::TWP>(tw_s, tw_g, tid);
+#if PR_S2_LDS
+  for (int i = tid; i < N; i += NT) s2_s[i] = s2_g[i];
+#endif
+  __syncthreads();
+  col_tile<N, T>(panel, tw, corr_sh, s2, partials, P, f, c0, sp, tid, ColLoad<N, T>{P});
+}
+
 // One block per column tile.
 template <int N, typename T>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col(
@@ -464,29 +516,19 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
     const double* __restrict__ partials, const cpx<T>* __restrict__ tw_g,
     const double* __restrict__ s2_g, StepParams sp_arg) {
   using C = cpx<T>;
-  constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT, BLK = ColCfg<N>::BLOCKS;
+  constexpr int CT = ColCfg<N>::CT, BLK = ColCfg<N>::BLOCKS;
   __shared__ C panel[CT * ColPanel<N, T>::value];
   __shared__ C tw_s[ColPanel<N, T>::TWN];
-  const auto tw = twiddle_source<ColPanel<N, T>::TWP>((const C*)tw_s);
 #if PR_S2_LDS
   __shared__ double s2[N];
 #else
-  const double* s2 = s2_g;
+  double* s2 = nullptr;
 #endif
   __shared__ double corr_sh;
-
-  const int tid = threadIdx.x;
   const int64_t f = blockIdx.x / BLK;
   if (f >= desc->nfields) return;
-  const StepParams sp = field_params(desc, f, sp_arg);
-  const int c0 = (blockIdx.x % BLK) * CT;
-  C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
-  load_twiddles<N, NT, ColPanel<N, T>::TWP>(tw_s, tw_g, tid);
-#if PR_S2_LDS
-  for (int i = tid; i < N; i += NT) s2[i] = s2_g[i];
-#endif
-  __syncthreads();
-  col_tile<N, T>(panel, tw, &corr_sh, s2, partials, P, f, c0, sp, tid, ColLoad<N, T>{P});
+  col_body<N, T>(panel, tw_s, s2, &corr_sh, desc, spec, partials, tw_g, s2_g, sp_arg, f,
+                 (int)(blockIdx.x % BLK), threadIdx.x);
 }
 
 // ------------------------------------------------ Crank-Nicolson + Picard
@@ -1040,6 +1082,315 @@ static hipError_t launch_steps_t(const StepJob& job, hipStream_t st) {
     case 1024: return launch_steps_n<1024, T>(job, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---- the work-queue fine sweep: one persistent launch for many groups
+//
+// The semi-implicit F calls of several launch groups (fields of one size
+// and precision each) run as one launch.  Its work items are the tiles of
+// every pass of every field: for field f, phase 0 is the first row pass
+// (RT row tiles), odd phases the column passes (CT column tiles) and even
+// phases p > 0 the middle row passes, the last one (p = 2 steps) writing
+// the state.  Items are numbered group by group; inside a group, working-
+// set chunk by chunk (the same chunks as the launch-by-launch sweep), and
+// inside a chunk phase by phase, field by field, tile by tile.  Blocks take
+// the next item from a queue counter; an item of phase p of field f first
+// waits until the field's counter shows every item of its phases < p done
+// (the tiles of one pass depend only on the previous pass of the same
+// field), then runs the same tile code as the per-pass kernels, then
+// counts itself done.  An item only waits for items numbered before it,
+// which blocks that are running have already taken, so every wait ends;
+// blocks leave when the queue is empty.  Results are bitwise those of the
+// per-pass launches.
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v);
+
+constexpr int kQueueMaxGroups = 12;
+constexpr int kQueueThreads = 256;
+
+// Tiles per work item: an item runs this many consecutive tiles of one
+// pass of one field, so that the per-item synchronisation (a device-scope
+// release before the field's counter is raised, an acquire after it is
+// read) is paid once per group of tiles.
+#ifndef PR_QUEUE_TILES
+#define PR_QUEUE_TILES 16
+#endif
+
+struct QGroup {
+  int n, f32, steps, rt, ct;   // tiles per row / column pass
+  int rti, cti;                // work items per row / column pass
+  int64_t nfields, chunk, chunk_items, item0, done0;
+  StepParams sp;
+  FineWs ws;
+};
+
+struct QArgs {
+  QGroup g[kQueueMaxGroups];
+  int ngroups;
+  int64_t total;
+};
+
+template <int N, typename T> struct QLds {
+  using C = cpx<T>;
+  static constexpr size_t al(size_t b) { return (b + 15) / 16 * 16; }
+  static constexpr size_t ROW_PANEL = al(sizeof(C) * RowCfg<N, T>::PAIRS * RowLS<N, T>::value);
+  static constexpr size_t ROW_TW = al(sizeof(C) * RowLS<N, T>::TWN);
+  static constexpr size_t ROW = ROW_PANEL + ROW_TW + al(sizeof(double) * (RowCfg<N, T>::NT / 64 + 1));
+  static constexpr size_t COL_PANEL = al(sizeof(C) * ColCfg<N>::CT * ColPanel<N, T>::value);
+  static constexpr size_t COL_TW = al(sizeof(C) * ColPanel<N, T>::TWN);
+  static constexpr size_t COL_S2 = PR_S2_LDS ? al(sizeof(double) * N) : 0;
+  static constexpr size_t COL = COL_PANEL + COL_TW + COL_S2 + 16;
+  static constexpr size_t BYTES = ROW > COL ? ROW : COL;
+};
+
+// Sizes and precisions whose row and column tiles both take 256 threads
+// (FP32 tiles at 512^2 and 1024^2 take 512 and stay with per-pass launches).
+template <int N, typename T> constexpr bool queue_item_ok() {
+  return RowCfg<N, T>::NT == kQueueThreads && ColCfg<N>::NT == kQueueThreads;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void q_item(unsigned char* lds, const QGroup& G, int p, int64_t f, int tile,
+                                    int tid) {
+  static_assert(queue_item_ok<N, T>(), "queue items are 256-thread tiles");
+  using C = cpx<T>;
+  using L = QLds<N, T>;
+  const C* twg = (const C*)(sizeof(T) == 8 ? (const void*)G.ws.tw64 : (const void*)G.ws.tw32);
+  C* spec = (C*)G.ws.spec;
+  if (p & 1) {
+    col_body<N, T>((C*)lds, (C*)(lds + L::COL_PANEL), (double*)(lds + L::COL_PANEL + L::COL_TW),
+                   (double*)(lds + L::COL_PANEL + L::COL_TW + L::COL_S2), G.ws.desc, spec,
+                   G.ws.partials, twg, G.ws.s2, G.sp, f, tile, tid);
+  } else {
+    C* panel = (C*)lds;
+    C* tw_s = (C*)(lds + L::ROW_PANEL);
+    double* red = (double*)(lds + L::ROW_PANEL + L::ROW_TW);
+    if (p == 0)
+      row_first_body<N, T>(panel, tw_s, red, G.ws.desc, spec, G.ws.partials, twg, G.sp, f, tile, tid);
+    else if (p == 2 * G.steps)
+      row_body<N, T, ROW_LAST>(panel, tw_s, red, G.ws.desc, spec, G.ws.partials, twg, G.sp, f, tile,
+                               tid);
+    else
+      row_body<N, T, ROW_MID>(panel, tw_s, red, G.ws.desc, spec, G.ws.partials, twg, G.sp, f, tile,
+                              tid);
+  }
+}
+
+// Writes the launch's group table into device memory (a kernel rather than
+// a copy, so that a captured graph replays it).
+__global__ void k_set_groups(QArgs a, QGroup* __restrict__ out) {
+  const int i = threadIdx.x;
+  if (i < a.ngroups) out[i] = a.g[i];
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(kQueueThreads) void k_fine_queue(const QGroup* __restrict__ groups,
+                                                              int ngroups, int64_t total,
+                                                              unsigned long long* __restrict__ qc) {
+  extern __shared__ __align__(16) unsigned char qlds[];
+  __shared__ long long item_sh;
+  const int tid = threadIdx.x;
+  unsigned long long* done = qc + 1;
+  for (;;) {
+    if (tid == 0) item_sh = (long long)atomicAdd(qc, 1ull);
+    __syncthreads();
+    // the item is the same for every thread; read it into scalar registers
+    // so that the loop's exit (and everything derived from the item) is a
+    // uniform branch: a loop whose exit the compiler takes for per-lane
+    // would be restructured so that lanes other than thread 0 re-enter the
+    // loop body without the queue update, and the block would never
+    // leave it
+    const unsigned long long raw = (unsigned long long)item_sh;
+    const int64_t it = (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane((int)(raw >> 32)) << 32) |
+                                 (unsigned)__builtin_amdgcn_readfirstlane((int)(raw & 0xffffffffu)));
+    __syncthreads();  // every thread has read item_sh before it is overwritten
+    if (it >= total) break;
+    int g = 0;
+    while (g + 1 < ngroups && it >= groups[g + 1].item0) ++g;
+    const QGroup& G = groups[g];
+    int64_t li = it - G.item0;
+    const int64_t ck = li / G.chunk_items;
+    li -= ck * G.chunk_items;
+    const int64_t f0 = ck * G.chunk;
+    const int64_t nf = G.nfields - f0 < G.chunk ? G.nfields - f0 : G.chunk;
+    const int64_t pair = nf * (G.rti + G.cti);
+    const int64_t q = li / pair;
+    int64_t rem = li - q * pair;
+    int p;
+    int64_t per;
+    int tiles;
+    if (rem < nf * G.rti) {
+      p = (int)(2 * q);
+      per = G.rti;
+      tiles = G.rt;
+    } else {
+      p = (int)(2 * q + 1);
+      rem -= nf * G.rti;
+      per = G.cti;
+      tiles = G.ct;
+    }
+    const int64_t f = f0 + rem / per;
+    const int t0 = (int)(rem % per) * PR_QUEUE_TILES;
+    const int t1 = t0 + PR_QUEUE_TILES < tiles ? t0 + PR_QUEUE_TILES : tiles;
+    // items of this field in phases < p: (p + 1) / 2 row passes, p / 2 column passes
+    const unsigned long long need =
+        (unsigned long long)((p + 1) / 2) * G.rti + (unsigned long long)(p / 2) * G.cti;
+    if (tid == 0 && need > 0) {
+      // poll without cache maintenance; one acquire once the count is there
+      while (__hip_atomic_load(&done[G.done0 + f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need)
+        __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    for (int tile = t0; tile < t1; ++tile) {
+      q_item<N, T>(qlds, G, p, f, tile, tid);
+      __syncthreads();  // the tile's LDS is free for the next one
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's results visible device-wide
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_fetch_add(&done[G.done0 + f], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // a barrier between this thread-0 region and the next iteration's:
+    // without it the compiler may join the two into one path for thread 0
+    // that bypasses the loop head the other threads return to
+    __syncthreads();
+  }
+}
+
+static std::atomic<bool> g_fine_queue{false};
+void set_fine_queue(bool on) { g_fine_queue.store(on); }
+bool fine_queue_enabled() { return g_fine_queue.load(); }
+
+bool fine_queue_supports(const StepJob& job) {
+  if (job.scheme != SCHEME_SSI) return false;
+  switch (job.n) {
+#define PR_CASE(NN) \
+  case NN: return job.f32 ? queue_item_ok<NN, float>() : queue_item_ok<NN, double>();
+    PR_CASE(64) PR_CASE(128) PR_CASE(256) PR_CASE(512) PR_CASE(1024)
+#undef PR_CASE
+    default: return false;
+  }
+}
+
+size_t fine_queue_ws_bytes(int64_t total_fields) {
+  return (size_t)(total_fields + 1) * sizeof(unsigned long long) + sizeof(QGroup) * kQueueMaxGroups +
+         512;
+}
+
+static int col_blocks(int n) {
+  switch (n) {
+#define PR_CASE(NN) case NN: return ColCfg<NN>::BLOCKS;
+    PR_CASE(16) PR_CASE(32) PR_CASE(64) PR_CASE(128) PR_CASE(256) PR_CASE(512) PR_CASE(1024)
+#undef PR_CASE
+    default: return 0;
+  }
+}
+
+// Blocks of the queue kernel for (N, T) that fill the GPU once.
+template <int N, typename T> static hipError_t queue_grid(int* grid) {
+  static int g = 0;
+  static hipError_t attr = hipSuccess;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    constexpr size_t lds = QLds<N, T>::BYTES;
+    if (lds > 64 * 1024)
+      attr = hipFuncSetAttribute((const void*)k_fine_queue<N, T>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int dev = 0, cus = 0, per_cu = 0;
+    if (attr == hipSuccess) attr = hipGetDevice(&dev);
+    if (attr == hipSuccess)
+      attr = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (attr == hipSuccess)
+      attr = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fine_queue<N, T>, kQueueThreads,
+                                                          lds);
+    g = std::max(1, cus * std::max(1, per_cu));
+  });
+  *grid = g;
+  return attr;
+}
+
+template <int N, typename T>
+static hipError_t queue_launch(const QGroup* gtab, int ngroups, int64_t total,
+                               unsigned long long* qc, hipStream_t st) {
+  if constexpr (queue_item_ok<N, T>()) {
+    int grid = 0;
+    hipError_t e = queue_grid<N, T>(&grid);
+    if (e != hipSuccess) return e;
+    k_fine_queue<N, T><<<dim3((unsigned)grid), dim3(kQueueThreads), QLds<N, T>::BYTES, st>>>(
+        gtab, ngroups, total, qc);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+// One persistent launch per (N, precision) class of the jobs, in the order
+// the classes first appear (a batch of one class: one launch).
+hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStream_t st) {
+  // workspace: the group table, then the counters
+  QGroup* gtab = (QGroup*)((char*)qws + 256);
+  unsigned long long* qc =
+      (unsigned long long*)((char*)qws + 256 + (sizeof(QGroup) * kQueueMaxGroups + 255) / 256 * 256);
+  std::vector<char> taken(njobs, 0);
+  for (int i0 = 0; i0 < njobs; ++i0) {
+    if (taken[i0]) continue;
+    const int n = jobs[i0].n;
+    const bool f32 = jobs[i0].f32;
+    QArgs a{};
+    a.ngroups = 0;
+    a.total = 0;
+    int64_t fields = 0;
+    for (int i = i0; i < njobs && a.ngroups < kQueueMaxGroups; ++i) {
+      const StepJob& j = jobs[i];
+      if (taken[i] || j.n != n || j.f32 != f32) continue;
+      if (!fine_queue_supports(j)) return hipErrorInvalidValue;
+      taken[i] = 1;
+      if (j.nfields <= 0 || j.steps <= 0) continue;
+      CallDesc v{j.nfields, j.in_base, j.in_offs, j.out_base, j.out_offs, j.out_f32, j.params, j.pidx};
+      k_set_desc<<<dim3(1), dim3(1), 0, st>>>(j.ws.desc, v);
+      QGroup& G = a.g[a.ngroups++];
+      G.n = j.n;
+      G.f32 = j.f32 ? 1 : 0;
+      G.steps = j.steps;
+      G.rt = row_tiles(j.n, j.f32);
+      G.ct = col_blocks(j.n);
+      G.rti = (G.rt + PR_QUEUE_TILES - 1) / PR_QUEUE_TILES;
+      G.cti = (G.ct + PR_QUEUE_TILES - 1) / PR_QUEUE_TILES;
+      G.nfields = j.nfields;
+      StepJob sj = j;
+      sj.resident = false;
+      G.chunk = chunk_fields(sj);
+      const int64_t per_field = (int64_t)(j.steps + 1) * G.rti + (int64_t)j.steps * G.cti;
+      G.chunk_items = G.chunk * per_field;
+      G.item0 = a.total;
+      G.done0 = fields;
+      G.sp = j.sp;
+      G.ws = j.ws;
+      a.total += j.nfields * per_field;
+      fields += j.nfields;
+    }
+    if (a.ngroups == 0) continue;
+    --i0;   // the same class may hold more groups than one launch takes
+    // counters: the queue, then one per field (kernels, so that a captured
+    // graph replays the clearing)
+    const int64_t nc = 1 + fields;
+    k_fill_u64<<<dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st>>>(qc, nc, 0ull);
+    k_set_groups<<<dim3(1), dim3(64), 0, st>>>(a, gtab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (n) {
+#define PR_QCASE(NN) \
+  case NN:                                                                            \
+    e = f32 ? queue_launch<NN, float>(gtab, a.ngroups, a.total, qc, st)                 \
+            : queue_launch<NN, double>(gtab, a.ngroups, a.total, qc, st);              \
+    break;
+      PR_QCASE(64) PR_QCASE(128) PR_QCASE(256) PR_QCASE(512) PR_QCASE(1024)
+#undef PR_QCASE
+      default: e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_tables(int n, int laplacian, const FineWs& ws, hipStream_t st) {

@@ -95,6 +95,8 @@ struct FineWs {
   void* spec;        // [nfields][N/2][N] complex in the step precision
   void* xspec;       // Crank-Nicolson only: [nfields][N/2][N] 2-D spectra
                      // (U_n between steps, the fixed part K during Picard)
+  void* queue;       // the work-queue sweep's table and counters
+                     // (fine_queue_ws_bytes(nfields))
 };
 
 struct StepJob {
@@ -203,6 +205,16 @@ hipError_t launch_tables(int n, int laplacian, const FineWs& ws, hipStream_t st)
 void set_graphs_enabled(bool on);
 bool graphs_enabled();
 hipError_t launch_steps(const StepJob& job, hipStream_t st);
+
+// The work-queue fine sweep: the semi-implicit F calls of several jobs as
+// one persistent launch per (N, precision) class, bitwise equal to
+// launch_steps of each.  Supported: N in 64..1024 in FP64, 64..256 in FP32,
+// semi-implicit scheme.  qws: fine_queue_ws_bytes(sum of the jobs' fields).
+bool fine_queue_supports(const StepJob& job);
+size_t fine_queue_ws_bytes(int64_t total_fields);
+hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStream_t st);
+void set_fine_queue(bool on);
+bool fine_queue_enabled();
 // Working-set budget of streaming F calls (bytes of spectra in flight; 0 =
 // all fields at once): the process-wide setting, the effective value for
 // (N, precision) and the autotuner's record.

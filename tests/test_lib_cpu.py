@@ -240,3 +240,11 @@ def test_scheme_loss_validation(L):
     assert f(C.byref(p), 1e-3, 2, u0, u1, loss, grad, None, ws, need - 1,
              None) == L.PR_ERR_WORKSPACE
     assert lib.pr_last_error()
+
+
+def test_fine_queue_setting(L):
+    lib = L.lib()
+    assert lib.pr_get_fine_queue() == 0
+    assert lib.pr_set_fine_queue(2) == L.PR_ERR_INVALID_ARG
+    assert lib.pr_set_fine_queue(1) == L.PR_OK and lib.pr_get_fine_queue() == 1
+    assert lib.pr_set_fine_queue(0) == L.PR_OK and lib.pr_get_fine_queue() == 0
