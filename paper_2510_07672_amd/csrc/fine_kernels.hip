@@ -1107,28 +1107,37 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
 
 constexpr int kQueueMaxGroups = 12;
 constexpr int kQueueThreads = 256;
+// One queue per XCD: the fields are split into kQueues contiguous ranges,
+// and the blocks of the XCD whose index a queue carries take its items.
+constexpr int kQueues = 8;
 
 // Tiles per work item: an item runs this many consecutive tiles of one
-// pass of one field, so that the per-item synchronisation (a device-scope
-// release before the field's counter is raised, an acquire after it is
-// read) is paid once per group of tiles.
+// pass of one field, so that the per-item synchronisation (a release before
+// the field's counter is raised, an acquire after it is read) is paid once
+// per group of tiles.
 #ifndef PR_QUEUE_TILES
-#define PR_QUEUE_TILES 16
+#define PR_QUEUE_TILES 8
 #endif
 
 struct QGroup {
-  int n, f32, steps, rt, ct;   // tiles per row / column pass
-  int rti, cti;                // work items per row / column pass
-  int64_t nfields, chunk, chunk_items, item0, done0;
+  int n, f32, steps, rt, ct;    // tiles per row / column pass
+  int rti, cti;                 // work items per row / column pass
+  int64_t nfields, chunk, per_field, done0;
+  int64_t lo[kQueues + 1];      // queue q takes fields [lo[q], lo[q + 1])
+  int64_t item0[kQueues];       // first item of this group in queue q
   StepParams sp;
   FineWs ws;
 };
 
-struct QArgs {
-  QGroup g[kQueueMaxGroups];
-  int ngroups;
-  int64_t total;
+struct QTotals {
+  int64_t t[kQueues];           // items per queue
 };
+
+// Counter words (64-bit) in the queue workspace: the head of queue q at
+// q * 16 and its mode at 128 + q * 16 (one 128-byte line each), then one
+// completion counter per field.
+constexpr int kQueueHeadWords = 256;
+constexpr unsigned long long kModeLocal = 1, kModeShared = 2;
 
 template <int N, typename T> struct QLds {
   using C = cpx<T>;
@@ -1176,61 +1185,76 @@ __device__ __forceinline__ void q_item(unsigned char* lds, const QGroup& G, int 
   }
 }
 
-// Writes the launch's group table into device memory (a kernel rather than
-// a copy, so that a captured graph replays it).
-__global__ void k_set_groups(QArgs a, QGroup* __restrict__ out) {
-  const int i = threadIdx.x;
-  if (i < a.ngroups) out[i] = a.g[i];
+// Writes one entry of the launch's group table into device memory (a
+// kernel rather than a copy, so that a captured graph replays it).
+__global__ void k_set_group(QGroup g, QGroup* __restrict__ out) {
+  if (threadIdx.x == 0) *out = g;
 }
 
+// Reads a value that thread 0 left in LDS into scalar registers: every
+// decision taken on it is then a uniform branch.  (A loop whose exit the
+// compiler takes for per-lane may be restructured so that lanes other than
+// thread 0 re-enter its body without the update thread 0 made, and the
+// block never leaves it.)
+__device__ __forceinline__ int64_t q_uniform(const long long* sh) {
+  const unsigned long long raw = (unsigned long long)*sh;
+  return (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane((int)(raw >> 32)) << 32) |
+                   (unsigned)__builtin_amdgcn_readfirstlane((int)(raw & 0xffffffffu)));
+}
+
+// Runs the items of queue q until it is empty.  local: every block that
+// takes items of q runs on one XCD, whose L2 all of them share; a tile's
+// stores are then visible to the next pass's blocks once they have left
+// the CU (waitcnt), and the reader only drops its CU's L1.  Otherwise the
+// writer publishes with a device-scope release, which writes back the dirty
+// lines of its L2.
 template <int N, typename T>
-__global__ __launch_bounds__(kQueueThreads) void k_fine_queue(const QGroup* __restrict__ groups,
-                                                              int ngroups, int64_t total,
-                                                              unsigned long long* __restrict__ qc) {
-  extern __shared__ __align__(16) unsigned char qlds[];
-  __shared__ long long item_sh;
-  const int tid = threadIdx.x;
-  unsigned long long* done = qc + 1;
+__device__ __forceinline__ void q_drain(unsigned char* qlds, long long* sh, const QGroup* __restrict__ groups,
+                                        int ngroups, int q, int64_t total,
+                                        unsigned long long* __restrict__ qc, bool local, int tid) {
+  unsigned long long* head = qc + q * 16;
+  unsigned long long* done = qc + kQueueHeadWords;
   for (;;) {
-    if (tid == 0) item_sh = (long long)atomicAdd(qc, 1ull);
+    if (tid == 0) *sh = (long long)atomicAdd(head, 1ull);
     __syncthreads();
-    // the item is the same for every thread; read it into scalar registers
-    // so that the loop's exit (and everything derived from the item) is a
-    // uniform branch: a loop whose exit the compiler takes for per-lane
-    // would be restructured so that lanes other than thread 0 re-enter the
-    // loop body without the queue update, and the block would never
-    // leave it
-    const unsigned long long raw = (unsigned long long)item_sh;
-    const int64_t it = (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane((int)(raw >> 32)) << 32) |
-                                 (unsigned)__builtin_amdgcn_readfirstlane((int)(raw & 0xffffffffu)));
-    __syncthreads();  // every thread has read item_sh before it is overwritten
+    const int64_t it = q_uniform(sh);
+    __syncthreads();  // every thread has read sh before it is overwritten
     if (it >= total) break;
     int g = 0;
-    while (g + 1 < ngroups && it >= groups[g + 1].item0) ++g;
+    while (g + 1 < ngroups && it >= groups[g + 1].item0[q]) ++g;
     const QGroup& G = groups[g];
-    int64_t li = it - G.item0;
-    const int64_t ck = li / G.chunk_items;
-    li -= ck * G.chunk_items;
-    const int64_t f0 = ck * G.chunk;
-    const int64_t nf = G.nfields - f0 < G.chunk ? G.nfields - f0 : G.chunk;
-    const int64_t pair = nf * (G.rti + G.cti);
-    const int64_t q = li / pair;
-    int64_t rem = li - q * pair;
+    // a chunk holds fewer than 2^31 items (the host caps it), so past the
+    // chunk index the decoding is 32-bit
+    int64_t li = it - G.item0[q];
+    const int64_t chunk_items = G.chunk * G.per_field;
+    int64_t ck = 0;
+    if (li >= chunk_items) {
+      ck = li / chunk_items;
+      li -= ck * chunk_items;
+    }
+    const int64_t lo = G.lo[q], hi = G.lo[q + 1];
+    const int64_t f0 = lo + ck * G.chunk;
+    const unsigned nf = (unsigned)(hi - f0 < G.chunk ? hi - f0 : G.chunk);
+    const unsigned l = (unsigned)li;
+    const unsigned pair = nf * (unsigned)(G.rti + G.cti);
+    const unsigned ph = l / pair;
+    unsigned rem = l - ph * pair;
     int p;
-    int64_t per;
+    unsigned per;
     int tiles;
-    if (rem < nf * G.rti) {
-      p = (int)(2 * q);
-      per = G.rti;
+    if (rem < nf * (unsigned)G.rti) {
+      p = (int)(2 * ph);
+      per = (unsigned)G.rti;
       tiles = G.rt;
     } else {
-      p = (int)(2 * q + 1);
-      rem -= nf * G.rti;
-      per = G.cti;
+      p = (int)(2 * ph + 1);
+      rem -= nf * (unsigned)G.rti;
+      per = (unsigned)G.cti;
       tiles = G.ct;
     }
-    const int64_t f = f0 + rem / per;
-    const int t0 = (int)(rem % per) * PR_QUEUE_TILES;
+    const unsigned fi = rem / per;
+    const int64_t f = f0 + fi;
+    const int t0 = (int)(rem - fi * per) * PR_QUEUE_TILES;
     const int t1 = t0 + PR_QUEUE_TILES < tiles ? t0 + PR_QUEUE_TILES : tiles;
     // items of this field in phases < p: (p + 1) / 2 row passes, p / 2 column passes
     const unsigned long long need =
@@ -1246,10 +1270,17 @@ __global__ __launch_bounds__(kQueueThreads) void k_fine_queue(const QGroup* __re
       q_item<N, T>(qlds, G, p, f, tile, tid);
       __syncthreads();  // the tile's LDS is free for the next one
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's results visible device-wide
+    if (local)
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's stores are in the L2
+    else
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // and written back from it
     __syncthreads();
-    if (tid == 0)
-      __hip_atomic_fetch_add(&done[G.done0 + f], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+      if (local)
+        __hip_atomic_fetch_add(&done[G.done0 + f], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        __hip_atomic_fetch_add(&done[G.done0 + f], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
     // a barrier between this thread-0 region and the next iteration's:
     // without it the compiler may join the two into one path for thread 0
     // that bypasses the loop head the other threads return to
@@ -1257,12 +1288,78 @@ __global__ __launch_bounds__(kQueueThreads) void k_fine_queue(const QGroup* __re
   }
 }
 
+// The block's XCD, from the hardware register that names it (4 bits).
+__device__ __forceinline__ int q_xcd() {
+  return (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u);
+}
+
+// Persistent blocks; queue q holds the items of fields [lo[q], lo[q + 1])
+// of every group.  A block first serves the queue of its own XCD, then
+// helps with any queue that no block of its XCD has claimed.  Each queue's
+// mode is fixed once, by whichever block comes first: local if a block of
+// its XCD claims it (then only blocks of that XCD take its items), shared
+// if a block of another XCD adopts it (every block that takes its items
+// then publishes device-wide).  Every queue is drained whatever the
+// placement of the blocks: a queue no block of its XCD reaches is adopted
+// by the first block to run out of work.  (Blocks are dealt out to the
+// XCDs round-robin, but the deal carries on from one launch to the next,
+// so block b is not on XCD b mod 8 in general: the register decides.)
+template <int N, typename T>
+__global__ __launch_bounds__(kQueueThreads) void k_fine_queue(const QGroup* __restrict__ groups,
+                                                              int ngroups, QTotals tot,
+                                                              unsigned long long* __restrict__ qc) {
+  extern __shared__ __align__(16) unsigned char qlds[];
+  __shared__ long long sh;
+  const int tid = threadIdx.x;
+  unsigned long long* mode = qc + 128;
+  const int xcd = q_xcd();
+  const int home = xcd < kQueues ? xcd : -1;
+  const int start = home >= 0 ? home + 1 : (int)(blockIdx.x % kQueues);
+  // i = -1: the home queue; then every other queue, to adopt
+  for (int i = home >= 0 ? -1 : 0; i < kQueues; ++i) {
+    const int q = i < 0 ? home : (start + i) % kQueues;
+    if (i >= 0 && q == home) continue;
+    const int64_t total = tot.t[q];
+    if (total == 0) continue;
+    if (tid == 0) {
+      unsigned long long m = 0;
+      if (i < 0) {
+        if (__hip_atomic_compare_exchange_strong(&mode[q * 16], &m, kModeLocal, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          m = kModeLocal;
+      } else {
+        m = __hip_atomic_load(&mode[q * 16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // give the blocks of q's own XCD time to claim it first (bounded)
+        for (int w = 0; w < 16 && m == 0; ++w) {
+          __builtin_amdgcn_s_sleep(127);
+          m = __hip_atomic_load(&mode[q * 16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (m == 0 && __hip_atomic_compare_exchange_strong(&mode[q * 16], &m, kModeShared,
+                                                           __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT))
+          m = kModeShared;
+      }
+      sh = (long long)m;
+    }
+    __syncthreads();
+    const int64_t m = q_uniform(&sh);
+    __syncthreads();
+    // the home queue in either mode; another queue only once adopted
+    if (i < 0 || m == (int64_t)kModeShared)
+      q_drain<N, T>(qlds, &sh, groups, ngroups, q, total, qc, m == (int64_t)kModeLocal, tid);
+  }
+}
+
 static std::atomic<bool> g_fine_queue{false};
 void set_fine_queue(bool on) { g_fine_queue.store(on); }
 bool fine_queue_enabled() { return g_fine_queue.load(); }
 
+static int col_blocks(int n);
+
 bool fine_queue_supports(const StepJob& job) {
   if (job.scheme != SCHEME_SSI) return false;
+  // one field's items are counted in 31 bits
+  if ((int64_t)(job.steps + 1) * (row_tiles(job.n, job.f32) + col_blocks(job.n)) >= INT32_MAX) return false;
   switch (job.n) {
 #define PR_CASE(NN) \
   case NN: return job.f32 ? queue_item_ok<NN, float>() : queue_item_ok<NN, double>();
@@ -1273,8 +1370,8 @@ bool fine_queue_supports(const StepJob& job) {
 }
 
 size_t fine_queue_ws_bytes(int64_t total_fields) {
-  return (size_t)(total_fields + 1) * sizeof(unsigned long long) + sizeof(QGroup) * kQueueMaxGroups +
-         512;
+  return (size_t)(kQueueHeadWords + total_fields) * sizeof(unsigned long long) +
+         sizeof(QGroup) * kQueueMaxGroups + 512;
 }
 
 static int col_blocks(int n) {
@@ -1310,14 +1407,14 @@ template <int N, typename T> static hipError_t queue_grid(int* grid) {
 }
 
 template <int N, typename T>
-static hipError_t queue_launch(const QGroup* gtab, int ngroups, int64_t total,
+static hipError_t queue_launch(const QGroup* gtab, int ngroups, const QTotals& tot,
                                unsigned long long* qc, hipStream_t st) {
   if constexpr (queue_item_ok<N, T>()) {
     int grid = 0;
     hipError_t e = queue_grid<N, T>(&grid);
     if (e != hipSuccess) return e;
     k_fine_queue<N, T><<<dim3((unsigned)grid), dim3(kQueueThreads), QLds<N, T>::BYTES, st>>>(
-        gtab, ngroups, total, qc);
+        gtab, ngroups, tot, qc);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -1336,11 +1433,11 @@ hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStrea
     if (taken[i0]) continue;
     const int n = jobs[i0].n;
     const bool f32 = jobs[i0].f32;
-    QArgs a{};
-    a.ngroups = 0;
-    a.total = 0;
+    QGroup gs[kQueueMaxGroups];
+    QTotals tot{};
+    int ngroups = 0;
     int64_t fields = 0;
-    for (int i = i0; i < njobs && a.ngroups < kQueueMaxGroups; ++i) {
+    for (int i = i0; i < njobs && ngroups < kQueueMaxGroups; ++i) {
       const StepJob& j = jobs[i];
       if (taken[i] || j.n != n || j.f32 != f32) continue;
       if (!fine_queue_supports(j)) return hipErrorInvalidValue;
@@ -1348,7 +1445,8 @@ hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStrea
       if (j.nfields <= 0 || j.steps <= 0) continue;
       CallDesc v{j.nfields, j.in_base, j.in_offs, j.out_base, j.out_offs, j.out_f32, j.params, j.pidx};
       k_set_desc<<<dim3(1), dim3(1), 0, st>>>(j.ws.desc, v);
-      QGroup& G = a.g[a.ngroups++];
+      QGroup& G = gs[ngroups++];
+      G = QGroup{};
       G.n = j.n;
       G.f32 = j.f32 ? 1 : 0;
       G.steps = j.steps;
@@ -1359,30 +1457,42 @@ hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStrea
       G.nfields = j.nfields;
       StepJob sj = j;
       sj.resident = false;
-      G.chunk = chunk_fields(sj);
-      const int64_t per_field = (int64_t)(j.steps + 1) * G.rti + (int64_t)j.steps * G.cti;
-      G.chunk_items = G.chunk * per_field;
-      G.item0 = a.total;
+      // the working-set chunk is shared out among the queues, which run
+      // side by side
+      G.chunk = std::max<int64_t>(1, (chunk_fields(sj) + kQueues - 1) / kQueues);
+      G.per_field = (int64_t)(j.steps + 1) * G.rti + (int64_t)j.steps * G.cti;
+      // a chunk's items are decoded in 32 bits
+      G.chunk = std::min<int64_t>(G.chunk, std::max<int64_t>(1, INT32_MAX / G.per_field));
       G.done0 = fields;
+      // contiguous field ranges of near-equal size; the queues that take
+      // one field more rotate with the fields placed so far
+      const int rot = (int)(fields % kQueues);
+      G.lo[0] = 0;
+      for (int q = 0; q < kQueues; ++q)
+        G.lo[q + 1] = G.lo[q] + j.nfields / kQueues +
+                      (((q - rot + kQueues) % kQueues) < j.nfields % kQueues ? 1 : 0);
+      for (int q = 0; q < kQueues; ++q) {
+        G.item0[q] = tot.t[q];
+        tot.t[q] += (G.lo[q + 1] - G.lo[q]) * G.per_field;
+      }
       G.sp = j.sp;
       G.ws = j.ws;
-      a.total += j.nfields * per_field;
       fields += j.nfields;
     }
-    if (a.ngroups == 0) continue;
+    if (ngroups == 0) continue;
     --i0;   // the same class may hold more groups than one launch takes
-    // counters: the queue, then one per field (kernels, so that a captured
-    // graph replays the clearing)
-    const int64_t nc = 1 + fields;
+    // counters: the queue heads and modes, then one per field (kernels, so
+    // that a captured graph replays the clearing)
+    const int64_t nc = kQueueHeadWords + fields;
     k_fill_u64<<<dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st>>>(qc, nc, 0ull);
-    k_set_groups<<<dim3(1), dim3(64), 0, st>>>(a, gtab);
+    for (int g = 0; g < ngroups; ++g) k_set_group<<<dim3(1), dim3(64), 0, st>>>(gs[g], gtab + g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (n) {
 #define PR_QCASE(NN) \
   case NN:                                                                            \
-    e = f32 ? queue_launch<NN, float>(gtab, a.ngroups, a.total, qc, st)                 \
-            : queue_launch<NN, double>(gtab, a.ngroups, a.total, qc, st);              \
+    e = f32 ? queue_launch<NN, float>(gtab, ngroups, tot, qc, st)                       \
+            : queue_launch<NN, double>(gtab, ngroups, tot, qc, st);                    \
     break;
       PR_QCASE(64) PR_QCASE(128) PR_QCASE(256) PR_QCASE(512) PR_QCASE(1024)
 #undef PR_QCASE
