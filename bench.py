@@ -69,13 +69,28 @@ def bytes_per_point_step(prec: str, scheme: str = "ssi", picard: int = 1) -> int
     return 4 * w
 
 
-def kernel_src_hash() -> str:
+def kernel_src_hash(files=("fine_kernels.hip", "fft_lds.h", "internal.h")) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("fine_kernels.hip", "fft_lds.h", "internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2510_07672_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def network_traffic(cfg_name):
+    """HBM bytes of one network call (every kernel of the call: weight
+    packing, hidden layers, gather) from the committed FETCH_SIZE /
+    WRITE_SIZE summary of the workload's network, scaled by a plain copy;
+    None if the network kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"coarse_cnn_{cfg_name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("src_hash") != kernel_src_hash(("cnn_kernels.hip", "internal.h")):
+        return None
+    return d["bytes_per_call"]
 
 
 def measured_traffic(cfg_name, prec, n, nfields):
@@ -247,7 +262,7 @@ def c5_jobs(api, torch, synth, f32_iters, fine_prec="f64", g_prec="f64"):
     return jobs
 
 
-def uneven_bench(args):
+def uneven_bench(args, reps=None, queue_compare=True):
     """The 48-solve uneven batch (c5) through pr_solve_many, FP64 plain
     form against the mixed form (FP32-then-FP64 fine schedule), each run
     until every job's sup-norm update is <= 5e-7, then checked against each
@@ -265,7 +280,9 @@ def uneven_bench(args):
         t_ser += time.perf_counter() - t0
     pts = sum(j.n_slices * j.problem.steps * j.problem.n ** 2 for j in ref_jobs)
 
-    def run(f32_iters, g_prec, reps):
+    outs = {}
+
+    def run(f32_iters, g_prec, reps, key=None):
         best, res = None, None
         for _ in range(reps):
             jobs = c5_jobs(api, torch, synth, f32_iters, g_prec=g_prec)
@@ -276,6 +293,8 @@ def uneven_bench(args):
             dt = time.perf_counter() - t0
             if best is None or dt < best:
                 best, res = dt, out
+        if key is not None:
+            outs[key] = [U for U, _ in res]
         errs = [float(torch.linalg.vector_norm(U - r) / torch.linalg.vector_norm(r))
                 for (U, _), r in zip(res, refs)]
         iters = [int(st.iterations) for _, st in res]
@@ -291,11 +310,25 @@ def uneven_bench(args):
                 "fine_gpts_per_s": round(fine_pts / best / 1e9, 1),
                 "fine_ms": round(longest.fine_ms, 1), "sweep_ms": round(longest.sweep_ms, 1)}
     note(f"serial FP64 of 48 jobs: {t_ser * 1e3:.0f} ms")
-    plain = run(0, "f64", args.steps)
+    reps = args.steps if reps is None else reps
+    plain = run(0, "f64", reps, key="pp")
     note(f"plain FP64 form: {plain['ms']} ms")
+    queue = None
+    if queue_compare:
+        # the same solves with the fine sweep of each iteration as one
+        # persistent work-queue launch per (N, precision) class
+        was = api.pr_get_fine_queue()
+        api.pr_set_fine_queue(1)
+        try:
+            queue = run(0, "f64", reps, key="q")
+        finally:
+            api.pr_set_fine_queue(was)
+        queue["bitwise_equal_to_per_pass"] = all(
+            bool(torch.equal(a, b)) for a, b in zip(outs["pp"], outs["q"]))
+        note(f"plain FP64 form, work queue: {queue['ms']} ms")
     # G stays FP64: an FP32 coarse step puts ~1e-7 of rounding noise into
     # G(U^k) - G(U^{k-1}), which keeps the sup-norm update from settling
-    mixed = {f"f32_iters_{K}": run(K, "f64", args.steps) for K in (1, 2)}
+    mixed = {f"f32_iters_{K}": run(K, "f64", reps) for K in (1, 2)}
     best_k = min(mixed, key=lambda k: mixed[k]["ms"] if mixed[k]["jobs_within_1e-6"] == 48 else 1e12)
     best = mixed[best_k]
     return {"metric": "uneven batched Parareal: speedup of the mixed-precision form over the "
@@ -308,6 +341,7 @@ def uneven_bench(args):
                                    "steps per slice, numerical G; all in one pr_solve_many"},
             "fine_point_steps_serial": pts, "serial_fp64_ms": round(t_ser * 1e3, 1),
             "plain_fp64": plain, "mixed": mixed, "best_mixed": best_k,
+            "plain_fp64_work_queue": queue,
             "speedup_vs_serial_fp64": round(t_ser * 1e3 / best["ms"], 3)}
 
 
@@ -460,7 +494,10 @@ def cnn_kernel_rate(api, p, g, u0, reps=20):
             "flops_per_px": 2 * 9 * (C + C * C * (L - 2) + C),
             "model_tflops": round(model_flops / ms / 1e9, 1), "peak_tflops": peak,
             "mfma_frac": round(model_flops / ms / 1e9 / peak, 4),
-            "issued_mfma_tflops": round(issued / ms / 1e9, 1)}
+            "issued_mfma_tflops": round(issued / ms / 1e9, 1),
+            "algorithmic_bytes_per_call": network_bytes(B, n, L, C, g.prec),
+            "algorithmic_GB_per_s": round(network_bytes(B, n, L, C, g.prec) / ms / 1e6, 1),
+            "hbm_frac": round(network_bytes(B, n, L, C, g.prec) / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
 def dram_traffic(cfg_name, prec, n, nfields):
@@ -512,6 +549,32 @@ def fine_rate(api, p, u0, steps, working_set=None):
     gbs = u0.shape[0] * p.n * p.n * steps * bpp / (ms * 1e-3) / 1e9
     return {"fields": u0.shape[0], "steps": steps, "ms": round(ms, 3), "GB/s": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def network_bytes(B, n, L, C, prec):
+    """HBM bytes one call of the folded network plan moves at least: the
+    first hidden layer reads the FP64 state and writes its activations,
+    each further hidden layer reads and writes activations (hi + lo
+    bfloat16 in the split form), the last hidden layer writes nine FP32
+    per-tap products instead, and the gather reads those and the state and
+    writes G(u) in FP64 (halo re-reads not counted)."""
+    px = B * n * n
+    act = C * (4 if prec == "bf16x2" else 2)
+    return px * (8 + act + 2 * act * (L - 4) + act + 36 + 36 + 8 + 8)
+
+
+def network_only(args, api, torch, synth):
+    """The workload's network G alone: per-call time, model flop rate and
+    the folded plan's algorithmic HBM rate."""
+    cfg = CONFIGS[args.config]
+    n, B = cfg["n"], cfg["ics"]
+    p = api.Problem(n=n, length=1.0, eps=cfg["eps"], conservative=cfg["conservative"], stab=2.0,
+                    dt=cfg["dt"], steps=cfg["steps"])
+    g, _ = trained_cnn(api, p, cfg, args.cnn_prec, 0)
+    u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
+    ck = cnn_kernel_rate(api, p, g, u0, reps=10 * args.steps)
+    ck["workload"] = cfg["workload"]
+    return ck
 
 
 def run_config(args, cname, api, torch, synth, full=True):
@@ -622,11 +685,22 @@ def run_config(args, cname, api, torch, synth, full=True):
         # one network call per slice in the initial sweep and one in the
         # correction sweep of the iteration
         coarse_ms = 2 * s * ck["ms_per_call"]
-        roof_coarse = {"bound": "mfma", "achieved": ck["model_tflops"], "peak": ck["peak_tflops"],
-                       "unit": "TFLOP/s", "frac": ck["mfma_frac"], "traffic": None,
+        # the network's arithmetic intensity (model flops over the folded
+        # plan's HBM bytes, ~130 flop/B at 6 x 48 split) is below the bf16
+        # ridge point (2500 TFLOP/s / 8 TB/s = 312 flop/B): its roofline is
+        # HBM; the matrix-core rate is reported beside it
+        nt = network_traffic(cname)
+        roof_coarse = {"bound": "hbm", "achieved": ck["algorithmic_GB_per_s"], "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": ck["hbm_frac"],
+                       "traffic": None if nt is None else round(nt),
+                       "traffic_unit": "bytes per call, FETCH_SIZE + WRITE_SIZE scaled by a plain copy",
+                       "algorithmic_bytes_per_call": ck["algorithmic_bytes_per_call"],
                        "kernel": f"network G call ({g.n_layers} conv x {g.channels} ch, {g.prec}) "
                                  f"on {B} fields, per call",
-                       "flops_per_call": ck["flops_per_px"] * B * n * n,
+                       "mfma": {"achieved": ck["model_tflops"], "peak": ck["peak_tflops"],
+                                "unit": "TFLOP/s", "frac": ck["mfma_frac"],
+                                "flops_per_call": ck["flops_per_px"] * B * n * n,
+                                "issued_tflops": ck["issued_mfma_tflops"]},
                        "ms_per_call": ck["ms_per_call"], "calls_per_step": 2 * s,
                        "ms_per_step": round(coarse_ms, 2)}
         out["roofline_coarse"] = roof_coarse
@@ -675,7 +749,8 @@ def main():
                     help="fine-batch chunks overlapped with the sequential sweep (1 = none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parareal", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the config-2 section")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 256^2 section (key config2) and the uneven batch (key uneven_batch)")
     ap.add_argument("--no-mall", action="store_true",
                     help="skip the fine-step rates with and without working-set chunking")
     ap.add_argument("--kmax", type=int, default=16)
@@ -708,6 +783,9 @@ def main():
                          "(0 = one chunk, every field through each step in turn)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--network-only", action="store_true",
+                    help="time only the network G of the workload (seed-0 weights, --steps x 10 "
+                         "calls) and print its per-call figures")
     ap.add_argument("--copy-rate", action="store_true",
                     help="only time plain device copies of 256 MiB, 1 GiB and 4 GiB")
     args = ap.parse_args()
@@ -734,6 +812,9 @@ def main():
     if args.config == "c4":
         print(json.dumps(training_bench(args)), flush=True)
         return
+    if args.network_only:
+        print(json.dumps(network_only(args, api, torch, synth)), flush=True)
+        return
     if args.config == "c5":
         print(json.dumps(uneven_bench(args)), flush=True)
         return
@@ -749,9 +830,15 @@ def main():
     out.update(res)
     if args.config == "c3" and not args.no_extra:
         torch.cuda.empty_cache()
-        note("config 2 section")
+        note("256^2 section")
         c2 = run_config(args, "c2", api, torch, synth, full=False)
         out["config2"] = c2
+        torch.cuda.empty_cache()
+        note("uneven batch section")
+        ub = uneven_bench(args, reps=2)
+        out["uneven_batch"] = {k: ub[k] for k in (
+            "metric", "value", "unit", "config", "serial_fp64_ms", "plain_fp64", "mixed",
+            "best_mixed", "plain_fp64_work_queue", "speedup_vs_serial_fp64")}
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

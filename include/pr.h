@@ -476,7 +476,11 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
  * other XCDs, which then publish device-wide).  Process-wide, default off:
  * on MI355X it stays slower than the replayed per-pass launches at every
  * size measured (512^2, 128 fields, 100 steps: 1.3x; 256^2, 128 fields,
- * 200 steps: 1.1x; a single field: 2.6x). */
+ * 200 steps: 1.1x; a single field: 2.6x).  on: 0 off, 1 on, 2 on with
+ * every queue adopted (the device-wide hand-over alone, which a placement
+ * of blocks that leaves an XCD without any would fall back to; for tests).
+ * Other values: PR_ERR_INVALID_ARG.  pr_get_fine_queue returns the
+ * setting. */
 pr_status pr_set_fine_queue(int32_t on);
 int32_t pr_get_fine_queue(void);
 

@@ -394,14 +394,15 @@ def pr_get_fine_working_set(n: int, prec: str) -> int:
     return int(L.lib().pr_get_fine_working_set(n, _PREC[prec]))
 
 
-def pr_set_fine_queue(on: bool) -> None:
+def pr_set_fine_queue(on) -> None:
     """Run the semi-implicit fine solves as one persistent work-queue launch
-    per (N, precision) class (True) or pass by pass (False, default)."""
-    L.check(L.lib().pr_set_fine_queue(int(bool(on))), "pr_set_fine_queue")
+    per (N, precision) class (True / 1) or pass by pass (False / 0, default);
+    2: the queue with every XCD queue adopted (device-wide hand-over only)."""
+    L.check(L.lib().pr_set_fine_queue(int(on)), "pr_set_fine_queue")
 
 
-def pr_get_fine_queue() -> bool:
-    return bool(L.lib().pr_get_fine_queue())
+def pr_get_fine_queue() -> int:
+    return int(L.lib().pr_get_fine_queue())
 
 
 def pr_set_overlap(chunks: int) -> None:

@@ -1160,12 +1160,12 @@ pr_status pr_fine_propagate_noalloc(const pr_problem* p, int64_t nfields, const 
 }
 
 pr_status pr_set_fine_queue(int32_t on) {
-  if (on != 0 && on != 1) return fail(PR_ERR_INVALID_ARG, "pr_set_fine_queue: on must be 0 or 1");
-  set_fine_queue(on != 0);
+  if (on < 0 || on > 2) return fail(PR_ERR_INVALID_ARG, "pr_set_fine_queue: on must be 0, 1 or 2");
+  set_fine_queue(on);
   return PR_OK;
 }
 
-int32_t pr_get_fine_queue(void) { return fine_queue_enabled() ? 1 : 0; }
+int32_t pr_get_fine_queue(void) { return fine_queue_mode(); }
 
 size_t pr_coarse_workspace_bytes(const pr_problem* p, const pr_coarse* g, int64_t nfields) {
   if (check_problem(p) != PR_OK || check_coarse(g, p->n) != PR_OK || nfields < 0) return 0;

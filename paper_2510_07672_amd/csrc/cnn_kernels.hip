@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 #include <utility>
 
 #include "internal.h"
@@ -40,9 +41,43 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
+// GELU(x) = x/2 (1 + erf(x / sqrt 2)) in FP32 without branches.  With
+// z = |x| / sqrt 2 and E = erfc(z), 1 + erf(x / sqrt 2) is 2 - E for x >= 0
+// and E for x < 0.  E comes from the Chebyshev-fitted form
+// erfc(z) = t exp(-z^2 + P(t)), t = 1 / (1 + z / 2), P of degree 9, whose
+// fractional error is below 1.2e-7 for every z >= 0 (Press et al.,
+// Numerical Recipes, 2nd ed., Section 6.2): one reciprocal, one exp2 and
+// eleven FMAs, where the library's erff evaluates two branches across a
+// wave.  Relative error of the result: a few FP32 ulps where the factor
+// 1 + erf is not small, and ~1e-6 of a value that is already below 1e-5
+// of x where it is (x < -5).
+__device__ __forceinline__ float gelu_f32(float x) {
+  const float z = fabsf(x) * 0.70710678118654752440f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
+  float p = 0.17087277f;
+  p = fmaf(p, t, -0.82215223f);
+  p = fmaf(p, t, 1.48851587f);
+  p = fmaf(p, t, -1.13520398f);
+  p = fmaf(p, t, 0.27886807f);
+  p = fmaf(p, t, -0.18628806f);
+  p = fmaf(p, t, 0.09678418f);
+  p = fmaf(p, t, 0.37409196f);
+  p = fmaf(p, t, 1.00002368f);
+  p = fmaf(p, t, -1.26551223f);
+  const float e = t * __builtin_amdgcn_exp2f(fmaf(-z, z, p) * 1.44269504088896340736f);
+  return 0.5f * x * (x >= 0.f ? 2.f - e : e);
+}
+
 __device__ __forceinline__ float act_fn(float x, int act) {
   if (act == kActTanh) return tanhf(x);
-  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752440f));  // exact GELU
+  return gelu_f32(x);
+}
+
+// The activation chosen at compile time (TANH: tanh, else GELU), for loops
+// that branch once on the activation instead of once per value.
+template <bool TANH> __device__ __forceinline__ float act_sel(float x) {
+  if constexpr (TANH) return tanhf(x);
+  else return gelu_f32(x);
 }
 
 template <typename T> __device__ __forceinline__ float to_f(T v) { return (float)v; }
@@ -275,13 +310,6 @@ struct FirstIn {
   const float* b;         // [C]
 };
 
-// Whether a hidden layer overlaps one 16-pixel block's epilogue with the
-// next block's matrix work (two sets of accumulators live).  Measured: at
-// C = 32 split (3 work-groups per CU by LDS) the extra registers cost no
-// occupancy and the layer gains ~6%; unsplit C = 32 (4 -> 2 waves per
-// SIMD) and C = 48 (2 -> 1) lose more than they gain.
-template <int C, bool SPLIT> constexpr bool hidden_pipelined() { return SPLIT && C == 32; }
-
 // A hidden layer C -> C, persistent over (TH x TW) output tiles.
 //
 // With FIRST the layer's input tile is not read from HBM: the work-group
@@ -351,67 +379,55 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
   if constexpr (TAIL && kTailRegs) last_weights<C>(WL, lane, lwhi, lwlo);
   const int64_t yplane = nfields * (int64_t)n * n;
 
-  // input tile t: chunk i (pixel i / (C/8) of the (TH+2) x (TW+2) region,
-  // channels 8 (i % (C/8)) ..) at element gidx(t, i) of `in`
-  auto gidx = [&](int64_t t, int i) -> int64_t {
-    const int64_t f = t / (tpy * tpx);
-    const int tt = (int)(t % (tpy * tpx));
-    const int y0 = (tt / tpx) * H::TH, x0 = (tt % tpx) * H::TW;
-    const int p = i / (C / 8), c8 = i % (C / 8);
-    const int ty = p / (H::TW + 2), tx = p % (H::TW + 2);
-    const int gy = (y0 + ty - 1) & (n - 1), gx = (x0 + tx - 1) & (n - 1);
-    return ((f * n + gy) * (int64_t)n + gx) * C + c8 * 8;
-  };
+  // LDS element of 16-byte chunk i of the tile (pixel i / (C/8) of the
+  // (TH+2) x (TW+2) region, channels 8 (i % (C/8)) ..)
   auto lidx = [&](int i) { return (i / (C / 8)) * HT::PS + (i % (C / 8)) * 8; };
   if constexpr (FIRST) {
     for (int i = tid; i < 9 * C; i += H::NT) sw0[i] = fi.W[i];
     for (int i = tid; i < C; i += H::NT) sb0[i] = fi.b[i];
   }
-  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-    const int64_t f = t / (tpy * tpx);
-    const int tt = (int)(t % (tpy * tpx));
-    const int y0 = (tt / tpx) * H::TH, x0 = (tt % tpx) * H::TW;
-    __syncthreads();  // the previous tile is no longer read
-    if constexpr (FIRST) {
-      // state patch: su[sy][sx] = u[y0 + sy - 2][x0 + sx - 2], periodic
-      const double* u = fi.u_base + (fi.u_offs ? fi.u_offs[f] : f * (int64_t)n * n);
-      for (int i = tid; i < HT::UH * HT::UW; i += H::NT) {
-        const int sy = i / HT::UW, sx = i % HT::UW;
-        su[i] = (float)u[(int64_t)((y0 + sy - 2) & (n - 1)) * n + ((x0 + sx - 2) & (n - 1))];
-      }
-      __syncthreads();
-      // tile pixel (ty, tx) is state point (y0 + ty - 1, x0 + tx - 1); its
-      // tap tp reads su[ty + tp / 3][tx + tp % 3].  Item = 8 channels of
-      // one pixel, as in k_cnn_first.
-      for (int item = tid; item < H::TCH; item += H::NT) {
-        const int c8 = item % (C / 8), px = item / (C / 8);
-        const int ty = px / (H::TW + 2), tx = px % (H::TW + 2);
-        float v[9];
-#pragma unroll
-        for (int tp = 0; tp < 9; ++tp) v[tp] = su[(ty + tp / 3) * HT::UW + tx + tp % 3];
-        bf16x8 h, l;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int co = c8 * 8 + j;
-          float s = sb0[co];
-#pragma unroll
-          for (int tp = 0; tp < 9; ++tp) s += sw0[co * 9 + tp] * v[tp];
-          const float r = act_fn(s, act);
-          h[j] = (__bf16)r;
-          l[j] = (__bf16)(r - (float)h[j]);
-        }
-        *(bf16x8*)&tile[lidx(item)] = h;
-        if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(item)] = l;
-      }
-    } else {
-      for (int i = tid; i < H::TCH; i += H::NT) {
-        const int64_t gi = gidx(t, i);
-        *(bf16x8*)&tile[lidx(i)] = *(const bf16x8*)&in[gi];
-        if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(i)] = *(const bf16x8*)&in_lo[gi];
+  // tile tt's decomposition: field, top row, left column
+  auto tile_at = [&](int64_t tt, int64_t& f_, int& y0_, int& x0_) {
+    f_ = tt / (tpy * tpx);
+    const int r_ = (int)(tt % (tpy * tpx));
+    y0_ = (r_ / tpx) * H::TH;
+    x0_ = (r_ % tpx) * H::TW;
+  };
+  // the input tile of tile tt straight from HBM into LDS at dst (16 bytes
+  // per lane, no registers), every load of the tile in flight at once:
+  // lane l of a wave's load at slot base s0 fills slot s0 + l, slot s being
+  // the 16-byte chunk s % SP of tile pixel s / SP (SP = PS / 8 chunks per
+  // pixel: C / 8 hi chunks, with SPLIT C / 8 lo chunks, then the pad, which
+  // no lane loads).  Offsets within a field are 32-bit.
+  auto load_tile = [&](int64_t tt, __bf16* dst) {
+    int64_t f_;
+    int y0_, x0_;
+    tile_at(tt, f_, y0_, x0_);
+    constexpr int SP = HT::PS / 8, NSLOT = H::TPIX * SP, DATA = (SPLIT ? 2 : 1) * (C / 8);
+    const __bf16* hb = in + f_ * (int64_t)n * n * C;
+    const __bf16* lb = SPLIT ? in_lo + f_ * (int64_t)n * n * C : hb;
+    for (int s0 = wave * 64; s0 < NSLOT; s0 += H::NT) {
+      const int sl = s0 + lane;
+      const int pp = sl / SP, j = sl - pp * SP;
+      if (sl < NSLOT && j < DATA) {
+        const bool lo = SPLIT && j >= C / 8;
+        const int c8 = lo ? j - C / 8 : j;
+        const int ty = pp / (H::TW + 2), tx = pp - ty * (H::TW + 2);
+        const int gy = (y0_ + ty - 1) & (n - 1), gx = (x0_ + tx - 1) & (n - 1);
+        const __bf16* src = (lo ? lb : hb) + ((gy * n + gx) * C + c8 * 8);
+        __builtin_amdgcn_global_load_lds((const void*)src,
+                                         (__attribute__((address_space(3))) void*)(dst + s0 * 8),
+                                         16, 0, 0);
       }
     }
-    __syncthreads();
-
+  };
+  // the products, activation and stores of tile t from the input tile tl
+  auto compute_tile = [&](int64_t t, const __bf16* tl) {
+    int64_t f;
+    int y0, x0;
+    tile_at(t, f, y0, x0);
+    const __bf16* tin = tl;              // the input tile
+    const __bf16* tin_lo = tl + HT::LO;  // its lo values (SPLIT)
     // block m's products
     auto mma_block = [&](int m, f32x4* acc) {
       const int mb = wave * H::MBW + m;
@@ -424,13 +440,13 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
         const bool live = k0 < 9 * C;
         const int tap = live ? k0 / C : 0, ci0 = live ? k0 % C : 0;
         const int a_off = ((oy + tap / 3) * (H::TW + 2) + ox0 + r + tap % 3) * HT::PS + ci0;
-        bf16x8 afr = *(const bf16x8*)&tile[a_off];
+        bf16x8 afr = *(const bf16x8*)&tin[a_off];
         if (!live) afr = bf16x8{};
 #pragma unroll
         for (int nb = 0; nb < H::NB; ++nb)
           acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb][nb], afr, acc[nb], 0, 0, 0);
         if constexpr (SPLIT) {
-          bf16x8 alo = *(const bf16x8*)&tile_lo[a_off];
+          bf16x8 alo = *(const bf16x8*)&tin_lo[a_off];
           if (!live) alo = bf16x8{};
 #pragma unroll
           for (int nb = 0; nb < H::NB; ++nb)
@@ -441,7 +457,8 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
     // lane (r, g) holds channels nb 16 + 4 g + i of pixel ox0 + r: bias,
     // activation and hi / lo rounding in registers, 8-byte stores (4
     // consecutive channels) straight to the channels-last output
-    auto epilogue = [&](int m, const f32x4* acc) {
+    auto epilogue_act = [&](int m, const f32x4* acc, auto tanh_tag) {
+      constexpr bool kTanh = decltype(tanh_tag)::value;
       const int mb = wave * H::MBW + m;
       const int oy = mb / (H::TW / 16), ox0 = (mb % (H::TW / 16)) * 16;
       const int64_t pb = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0 + r) * C + 4 * g;
@@ -469,7 +486,7 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
         bf16x4 h, l;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float v = act_fn(z[i], act);
+          const float v = act_sel<kTanh>(z[i]);
           h[i] = (__bf16)v;
           l[i] = (__bf16)(v - (float)h[i]);
         }
@@ -505,29 +522,63 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
           *(f32x4*)&Yp[r * yplane + (f * n + y0 + oy) * (int64_t)n + x0 + ox0 + 4 * g] = y;
       }
     };
-    // (not with TAIL: the folded last layer's operands and the second set
-    // of accumulators exceed the registers of 3 waves per SIMD; bounded to
-    // 3 it spills, and measured 5% slower than unpipelined)
-    if constexpr (hidden_pipelined<C, SPLIT>() && !TAIL) {
-      // software pipeline: block m's matrix work is issued before block
-      // m - 1's epilogue, so the two overlap within the wave
-      f32x4 prev[H::NB];
-#pragma unroll
-      for (int m = 0; m < H::MBW; ++m) {
-        f32x4 acc[H::NB];
-        mma_block(m, acc);
-        if (m > 0) epilogue(m - 1, prev);
-#pragma unroll
-        for (int nb = 0; nb < H::NB; ++nb) prev[nb] = acc[nb];
-      }
-      epilogue(H::MBW - 1, prev);
-    } else {
-      for (int m = 0; m < H::MBW; ++m) {
-        f32x4 acc[H::NB];
-        mma_block(m, acc);
-        epilogue(m, acc);
-      }
+    auto epilogue = [&](int m, const f32x4* acc) {
+      if (act == kActTanh) epilogue_act(m, acc, std::true_type{});
+      else epilogue_act(m, acc, std::false_type{});
+    };
+    for (int m = 0; m < H::MBW; ++m) {
+      f32x4 acc[H::NB];
+      mma_block(m, acc);
+      epilogue(m, acc);
     }
+  };
+  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    int64_t f;
+    int y0, x0;
+    tile_at(t, f, y0, x0);
+    __syncthreads();  // the previous tile is no longer read
+    if constexpr (FIRST) {
+      // state patch: su[sy][sx] = u[y0 + sy - 2][x0 + sx - 2], periodic
+      const double* u = fi.u_base + (fi.u_offs ? fi.u_offs[f] : f * (int64_t)n * n);
+      for (int i = tid; i < HT::UH * HT::UW; i += H::NT) {
+        const int sy = i / HT::UW, sx = i % HT::UW;
+        su[i] = (float)u[(int64_t)((y0 + sy - 2) & (n - 1)) * n + ((x0 + sx - 2) & (n - 1))];
+      }
+      __syncthreads();
+      // tile pixel (ty, tx) is state point (y0 + ty - 1, x0 + tx - 1); its
+      // tap tp reads su[ty + tp / 3][tx + tp % 3].  Item = 8 channels of
+      // one pixel, as in k_cnn_first.
+      auto first_tile = [&](auto tanh_tag) {
+        constexpr bool kTanh = decltype(tanh_tag)::value;
+        for (int item = tid; item < H::TCH; item += H::NT) {
+          const int c8 = item % (C / 8), px = item / (C / 8);
+          const int ty = px / (H::TW + 2), tx = px % (H::TW + 2);
+          float v[9];
+#pragma unroll
+          for (int tp = 0; tp < 9; ++tp) v[tp] = su[(ty + tp / 3) * HT::UW + tx + tp % 3];
+          bf16x8 h, l;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int co = c8 * 8 + j;
+            float s = sb0[co];
+#pragma unroll
+            for (int tp = 0; tp < 9; ++tp) s += sw0[co * 9 + tp] * v[tp];
+            const float r = act_sel<kTanh>(s);
+            h[j] = (__bf16)r;
+            l[j] = (__bf16)(r - (float)h[j]);
+          }
+          *(bf16x8*)&tile[lidx(item)] = h;
+          if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(item)] = l;
+        }
+      };
+      if (act == kActTanh) first_tile(std::true_type{});
+      else first_tile(std::false_type{});
+    } else {
+      load_tile(t, tile);
+      __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed in LDS
+    }
+    __syncthreads();
+    compute_tile(t, tile);
   }
 }
 
@@ -1642,7 +1693,6 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
       const bool first = folded && l == 1, last = tail && l == L - 2;
       const size_t lds = cnn_lds_bytes(C, split, first);
       const int64_t tiles = j.nfields * (n / H::TH) * (n / H::TW);
-      const dim3 bh(H::NT);
       const FirstIn fi{j.in_base, j.in_offs, W, B};
       const float* WL = W + cnn_woff(L - 1, L, C);
       const bf16x8* WLp = (const bf16x8*)((const __bf16*)j.ws.wpack + (int64_t)(L - 2) * C * H::KP);
@@ -1658,6 +1708,7 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
   {                                                                                              \
     static const int cap = hidden_cap<C, SP, FI, TA>();                                          \
     const dim3 gh((unsigned)std::min<int64_t>(tiles, cap));                                      \
+    const dim3 bh(H::NT);                                                                      \
     k_cnn_hidden<C, SP, FI, TA><<<gh, bh, lds, st>>>(ih, il, n, j.nfields, wp, B + cnn_boff(l, C), \
                                                      j.act, oh, ol, zo, fi, WL, WLp, Yp);        \
   }

@@ -1301,19 +1301,21 @@ __device__ __forceinline__ int q_xcd() {
 // if a block of another XCD adopts it (every block that takes its items
 // then publishes device-wide).  Every queue is drained whatever the
 // placement of the blocks: a queue no block of its XCD reaches is adopted
-// by the first block to run out of work.  (Blocks are dealt out to the
+// by the first block to run out of work (local_ok = 0 makes every queue
+// adopted: the device-wide hand-over alone).  (Blocks are dealt out to the
 // XCDs round-robin, but the deal carries on from one launch to the next,
 // so block b is not on XCD b mod 8 in general: the register decides.)
 template <int N, typename T>
 __global__ __launch_bounds__(kQueueThreads) void k_fine_queue(const QGroup* __restrict__ groups,
                                                               int ngroups, QTotals tot,
-                                                              unsigned long long* __restrict__ qc) {
+                                                              unsigned long long* __restrict__ qc,
+                                                              int local_ok) {
   extern __shared__ __align__(16) unsigned char qlds[];
   __shared__ long long sh;
   const int tid = threadIdx.x;
   unsigned long long* mode = qc + 128;
   const int xcd = q_xcd();
-  const int home = xcd < kQueues ? xcd : -1;
+  const int home = local_ok && xcd < kQueues ? xcd : -1;
   const int start = home >= 0 ? home + 1 : (int)(blockIdx.x % kQueues);
   // i = -1: the home queue; then every other queue, to adopt
   for (int i = home >= 0 ? -1 : 0; i < kQueues; ++i) {
@@ -1330,7 +1332,7 @@ __global__ __launch_bounds__(kQueueThreads) void k_fine_queue(const QGroup* __re
       } else {
         m = __hip_atomic_load(&mode[q * 16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // give the blocks of q's own XCD time to claim it first (bounded)
-        for (int w = 0; w < 16 && m == 0; ++w) {
+        for (int w = 0; w < 16 && m == 0 && local_ok; ++w) {
           __builtin_amdgcn_s_sleep(127);
           m = __hip_atomic_load(&mode[q * 16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1350,9 +1352,10 @@ __global__ __launch_bounds__(kQueueThreads) void k_fine_queue(const QGroup* __re
   }
 }
 
-static std::atomic<bool> g_fine_queue{false};
-void set_fine_queue(bool on) { g_fine_queue.store(on); }
-bool fine_queue_enabled() { return g_fine_queue.load(); }
+static std::atomic<int> g_fine_queue{0};   // 0 off, 1 on, 2 on with every queue adopted
+void set_fine_queue(int mode) { g_fine_queue.store(mode); }
+int fine_queue_mode() { return g_fine_queue.load(); }
+bool fine_queue_enabled() { return g_fine_queue.load() != 0; }
 
 static int col_blocks(int n);
 
@@ -1414,7 +1417,7 @@ static hipError_t queue_launch(const QGroup* gtab, int ngroups, const QTotals& t
     hipError_t e = queue_grid<N, T>(&grid);
     if (e != hipSuccess) return e;
     k_fine_queue<N, T><<<dim3((unsigned)grid), dim3(kQueueThreads), QLds<N, T>::BYTES, st>>>(
-        gtab, ngroups, tot, qc);
+        gtab, ngroups, tot, qc, fine_queue_mode() == 2 ? 0 : 1);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;

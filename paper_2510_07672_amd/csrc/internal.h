@@ -213,7 +213,8 @@ hipError_t launch_steps(const StepJob& job, hipStream_t st);
 bool fine_queue_supports(const StepJob& job);
 size_t fine_queue_ws_bytes(int64_t total_fields);
 hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStream_t st);
-void set_fine_queue(bool on);
+void set_fine_queue(int mode);   // 0 off, 1 on, 2 on with no XCD-local hand-over
+int fine_queue_mode();
 bool fine_queue_enabled();
 // Working-set budget of streaming F calls (bytes of spectra in flight; 0 =
 // all fields at once): the process-wide setting, the effective value for

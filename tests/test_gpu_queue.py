@@ -24,10 +24,10 @@ def api():
     A.pr_set_fine_working_set(256 << 20)
 
 
-def both(api, fn):
-    api.pr_set_fine_queue(False)
+def both(api, fn, mode=1):
+    api.pr_set_fine_queue(0)
     a = fn()
-    api.pr_set_fine_queue(True)
+    api.pr_set_fine_queue(mode)
     try:
         b = fn()
     finally:
@@ -49,6 +49,21 @@ def test_queue_fine_matches_per_pass(api, n, prec, nf, cons):
         a, b = both(api, lambda: api.pr_fine_propagate(p, u0))
     finally:
         api.pr_set_fine_plan(n, prec, "auto")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n,prec,nf,cons", [(64, "f32", 5, True), (256, "f64", 9, True),
+                                            (512, "f64", 3, False)])
+def test_queue_adopted_matches_per_pass(api, n, prec, nf, cons):
+    """Every XCD queue adopted (mode 2): the items of a queue run on blocks
+    of any XCD, which hand results over with device-wide releases; the
+    fallback for a placement of blocks that leaves an XCD without any."""
+    print(f"case queue F adopted n={n} {prec} fields={nf} conservative={cons}", flush=True)
+    p = api.Problem(n=n, length=1.0, eps=0.01, conservative=cons, stab=2.0, dt=2e-5, steps=6,
+                    fine_prec=prec)
+    u0 = torch.from_numpy(synth.random_ic(n, range(20, 20 + nf))).cuda()
+    a, b = both(api, lambda: api.pr_fine_propagate(p, u0), mode=2)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
 
@@ -88,10 +103,10 @@ def uneven_jobs(api, f32_iters):
     return jobs
 
 
-@pytest.mark.parametrize("f32_iters", [0, 1])
-def test_queue_solve_many_matches_per_pass(api, f32_iters):
-    print(f"case queue pr_solve_many 6 jobs f32_iters={f32_iters}", flush=True)
-    a, b = both(api, lambda: api.pr_solve_many(uneven_jobs(api, f32_iters)))
+@pytest.mark.parametrize("f32_iters,mode", [(0, 1), (1, 1), (1, 2)])
+def test_queue_solve_many_matches_per_pass(api, f32_iters, mode):
+    print(f"case queue pr_solve_many 6 jobs f32_iters={f32_iters} mode={mode}", flush=True)
+    a, b = both(api, lambda: api.pr_solve_many(uneven_jobs(api, f32_iters)), mode=mode)
     for (Ua, sa), (Ub, sb) in zip(a, b):
         assert torch.equal(Ua, Ub)
         assert sa.iterations == sb.iterations
@@ -99,9 +114,9 @@ def test_queue_solve_many_matches_per_pass(api, f32_iters):
 
 
 def test_queue_parareal_matches_oracle(api):
-    """Config-1 Parareal (64^2, 8 slices, numerical G) through the queue
+    """Parareal on 64^2 with 8 slices and the numerical G through the queue
     against the oracle's Algorithm 2: same iterations, rel-L2 <= 1e-12."""
-    print("case queue Parareal config 1", flush=True)
+    print("case queue Parareal 64^2 x 8 slices", flush=True)
     n, s = 64, 8
     p = api.Problem(n=n, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4, steps=100)
     po = ac.Problem(n=n, length=1.0, eps=0.02, conservative=False, stab=2.0, dt=1e-4, steps=100)

@@ -245,6 +245,9 @@ def test_scheme_loss_validation(L):
 def test_fine_queue_setting(L):
     lib = L.lib()
     assert lib.pr_get_fine_queue() == 0
-    assert lib.pr_set_fine_queue(2) == L.PR_ERR_INVALID_ARG
+    assert lib.pr_set_fine_queue(3) == L.PR_ERR_INVALID_ARG
+    assert lib.pr_set_fine_queue(-1) == L.PR_ERR_INVALID_ARG
+    assert lib.pr_get_fine_queue() == 0
+    assert lib.pr_set_fine_queue(2) == L.PR_OK and lib.pr_get_fine_queue() == 2
     assert lib.pr_set_fine_queue(1) == L.PR_OK and lib.pr_get_fine_queue() == 1
     assert lib.pr_set_fine_queue(0) == L.PR_OK and lib.pr_get_fine_queue() == 0
