@@ -551,6 +551,55 @@ def fine_rate(api, p, u0, steps, working_set=None):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def fp32_fine_section(api, torch, p, g, u0, s, k=6, steps=3):
+    """The workload with the FP32 fine step the workload text names: the
+    timed Parareal iteration with FP32 fine solves (16 B per point and
+    step), and what an FP32 fine state does to the accuracy: the serial
+    FP32 fine solve and Parareal with FP32 F after k iterations, each
+    against the FP64 serial fine solve, worst slice over the ICs."""
+    import dataclasses
+    p32 = dataclasses.replace(p, fine_prec="f32", f32_iters=0)
+    p64 = dataclasses.replace(p, fine_prec="f64", f32_iters=0)
+    B, n, c = u0.shape[0], p.n, p.steps
+    U = torch.empty((B, s + 1, n, n), dtype=torch.float64, device="cuda")
+
+    def one(max_iter):
+        return api.pr_solve(p32, g, u0, s, tol=0.0, max_iter=max_iter, U=U, allow_not_converged=True)
+    one(1)
+    torch.cuda.synchronize()
+    fine = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = one(1)
+        fine.append(st.fine_ms)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    pts = B * s * c * n * n
+    fine_ms = float(np.mean(fine))
+    ref = api.pr_serial_fine(p64, u0, s)
+    ref_slice = torch.linalg.vector_norm(ref, dim=(-2, -1))
+
+    def worst(V):
+        return float((torch.linalg.vector_norm(V - ref, dim=(-2, -1)) / ref_slice).max())
+    ser32 = worst(api.pr_serial_fine(p32, u0, s))
+    one(k)
+    par32 = worst(U)
+    del U, ref
+    gbs = pts * 16 / (fine_ms * 1e-3) / 1e9
+    note(f"FP32 fine step: {ms:.1f} ms per iteration, fine sweep {gbs:.1f} GB/s; serial FP32 "
+         f"{ser32:.2e}, Parareal k={k} {par32:.2e} from the FP64 serial solve (worst slice)")
+    return {"value": round(pts / (ms * 1e-3) / 1e9, 2), "unit": "Gpts/s", "ms_per_step": round(ms, 3),
+            "fine_prec": "f32", "fine_sweep_ms": round(fine_ms, 3),
+            "fine_GB_per_s": round(gbs, 1), "fine_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_point_step": 16,
+            "serial_fp32_worst_slice_rel_l2": float(f"{ser32:.3e}"),
+            f"parareal_k{k}_worst_slice_rel_l2": float(f"{par32:.3e}"),
+            "note": "an FP32 fine state drifts from the FP64 serial fine solve by the FP32 "
+                    "transforms' rounding, step after step: neither the serial FP32 solve nor "
+                    "Parareal with FP32 F meets rel-L2 1e-6; the precision schedule (FP32 first "
+                    "iterations, then FP64) does, see parareal_schedule"}
+
+
 def network_bytes(B, n, L, C, prec):
     """HBM bytes one call of the folded network plan moves at least: the
     first hidden layer reads the FP64 state and writes its activations,
@@ -729,6 +778,8 @@ def run_config(args, cname, api, torch, synth, full=True):
             out["parareal_numerical_coarse"] = parareal_vs_serial(api, p, g_num, u0, s, args.kmax)
     if not args.no_cpu and full:
         out["cpu_baseline"] = cpu_baseline(cfg, args.prec)
+    if full and args.prec == "f64" and not args.no_extra:
+        out["fp32_fine"] = fp32_fine_section(api, torch, p, g, u0, s)
     return out
 
 

@@ -195,9 +195,9 @@ __global__ __launch_bounds__(256) void k_cnn_first(const double* __restrict__ u_
 
 // ----------------------------------------------------------- hidden layers
 
-template <int C> struct HidCfg {
+template <int C, int NWAVES = 4> struct HidCfg {
   static constexpr int TH = 8, TW = 32;              // output tile (rows, columns)
-  static constexpr int NW = 4, NT = 64 * NW;         // waves, threads
+  static constexpr int NW = NWAVES, NT = 64 * NW;    // waves, threads
   static constexpr int CS = C + 8;                   // LDS pixel stride (elements), one plane
   static constexpr int KP = (9 * C + 31) / 32 * 32;  // K padded to the MFMA depth
   static constexpr int MB = TH * TW / 16;            // 16-pixel blocks per tile
@@ -226,10 +226,14 @@ template <int C, bool SPLIT> struct HidTile {
 };
 
 // Tuning knobs (compile time): whether the last layer folds into the last
-// hidden layer at 48 channels, and the waves per SIMD the 48-channel hidden
-// layer's registers are bounded to.
+// hidden layer at 48 channels, the waves per SIMD the 48-channel hidden
+// layer's registers are bounded to, and whether the 48-channel layers other
+// than the folded last one split their output channels over waves.
 #ifndef PR_TAIL48
 #define PR_TAIL48 1
+#endif
+#ifndef PR_HID48_NBW
+#define PR_HID48_NBW 0
 #endif
 #ifndef PR_HID48_WAVES
 #define PR_HID48_WAVES 2
@@ -327,15 +331,37 @@ struct FirstIn {
 // output channels 8 g .. 8 g + 7 of its pixel: those registers are then
 // the 16x16x32 A fragment that k_cnn_last_mma loads for the pixel, and the
 // same three products in the same order give Y bit for bit.
+// Whether a hidden layer splits its output channels over waves: wave w then
+// computes output-channel block w % NB (16 channels) of pixel group w / NB
+// and holds only that block's weight fragments (KB x 4 registers instead of
+// KB x NB x 4), so more waves share a SIMD, while each input fragment is
+// read from LDS by NB waves instead of one.  Six waves per work-group at
+// 48 channels (2 pixel groups of 8 blocks), 3 waves per SIMD.  Not with
+// TAIL, whose folded last layer needs all of a pixel's channels in one wave.
+// Off: measured slower (6 x 48 split network on 16 fields of 512^2: 2.37 ->
+// 2.95 ms per call), the tripled LDS reads of the input fragments costing
+// more than the third wave per SIMD gains.
+template <int C, bool TAIL> constexpr bool hidden_nbw() { return PR_HID48_NBW && C == 48 && !TAIL; }
+template <int C, bool TAIL> constexpr int hidden_waves() { return hidden_nbw<C, TAIL>() ? 6 : 4; }
+
 template <int C, bool SPLIT, bool FIRST = false, bool TAIL = false>
-__global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C == 48 ? PR_HID48_WAVES : 1))) void k_cnn_hidden(
+__global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribute__((amdgpu_waves_per_eu(C == 48 ? (hidden_nbw<C, TAIL>() ? 3 : PR_HID48_WAVES) : 1))) void k_cnn_hidden(
     const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
     const __bf16* __restrict__ Wp, const float* __restrict__ b, int act,
     __bf16* __restrict__ out, __bf16* __restrict__ out_lo, float* __restrict__ zout,
     FirstIn fi, const float* __restrict__ WL, const bf16x8* __restrict__ WLp,
     float* __restrict__ Yp) {
-  using H = HidCfg<C>;
+  using H = HidCfg<C, hidden_waves<C, TAIL>()>;
   static_assert(C % 16 == 0, "hidden width must be a multiple of 16");
+  constexpr bool kNBW = hidden_nbw<C, TAIL>();
+  constexpr int NBL = kNBW ? 1 : H::NB;              // channel blocks per wave
+  constexpr int PG = kNBW ? H::NW / H::NB : H::NW;   // pixel groups
+  static_assert(!kNBW || PG * H::NB == H::NW, "waves must cover the channel blocks");
+  constexpr int MBW = H::MB / PG;                    // 16-pixel blocks per wave and tile
+  // blocks whose products one pass over K computes together: 4 with one
+  // channel block per wave, so consecutive MFMAs do not depend on each other
+  constexpr int NBLK = kNBW ? 4 : 1;
+  static_assert(MBW % NBLK == 0, "blocks per wave");
   static_assert(!TAIL || C == 32 || C == 48,
                 "the last layer folds into a hidden layer of 32 or 48 channels");
   extern __shared__ __align__(16) unsigned char smem[];
@@ -350,25 +376,29 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
   const int r = lane & 15, g = lane >> 4;
   const int tpy = n / H::TH, tpx = n / H::TW;
   const int64_t tiles = nfields * tpy * tpx;
+  const int wpg = kNBW ? wave / H::NB : wave;         // the wave's pixel group
+  // channel block of the wave's j-th set of fragments
+  auto nbof = [&](int j) { return kNBW ? wave % H::NB : j; };
 
   // this lane's weight fragments and biases, for the whole kernel; och is
   // the output channel of row m of channel block nb
   auto och = [](int nb, int m) { return TAIL ? (C / 4) * (m / 4) + 4 * nb + m % 4 : nb * 16 + m; };
-  bf16x8 bfr[H::KB][H::NB];
+  bf16x8 bfr[H::KB][NBL];
   // biases of channels och(nb, 4 g + i), consecutive in i: in registers for
   // the whole kernel, or at C = 48 read per 16-pixel block (16-byte loads),
   // which leaves the registers the folded last layer needs at 2 waves per SIMD
   constexpr bool kBiasRegs = C != 48;
-  float bias[H::NB][4];
+  float bias[NBL][4];
 #pragma unroll
-  for (int nb = 0; nb < H::NB; ++nb) {
+  for (int j = 0; j < NBL; ++j) {
+    const int nb = nbof(j);
     if constexpr (kBiasRegs) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) bias[nb][i] = b[och(nb, 4 * g + i)];
+      for (int i = 0; i < 4; ++i) bias[j][i] = b[och(nb, 4 * g + i)];
     }
 #pragma unroll
     for (int kb = 0; kb < H::KB; ++kb)
-      bfr[kb][nb] = *(const bf16x8*)&Wp[(int64_t)och(nb, r) * H::KP + kb * 32 + 8 * g];
+      bfr[kb][j] = *(const bf16x8*)&Wp[(int64_t)och(nb, r) * H::KP + kb * 32 + 8 * g];
   }
   constexpr int LKB = LastCfg<C>::KB;
   // TAIL: the last layer's weights, as in k_cnn_last_mma; held in registers
@@ -428,29 +458,44 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
     tile_at(t, f, y0, x0);
     const __bf16* tin = tl;              // the input tile
     const __bf16* tin_lo = tl + HT::LO;  // its lo values (SPLIT)
-    // block m's products
-    auto mma_block = [&](int m, f32x4* acc) {
-      const int mb = wave * H::MBW + m;
-      const int oy = mb / (H::TW / 16), ox0 = (mb % (H::TW / 16)) * 16;
+    // the products of blocks m0 .. m0 + NBLK - 1; every accumulator takes
+    // its hi then its lo product at each K step, in K order
+    auto mma_blocks = [&](int m0, f32x4 (*acc)[NBL]) {
+      int aoff[NBLK];
 #pragma unroll
-      for (int nb = 0; nb < H::NB; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int q = 0; q < NBLK; ++q) {
+        const int mb = wpg * MBW + m0 + q;
+        aoff[q] = ((mb / (H::TW / 16)) * (H::TW + 2) + (mb % (H::TW / 16)) * 16 + r) * HT::PS;
+#pragma unroll
+        for (int j = 0; j < NBL; ++j) acc[q][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
 #pragma unroll
       for (int kb = 0; kb < H::KB; ++kb) {
         const int k0 = kb * 32 + 8 * g;
         const bool live = k0 < 9 * C;
         const int tap = live ? k0 / C : 0, ci0 = live ? k0 % C : 0;
-        const int a_off = ((oy + tap / 3) * (H::TW + 2) + ox0 + r + tap % 3) * HT::PS + ci0;
-        bf16x8 afr = *(const bf16x8*)&tin[a_off];
-        if (!live) afr = bf16x8{};
+        const int kofs = ((tap / 3) * (H::TW + 2) + tap % 3) * HT::PS + ci0;
+        bf16x8 afr[NBLK], alo[NBLK];
 #pragma unroll
-        for (int nb = 0; nb < H::NB; ++nb)
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb][nb], afr, acc[nb], 0, 0, 0);
+        for (int q = 0; q < NBLK; ++q) {
+          afr[q] = *(const bf16x8*)&tin[aoff[q] + kofs];
+          if (!live) afr[q] = bf16x8{};
+          if constexpr (SPLIT) {
+            alo[q] = *(const bf16x8*)&tin_lo[aoff[q] + kofs];
+            if (!live) alo[q] = bf16x8{};
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q)
+#pragma unroll
+          for (int j = 0; j < NBL; ++j)
+            acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb][j], afr[q], acc[q][j], 0, 0, 0);
         if constexpr (SPLIT) {
-          bf16x8 alo = *(const bf16x8*)&tin_lo[a_off];
-          if (!live) alo = bf16x8{};
 #pragma unroll
-          for (int nb = 0; nb < H::NB; ++nb)
-            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb][nb], alo, acc[nb], 0, 0, 0);
+          for (int q = 0; q < NBLK; ++q)
+#pragma unroll
+            for (int j = 0; j < NBL; ++j)
+              acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[kb][j], alo[q], acc[q][j], 0, 0, 0);
         }
       }
     };
@@ -459,7 +504,7 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
     // consecutive channels) straight to the channels-last output
     auto epilogue_act = [&](int m, const f32x4* acc, auto tanh_tag) {
       constexpr bool kTanh = decltype(tanh_tag)::value;
-      const int mb = wave * H::MBW + m;
+      const int mb = wpg * MBW + m;
       const int oy = mb / (H::TW / 16), ox0 = (mb % (H::TW / 16)) * 16;
       const int64_t pb = ((f * n + y0 + oy) * (int64_t)n + x0 + ox0 + r) * C + 4 * g;
       // TAIL: the lane's channels (C/4) g + q of pixel ox0 + r, q = 4 nb + i,
@@ -470,17 +515,18 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
       bf16x8 xh = bf16x8{}, xl = bf16x8{};
       f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int nb = 0; nb < H::NB; ++nb) {
+      for (int j = 0; j < NBL; ++j) {
+        const int nb = nbof(j);
         float z[4];
         if constexpr (kBiasRegs) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) z[i] = acc[nb][i] + bias[nb][i];
+          for (int i = 0; i < 4; ++i) z[i] = acc[j][i] + bias[j][i];
         } else {
           const float4 bv = *(const float4*)&b[och(nb, 4 * g)];
-          z[0] = acc[nb][0] + bv.x;
-          z[1] = acc[nb][1] + bv.y;
-          z[2] = acc[nb][2] + bv.z;
-          z[3] = acc[nb][3] + bv.w;
+          z[0] = acc[j][0] + bv.x;
+          z[1] = acc[j][1] + bv.y;
+          z[2] = acc[j][2] + bv.z;
+          z[3] = acc[j][3] + bv.w;
         }
         if (zout) *(float4*)&zout[pb + nb * 16] = float4{z[0], z[1], z[2], z[3]};
         bf16x4 h, l;
@@ -526,10 +572,11 @@ __global__ __launch_bounds__(HidCfg<C>::NT) __attribute__((amdgpu_waves_per_eu(C
       if (act == kActTanh) epilogue_act(m, acc, std::true_type{});
       else epilogue_act(m, acc, std::false_type{});
     };
-    for (int m = 0; m < H::MBW; ++m) {
-      f32x4 acc[H::NB];
-      mma_block(m, acc);
-      epilogue(m, acc);
+    for (int m = 0; m < MBW; m += NBLK) {
+      f32x4 acc[NBLK][NBL];
+      mma_blocks(m, acc);
+#pragma unroll
+      for (int q = 0; q < NBLK; ++q) epilogue(m + q, acc[q]);
     }
   };
   for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
@@ -1490,7 +1537,7 @@ static int hidden_cap() {
   if (hipGetDevice(&dev) != hipSuccess) return 512;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cnn_hidden<C, SPLIT, FIRST, TAIL>,
-                                                   HidCfg<C>::NT,
+                                                   HidCfg<C, hidden_waves<C, TAIL>()>::NT,
                                                    cnn_lds_bytes(C, SPLIT, FIRST)) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -1708,7 +1755,7 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
   {                                                                                              \
     static const int cap = hidden_cap<C, SP, FI, TA>();                                          \
     const dim3 gh((unsigned)std::min<int64_t>(tiles, cap));                                      \
-    const dim3 bh(H::NT);                                                                      \
+    const dim3 bh(HidCfg<C, hidden_waves<C, TA>()>::NT);                                       \
     k_cnn_hidden<C, SP, FI, TA><<<gh, bh, lds, st>>>(ih, il, n, j.nfields, wp, B + cnn_boff(l, C), \
                                                      j.act, oh, ol, zo, fi, WL, WLp, Yp);        \
   }
