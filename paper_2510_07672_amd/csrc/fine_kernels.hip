@@ -1305,8 +1305,13 @@ __device__ __forceinline__ int q_xcd() {
 // adopted: the device-wide hand-over alone).  (Blocks are dealt out to the
 // XCDs round-robin, but the deal carries on from one launch to the next,
 // so block b is not on XCD b mod 8 in general: the register decides.)
+// Registers bounded for 3 waves per SIMD (2 at 1024^2): the row and column
+// bodies in one kernel need more registers than either per-pass kernel,
+// and the bound, with a few spilled bytes, measured faster than the
+// occupancy left unbounded (512^2 FP64, 2048 fields, 100 steps: 432 ->
+// 398 ms; bounded to 4 waves it spills more and was slower).
 template <int N, typename T>
-__global__ __launch_bounds__(kQueueThreads) void k_fine_queue(const QGroup* __restrict__ groups,
+__global__ __launch_bounds__(kQueueThreads) __attribute__((amdgpu_waves_per_eu(N >= 1024 ? 2 : 3))) void k_fine_queue(const QGroup* __restrict__ groups,
                                                               int ngroups, QTotals tot,
                                                               unsigned long long* __restrict__ qc,
                                                               int local_ok) {
