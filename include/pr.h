@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 10
+#define PR_ABI_VERSION 11
 
 typedef enum {
   PR_OK = 0,
@@ -454,7 +454,10 @@ int32_t pr_get_fine_plan(int32_t n, pr_dtype prec);
  * available for p->n (u_in read, u_out overwritten with scratch results;
  * workspace as for pr_fine_propagate), records the faster one as the AUTO
  * choice for (p->n, p->fine_prec) and returns it in *chosen (may be NULL).
- * Blocks until the timing runs finish. */
+ * For the streaming plan it also times the working-set budgets and, where
+ * the work queue covers the class, the queue against the per-pass launches
+ * (the faster is recorded; see pr_set_fine_queue).  Blocks until the timing
+ * runs finish. */
 pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u_in,
                            void* u_out, void* ws, size_t ws_bytes, void* stream,
                            int32_t* chosen);
@@ -476,13 +479,20 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
  * other XCDs, which then publish device-wide).  Process-wide, default off:
  * on MI355X it stays slower than the replayed per-pass launches at every
  * size measured (512^2, 128 fields, 100 steps: 1.3x; 256^2, 128 fields,
- * 200 steps: 1.1x; a single field: 2.6x).  on: 0 off, 1 on, 2 on with
- * every queue adopted (the device-wide hand-over alone, which a placement
- * of blocks that leaves an XCD without any would fall back to; for tests).
- * Other values: PR_ERR_INVALID_ARG.  pr_get_fine_queue returns the
- * setting. */
+ * 200 steps: 1.01x; the 48-solve uneven batch of pr_solve_many: 1.3x; a
+ * single field: 2.6x).  on: 0 pass by pass, except for the (N, precision)
+ * classes for which pr_autotune_fine measured the queue faster; 1 on; 2 on
+ * with every queue adopted (the device-wide hand-over alone, which a
+ * placement of blocks that leaves an XCD without any would fall back to;
+ * for tests).  Other values: PR_ERR_INVALID_ARG.  pr_get_fine_queue returns
+ * the setting. */
 pr_status pr_set_fine_queue(int32_t on);
 int32_t pr_get_fine_queue(void);
+
+/* Whether the semi-implicit fine solves of (n, prec) take the work queue
+ * under the current setting and the autotuner's record: 1 yes, 0 no, -1
+ * for an unsupported (n, prec). */
+int32_t pr_get_fine_queue_choice(int32_t n, pr_dtype prec);
 
 /* A streaming F (or numerical G) call is 2*steps + 1 launches.  With
  * graphs on (the default), that sequence is captured once per (problem,

@@ -31,7 +31,7 @@ EXPORTED = [
     "pr_set_fine_plan", "pr_get_fine_plan", "pr_autotune_fine", "pr_set_graphs", "pr_get_graphs",
     "pr_set_coarse_plan", "pr_get_coarse_plan", "pr_autotune_coarse",
     "pr_set_overlap", "pr_get_overlap", "pr_set_fine_working_set", "pr_get_fine_working_set",
-    "pr_set_fine_queue", "pr_get_fine_queue",
+    "pr_set_fine_queue", "pr_get_fine_queue", "pr_get_fine_queue_choice",
     "pr_status_string", "pr_last_error", "pr_abi_version",
 ]
 PR_PLAN_AUTO, PR_PLAN_STREAM, PR_PLAN_RESIDENT = 0, 1, 2
@@ -109,6 +109,7 @@ def lib() -> C.CDLL:
             "pr_get_overlap": (i32, []),
             "pr_set_fine_queue": (C.c_int, [i32]),
             "pr_get_fine_queue": (i32, []),
+            "pr_get_fine_queue_choice": (i32, [i32, i32]),
             "pr_get_coarse_plan": (i32, [G, i32]),
             "pr_autotune_coarse": (C.c_int, [P, G, i64, vp, vp, vp, sz, vp, C.POINTER(i32)]),
             "pr_get_graphs": (i32, []),

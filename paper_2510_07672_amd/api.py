@@ -344,7 +344,8 @@ def pr_get_fine_plan(n: int, prec: str) -> str:
 
 
 def pr_autotune_fine(p: Problem, u_in: torch.Tensor) -> str:
-    """Time both plans on u_in and keep the faster as the 'auto' choice."""
+    """Time both plans on u_in and keep the faster as the 'auto' choice (and,
+    for the streaming plan, the working-set budget and queue vs per-pass)."""
     B = _fields(u_in, p.n, "u_in")
     pc = p.c()
     out = torch.empty_like(u_in)
@@ -403,6 +404,12 @@ def pr_set_fine_queue(on) -> None:
 
 def pr_get_fine_queue() -> int:
     return int(L.lib().pr_get_fine_queue())
+
+
+def pr_get_fine_queue_choice(n: int, prec: str = "f64") -> int:
+    """1 if the fine solves of (n, prec) take the work queue now, 0 if not,
+    -1 for an unsupported pair."""
+    return int(L.lib().pr_get_fine_queue_choice(int(n), _PREC[prec]))
 
 
 def pr_set_overlap(chunks: int) -> None:

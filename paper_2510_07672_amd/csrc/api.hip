@@ -899,7 +899,7 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
           fj.params = P.params;
           fj.pidx = P.t32 + sg.i32[0];
         }
-        if (fine_queue_enabled() && fine_queue_supports(fj))
+        if (fine_queue_use(fj))
           queued.push_back(fj);
         else
           PR_HIP(launch_steps(fj, sf));
@@ -1094,7 +1094,7 @@ static pr_status fine_propagate(const pr_problem* p, int64_t nfields, const doub
   j.out_f32 = out_dtype == PR_F32;
   j.eager = eager;
   PR_HIP(launch_tables(p->n, p->laplacian, w, s));
-  if (fine_queue_enabled() && fine_queue_supports(j))
+  if (fine_queue_use(j))
     PR_HIP(launch_fine_queue(&j, 1, w.queue, s));
   else
     PR_HIP(launch_steps(j, s));
@@ -1166,6 +1166,16 @@ pr_status pr_set_fine_queue(int32_t on) {
 }
 
 int32_t pr_get_fine_queue(void) { return fine_queue_mode(); }
+
+int32_t pr_get_fine_queue_choice(int32_t n, pr_dtype prec) {
+  if (n < 16 || n > 1024 || (n & (n - 1)) || (prec != PR_F64 && prec != PR_F32)) return -1;
+  StepJob j{};
+  j.scheme = SCHEME_SSI;
+  j.n = n;
+  j.f32 = prec == PR_F32;
+  j.steps = 1;
+  return fine_queue_use(j) ? 1 : 0;
+}
 
 size_t pr_coarse_workspace_bytes(const pr_problem* p, const pr_coarse* g, int64_t nfields) {
   if (check_problem(p) != PR_OK || check_coarse(g, p->n) != PR_OK || nfields < 0) return 0;
@@ -1505,6 +1515,31 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
       }
     }
     record_working_set(p->n, f32, bbest);
+  }
+  // the work queue against the per-pass launches (with the plan and the
+  // working set just recorded), for the classes the queue covers
+  {
+    StepJob j = make_job(p, p->dt, p->steps, f32, nfields, w);
+    j.in_base = u_in;
+    j.out_base = u_out;
+    j.out_f32 = 0;
+    if (fine_queue_supports(j) && !j.resident) {
+      Events ev;
+      if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
+      PR_HIP(launch_tables(p->n, p->laplacian, w, s));
+      float t[2] = {0.f, 0.f};
+      for (int q = 0; q < 2; ++q) {
+        for (int rep = 0; rep < 2; ++rep) {   // warm-up, then timed
+          if (rep == 1) PR_HIP(hipEventRecord(ev.e[0], s));
+          if (q) PR_HIP(launch_fine_queue(&j, 1, w.queue, s));
+          else PR_HIP(launch_steps(j, s));
+        }
+        PR_HIP(hipEventRecord(ev.e[1], s));
+        PR_HIP(hipEventSynchronize(ev.e[1]));
+        t[q] = event_ms(ev.e[0], ev.e[1]);
+      }
+      record_fine_queue(p->n, f32, t[1] < t[0]);
+    }
   }
   if (chosen) *chosen = best;
   return PR_OK;

@@ -1111,16 +1111,20 @@ constexpr int kQueueThreads = 256;
 // and the blocks of the XCD whose index a queue carries take its items.
 constexpr int kQueues = 8;
 
-// Tiles per work item: an item runs this many consecutive tiles of one
-// pass of one field, so that the per-item synchronisation (a release before
-// the field's counter is raised, an acquire after it is read) is paid once
-// per group of tiles.
+// Most tiles per work item: an item runs up to this many consecutive tiles
+// of one pass of one field, so that the per-item synchronisation (a release
+// before the field's counter is raised, an acquire after it is read) is
+// paid once per group of tiles.  A launch halves it (down to 1) while a
+// pass would give a queue fewer items than a quarter of its XCD's blocks
+// (more, smaller items measured slower: with one field per queue every
+// block then polls the same counter).
 #ifndef PR_QUEUE_TILES
 #define PR_QUEUE_TILES 8
 #endif
 
 struct QGroup {
   int n, f32, steps, rt, ct;    // tiles per row / column pass
+  int tpi;                      // tiles per work item
   int rti, cti;                 // work items per row / column pass
   int64_t nfields, chunk, per_field, done0;
   int64_t lo[kQueues + 1];      // queue q takes fields [lo[q], lo[q + 1])
@@ -1254,8 +1258,8 @@ __device__ __forceinline__ void q_drain(unsigned char* qlds, long long* sh, cons
     }
     const unsigned fi = rem / per;
     const int64_t f = f0 + fi;
-    const int t0 = (int)(rem - fi * per) * PR_QUEUE_TILES;
-    const int t1 = t0 + PR_QUEUE_TILES < tiles ? t0 + PR_QUEUE_TILES : tiles;
+    const int t0 = (int)(rem - fi * per) * G.tpi;
+    const int t1 = t0 + G.tpi < tiles ? t0 + G.tpi : tiles;
     // items of this field in phases < p: (p + 1) / 2 row passes, p / 2 column passes
     const unsigned long long need =
         (unsigned long long)((p + 1) / 2) * G.rti + (unsigned long long)(p / 2) * G.cti;
@@ -1362,6 +1366,26 @@ void set_fine_queue(int mode) { g_fine_queue.store(mode); }
 int fine_queue_mode() { return g_fine_queue.load(); }
 bool fine_queue_enabled() { return g_fine_queue.load() != 0; }
 
+// The autotuner's choice per (log2 N, FP32): 0 none, 1 pass by pass, 2 queue.
+static std::atomic<int> g_queue_tuned[11][2];
+static int qlog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+void record_fine_queue(int n, bool f32, bool queue) {
+  const int l = qlog2(n);
+  if (l >= 0 && l <= 10) g_queue_tuned[l][f32 ? 1 : 0].store(queue ? 2 : 1);
+}
+bool fine_queue_tuned(int n, bool f32) {
+  const int l = qlog2(n);
+  return l >= 0 && l <= 10 && g_queue_tuned[l][f32 ? 1 : 0].load() == 2;
+}
+bool fine_queue_use(const StepJob& job) {
+  if (!fine_queue_supports(job)) return false;
+  return fine_queue_enabled() || fine_queue_tuned(job.n, job.f32);
+}
+
 static int col_blocks(int n);
 
 bool fine_queue_supports(const StepJob& job) {
@@ -1429,6 +1453,26 @@ static hipError_t queue_launch(const QGroup* gtab, int ngroups, const QTotals& t
   }
 }
 
+// Blocks of the queue kernel for (n, precision) (0: no such kernel).
+static int queue_blocks(int n, bool f32) {
+  int grid = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (n) {
+#define PR_QB(NN)                                                                                  \
+  case NN:                                                                                         \
+    if (f32) {                                                                                     \
+      if constexpr (queue_item_ok<NN, float>()) e = queue_grid<NN, float>(&grid);                 \
+    } else {                                                                                       \
+      if constexpr (queue_item_ok<NN, double>()) e = queue_grid<NN, double>(&grid);               \
+    }                                                                                              \
+    break;
+    PR_QB(64) PR_QB(128) PR_QB(256) PR_QB(512) PR_QB(1024)
+#undef PR_QB
+    default: break;
+  }
+  return e == hipSuccess ? grid : 0;
+}
+
 // One persistent launch per (N, precision) class of the jobs, in the order
 // the classes first appear (a batch of one class: one launch).
 hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStream_t st) {
@@ -1441,6 +1485,7 @@ hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStrea
     if (taken[i0]) continue;
     const int n = jobs[i0].n;
     const bool f32 = jobs[i0].f32;
+    const int per_queue = std::max(1, queue_blocks(n, f32) / kQueues);   // blocks per XCD
     QGroup gs[kQueueMaxGroups];
     QTotals tot{};
     int ngroups = 0;
@@ -1460,8 +1505,13 @@ hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStrea
       G.steps = j.steps;
       G.rt = row_tiles(j.n, j.f32);
       G.ct = col_blocks(j.n);
-      G.rti = (G.rt + PR_QUEUE_TILES - 1) / PR_QUEUE_TILES;
-      G.cti = (G.ct + PR_QUEUE_TILES - 1) / PR_QUEUE_TILES;
+      // tiles per item: the most that still give a quarter of a queue's
+      // blocks an item of each pass
+      const int64_t fq = (j.nfields + kQueues - 1) / kQueues;
+      G.tpi = PR_QUEUE_TILES;
+      while (G.tpi > 1 && 4 * fq * ((G.rt + G.tpi - 1) / G.tpi) < per_queue) G.tpi /= 2;
+      G.rti = (G.rt + G.tpi - 1) / G.tpi;
+      G.cti = (G.ct + G.tpi - 1) / G.tpi;
       G.nfields = j.nfields;
       StepJob sj = j;
       sj.resident = false;

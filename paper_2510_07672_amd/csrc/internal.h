@@ -216,6 +216,11 @@ hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStrea
 void set_fine_queue(int mode);   // 0 off, 1 on, 2 on with no XCD-local hand-over
 int fine_queue_mode();
 bool fine_queue_enabled();
+// The autotuner's record for (n, precision), and whether a job takes the
+// queue: supported, and the queue on or recorded faster for its class.
+void record_fine_queue(int n, bool f32, bool queue);
+bool fine_queue_tuned(int n, bool f32);
+bool fine_queue_use(const StepJob& job);
 // Working-set budget of streaming F calls (bytes of spectra in flight; 0 =
 // all fields at once): the process-wide setting, the effective value for
 // (N, precision) and the autotuner's record.

@@ -131,3 +131,24 @@ def test_queue_parareal_matches_oracle(api):
     assert st.iterations == int(res.iterations.max())
     assert list(st.ic_iterations) == list(res.iterations)
     assert np.linalg.norm(U.cpu().numpy() - res.U) <= 1e-12 * np.linalg.norm(res.U)
+
+
+def test_autotune_records_a_queue_choice(api):
+    """pr_autotune_fine times the queue against the per-pass launches for a
+    class the queue covers and records the faster one; F gives the same
+    bits either way, before and after."""
+    print("case queue autotune 256^2 x 16", flush=True)
+    n, nf = 256, 16
+    p = api.Problem(n=n, length=1.0, eps=0.01, conservative=True, stab=2.0, dt=2e-5, steps=8)
+    u0 = torch.from_numpy(synth.random_ic(n, range(40, 40 + nf))).cuda()
+    api.pr_set_fine_queue(0)
+    api.pr_set_fine_queue(1)
+    ref_q = api.pr_fine_propagate(p, u0)
+    api.pr_set_fine_queue(0)
+    assert api.pr_autotune_fine(p, u0) == "stream"
+    assert api.pr_get_fine_queue_choice(n, "f64") in (0, 1)
+    out = api.pr_fine_propagate(p, u0)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref_q)
+    assert api.pr_get_fine_queue_choice(500, "f64") == -1
+

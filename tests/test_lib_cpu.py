@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 10
+    assert lib.pr_abi_version() == 11
 
 
 def test_library_exports_match_nm(L):
@@ -248,6 +248,14 @@ def test_fine_queue_setting(L):
     assert lib.pr_set_fine_queue(3) == L.PR_ERR_INVALID_ARG
     assert lib.pr_set_fine_queue(-1) == L.PR_ERR_INVALID_ARG
     assert lib.pr_get_fine_queue() == 0
+    # off and nothing tuned: pass by pass for every class
+    assert lib.pr_get_fine_queue_choice(512, L.PR_F64) == 0
+    assert lib.pr_get_fine_queue_choice(500, L.PR_F64) == -1
+    assert lib.pr_get_fine_queue_choice(512, L.PR_BF16) == -1
     assert lib.pr_set_fine_queue(2) == L.PR_OK and lib.pr_get_fine_queue() == 2
+    assert lib.pr_get_fine_queue_choice(256, L.PR_F64) == 1
     assert lib.pr_set_fine_queue(1) == L.PR_OK and lib.pr_get_fine_queue() == 1
+    assert lib.pr_get_fine_queue_choice(512, L.PR_F64) == 1
+    assert lib.pr_get_fine_queue_choice(32, L.PR_F64) == 0      # outside the queue's sizes
+    assert lib.pr_get_fine_queue_choice(512, L.PR_F32) == 0     # FP32 at 512^2: 512-thread tiles
     assert lib.pr_set_fine_queue(0) == L.PR_OK and lib.pr_get_fine_queue() == 0
