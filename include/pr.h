@@ -478,9 +478,9 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
  * that XCD's L2 (a queue that no block of its XCD reaches is adopted by
  * other XCDs, which then publish device-wide).  Process-wide, default off:
  * on MI355X it stays slower than the replayed per-pass launches at every
- * size measured (512^2, 128 fields, 100 steps: 1.3x; 256^2, 128 fields,
- * 200 steps: 1.01x; the 48-solve uneven batch of pr_solve_many: 1.3x; a
- * single field: 2.6x).  on: 0 pass by pass, except for the (N, precision)
+ * size measured (2048 fields of 512^2, 100 steps: 1.18x; 512 fields of
+ * 256^2, 200 steps: 1.04x; the 48-solve uneven batch of pr_solve_many:
+ * 1.3x; one field of 512^2: 1.9x).  on: 0 pass by pass, except for the (N, precision)
  * classes for which pr_autotune_fine measured the queue faster; 1 on; 2 on
  * with every queue adopted (the device-wide hand-over alone, which a
  * placement of blocks that leaves an XCD without any would fall back to;
