@@ -466,6 +466,24 @@ def training_bench(args):
             "loss_first": log.loss[0], "loss_last": log.loss[-1]}
 
 
+def tune_network(api, p, g, u0, args):
+    """Untimed set-up: pr_autotune_coarse times the network's plans and
+    hidden-layer tiles on the batch and keeps the fastest as the AUTO
+    choice, which every later call (the timed ones included) then takes.
+    --cnn-plan / --cnn-tile pin them instead."""
+    if args.cnn_plan or args.cnn_tile:
+        if args.cnn_plan:
+            api.pr_set_coarse_plan(args.cnn_plan)
+        if args.cnn_tile:
+            api.pr_set_coarse_tile(args.cnn_tile)
+        how = "pinned"
+    else:
+        api.pr_autotune_coarse(p, g, u0)
+        how = "pr_autotune_coarse"
+    return {"plan": api.pr_get_coarse_plan(g, p.n), "tile": api.pr_get_coarse_tile(g, p.n),
+            "chosen_by": how}
+
+
 def cnn_kernel_rate(api, p, g, u0, reps=20):
     """Average duration of one network application on the batch (torch
     events on the stream the library launches on) and its rate against the
@@ -621,7 +639,9 @@ def network_only(args, api, torch, synth):
                     dt=cfg["dt"], steps=cfg["steps"])
     g, _ = trained_cnn(api, p, cfg, args.cnn_prec, 0)
     u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
+    tuned = tune_network(api, p, g, u0, args)
     ck = cnn_kernel_rate(api, p, g, u0, reps=10 * args.steps)
+    ck.update(tuned)
     ck["workload"] = cfg["workload"]
     return ck
 
@@ -647,6 +667,7 @@ def run_config(args, cname, api, torch, synth, full=True):
     else:
         g = g_num
     u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
+    tuned = tune_network(api, p, g, u0, args) if coarse == "cnn" else None
     U = torch.empty((B, s + 1, n, n), dtype=torch.float64, device="cuda")
     ws = None
 
@@ -730,6 +751,7 @@ def run_config(args, cname, api, torch, synth, full=True):
     roof = roof_fine
     if coarse == "cnn":
         ck = cnn_kernel_rate(api, p, g, u0)
+        ck.update(tuned)
         out["coarse_kernel"] = ck
         # one network call per slice in the initial sweep and one in the
         # correction sweep of the iteration
@@ -744,8 +766,8 @@ def run_config(args, cname, api, torch, synth, full=True):
                        "traffic": None if nt is None else round(nt),
                        "traffic_unit": "bytes per call, FETCH_SIZE + WRITE_SIZE scaled by a plain copy",
                        "algorithmic_bytes_per_call": ck["algorithmic_bytes_per_call"],
-                       "kernel": f"network G call ({g.n_layers} conv x {g.channels} ch, {g.prec}) "
-                                 f"on {B} fields, per call",
+                       "kernel": f"network G call ({g.n_layers} conv x {g.channels} ch, {g.prec}; "
+                                 f"{ck['plan']} plan, {ck['tile']} tiles) on {B} fields, per call",
                        "mfma": {"achieved": ck["model_tflops"], "peak": ck["peak_tflops"],
                                 "unit": "TFLOP/s", "frac": ck["mfma_frac"],
                                 "flops_per_call": ck["flops_per_px"] * B * n * n,
@@ -809,6 +831,12 @@ def main():
                     help="numerical coarse step, or the workload's convolutional network "
                          "(default: the network for c2 and c3, the scheme for c1)")
     ap.add_argument("--cnn-prec", default="bf16x2", choices=["bf16", "bf16x2", "f32"])
+    ap.add_argument("--cnn-plan", default=None, choices=["layered", "fused", "folded"],
+                    help="pin the network plan and hidden-layer tile (with --cnn-tile) "
+                         "instead of running pr_autotune_coarse before the timed region; "
+                         "a counter run pins the autotuner's choice so that it sees only "
+                         "those kernels")
+    ap.add_argument("--cnn-tile", default=None, choices=["8x32", "16x16"])
     ap.add_argument("--train-steps", type=int, default=None,
                     help="Adam steps on fine trajectories before timing (network only); "
                          "default 2000 for c2 and 60 for c3")

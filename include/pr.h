@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 11
+#define PR_ABI_VERSION 12
 
 typedef enum {
   PR_OK = 0,
@@ -408,9 +408,37 @@ pr_status pr_set_coarse_plan(int32_t plan);
  * or FOLDED), or -1 if g is not a valid network. */
 int32_t pr_get_coarse_plan(const pr_coarse* g, int32_t n);
 
+/* Output tile of each work-group in the hidden-layer launches of a
+ * bfloat16 network (plans LAYERED and FOLDED), process-wide.  A tile is the
+ * layer's outputs for a block of pixels, computed from the block's input
+ * activations plus a one-pixel halo staged in LDS.
+ *   PR_CNN_TILE_8X32   8 rows x 32 columns (340 staged pixels per 256);
+ *   PR_CNN_TILE_16X16  16 x 16 (324 staged pixels per 256); built for 32
+ *                      and 48 channels, other widths use 8 x 32;
+ *   PR_CNN_TILE_AUTO   the autotuner's measured choice for (channels,
+ *                      prec, N) if pr_autotune_coarse ran, else 16 x 16
+ *                      at 48 channels and 8 x 32 at other widths.
+ * Each output takes the same products in the same order under either
+ * tile, so the result is the same bit for bit. */
+typedef enum {
+  PR_CNN_TILE_AUTO = 0,
+  PR_CNN_TILE_8X32 = 1,
+  PR_CNN_TILE_16X16 = 2
+} pr_cnn_tile;
+
+pr_status pr_set_coarse_tile(int32_t tile);
+
+/* The tile pr_coarse_apply will use for g's hidden layers on N x N fields
+ * (8X32 or 16X16), 0 for a network without bfloat16 hidden layers, or -1
+ * if g is not a valid network or N is not a power of two in [32, 1024]. */
+int32_t pr_get_coarse_tile(const pr_coarse* g, int32_t n);
+
 /* Times every plan available for g on the caller's batch (u_in -> g_out,
- * workspace as for pr_coarse_apply) and records the fastest as the AUTO
- * choice for the shape (channels, n_layers, prec).  *chosen receives it. */
+ * workspace as for pr_coarse_apply), with LAYERED and FOLDED under both
+ * hidden-layer tiles where both exist, and records the fastest pair: the
+ * plan as the AUTO choice for the shape (channels, n_layers, prec), the
+ * tile as the AUTO choice for (channels, prec, N).  *chosen receives the
+ * plan; pr_get_coarse_tile reports the tile. */
 pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nfields,
                              const double* u_in, double* g_out, void* ws, size_t ws_bytes,
                              void* stream, int32_t* chosen);

@@ -372,9 +372,29 @@ def pr_get_coarse_plan(g: "CnnCoarse", n: int) -> str:
     return _CPLAN_NAME[L.lib().pr_get_coarse_plan(C.byref(g.c()), n)]
 
 
+_CTILE = {"auto": L.PR_CNN_TILE_AUTO, "8x32": L.PR_CNN_TILE_8X32, "16x16": L.PR_CNN_TILE_16X16}
+_CTILE_NAME = {v: k for k, v in _CTILE.items()}
+
+
+def pr_set_coarse_tile(tile: str) -> None:
+    """Output tile of the bf16 hidden-layer launches, process-wide: 'auto',
+    '8x32' or '16x16' (32 and 48 channels).  Same bits under either."""
+    L.check(L.lib().pr_set_coarse_tile(_CTILE[tile]), "pr_set_coarse_tile")
+
+
+def pr_get_coarse_tile(g: "CnnCoarse", n: int) -> str:
+    """The tile pr_coarse_apply uses for g on n x n fields; 'none' for a
+    network without bf16 hidden layers."""
+    v = L.lib().pr_get_coarse_tile(C.byref(g.c()), n)
+    if v < 0:
+        raise ValueError("not a valid network for n = %d" % n)
+    return _CTILE_NAME.get(v, "none") if v else "none"
+
+
 def pr_autotune_coarse(p: Problem, g: "CnnCoarse", u_in: torch.Tensor) -> str:
-    """Time the network plans available for g on u_in and keep the fastest
-    as the 'auto' choice."""
+    """Time the network plans available for g on u_in, each bf16 layered or
+    folded plan under both hidden-layer tiles, and keep the fastest pair as
+    the 'auto' choices (pr_get_coarse_tile reports the tile)."""
     B = _fields(u_in, p.n, "u_in")
     pc, gc = p.c(), g.c()
     out = torch.empty_like(u_in)

@@ -1374,6 +1374,19 @@ int32_t pr_get_coarse_plan(const pr_coarse* g, int32_t n) {
   return cnn_effective_plan(g->channels, g->n_layers, g->prec);
 }
 
+pr_status pr_set_coarse_tile(int32_t tile) {
+  if (tile != PR_CNN_TILE_AUTO && tile != PR_CNN_TILE_8X32 && tile != PR_CNN_TILE_16X16)
+    return fail(PR_ERR_INVALID_ARG, "coarse tile %d unknown", tile);
+  cnn_set_tile(tile);
+  return PR_OK;
+}
+
+int32_t pr_get_coarse_tile(const pr_coarse* g, int32_t n) {
+  if (!g || g->kind != PR_G_CNN || !is_pow2(n) || n > 1024 || check_coarse(g, n) != PR_OK) return -1;
+  if ((g->prec != PR_BF16 && g->prec != PR_BF16X2) || g->n_layers < 3) return 0;
+  return cnn_effective_tile(g->channels, g->prec, n) ? PR_CNN_TILE_16X16 : PR_CNN_TILE_8X32;
+}
+
 pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nfields,
                              const double* u_in, double* g_out, void* ws, size_t ws_bytes,
                              void* stream, int32_t* chosen) {
@@ -1388,36 +1401,51 @@ pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nf
   if (!ws || ws_bytes < c.used)
     return fail(PR_ERR_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, c.used);
   if ((st = cnn_lds_once()) != PR_OK) return st;
-  int best = PR_CNN_PLAN_LAYERED;
+  // every (plan, hidden-layer tile) pair that exists for the shape; the
+  // tile matters only to the plans with hidden-layer launches of 32 or 48
+  // channels (LAYERED, FOLDED)
+  int best = PR_CNN_PLAN_LAYERED, best_tile = 0;
+  const bool bf16 = g->prec == PR_BF16 || g->prec == PR_BF16X2;
   const bool fused = cnn_fused_available(g->channels, g->n_layers, g->prec) && g->n_layers <= 10;
   const bool folded = cnn_folded_available(g->channels, g->n_layers, g->prec);
-  if (fused || folded) {
+  const bool tiles = bf16 && g->n_layers >= 3 && (g->channels == 32 || g->channels == 48);
+  if (fused || folded || tiles) {
     hipStream_t s = (hipStream_t)stream;
     Events ev;
     if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
-    const int saved = cnn_get_plan();
+    const int saved = cnn_get_plan(), saved_tile = cnn_get_tile();
     PR_HIP(coarse_setup(p, g, w, s));
-    float ms[4] = {0, 0, 0, 0};
+    float best_ms = -1.f;
     for (int plan = PR_CNN_PLAN_LAYERED; plan <= PR_CNN_PLAN_FOLDED; ++plan) {
       if ((plan == PR_CNN_PLAN_FUSED && !fused) || (plan == PR_CNN_PLAN_FOLDED && !folded)) continue;
-      cnn_set_plan(plan);
-      hipError_t e = coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s);  // warm-up
-      if (e == hipSuccess) e = hipEventRecord(ev.e[0], s);
-      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
-        e = coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s);
-      if (e == hipSuccess) e = hipEventRecord(ev.e[1], s);
-      if (e == hipSuccess) e = hipEventSynchronize(ev.e[1]);
-      if (e != hipSuccess) {
-        cnn_set_plan(saved);
-        return fail(PR_ERR_DEVICE, "autotune: %s", hipGetErrorString(e));
+      const int ntiles = tiles && plan != PR_CNN_PLAN_FUSED ? 2 : 1;
+      for (int tile = 0; tile < ntiles; ++tile) {
+        cnn_set_plan(plan);
+        cnn_set_tile(tile ? PR_CNN_TILE_16X16 : PR_CNN_TILE_8X32);
+        hipError_t e = coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(ev.e[0], s);
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+          e = coarse_run(p, g, w, nfields, u_in, nullptr, g_out, nullptr, s);
+        if (e == hipSuccess) e = hipEventRecord(ev.e[1], s);
+        if (e == hipSuccess) e = hipEventSynchronize(ev.e[1]);
+        if (e != hipSuccess) {
+          cnn_set_plan(saved);
+          cnn_set_tile(saved_tile);
+          return fail(PR_ERR_DEVICE, "autotune: %s", hipGetErrorString(e));
+        }
+        const float ms = event_ms(ev.e[0], ev.e[1]);
+        if (best_ms < 0.f || ms < best_ms) {
+          best_ms = ms;
+          best = plan;
+          best_tile = tile;
+        }
       }
-      ms[plan] = event_ms(ev.e[0], ev.e[1]);
     }
     cnn_set_plan(saved);
-    for (int plan = PR_CNN_PLAN_FUSED; plan <= PR_CNN_PLAN_FOLDED; ++plan)
-      if (ms[plan] > 0 && ms[plan] <= ms[best]) best = plan;
+    cnn_set_tile(saved_tile);
   }
   cnn_record_tuned(g->channels, g->n_layers, g->prec, best);
+  if (tiles) cnn_record_tile(g->channels, g->prec, p->n, best_tile);
   if (chosen) *chosen = best;
   return PR_OK;
 }

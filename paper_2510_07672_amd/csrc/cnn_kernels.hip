@@ -195,8 +195,8 @@ __global__ __launch_bounds__(256) void k_cnn_first(const double* __restrict__ u_
 
 // ----------------------------------------------------------- hidden layers
 
-template <int C, int NWAVES = 4> struct HidCfg {
-  static constexpr int TH = 8, TW = 32;              // output tile (rows, columns)
+template <int C, int NWAVES = 4, int TH_ = 8, int TW_ = 32> struct HidCfg {
+  static constexpr int TH = TH_, TW = TW_;           // output tile (rows, columns)
   static constexpr int NW = NWAVES, NT = 64 * NW;    // waves, threads
   static constexpr int CS = C + 8;                   // LDS pixel stride (elements), one plane
   static constexpr int KP = (9 * C + 31) / 32 * 32;  // K padded to the MFMA depth
@@ -214,14 +214,15 @@ template <int C, int NWAVES = 4> struct HidCfg {
 // an odd number of 16-byte bank quads, as one plane of stride C + 8 would,
 // while the pair costs 8 pad elements per pixel instead of 16 (at C = 32
 // that lets 3 work-groups share a CU instead of 2).
-template <int C, bool SPLIT> struct HidTile {
+template <int C, bool SPLIT, int TH_ = 8, int TW_ = 32> struct HidTile {
+  using HC = HidCfg<C, 4, TH_, TW_>;
   static constexpr int PS = SPLIT ? 2 * C + 8 : C + 8;
   static constexpr int LO = SPLIT ? C : 0;   // offset of the lo values
-  static constexpr size_t BYTES = (size_t)HidCfg<C>::TPIX * PS * 2;
+  static constexpr size_t BYTES = (size_t)HC::TPIX * PS * 2;
   // With the first layer computed in the same launch: after the tile, the
   // (TH+4) x (TW+4) patch of the state that the tile's first-layer outputs
   // read, then the first layer's C x 9 weights and C biases (FP32).
-  static constexpr int UH = HidCfg<C>::TH + 4, UW = HidCfg<C>::TW + 4;
+  static constexpr int UH = HC::TH + 4, UW = HC::TW + 4;
   static constexpr size_t FIRST_BYTES = BYTES + (size_t)(UH * UW + 10 * C) * 4;
 };
 
@@ -331,6 +332,15 @@ struct FirstIn {
 // output channels 8 g .. 8 g + 7 of its pixel: those registers are then
 // the 16x16x32 A fragment that k_cnn_last_mma loads for the pixel, and the
 // same three products in the same order give Y bit for bit.
+// Output tile shapes of the hidden layers: 0 is 8 x 32 pixels, 1 is 16 x 16
+// (fewer halo pixels per tile, 324 instead of 340 for 256 outputs; rows of
+// one 16-pixel block).  The per-pixel arithmetic does not depend on the
+// shape, so both give the same bits; pr_autotune_coarse times them at 32
+// and 48 channels, the only widths built with both.
+template <int SHAPE> constexpr int tile_h() { return SHAPE ? 16 : 8; }
+template <int SHAPE> constexpr int tile_w() { return SHAPE ? 16 : 32; }
+template <int C> constexpr bool both_tile_shapes() { return C == 32 || C == 48; }
+
 // Whether a hidden layer splits its output channels over waves: wave w then
 // computes output-channel block w % NB (16 channels) of pixel group w / NB
 // and holds only that block's weight fragments (KB x 4 registers instead of
@@ -344,14 +354,14 @@ struct FirstIn {
 template <int C, bool TAIL> constexpr bool hidden_nbw() { return PR_HID48_NBW && C == 48 && !TAIL; }
 template <int C, bool TAIL> constexpr int hidden_waves() { return hidden_nbw<C, TAIL>() ? 6 : 4; }
 
-template <int C, bool SPLIT, bool FIRST = false, bool TAIL = false>
+template <int C, bool SPLIT, bool FIRST = false, bool TAIL = false, int SHAPE = 0>
 __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribute__((amdgpu_waves_per_eu(C == 48 ? (hidden_nbw<C, TAIL>() ? 3 : PR_HID48_WAVES) : 1))) void k_cnn_hidden(
     const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
     const __bf16* __restrict__ Wp, const float* __restrict__ b, int act,
     __bf16* __restrict__ out, __bf16* __restrict__ out_lo, float* __restrict__ zout,
     FirstIn fi, const float* __restrict__ WL, const bf16x8* __restrict__ WLp,
     float* __restrict__ Yp) {
-  using H = HidCfg<C, hidden_waves<C, TAIL>()>;
+  using H = HidCfg<C, hidden_waves<C, TAIL>(), tile_h<SHAPE>(), tile_w<SHAPE>()>;
   static_assert(C % 16 == 0, "hidden width must be a multiple of 16");
   constexpr bool kNBW = hidden_nbw<C, TAIL>();
   constexpr int NBL = kNBW ? 1 : H::NB;              // channel blocks per wave
@@ -365,7 +375,7 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
   static_assert(!TAIL || C == 32 || C == 48,
                 "the last layer folds into a hidden layer of 32 or 48 channels");
   extern __shared__ __align__(16) unsigned char smem[];
-  using HT = HidTile<C, SPLIT>;
+  using HT = HidTile<C, SPLIT, tile_h<SHAPE>(), tile_w<SHAPE>()>;
   __bf16* tile = (__bf16*)smem;                               // [TPIX][PS]
   __bf16* tile_lo = tile + HT::LO;                            // SPLIT only
   float* su = (float*)(smem + HT::BYTES);                     // FIRST: [UH][UW]
@@ -1528,17 +1538,17 @@ __global__ void k_add_into(double* __restrict__ du, const T* __restrict__ d, int
 
 // --------------------------------------------------------------- launch
 
-size_t cnn_lds_bytes(int C, bool split, bool first);
+size_t cnn_lds_bytes(int C, bool split, bool first, int shape);
 
 // Blocks of the persistent hidden-layer kernel that fill the GPU once.
-template <int C, bool SPLIT, bool FIRST = false, bool TAIL = false>
+template <int C, bool SPLIT, bool FIRST = false, bool TAIL = false, int SHAPE = 0>
 static int hidden_cap() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 512;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cnn_hidden<C, SPLIT, FIRST, TAIL>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cnn_hidden<C, SPLIT, FIRST, TAIL, SHAPE>,
                                                    HidCfg<C, hidden_waves<C, TAIL>()>::NT,
-                                                   cnn_lds_bytes(C, SPLIT, FIRST)) != hipSuccess ||
+                                                   cnn_lds_bytes(C, SPLIT, FIRST, SHAPE)) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   return cus * per_cu;
@@ -1589,6 +1599,8 @@ static void cnn_fwd_ref(const CnnJob& j, bool train, double* g_out, hipStream_t 
 }
 
 std::atomic<int> g_cnn_plan{0};          // pr_cnn_plan, process-wide setting
+std::atomic<int> g_cnn_tile{0};          // pr_cnn_tile, process-wide setting
+std::atomic<int> g_cnn_tile_tuned[2][2][7];  // [C 32 / 48][split][log2 N - 4]: measured tile + 1 (0 = none)
 std::atomic<int> g_cnn_tuned[5][8][2];     // [C index][L - 3][split]: measured choice (0 = none)
 
 static int c_index(int C) { return C == 8 ? 0 : C == 16 ? 1 : C == 32 ? 2 : C == 48 ? 3 : 4; }
@@ -1697,6 +1709,34 @@ int cnn_effective_plan(int C, int L, int prec) {
   return pl;
 }
 
+// Hidden-layer output tile shape (0 = 8 x 32, 1 = 16 x 16) for a bf16
+// network of C channels on N x N fields: the pr_cnn_tile setting, else the
+// autotuner's measured choice for (C, prec, N), else 16 x 16 at 48 channels
+// (faster on every batch measured, 1-5%) and 8 x 32 at 32 (either way by
+// batch and N, within 2%).
+static int tile_slot(int n) {
+  int lg = 0;
+  while ((1 << lg) < n) ++lg;
+  return lg - 4;
+}
+int cnn_effective_tile(int C, int prec, int n) {
+  if (C != 32 && C != 48) return 0;
+  const int t = g_cnn_tile.load();
+  if (t == CNN_TILE_8X32) return 0;
+  if (t == CNN_TILE_16X16) return 1;
+  const int k = tile_slot(n);
+  if (k < 0 || k > 6) return C == 48 ? 1 : 0;
+  const int tuned = g_cnn_tile_tuned[C == 48][prec == kCnnBf16x2][k].load();
+  return tuned > 0 ? tuned - 1 : (C == 48 ? 1 : 0);
+}
+void cnn_set_tile(int tile) { g_cnn_tile.store(tile); }
+int cnn_get_tile() { return g_cnn_tile.load(); }
+void cnn_record_tile(int C, int prec, int n, int shape) {
+  const int k = tile_slot(n);
+  if ((C == 32 || C == 48) && k >= 0 && k <= 6)
+    g_cnn_tile_tuned[C == 48][prec == kCnnBf16x2][k].store(shape + 1);
+}
+
 void cnn_set_plan(int plan) { g_cnn_plan.store(plan); }
 int cnn_get_plan() { return g_cnn_plan.load(); }
 void cnn_record_tuned(int C, int L, int prec, int plan) {
@@ -1738,8 +1778,9 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
       using H = HidCfg<C>;
       const __bf16* wp = (const __bf16*)j.ws.wpack + (int64_t)(l - 1) * C * H::KP;
       const bool first = folded && l == 1, last = tail && l == L - 2;
-      const size_t lds = cnn_lds_bytes(C, split, first);
-      const int64_t tiles = j.nfields * (n / H::TH) * (n / H::TW);
+      const int shape = both_tile_shapes<C>() ? cnn_effective_tile(C, j.prec, n) : 0;
+      const size_t lds = cnn_lds_bytes(C, split, first, shape);
+      const int64_t tiles = j.nfields * (n / H::TH) * (n / H::TW);  // the same for both shapes
       const FirstIn fi{j.in_base, j.in_offs, W, B};
       const float* WL = W + cnn_woff(L - 1, L, C);
       const bf16x8* WLp = (const bf16x8*)((const __bf16*)j.ws.wpack + (int64_t)(L - 2) * C * H::KP);
@@ -1751,13 +1792,21 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
       const __bf16* il = first ? nullptr : lo(l - 1);
       __bf16* oh = last ? nullptr : hi(l);
       __bf16* ol = last ? nullptr : lo(l);
-#define PR_HID(SP, FI, TA)                                                                       \
+#define PR_HID_S(SP, FI, TA, SH)                                                                 \
   {                                                                                              \
-    static const int cap = hidden_cap<C, SP, FI, TA>();                                          \
+    static const int cap = hidden_cap<C, SP, FI, TA, SH>();                                      \
     const dim3 gh((unsigned)std::min<int64_t>(tiles, cap));                                      \
     const dim3 bh(HidCfg<C, hidden_waves<C, TA>()>::NT);                                       \
-    k_cnn_hidden<C, SP, FI, TA><<<gh, bh, lds, st>>>(ih, il, n, j.nfields, wp, B + cnn_boff(l, C), \
-                                                     j.act, oh, ol, zo, fi, WL, WLp, Yp);        \
+    k_cnn_hidden<C, SP, FI, TA, SH><<<gh, bh, lds, st>>>(ih, il, n, j.nfields, wp,               \
+                                                         B + cnn_boff(l, C), j.act, oh, ol, zo,  \
+                                                         fi, WL, WLp, Yp);                       \
+  }
+#define PR_HID(SP, FI, TA)                                                                       \
+  {                                                                                              \
+    if constexpr (both_tile_shapes<C>()) {                                                       \
+      if (shape) PR_HID_S(SP, FI, TA, 1)                                                         \
+      else PR_HID_S(SP, FI, TA, 0)                                                               \
+    } else PR_HID_S(SP, FI, TA, 0)                                                               \
   }
       if constexpr (C == 32 || C == 48) {
         if (split) {
@@ -1781,6 +1830,7 @@ static int cnn_fwd_bf16(const CnnJob& j, bool train, double* g_out, hipStream_t 
         }
       }
 #undef PR_HID
+#undef PR_HID_S
     }
   }
   const bool fold_corr = Yp && j.corr && !j.mass_fix && !j.limiter;
@@ -2000,14 +2050,19 @@ hipError_t launch_cnn_backward(const CnnJob& j, const double* dG, double* du, vo
   }
 }
 
-size_t cnn_lds_bytes(int C, bool split, bool first) {
+template <int C, int SHAPE>
+static size_t hid_lds(bool split, bool first) {
+  using S = HidTile<C, true, tile_h<SHAPE>(), tile_w<SHAPE>()>;
+  using U = HidTile<C, false, tile_h<SHAPE>(), tile_w<SHAPE>()>;
+  return split ? (first ? S::FIRST_BYTES : S::BYTES) : (first ? U::FIRST_BYTES : U::BYTES);
+}
+
+size_t cnn_lds_bytes(int C, bool split, bool first, int shape) {
   switch (C) {
-#define PR_L(CC)                                                                               \
-  case CC:                                                                                     \
-    return split ? (first ? HidTile<CC, true>::FIRST_BYTES : HidTile<CC, true>::BYTES)         \
-                 : (first ? HidTile<CC, false>::FIRST_BYTES : HidTile<CC, false>::BYTES);
-    PR_L(16) PR_L(32) PR_L(48) PR_L(64)
-#undef PR_L
+    case 16: return hid_lds<16, 0>(split, first);
+    case 32: return shape ? hid_lds<32, 1>(split, first) : hid_lds<32, 0>(split, first);
+    case 48: return shape ? hid_lds<48, 1>(split, first) : hid_lds<48, 0>(split, first);
+    case 64: return hid_lds<64, 0>(split, first);
     default: return 0;
   }
 }
@@ -2034,23 +2089,18 @@ hipError_t cnn_set_lds_limits() {
   PR_F(16, 1) PR_F(16, 2) PR_F(16, 3) PR_F(16, 4) PR_F(32, 1) PR_F(32, 2)
 #undef PR_F
   if (e == hipSuccess) e = fused_lds_limit<48, 1, false>();
-#define PR_A(CC, SP, FI)                                                                     \
-  if (e == hipSuccess && cnn_lds_bytes(CC, SP, FI) <= kMaxLds)                               \
-    e = hipFuncSetAttribute((const void*)k_cnn_hidden<CC, SP, FI>,                           \
+#define PR_A(CC, SP, FI, TA, SH)                                                             \
+  if (e == hipSuccess && cnn_lds_bytes(CC, SP, FI, SH) <= kMaxLds)                           \
+    e = hipFuncSetAttribute((const void*)k_cnn_hidden<CC, SP, FI, TA, SH>,                   \
                             hipFuncAttributeMaxDynamicSharedMemorySize,                      \
-                            (int)cnn_lds_bytes(CC, SP, FI));
-#define PR_B(CC) PR_A(CC, false, false) PR_A(CC, true, false) PR_A(CC, false, true) PR_A(CC, true, true)
-  PR_B(16) PR_B(32) PR_B(48) PR_B(64)
+                            (int)cnn_lds_bytes(CC, SP, FI, SH));
+#define PR_B(CC, TA, SH) \
+  PR_A(CC, false, false, TA, SH) PR_A(CC, true, false, TA, SH) PR_A(CC, false, true, TA, SH) PR_A(CC, true, true, TA, SH)
+  PR_B(16, false, 0) PR_B(32, false, 0) PR_B(48, false, 0) PR_B(64, false, 0)
+  PR_B(32, true, 0) PR_B(48, true, 0)
+  PR_B(32, false, 1) PR_B(48, false, 1) PR_B(32, true, 1) PR_B(48, true, 1)
 #undef PR_B
 #undef PR_A
-#define PR_T(CC, SP, FI)                                                                     \
-  if (e == hipSuccess && cnn_lds_bytes(CC, SP, FI) <= kMaxLds)                               \
-    e = hipFuncSetAttribute((const void*)k_cnn_hidden<CC, SP, FI, true>,                     \
-                            hipFuncAttributeMaxDynamicSharedMemorySize,                      \
-                            (int)cnn_lds_bytes(CC, SP, FI));
-  PR_T(32, false, false) PR_T(32, true, false) PR_T(32, false, true) PR_T(32, true, true)
-  PR_T(48, false, false) PR_T(48, true, false) PR_T(48, false, true) PR_T(48, true, true)
-#undef PR_T
   return e;
 }
 

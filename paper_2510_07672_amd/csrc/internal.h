@@ -190,6 +190,13 @@ int cnn_effective_plan(int C, int L, int prec);
 void cnn_set_plan(int plan);
 int cnn_get_plan();
 void cnn_record_tuned(int C, int L, int prec, int plan);
+// Output tile of the bf16 hidden layers (layered and folded plans): the
+// pr_cnn_tile values; cnn_effective_tile returns 0 for 8 x 32, 1 for 16 x 16.
+enum { CNN_TILE_AUTO = 0, CNN_TILE_8X32 = 1, CNN_TILE_16X16 = 2 };
+int cnn_effective_tile(int C, int prec, int n);
+void cnn_set_tile(int tile);
+int cnn_get_tile();
+void cnn_record_tile(int C, int prec, int n, int shape);
 
 hipError_t launch_cnn_pack(const CnnJob& j, hipStream_t st);
 hipError_t launch_cnn(const CnnJob& j, hipStream_t st);
@@ -197,7 +204,7 @@ hipError_t launch_cnn_backward(const CnnJob& j, const double* dG, double* du, vo
                                hipStream_t st);
 int cnn_act_bytes(int prec);
 int cnn_grad_bytes(int prec);
-size_t cnn_lds_bytes(int C, bool split, bool first = false);
+size_t cnn_lds_bytes(int C, bool split, bool first = false, int shape = 0);
 hipError_t cnn_set_lds_limits();
 
 hipError_t launch_tables(int n, int laplacian, const FineWs& ws, hipStream_t st);

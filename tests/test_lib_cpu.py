@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 11
+    assert lib.pr_abi_version() == 12
 
 
 def test_library_exports_match_nm(L):
@@ -190,6 +190,42 @@ def test_coarse_plan_setting(L):
         assert lib.pr_set_coarse_plan(bad) == L.PR_ERR_INVALID_ARG
     for ok in (3, 2, 1, 0):
         assert lib.pr_set_coarse_plan(ok) == L.PR_OK
+
+
+def test_coarse_tile_setting(L):
+    """The hidden-layer tiles are AUTO, 8X32 and 16X16; anything else is
+    rejected and leaves the setting alone.  The getter reports the tile a
+    bf16 network's hidden layers take: 16 x 16 only where it is built (32 and
+    48 channels), 0 without bf16 hidden layers, -1 for an invalid network."""
+    lib = L.lib()
+    assert (L.PR_CNN_TILE_AUTO, L.PR_CNN_TILE_8X32, L.PR_CNN_TILE_16X16) == (0, 1, 2)
+    for bad in (-1, 3, 99):
+        assert lib.pr_set_coarse_tile(bad) == L.PR_ERR_INVALID_ARG
+    d = dict(kind=L.PR_G_CNN, prec=L.PR_BF16X2, n_layers=6, channels=48, weights=64, biases=128,
+             act=L.PR_ACT_GELU, residual=1)
+    g48, g32 = L.Coarse(**d), L.Coarse(**dict(d, channels=32, n_layers=4))
+    g64, g16 = L.Coarse(**dict(d, channels=64, prec=L.PR_BF16)), L.Coarse(**dict(d, channels=16))
+    g2 = L.Coarse(**dict(d, n_layers=2))
+    gf = L.Coarse(**dict(d, prec=L.PR_F32))
+    try:
+        # untuned: 16 x 16 at 48 channels, 8 x 32 at 32
+        assert lib.pr_get_coarse_tile(C.byref(g48), 512) == L.PR_CNN_TILE_16X16
+        assert lib.pr_get_coarse_tile(C.byref(g32), 512) == L.PR_CNN_TILE_8X32
+        assert lib.pr_set_coarse_tile(L.PR_CNN_TILE_16X16) == L.PR_OK
+        assert lib.pr_set_coarse_tile(3) == L.PR_ERR_INVALID_ARG
+        for g in (g48, g32):
+            assert lib.pr_get_coarse_tile(C.byref(g), 512) == L.PR_CNN_TILE_16X16
+            assert lib.pr_get_coarse_tile(C.byref(g), 32) == L.PR_CNN_TILE_16X16
+        for g in (g64, g16):
+            assert lib.pr_get_coarse_tile(C.byref(g), 512) == L.PR_CNN_TILE_8X32
+        assert lib.pr_get_coarse_tile(C.byref(g2), 512) == 0
+        assert lib.pr_get_coarse_tile(C.byref(gf), 512) == 0
+        assert lib.pr_get_coarse_tile(C.byref(g48), 16) == -1    # the network needs N >= 32
+        assert lib.pr_get_coarse_tile(C.byref(g48), 100) == -1
+        assert lib.pr_set_coarse_tile(L.PR_CNN_TILE_8X32) == L.PR_OK
+        assert lib.pr_get_coarse_tile(C.byref(g32), 256) == L.PR_CNN_TILE_8X32
+    finally:
+        assert lib.pr_set_coarse_tile(L.PR_CNN_TILE_AUTO) == L.PR_OK
 
 
 def test_working_set_setting(L):
