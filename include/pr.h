@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 12
+#define PR_ABI_VERSION 13
 
 typedef enum {
   PR_OK = 0,
@@ -478,14 +478,41 @@ pr_status pr_set_fine_plan(int32_t n, pr_dtype prec, int32_t plan);
  * an unsupported (n, prec). */
 int32_t pr_get_fine_plan(int32_t n, pr_dtype prec);
 
+/* Radix split of the length-N transforms of the streaming semi-implicit
+ * passes (Section 3.1's FFT-diagonalised step), per (N, precision),
+ * process-wide.  Every stage of a transform is one round trip through LDS
+ * with 8 elements per thread, so both splits take the fewest stages:
+ *   PR_FFT_SPLIT_R8       radix 8 while it fits, the leftover radix 2 or 4
+ *                         last (N = 8^a * {1, 2, 4});
+ *   PR_FFT_SPLIT_R4_TAIL  the same, but a trailing 8 x 2 becomes 4 x 4, so
+ *                         that N = 16, 128 and 1024 have no radix-2 stage;
+ *                         other N have no such split and take R8;
+ *   PR_FFT_SPLIT_AUTO     the autotuner's measured choice for (N,
+ *                         precision) if pr_autotune_fine ran, else R8.
+ * The two differ in rounding only (the same DFT, other operation order).
+ * The resident plan, the Crank-Nicolson passes and the work queue keep R8.
+ * Invalid n, prec or split: PR_ERR_UNSUPPORTED / PR_ERR_INVALID_ARG. */
+typedef enum {
+  PR_FFT_SPLIT_AUTO = 0,
+  PR_FFT_SPLIT_R8 = 1,
+  PR_FFT_SPLIT_R4_TAIL = 2
+} pr_fft_split;
+
+pr_status pr_set_fft_split(int32_t n, pr_dtype prec, int32_t split);
+
+/* The split the streaming semi-implicit passes use for (n, prec): R8 or
+ * R4_TAIL; -1 for an unsupported (n, prec). */
+int32_t pr_get_fft_split(int32_t n, pr_dtype prec);
+
 /* Autotuner: times one F call of p on `nfields` fields under each plan
  * available for p->n (u_in read, u_out overwritten with scratch results;
  * workspace as for pr_fine_propagate), records the faster one as the AUTO
  * choice for (p->n, p->fine_prec) and returns it in *chosen (may be NULL).
- * For the streaming plan it also times the working-set budgets and, where
- * the work queue covers the class, the queue against the per-pass launches
- * (the faster is recorded; see pr_set_fine_queue).  Blocks until the timing
- * runs finish. */
+ * For the streaming plan it also times the working-set budgets, then (for
+ * the semi-implicit step, where N has two) both FFT radix splits, then,
+ * where the work queue covers the class, the queue against the per-pass
+ * launches; the faster of each is recorded (see pr_set_fft_split,
+ * pr_set_fine_queue).  Blocks until the timing runs finish. */
 pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u_in,
                            void* u_out, void* ws, size_t ws_bytes, void* stream,
                            int32_t* chosen);
@@ -498,7 +525,8 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
  * blocks take the tiles of every pass of every field from a queue, and a
  * tile waits only for the previous pass of its own field (per-field
  * counters), so passes of different fields and groups overlap.  The
- * results are bitwise those of the per-pass launches.  It covers N = 64 ..
+ * results are bitwise those of the per-pass launches under the R8 radix
+ * split (the queue's transforms always take R8; see pr_set_fft_split).  It covers N = 64 ..
  * 1024 in PR_F64 and N = 64 .. 256 in PR_F32 (other sizes, FP32 at 512 and
  * 1024, and Crank-Nicolson keep the per-pass launches).  The fields are
  * split among eight queues, one per XCD, and a queue's items run on the

@@ -30,7 +30,7 @@ EXPORTED = [
     "pr_serial_workspace_bytes", "pr_serial_fine",
     "pr_set_fine_plan", "pr_get_fine_plan", "pr_autotune_fine", "pr_set_graphs", "pr_get_graphs",
     "pr_set_coarse_plan", "pr_get_coarse_plan", "pr_autotune_coarse",
-    "pr_set_coarse_tile", "pr_get_coarse_tile",
+    "pr_set_coarse_tile", "pr_get_coarse_tile", "pr_set_fft_split", "pr_get_fft_split",
     "pr_set_overlap", "pr_get_overlap", "pr_set_fine_working_set", "pr_get_fine_working_set",
     "pr_set_fine_queue", "pr_get_fine_queue", "pr_get_fine_queue_choice",
     "pr_status_string", "pr_last_error", "pr_abi_version",
@@ -38,6 +38,7 @@ EXPORTED = [
 PR_PLAN_AUTO, PR_PLAN_STREAM, PR_PLAN_RESIDENT = 0, 1, 2
 PR_CNN_PLAN_AUTO, PR_CNN_PLAN_LAYERED, PR_CNN_PLAN_FUSED, PR_CNN_PLAN_FOLDED = 0, 1, 2, 3
 PR_CNN_TILE_AUTO, PR_CNN_TILE_8X32, PR_CNN_TILE_16X16 = 0, 1, 2
+PR_FFT_SPLIT_AUTO, PR_FFT_SPLIT_R8, PR_FFT_SPLIT_R4_TAIL = 0, 1, 2
 
 
 class Problem(C.Structure):
@@ -114,6 +115,8 @@ def lib() -> C.CDLL:
             "pr_get_fine_queue_choice": (i32, [i32, i32]),
             "pr_get_coarse_plan": (i32, [G, i32]),
             "pr_set_coarse_tile": (C.c_int, [i32]),
+            "pr_set_fft_split": (C.c_int, [i32, C.c_int, i32]),
+            "pr_get_fft_split": (i32, [i32, C.c_int]),
             "pr_get_coarse_tile": (i32, [G, i32]),
             "pr_autotune_coarse": (C.c_int, [P, G, i64, vp, vp, vp, sz, vp, C.POINTER(i32)]),
             "pr_get_graphs": (i32, []),

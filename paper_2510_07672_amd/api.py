@@ -343,9 +343,28 @@ def pr_get_fine_plan(n: int, prec: str) -> str:
     return _PLAN_NAME[L.lib().pr_get_fine_plan(n, _PREC[prec])]
 
 
+_SPLIT = {"auto": L.PR_FFT_SPLIT_AUTO, "r8": L.PR_FFT_SPLIT_R8, "r4_tail": L.PR_FFT_SPLIT_R4_TAIL}
+_SPLIT_NAME = {v: k for k, v in _SPLIT.items()}
+
+
+def pr_set_fft_split(n: int, prec: str, split: str) -> None:
+    """FFT radix split of the streaming semi-implicit passes for (n, prec):
+    'auto', 'r8' (radix 8 first, the leftover last) or 'r4_tail' (a trailing
+    8 x 2 as 4 x 4; differs for n = 16, 128, 1024)."""
+    L.check(L.lib().pr_set_fft_split(n, _PREC[prec], _SPLIT[split]), "pr_set_fft_split")
+
+
+def pr_get_fft_split(n: int, prec: str) -> str:
+    v = L.lib().pr_get_fft_split(n, _PREC[prec])
+    if v < 0:
+        raise ValueError("unsupported (n, prec) = (%d, %s)" % (n, prec))
+    return _SPLIT_NAME[v]
+
+
 def pr_autotune_fine(p: Problem, u_in: torch.Tensor) -> str:
     """Time both plans on u_in and keep the faster as the 'auto' choice (and,
-    for the streaming plan, the working-set budget and queue vs per-pass)."""
+    for the streaming plan, the working-set budget, the FFT radix split and
+    queue vs per-pass)."""
     B = _fields(u_in, p.n, "u_in")
     pc = p.c()
     out = torch.empty_like(u_in)

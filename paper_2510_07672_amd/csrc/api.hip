@@ -146,6 +146,8 @@ constexpr int kMaxChunks = 16;
 
 std::atomic<int> g_plan[11][2];     // [log2 N][f32], user setting
 std::atomic<int> g_tuned[11][2];    // [log2 N][f32], autotuner result (0 = none)
+std::atomic<int> g_split[11][2];    // [log2 N][f32], pr_fft_split setting
+std::atomic<int> g_split_tuned[11][2];  // [log2 N][f32], autotuner result (0 = none)
 
 int log2i(int n) {
   int l = 0;
@@ -163,12 +165,24 @@ int effective_plan(int n, bool f32) {
   return pl;
 }
 
+// FFT radix split of the streaming semi-implicit passes for (N, precision):
+// the setting, else the autotuner's measured choice, else radix 8 first
+// with the leftover last; PR_FFT_SPLIT_* values.
+int effective_split(int n, bool f32) {
+  const int l = log2i(n);
+  if (l < 0 || l > 10 || !fine_radix_differs(n)) return PR_FFT_SPLIT_R8;
+  int sp = g_split[l][f32 ? 1 : 0].load();
+  if (sp == PR_FFT_SPLIT_AUTO) sp = g_split_tuned[l][f32 ? 1 : 0].load();
+  return sp == PR_FFT_SPLIT_R4_TAIL ? PR_FFT_SPLIT_R4_TAIL : PR_FFT_SPLIT_R8;
+}
+
 StepJob make_job(const pr_problem* p, double dt, int steps, bool f32, int64_t nfields,
                  const FineWs& ws) {
   StepJob j{};
   j.scheme = p->scheme;
   j.picard = p->picard_iters;
   j.resident = p->scheme == PR_SCHEME_SSI && effective_plan(p->n, f32) == PR_PLAN_RESIDENT;
+  j.radix = effective_split(p->n, f32) == PR_FFT_SPLIT_R4_TAIL ? 1 : 0;
   j.n = p->n;
   j.f32 = f32;
   j.steps = steps;
@@ -888,6 +902,7 @@ pr_status solve_jobs(int32_t n_jobs, pr_job* jobs, void* ws, size_t ws_bytes, hi
         fj.nfields = sg.count;
         fj.ws = G.ws;
         fj.resident = G.scheme == PR_SCHEME_SSI && effective_plan(G.N, G.f32) == PR_PLAN_RESIDENT;
+        fj.radix = effective_split(G.N, G.f32) == PR_FFT_SPLIT_R4_TAIL ? 1 : 0;
         fj.in_base = UB;
         fj.in_offs = P.t64 + sg.i64[0];
         fj.out_base = WB;
@@ -1474,6 +1489,20 @@ void pr_set_graphs(int32_t enabled) { set_graphs_enabled(enabled != 0); }
 
 int32_t pr_get_graphs(void) { return graphs_enabled() ? 1 : 0; }
 
+pr_status pr_set_fft_split(int32_t n, pr_dtype prec, int32_t split) {
+  if (!is_pow2(n) || n < 16 || n > 1024) return fail(PR_ERR_UNSUPPORTED, "n=%d not supported", n);
+  if (prec != PR_F64 && prec != PR_F32) return fail(PR_ERR_INVALID_ARG, "prec must be PR_F64 or PR_F32");
+  if (split != PR_FFT_SPLIT_AUTO && split != PR_FFT_SPLIT_R8 && split != PR_FFT_SPLIT_R4_TAIL)
+    return fail(PR_ERR_INVALID_ARG, "FFT split %d unknown", split);
+  g_split[log2i(n)][prec == PR_F32 ? 1 : 0].store(split);
+  return PR_OK;
+}
+
+int32_t pr_get_fft_split(int32_t n, pr_dtype prec) {
+  if (!is_pow2(n) || n < 16 || n > 1024 || (prec != PR_F64 && prec != PR_F32)) return -1;
+  return effective_split(n, prec == PR_F32);
+}
+
 int32_t pr_get_fine_plan(int32_t n, pr_dtype prec) {
   if (!is_pow2(n) || n < 16 || n > 1024 || (prec != PR_F64 && prec != PR_F32)) return -1;
   return effective_plan(n, prec == PR_F32);
@@ -1543,6 +1572,29 @@ pr_status pr_autotune_fine(const pr_problem* p, int64_t nfields, const double* u
       }
     }
     record_working_set(p->n, f32, bbest);
+  }
+  // the radix split of the streaming semi-implicit passes, where N has two
+  // (with the working set just recorded)
+  if (best == PR_PLAN_STREAM && !is_cn(p) && fine_radix_differs(p->n)) {
+    Events ev;
+    if (!ev.ok) return fail(PR_ERR_DEVICE, "hipEventCreate failed");
+    PR_HIP(launch_tables(p->n, p->laplacian, w, s));
+    float t[2] = {0.f, 0.f};
+    for (int r = 0; r < 2; ++r) {
+      StepJob j = make_job(p, p->dt, p->steps, f32, nfields, w);
+      j.resident = false;
+      j.radix = r;
+      j.in_base = u_in;
+      j.out_base = u_out;
+      j.out_f32 = 0;
+      PR_HIP(launch_steps(j, s));  // warm-up
+      PR_HIP(hipEventRecord(ev.e[0], s));
+      PR_HIP(launch_steps(j, s));
+      PR_HIP(hipEventRecord(ev.e[1], s));
+      PR_HIP(hipEventSynchronize(ev.e[1]));
+      t[r] = event_ms(ev.e[0], ev.e[1]);
+    }
+    g_split_tuned[l][f32 ? 1 : 0].store(t[1] < t[0] ? PR_FFT_SPLIT_R4_TAIL : PR_FFT_SPLIT_R8);
   }
   // the work queue against the per-pass launches (with the plan and the
   // working set just recorded), for the classes the queue covers

@@ -114,21 +114,39 @@ template <int LS, int SH = PR_PAD_SHIFT> struct LinePanel {
 // Twiddles.  Stage (Ns, R) needs w^(r k) = exp(-2 pi i r k / (Ns R)) for
 // r = 1..R-1, k = 0..Ns-1.  They are kept per stage as [r-1][k], so the
 // lanes of a wave (consecutive k) read consecutive entries.
-// Radix of the stage that follows Ns: 8 while it fits, the leftover 2 or 4
-// last.  (The leftover first measured 1.2-1.6x slower per step: a radix-2
-// or -4 first stage gives each thread two or four butterflies of strided
-// global loads.)
-template <int N> constexpr int stage_radix(int ns) { return (N / ns) >= 8 ? 8 : N / ns; }
+// Radix split: the radix of the stage that follows Ns.
+//   RS = 0: 8 while it fits, the leftover 2 or 4 last (N = 8^a * {1, 2, 4}).
+//   RS = 1: the same, except that a trailing 8 x 2 becomes 4 x 4, so that
+//           N = 8^a * 2 (16, 128, 1024) has no radix-2 stage; the other N
+//           have no such split and take RS = 0's stages.
+// Both take the fewest stages (LDS round trips) a thread's 8 elements
+// allow; which is faster is measured (pr_autotune_fine).  (The leftover
+// first measured 1.2-1.6x slower per step: a radix-2 or -4 first stage
+// gives each thread two or four butterflies of strided global loads.)
+template <int N, int RS = 0> constexpr int stage_radix(int ns) {
+  return (RS == 1 && N / ns == 16) ? 4 : (N / ns) >= 8 ? 8 : N / ns;
+}
+// Whether RS = 1 differs from RS = 0 for length N.
+template <int N> constexpr bool radix_split_differs() {
+  int l = 0;
+  while ((1 << l) < N) ++l;
+  return N >= 16 && l % 3 == 1;   // N = 8^a * 2, a >= 1
+}
+static_assert(radix_split_differs<16>() && radix_split_differs<128>() &&
+                  radix_split_differs<1024>() && !radix_split_differs<256>() &&
+                  !radix_split_differs<512>() && !radix_split_differs<64>() &&
+                  !radix_split_differs<32>(),
+              "radix splits");
 
-template <int N> constexpr int tw_offset(int ns_target) {
+template <int N, int RS = 0> constexpr int tw_offset(int ns_target) {
   int off = 0;
-  for (int ns = 1; ns < ns_target; ns *= stage_radix<N>(ns))
-    if (ns > 1) off += (stage_radix<N>(ns) - 1) * ns;
+  for (int ns = 1; ns < ns_target; ns *= stage_radix<N, RS>(ns))
+    if (ns > 1) off += (stage_radix<N, RS>(ns) - 1) * ns;
   return off;
 }
 
-template <int N> struct TwSize {
-  static constexpr int value = tw_offset<N>(N) > 0 ? tw_offset<N>(N) : 1;
+template <int N, int RS = 0> struct TwSize {
+  static constexpr int value = tw_offset<N, RS>(N) > 0 ? tw_offset<N, RS>(N) : 1;
 };
 
 // Compact table: per stage only the r = 1 row, w^k for k < Ns; the other
@@ -138,14 +156,14 @@ template <int N> struct TwSize {
 // entries and one more product.  Passed to the transforms wrapped in
 // TwPow, so that the stage code selects the form.
 constexpr int tw_pow_rows(int ns) { return ns > 64 ? ns / 8 + 8 : ns; }
-template <int N> constexpr int tw_offset_pow(int ns_target) {
+template <int N, int RS = 0> constexpr int tw_offset_pow(int ns_target) {
   int off = 0;
-  for (int ns = 1; ns < ns_target; ns *= stage_radix<N>(ns))
+  for (int ns = 1; ns < ns_target; ns *= stage_radix<N, RS>(ns))
     if (ns > 1) off += tw_pow_rows(ns);
   return off;
 }
-template <int N> struct TwSizePow {
-  static constexpr int value = tw_offset_pow<N>(N) > 0 ? tw_offset_pow<N>(N) : 1;
+template <int N, int RS = 0> struct TwSizePow {
+  static constexpr int value = tw_offset_pow<N, RS>(N) > 0 ? tw_offset_pow<N, RS>(N) : 1;
 };
 template <typename C> struct TwPow {
   const C* p;
@@ -153,12 +171,12 @@ template <typename C> struct TwPow {
 
 // Fill the per-stage table from g[t] = exp(-2 pi i t / N).  The caller
 // synchronises the block before the first transform.
-template <int N, int NT, typename C>
+template <int N, int NT, int RS = 0, typename C>
 __device__ __forceinline__ void load_stage_twiddles(C* tw, const C* g, int tid) {
-  for (int ns = 1; ns < N; ns *= stage_radix<N>(ns)) {
-    const int R = stage_radix<N>(ns);
+  for (int ns = 1; ns < N; ns *= stage_radix<N, RS>(ns)) {
+    const int R = stage_radix<N, RS>(ns);
     if (ns == 1) continue;
-    const int off = tw_offset<N>(ns), cnt = (R - 1) * ns;
+    const int off = tw_offset<N, RS>(ns), cnt = (R - 1) * ns;
     for (int i = tid; i < cnt; i += NT) {
       const int r = i / ns + 1, k = i % ns;
       tw[off + i] = g[r * k * (N / (ns * R))];
@@ -187,12 +205,12 @@ template <int N, int LINES, int ESIZE, int OTHER, int PLUS, int THREADS> struct 
 
 // Fill the compact table: stage (Ns, R) gets w^k = g[k N / (Ns R)], k < Ns
 // (factored into w^(8a), a < Ns / 8, and w^b, b < 8, when Ns > 64).
-template <int N, int NT, typename C>
+template <int N, int NT, int RS = 0, typename C>
 __device__ __forceinline__ void load_stage_twiddles_pow(C* tw, const C* g, int tid) {
-  for (int ns = 1; ns < N; ns *= stage_radix<N>(ns)) {
-    const int R = stage_radix<N>(ns);
+  for (int ns = 1; ns < N; ns *= stage_radix<N, RS>(ns)) {
+    const int R = stage_radix<N, RS>(ns);
     if (ns == 1) continue;
-    const int off = tw_offset_pow<N>(ns), stride = N / (ns * R);
+    const int off = tw_offset_pow<N, RS>(ns), stride = N / (ns * R);
     if (ns > 64) {
       for (int a = tid; a < ns / 8; a += NT) tw[off + a] = g[8 * a * stride];
       for (int b = tid; b < 8; b += NT) tw[off + ns / 8 + b] = g[b * stride];
@@ -226,8 +244,8 @@ struct NoEpi {
 // SIGN = -1 forward,
 // +1 inverse.  Each of the NT threads owns
 // G groups of eight elements.
-template <int N, int R, int NS, int SIGN, int NT, int G, bool LF, typename T, class TW, class Lay,
-          class Pro, class Epi>
+template <int N, int R, int NS, int SIGN, int NT, int G, bool LF, typename T, int RS, class TW,
+          class Lay, class Pro, class Epi>
 __device__ __forceinline__ void fft_stage(cpx<T>* buf, TW tw, Lay lay, int tid, Pro& pro,
                                           Epi& epi) {
   constexpr int NB = N / R;        // butterflies per line
@@ -257,7 +275,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, TW tw, Lay lay, int tid, 
     const int k = jj[q] % NS;
     if constexpr (NS > 1) {
       if constexpr (std::is_same<TW, TwPow<cpx<T>>>::value) {
-        constexpr int off = tw_offset_pow<N>(NS);
+        constexpr int off = tw_offset_pow<N, RS>(NS);
         cpx<T> w1;
         if constexpr (NS > 64) w1 = cmul(tw.p[off + k / 8], tw.p[off + NS / 8 + k % 8]);
         else w1 = tw.p[off + k];
@@ -271,7 +289,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, TW tw, Lay lay, int tid, 
       } else {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cpx<T> w = tw[tw_offset<N>(NS) + (r - 1) * NS + k];
+          cpx<T> w = tw[tw_offset<N, RS>(NS) + (r - 1) * NS + k];
           if constexpr (SIGN > 0) w.y = -w.y;
           v[q * R + r] = cmul(v[q * R + r], w);
         }
@@ -288,13 +306,13 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, TW tw, Lay lay, int tid, 
   if constexpr (kToLds) __syncthreads();
 }
 
-template <int N, int NS, int SIGN, int NT, int G, bool LF, typename T, class TW, class Lay, class Pro,
-          class Epi>
+template <int N, int NS, int SIGN, int NT, int G, bool LF, typename T, int RS, class TW, class Lay,
+          class Pro, class Epi>
 __device__ __forceinline__ void fft_from(cpx<T>* buf, TW tw, Lay lay, int tid, Pro& pro, Epi& epi) {
   if constexpr (NS < N) {
-    constexpr int R = stage_radix<N>(NS);
-    fft_stage<N, R, NS, SIGN, NT, G, LF, T>(buf, tw, lay, tid, pro, epi);
-    fft_from<N, NS * R, SIGN, NT, G, LF, T>(buf, tw, lay, tid, pro, epi);
+    constexpr int R = stage_radix<N, RS>(NS);
+    fft_stage<N, R, NS, SIGN, NT, G, LF, T, RS>(buf, tw, lay, tid, pro, epi);
+    fft_from<N, NS * R, SIGN, NT, G, LF, T, RS>(buf, tw, lay, tid, pro, epi);
   }
 }
 
@@ -305,11 +323,11 @@ __device__ __forceinline__ void fft_from(cpx<T>* buf, TW tw, Lay lay, int tid, P
 // of a stage belongs to line b / (N/R), position b % (N/R) (a line's
 // elements in consecutive lanes) or, with LF, to line b % lines, position
 // b / lines (the lines in consecutive lanes).
-template <int N, int SIGN, int NT, typename T, int G = 1, bool LF = false, class TW, class Lay,
-          class Pro = NoPro, class Epi = NoEpi>
+template <int N, int SIGN, int NT, typename T, int G = 1, bool LF = false, int RS = 0, class TW,
+          class Lay, class Pro = NoPro, class Epi = NoEpi>
 __device__ __forceinline__ void fft_lines(cpx<T>* buf, TW tw, Lay lay, int tid, Pro pro = Pro{},
                                           Epi epi = Epi{}) {
-  fft_from<N, 1, SIGN, NT, G, LF, T>(buf, tw, lay, tid, pro, epi);
+  fft_from<N, 1, SIGN, NT, G, LF, T, RS>(buf, tw, lay, tid, pro, epi);
 }
 
 // Deterministic block sum of one double per thread (fixed tree order).

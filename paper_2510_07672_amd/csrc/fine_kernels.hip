@@ -208,36 +208,38 @@ __device__ __forceinline__ void row_split_store(const cpx<T>* panel, cpx<T>* S, 
 // 16-byte elements, where it lets one more work-group share a CU) the
 // compact one of r = 1 rows, whose other powers the butterflies multiply
 // out.  TWN is the table's length in elements.
-template <int N, typename T> struct RowLS {
+template <int N, typename T, int RS = 0> struct RowLS {
   static constexpr bool kQuad = sizeof(T) == 8 && RowCfg<N, T>::PAIRS == 4 && N >= 128;
   static constexpr int E = (int)sizeof(cpx<T>), kOther = (RowCfg<N, T>::NT / 64 + 1) * 8 + 64;
-  using PF = LdsPlan<N, RowCfg<N, T>::PAIRS, E, TwSize<N>::value * E + kOther, kQuad ? 4 : 1,
+  using PF = LdsPlan<N, RowCfg<N, T>::PAIRS, E, TwSize<N, RS>::value * E + kOther, kQuad ? 4 : 1,
                      RowCfg<N, T>::NT>;
-  using PP = LdsPlan<N, RowCfg<N, T>::PAIRS, E, TwSizePow<N>::value * E + kOther, kQuad ? 4 : 1,
-                     RowCfg<N, T>::NT>;
+  using PP = LdsPlan<N, RowCfg<N, T>::PAIRS, E, TwSizePow<N, RS>::value * E + kOther,
+                     kQuad ? 4 : 1, RowCfg<N, T>::NT>;
   static constexpr bool TWP = E == 16 && PP::FIT > PF::FIT;
-  static constexpr int TWN = TWP ? TwSizePow<N>::value : TwSize<N>::value;
+  static constexpr int TWN = TWP ? TwSizePow<N, RS>::value : TwSize<N, RS>::value;
   static constexpr int SH = TWP ? PP::SH : PF::SH;
   static constexpr int value = N + (N >> SH) + (kQuad ? 4 : 1);
 };
 
 // Column-pass panel: CT whole columns next to the twiddles (and, for the
 // Picard pass, the symbol table).
-template <int N, typename T, int EXTRA = 0> struct ColLS {
+template <int N, typename T, int EXTRA = 0, int RS = 0> struct ColLS {
   static constexpr int E = (int)sizeof(cpx<T>);
-  using PF = LdsPlan<N, ColCfg<N>::CT, E, TwSize<N>::value * E + EXTRA + 64, 1, ColCfg<N>::NT>;
-  using PP = LdsPlan<N, ColCfg<N>::CT, E, TwSizePow<N>::value * E + EXTRA + 64, 1, ColCfg<N>::NT>;
+  using PF = LdsPlan<N, ColCfg<N>::CT, E, TwSize<N, RS>::value * E + EXTRA + 64, 1, ColCfg<N>::NT>;
+  using PP =
+      LdsPlan<N, ColCfg<N>::CT, E, TwSizePow<N, RS>::value * E + EXTRA + 64, 1, ColCfg<N>::NT>;
   static constexpr bool TWP = E == 16 && PP::FIT > PF::FIT;
-  static constexpr int TWN = TWP ? TwSizePow<N>::value : TwSize<N>::value;
+  static constexpr int TWN = TWP ? TwSizePow<N, RS>::value : TwSize<N, RS>::value;
   static constexpr int SH = TWP ? PP::SH : PF::SH;
   static constexpr int value = N + (N >> SH) + 1;
 };
 
-// Stage the block's twiddle table in LDS in the plan's form.
-template <int N, int NT, bool TWP, typename C>
+// Stage the block's twiddle table in LDS in the plan's form, for radix
+// split RS.
+template <int N, int NT, bool TWP, int RS = 0, typename C>
 __device__ __forceinline__ void load_twiddles(C* tw, const C* g, int tid) {
-  if constexpr (TWP) load_stage_twiddles_pow<N, NT>(tw, g, tid);
-  else load_stage_twiddles<N, NT>(tw, g, tid);
+  if constexpr (TWP) load_stage_twiddles_pow<N, NT, RS>(tw, g, tid);
+  else load_stage_twiddles<N, NT, RS>(tw, g, tid);
 }
 
 // The step parameters of field f: the launch argument, or the field's entry
@@ -267,17 +269,17 @@ __device__ __forceinline__ void row_rebuild_entry(cpx<T>* panel, Lay lay, int p,
 // Middle row pass of one tile whose pair spectra are in the panel: inverse
 // transforms, the right-hand side (with the tile's FP64 sum of f for the
 // mass multiplier), forward transforms, split and store to S.
-template <int N, typename T, int RHS, class TW>
+template <int N, typename T, int RHS, int RS = 0, class TW>
 __device__ __forceinline__ void row_mid_tile(cpx<T>* panel, TW tw, double* red,
                                              double* __restrict__ partials, cpx<T>* S, int64_t f,
                                              int tile, T a, T dt, int conservative, int tid) {
   using Cfg = RowCfg<N, T>;
   constexpr int PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
-  using Lay = LinePanel<RowLS<N, T>::value, RowLS<N, T>::SH>;
+  using Lay = LinePanel<RowLS<N, T, RS>::value, RowLS<N, T, RS>::SH>;
   const Lay lay{};
   double fsum = 0.0;
-  fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{}, RhsEpi<T, RHS>{a, dt, &fsum});
-  fft_lines<N, -1, NT, T>(panel, tw, lay, tid);
+  fft_lines<N, +1, NT, T, 1, false, RS>(panel, tw, lay, tid, NoPro{}, RhsEpi<T, RHS>{a, dt, &fsum});
+  fft_lines<N, -1, NT, T, 1, false, RS>(panel, tw, lay, tid);
   if (RHS == RHS_SSI && conservative) {
     const double s = block_sum<NT>(fsum, red, tid);
     if (tid == 0) partials[f * TILES + tile] = s;
@@ -287,7 +289,7 @@ __device__ __forceinline__ void row_mid_tile(cpx<T>* panel, TW tw, double* red,
 
 // First row pass of a call: the real FP64 state in, half spectra out.
 // Tile `tile` of field f; panel, tw_s and red are the block's LDS.
-template <int N, typename T, int RHS = RHS_SSI>
+template <int N, typename T, int RHS = RHS_SSI, int RS = 0>
 __device__ __forceinline__ void row_first_body(cpx<T>* panel, cpx<T>* tw_s, double* red,
                                                const CallDesc* __restrict__ desc,
                                                cpx<T>* __restrict__ spec,
@@ -298,18 +300,19 @@ __device__ __forceinline__ void row_first_body(cpx<T>* panel, cpx<T>* tw_s, doub
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT, TILES = Cfg::TILES;
-  constexpr int LS = RowLS<N, T>::value;
-  using Lay = LinePanel<LS, RowLS<N, T>::SH>;
-  const auto tw = twiddle_source<RowLS<N, T>::TWP>((const C*)tw_s);
+  using RL = RowLS<N, T, RS>;
+  using Lay = LinePanel<RL::value, RL::SH>;
+  const auto tw = twiddle_source<RL::TWP>((const C*)tw_s);
   const StepParams sp = field_params(desc, f, sp_arg);
   const int r0 = tile * TR;
   const Lay lay{};
-  load_twiddles<N, NT, RowLS<N, T>::TWP>(tw_s, tw_g, tid);
+  load_twiddles<N, NT, RL::TWP, RS>(tw_s, tw_g, tid);
   const T a = (T)sp.a, dt = (T)sp.dt;
   double fsum = 0.0;
   const double* u = desc->in_base + (desc->in_offs ? desc->in_offs[f] : f * (int64_t)N * N);
   __syncthreads();
-  fft_lines<N, -1, NT, T>(panel, tw, lay, tid, RealRowsPro<N, T, RHS>{u, r0, a, dt, &fsum});
+  fft_lines<N, -1, NT, T, 1, false, RS>(panel, tw, lay, tid,
+                                        RealRowsPro<N, T, RHS>{u, r0, a, dt, &fsum});
   if (RHS == RHS_SSI && sp.conservative) {
     const double s = block_sum<NT>(fsum, red, tid);
     if (tid == 0) partials[f * TILES + tile] = s;
@@ -317,23 +320,23 @@ __device__ __forceinline__ void row_first_body(cpx<T>* panel, cpx<T>* tw_s, doub
   row_split_store<N, T, PAIRS, NT>(panel, spec + f * (int64_t)(N / 2) * N, r0, tid, lay);
 }
 
-template <int N, typename T, int RHS = RHS_SSI>
+template <int N, typename T, int RHS = RHS_SSI, int RS = 0>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row_first(
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
     const cpx<T>* __restrict__ tw_g, StepParams sp_arg) {
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
-  __shared__ C panel[Cfg::PAIRS * RowLS<N, T>::value];
-  __shared__ C tw_s[RowLS<N, T>::TWN];
+  __shared__ C panel[Cfg::PAIRS * RowLS<N, T, RS>::value];
+  __shared__ C tw_s[RowLS<N, T, RS>::TWN];
   __shared__ double red[Cfg::NT / 64 + 1];
   const int64_t f = blockIdx.x / Cfg::TILES;
   if (f >= desc->nfields) return;
-  row_first_body<N, T, RHS>(panel, tw_s, red, desc, spec, partials, tw_g, sp_arg, f,
-                            (int)(blockIdx.x % Cfg::TILES), threadIdx.x);
+  row_first_body<N, T, RHS, RS>(panel, tw_s, red, desc, spec, partials, tw_g, sp_arg, f,
+                                (int)(blockIdx.x % Cfg::TILES), threadIdx.x);
 }
 
 // Middle and last row passes: tile `tile` (TR rows) of field f.
-template <int N, typename T, int MODE, int RHS = RHS_SSI>
+template <int N, typename T, int MODE, int RHS = RHS_SSI, int RS = 0>
 __device__ __forceinline__ void row_body(cpx<T>* panel, cpx<T>* tw_s, double* red,
                                          const CallDesc* __restrict__ desc,
                                          cpx<T>* __restrict__ spec, double* __restrict__ partials,
@@ -342,13 +345,13 @@ __device__ __forceinline__ void row_body(cpx<T>* panel, cpx<T>* tw_s, double* re
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
   constexpr int TR = Cfg::TR, PAIRS = Cfg::PAIRS, NT = Cfg::NT;
-  constexpr int LS = RowLS<N, T>::value;
-  using Lay = LinePanel<LS, RowLS<N, T>::SH>;
-  const auto tw = twiddle_source<RowLS<N, T>::TWP>((const C*)tw_s);
+  using RL = RowLS<N, T, RS>;
+  using Lay = LinePanel<RL::value, RL::SH>;
+  const auto tw = twiddle_source<RL::TWP>((const C*)tw_s);
   const StepParams sp = field_params(desc, f, sp_arg);
   const int r0 = tile * TR;
   const Lay lay{};
-  load_twiddles<N, NT, RowLS<N, T>::TWP>(tw_s, tw_g, tid);
+  load_twiddles<N, NT, RL::TWP, RS>(tw_s, tw_g, tid);
   C* S = spec + f * (int64_t)(N / 2) * N;
   const T a = (T)sp.a, dt = (T)sp.dt;
   // rebuild Z_j[kx] = R_2j[kx] + i R_2j+1[kx] for kx = 0..N-1
@@ -361,27 +364,27 @@ __device__ __forceinline__ void row_body(cpx<T>* panel, cpx<T>* tw_s, double* re
   __syncthreads();
   if constexpr (MODE == ROW_LAST) {
     const int64_t ob = desc->out_offs ? desc->out_offs[f] : f * (int64_t)N * N;
-    fft_lines<N, +1, NT, T>(panel, tw, lay, tid, NoPro{},
-                            RealRowsStore<N, T>{desc->out_base, ob, r0, desc->out_f32});
+    fft_lines<N, +1, NT, T, 1, false, RS>(panel, tw, lay, tid, NoPro{},
+                                          RealRowsStore<N, T>{desc->out_base, ob, r0, desc->out_f32});
   } else {
-    row_mid_tile<N, T, RHS>(panel, tw, red, partials, S, f, tile, a, dt, sp.conservative, tid);
+    row_mid_tile<N, T, RHS, RS>(panel, tw, red, partials, S, f, tile, a, dt, sp.conservative, tid);
   }
 }
 
 // One block per tile of TR rows of one field.
-template <int N, typename T, int MODE, int RHS = RHS_SSI>
+template <int N, typename T, int MODE, int RHS = RHS_SSI, int RS = 0>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, RowCfg<N, T>::NT))) void k_row(
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec, double* __restrict__ partials,
     const cpx<T>* __restrict__ tw_g, StepParams sp_arg) {
   using C = cpx<T>;
   using Cfg = RowCfg<N, T>;
-  __shared__ C panel[Cfg::PAIRS * RowLS<N, T>::value];
-  __shared__ C tw_s[RowLS<N, T>::TWN];
+  __shared__ C panel[Cfg::PAIRS * RowLS<N, T, RS>::value];
+  __shared__ C tw_s[RowLS<N, T, RS>::TWN];
   __shared__ double red[Cfg::NT / 64 + 1];
   const int64_t f = blockIdx.x / Cfg::TILES;
   if (f >= desc->nfields) return;
-  row_body<N, T, MODE, RHS>(panel, tw_s, red, desc, spec, partials, tw_g, sp_arg, f,
-                            (int)(blockIdx.x % Cfg::TILES), threadIdx.x);
+  row_body<N, T, MODE, RHS, RS>(panel, tw_s, red, desc, spec, partials, tw_g, sp_arg, f,
+                                (int)(blockIdx.x % Cfg::TILES), threadIdx.x);
 }
 
 // ------------------------------------------------------------ column pass
@@ -421,13 +424,13 @@ template <typename T> struct DivideEpi {
 
 // Column panel of CT columns next to the twiddles (and the symbol table
 // when it is kept in LDS).
-template <int N, typename T> using ColPanel = ColLS<N, T, PR_S2_LDS ? N * 8 : 0>;
+template <int N, typename T, int RS = 0> using ColPanel = ColLS<N, T, PR_S2_LDS ? N * 8 : 0, RS>;
 
 // One column tile: CT columns of field f from c0, at P.  Forward transform
 // (inputs from `pro`), division by the symbol (the packed column c = 0 with
 // the mass correction), inverse transform straight to P.  corr_sh must not
 // be read by any thread of the block from a previous tile any more.
-template <int N, typename T, class TW, class Pro>
+template <int N, typename T, int RS = 0, class TW, class Pro>
 __device__ __forceinline__ void col_tile(cpx<T>* panel, TW tw, double* corr_sh,
                                          const double* s2, const double* __restrict__ partials,
                                          cpx<T>* P, int64_t f, int c0, const StepParams& sp,
@@ -436,7 +439,7 @@ __device__ __forceinline__ void col_tile(cpx<T>* panel, TW tw, double* corr_sh,
   constexpr int NT = ColCfg<N>::NT;
   constexpr int TILES = RowCfg<N, T>::TILES;
   constexpr int E0 = (N + NT - 1) / NT;  // packed-column elements per thread
-  using Lay = LinePanel<ColPanel<N, T>::value, ColPanel<N, T>::SH>;
+  using Lay = LinePanel<ColPanel<N, T, RS>::value, ColPanel<N, T, RS>::SH>;
   const Lay lay{};
   if (tid == 0) {
     double corr = 0.0;
@@ -449,7 +452,8 @@ __device__ __forceinline__ void col_tile(cpx<T>* panel, TW tw, double* corr_sh,
   }
   // the forward transform's last stage ends with a block barrier, which
   // also publishes corr_sh
-  fft_lines<N, -1, NT, T, 1, SpecLayout<N>::LF>(panel, tw, lay, tid, pro, DivideEpi<T>{s2, sp, c0});
+  fft_lines<N, -1, NT, T, 1, SpecLayout<N>::LF, RS>(panel, tw, lay, tid, pro,
+                                                     DivideEpi<T>{s2, sp, c0});
   if (c0 == 0) {
     // packed column: z = A + iB with A the kx = 0 and B the kx = N/2
     // column spectra (both Hermitian in ky); scale A and B separately
@@ -476,12 +480,13 @@ __device__ __forceinline__ void col_tile(cpx<T>* panel, TW tw, double* corr_sh,
     }
     __syncthreads();
   }
-  fft_lines<N, +1, NT, T, 1, SpecLayout<N>::LF>(panel, tw, lay, tid, NoPro{}, ColStore<N, T>{P});
+  fft_lines<N, +1, NT, T, 1, SpecLayout<N>::LF, RS>(panel, tw, lay, tid, NoPro{},
+                                                     ColStore<N, T>{P});
 }
 
 // Column tile `blk` (CT columns) of field f; panel, tw_s, s2_s (PR_S2_LDS
 // only) and corr_sh are the block's LDS.
-template <int N, typename T>
+template <int N, typename T, int RS = 0>
 __device__ __forceinline__ void col_body(cpx<T>* panel, cpx<T>* tw_s, double* s2_s,
                                          double* corr_sh, const CallDesc* __restrict__ desc,
                                          cpx<T>* __restrict__ spec,
@@ -491,7 +496,7 @@ __device__ __forceinline__ void col_body(cpx<T>* panel, cpx<T>* tw_s, double* s2
                                          int64_t f, int blk, int tid) {
   using C = cpx<T>;
   constexpr int CT = ColCfg<N>::CT, NT = ColCfg<N>::NT;
-  const auto tw = twiddle_source<ColPanel<N, T>::TWP>((const C*)tw_s);
+  const auto tw = twiddle_source<ColPanel<N, T, RS>::TWP>((const C*)tw_s);
 #if PR_S2_LDS
   const double* s2 = s2_s;
 #else
@@ -501,24 +506,24 @@ __device__ __forceinline__ void col_body(cpx<T>* panel, cpx<T>* tw_s, double* s2
   const StepParams sp = field_params(desc, f, sp_arg);
   const int c0 = blk * CT;
   C* P = spec + f * (int64_t)(N / 2) * N + (int64_t)c0 * N;
-  load_twiddles<N, NT, ColPanel<N, T>::TWP>(tw_s, tw_g, tid);
+  load_twiddles<N, NT, ColPanel<N, T, RS>::TWP, RS>(tw_s, tw_g, tid);
 #if PR_S2_LDS
   for (int i = tid; i < N; i += NT) s2_s[i] = s2_g[i];
 #endif
   __syncthreads();
-  col_tile<N, T>(panel, tw, corr_sh, s2, partials, P, f, c0, sp, tid, ColLoad<N, T>{P});
+  col_tile<N, T, RS>(panel, tw, corr_sh, s2, partials, P, f, c0, sp, tid, ColLoad<N, T>{P});
 }
 
 // One block per column tile.
-template <int N, typename T>
+template <int N, typename T, int RS = 0>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k_col(
     const CallDesc* __restrict__ desc, cpx<T>* __restrict__ spec,
     const double* __restrict__ partials, const cpx<T>* __restrict__ tw_g,
     const double* __restrict__ s2_g, StepParams sp_arg) {
   using C = cpx<T>;
   constexpr int CT = ColCfg<N>::CT, BLK = ColCfg<N>::BLOCKS;
-  __shared__ C panel[CT * ColPanel<N, T>::value];
-  __shared__ C tw_s[ColPanel<N, T>::TWN];
+  __shared__ C panel[CT * ColPanel<N, T, RS>::value];
+  __shared__ C tw_s[ColPanel<N, T, RS>::TWN];
 #if PR_S2_LDS
   __shared__ double s2[N];
 #else
@@ -527,8 +532,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ColCfg<N>::NT))) void k
   __shared__ double corr_sh;
   const int64_t f = blockIdx.x / BLK;
   if (f >= desc->nfields) return;
-  col_body<N, T>(panel, tw_s, s2, &corr_sh, desc, spec, partials, tw_g, s2_g, sp_arg, f,
-                 (int)(blockIdx.x % BLK), threadIdx.x);
+  col_body<N, T, RS>(panel, tw_s, s2, &corr_sh, desc, spec, partials, tw_g, s2_g, sp_arg, f,
+                     (int)(blockIdx.x % BLK), threadIdx.x);
 }
 
 // ------------------------------------------------ Crank-Nicolson + Picard
@@ -849,9 +854,22 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, ResCfg<N>::NT))) void k
 
 __global__ void k_set_desc(CallDesc* d, CallDesc v) { *d = v; }
 
+bool fine_radix_differs(int n) {
+  switch (n) {
+    case 16: return radix_split_differs<16>();
+    case 32: return radix_split_differs<32>();
+    case 64: return radix_split_differs<64>();
+    case 128: return radix_split_differs<128>();
+    case 256: return radix_split_differs<256>();
+    case 512: return radix_split_differs<512>();
+    case 1024: return radix_split_differs<1024>();
+    default: return false;
+  }
+}
+
 // The 2 * steps + 1 launches of one streaming F call, for a grid of
 // `grid_fields` fields (blocks of fields beyond desc->nfields exit).
-template <int N, typename T>
+template <int N, typename T, int RS>
 static void enqueue_stream_steps(const StepJob& job, int64_t grid_fields, hipStream_t st) {
   using RC = RowCfg<N, T>;
   using CC = ColCfg<N>;
@@ -861,13 +879,13 @@ static void enqueue_stream_steps(const StepJob& job, int64_t grid_fields, hipStr
   const int64_t row_tiles = grid_fields * RC::TILES, col_tiles = grid_fields * CC::BLOCKS;
   const dim3 gfirst((unsigned)row_tiles), brow(RC::NT), bcol(CC::NT);
   const dim3 grow((unsigned)row_tiles), glast((unsigned)row_tiles), gcol((unsigned)col_tiles);
-  k_row_first<N, T><<<gfirst, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
+  k_row_first<N, T, RHS_SSI, RS><<<gfirst, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
   for (int s = 0; s < job.steps; ++s) {
-    k_col<N, T><<<gcol, bcol, 0, st>>>(d, spec, job.ws.partials, tw, job.ws.s2, job.sp);
+    k_col<N, T, RS><<<gcol, bcol, 0, st>>>(d, spec, job.ws.partials, tw, job.ws.s2, job.sp);
     if (s + 1 < job.steps)
-      k_row<N, T, ROW_MID><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
+      k_row<N, T, ROW_MID, RHS_SSI, RS><<<grow, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
   }
-  k_row<N, T, ROW_LAST><<<glast, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
+  k_row<N, T, ROW_LAST, RHS_SSI, RS><<<glast, brow, 0, st>>>(d, spec, job.ws.partials, tw, job.sp);
 }
 
 template <int N, typename T, int MODE>
@@ -912,8 +930,14 @@ static void enqueue_cn_steps(const StepJob& job, int64_t grid_fields, hipStream_
 
 template <int N, typename T>
 static void enqueue_steps(const StepJob& job, int64_t grid_fields, hipStream_t st) {
-  if (job.scheme == SCHEME_CN) enqueue_cn_steps<N, T>(job, grid_fields, st);
-  else enqueue_stream_steps<N, T>(job, grid_fields, st);
+  if (job.scheme == SCHEME_CN) {
+    enqueue_cn_steps<N, T>(job, grid_fields, st);
+  } else if constexpr (radix_split_differs<N>()) {
+    if (job.radix == 1) enqueue_stream_steps<N, T, 1>(job, grid_fields, st);
+    else enqueue_stream_steps<N, T, 0>(job, grid_fields, st);
+  } else {
+    enqueue_stream_steps<N, T, 0>(job, grid_fields, st);
+  }
 }
 
 // ---- replay of captured launch sequences
@@ -924,12 +948,13 @@ static void enqueue_steps(const StepJob& job, int64_t grid_fields, hipStream_t s
 // replayed; a replay serves any batch no larger than the captured grid.
 
 struct GraphKey {
-  int n, f32, steps, conservative, scheme, picard;
+  int n, f32, steps, conservative, scheme, picard, radix;
   double a, dt, lam, inv_n2;
   const void *desc, *spec, *xspec, *partials, *tw, *s2;
   bool same(const GraphKey& o) const {
     return n == o.n && f32 == o.f32 && steps == o.steps && conservative == o.conservative &&
-           scheme == o.scheme && picard == o.picard && a == o.a && dt == o.dt && lam == o.lam &&
+           scheme == o.scheme && picard == o.picard && radix == o.radix && a == o.a &&
+           dt == o.dt && lam == o.lam &&
            inv_n2 == o.inv_n2 && desc == o.desc && spec == o.spec && xspec == o.xspec &&
            partials == o.partials && tw == o.tw && s2 == o.s2;
   }
@@ -969,7 +994,8 @@ static hipError_t launch_stream_graph(const StepJob& job, hipStream_t st) {
   // such sequence with the same shape and workspace is the same graph
   const StepParams sp = job.params ? StepParams{0, 0, 0, 0, -1} : job.sp;
   GraphKey key{job.n, job.f32 ? 1 : 0, job.steps, sp.conservative, job.scheme,
-               job.scheme == SCHEME_CN ? job.picard : 0, sp.a, sp.dt, sp.lam, sp.inv_n2,
+               job.scheme == SCHEME_CN ? job.picard : 0, job.scheme == SCHEME_CN ? 0 : job.radix,
+               sp.a, sp.dt, sp.lam, sp.inv_n2,
                job.ws.desc, job.ws.spec, job.scheme == SCHEME_CN ? job.ws.xspec : nullptr,
                job.ws.partials, job.f32 ? (const void*)job.ws.tw32 : (const void*)job.ws.tw64,
                job.ws.s2};

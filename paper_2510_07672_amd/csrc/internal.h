@@ -117,6 +117,7 @@ struct StepJob {
   bool resident;             // one block per field, all steps in LDS (N <= 128)
   int64_t ws_override = -1;  // working-set budget in bytes for this call (-1: the setting)
   bool eager = false;        // launch kernel by kernel even with graphs on
+  int radix = 0;             // FFT radix split of the streaming semi-implicit passes (0, 1)
   FineWs ws;
 };
 
@@ -220,6 +221,10 @@ hipError_t launch_steps(const StepJob& job, hipStream_t st);
 bool fine_queue_supports(const StepJob& job);
 size_t fine_queue_ws_bytes(int64_t total_fields);
 hipError_t launch_fine_queue(const StepJob* jobs, int njobs, void* qws, hipStream_t st);
+// Whether N has a second FFT radix split (StepJob::radix = 1: a trailing
+// 8 x 2 as 4 x 4; N = 16, 128, 1024), built for the streaming
+// semi-implicit passes.
+bool fine_radix_differs(int n);
 void set_fine_queue(int mode);   // 0 off, 1 on, 2 on with no XCD-local hand-over
 int fine_queue_mode();
 bool fine_queue_enabled();

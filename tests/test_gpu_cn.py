@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def api():
     from paper_2510_07672_amd import api as A
-    assert A.pr_abi_version() == 12
+    assert A.pr_abi_version() == 13
     return A
 
 

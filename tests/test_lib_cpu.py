@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(L):
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(L.EXPORTED) == set(declared_functions())
-    assert lib.pr_abi_version() == 12
+    assert lib.pr_abi_version() == 13
 
 
 def test_library_exports_match_nm(L):
@@ -226,6 +226,33 @@ def test_coarse_tile_setting(L):
         assert lib.pr_get_coarse_tile(C.byref(g32), 256) == L.PR_CNN_TILE_8X32
     finally:
         assert lib.pr_set_coarse_tile(L.PR_CNN_TILE_AUTO) == L.PR_OK
+
+
+def test_fft_split_setting(L):
+    """The radix splits are AUTO, R8 and R4_TAIL per (N, precision); only
+    N = 16, 128 and 1024 have a second split, other N report R8 whatever
+    is set; bad N, precision or split values are rejected."""
+    lib = L.lib()
+    assert (L.PR_FFT_SPLIT_AUTO, L.PR_FFT_SPLIT_R8, L.PR_FFT_SPLIT_R4_TAIL) == (0, 1, 2)
+    try:
+        for n in (16, 32, 64, 128, 256, 512, 1024):
+            for prec in (L.PR_F64, L.PR_F32):
+                assert lib.pr_get_fft_split(n, prec) == L.PR_FFT_SPLIT_R8   # untuned
+                assert lib.pr_set_fft_split(n, prec, L.PR_FFT_SPLIT_R4_TAIL) == L.PR_OK
+                want = L.PR_FFT_SPLIT_R4_TAIL if n in (16, 128, 1024) else L.PR_FFT_SPLIT_R8
+                assert lib.pr_get_fft_split(n, prec) == want
+        assert lib.pr_set_fft_split(1000, L.PR_F64, 1) == L.PR_ERR_UNSUPPORTED
+        assert lib.pr_set_fft_split(2048, L.PR_F64, 1) == L.PR_ERR_UNSUPPORTED
+        assert lib.pr_set_fft_split(128, L.PR_BF16, 1) == L.PR_ERR_INVALID_ARG
+        for bad in (-1, 3):
+            assert lib.pr_set_fft_split(128, L.PR_F64, bad) == L.PR_ERR_INVALID_ARG
+        assert lib.pr_get_fft_split(128, L.PR_F64) == L.PR_FFT_SPLIT_R4_TAIL   # unchanged
+        assert lib.pr_get_fft_split(100, L.PR_F64) == -1
+        assert lib.pr_get_fft_split(128, L.PR_BF16) == -1
+    finally:
+        for n in (16, 32, 64, 128, 256, 512, 1024):
+            for prec in (L.PR_F64, L.PR_F32):
+                assert lib.pr_set_fft_split(n, prec, L.PR_FFT_SPLIT_AUTO) == L.PR_OK
 
 
 def test_working_set_setting(L):
