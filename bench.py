@@ -114,9 +114,11 @@ def measured_traffic(cfg_name, prec, n, nfields):
     def biggest(names):
         cands = [(int(k.split("@")[1]), v) for k, v in per.items() if k.split("@")[0] in names]
         return max(cands, key=lambda c: c[0]) if cands else None
-    # the middle row pass, with or without its right-hand-side template argument
-    row = biggest({f"pr::k_row<{n}, {t}, 1>", f"pr::k_row<{n}, {t}, 1, 0>"})
-    col = biggest({f"pr::k_col<{n}, {t}>"})
+    # the middle row pass and the column pass, named with or without their
+    # right-hand-side and radix-split template arguments
+    row = biggest({f"pr::k_row<{n}, {t}, 1>", f"pr::k_row<{n}, {t}, 1, 0>",
+                   f"pr::k_row<{n}, {t}, 1, 0, 0>", f"pr::k_row<{n}, {t}, 1, 0, 1>"})
+    col = biggest({f"pr::k_col<{n}, {t}>", f"pr::k_col<{n}, {t}, 0>", f"pr::k_col<{n}, {t}, 1>"})
     if row is None or col is None:
         return None
     fields_per_dispatch = col[0] * 16 // (n * n)
