@@ -439,6 +439,40 @@ def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32, los
     return api.CnnCoarse(ws, bs, act="gelu", residual=True, prec=prec), info
 
 
+WEIGHTS_DIR = os.path.join(ROOT, "paper_2510_07672_amd", "weights")
+
+
+def save_weights(path, g, info, cname, cfg):
+    """The workload's trained network as a plain .npz (FP32 arrays and a
+    JSON string: no pickles), with the recipe and the command that made it."""
+    import numpy as np
+    arrays = {}
+    for l, (w, b) in enumerate(g.layers()):
+        arrays[f"w{l}"] = w.detach().float().cpu().numpy()
+        arrays[f"b{l}"] = b.detach().float().cpu().numpy()
+    meta = {"workload": cname, "cnn": list(cfg["cnn"]), "training": info,
+            "command": "python bench.py " + " ".join(sys.argv[1:])}
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    np.savez(path, meta=np.array(json.dumps(meta)), **arrays)
+    note(f"weights saved to {path}")
+
+
+def load_weights(api, path, prec):
+    """A network stored by save_weights, evaluated in `prec`, and its
+    training record (recipe, command, file)."""
+    import numpy as np
+    import torch
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(str(z["meta"]))
+        L = meta["cnn"][0]
+        ws = [torch.from_numpy(z[f"w{l}"].copy()) for l in range(L)]
+        bs = [torch.from_numpy(z[f"b{l}"].copy()) for l in range(L)]
+    info = dict(meta.get("training") or {})
+    info["stored"] = os.path.relpath(path, ROOT)
+    info["command"] = meta.get("command")
+    return api.CnnCoarse(ws, bs, act="gelu", residual=True, prec=prec), info
+
+
 def training_bench(args):
     """Training (c4): one step = an 8-step rollout of the network on a
     batch of 32 trajectories at 256^2 (bf16 forward, FP32 gradients,
@@ -659,13 +693,23 @@ def run_config(args, cname, api, torch, synth, full=True):
     g_num = api.Coarse(dt=cfg["dt"] * c / cfg["g_steps"], steps=cfg["g_steps"], prec="f64")
     train_info = None
     if coarse == "cnn":
-        steps = cfg.get("train_steps", 0) if (args.train_steps is None or not full) else args.train_steps
-        n_traj = cfg.get("train_traj", 128) if (args.train_traj is None or not full) else args.train_traj
-        g, train_info = trained_cnn(api, p, cfg, args.cnn_prec, steps,
-                                    n_traj=n_traj, batch=args.train_batch,
-                                    loss=args.train_loss, lr_final=args.train_lr_final,
-                                    lr_drop=cfg.get("train_lr_drop") if args.train_lr_drop is None
-                                    else args.train_lr_drop, train_prec=args.train_prec)
+        # the network stored for the workload (paper_2510_07672_amd/weights,
+        # made by this script with --save-weights), unless training is asked for
+        stored = os.path.join(WEIGHTS_DIR, f"{cname}.npz")
+        asked = full and (args.train_steps is not None or args.train_loss != "mse")
+        if os.path.exists(stored) and not asked and not args.no_stored_weights:
+            g, train_info = load_weights(api, stored, args.cnn_prec)
+            note(f"{cname}: network loaded from {train_info['stored']}")
+        else:
+            steps = cfg.get("train_steps", 0) if (args.train_steps is None or not full) else args.train_steps
+            n_traj = cfg.get("train_traj", 128) if (args.train_traj is None or not full) else args.train_traj
+            g, train_info = trained_cnn(api, p, cfg, args.cnn_prec, steps,
+                                        n_traj=n_traj, batch=args.train_batch,
+                                        loss=args.train_loss, lr_final=args.train_lr_final,
+                                        lr_drop=cfg.get("train_lr_drop") if args.train_lr_drop is None
+                                        else args.train_lr_drop, train_prec=args.train_prec)
+            if full and args.save_weights:
+                save_weights(args.save_weights, g, train_info, cname, cfg)
     else:
         g = g_num
     u0 = torch.from_numpy(synth.random_ic(n, range(cfg["seed0"], cfg["seed0"] + B))).to("cuda")
@@ -842,6 +886,11 @@ def main():
     ap.add_argument("--train-steps", type=int, default=None,
                     help="Adam steps on fine trajectories before timing (network only); "
                          "default 2000 for c2 and 60 for c3")
+    ap.add_argument("--save-weights", default=None,
+                    help="store the network trained in this run (.npz) for later runs")
+    ap.add_argument("--no-stored-weights", action="store_true",
+                    help="train at run time even where paper_2510_07672_amd/weights holds "
+                         "the workload's network")
     ap.add_argument("--train-traj", type=int, default=None,
                     help="fine trajectories (16 slices each) the network is trained on "
                          "(default 512 for c2, 128 for c3)")

@@ -205,3 +205,28 @@ def test_pins_catch_zero_padding(monkeypatch):
     monkeypatch.setattr(cnn, "conv3x3_periodic", zero_pad)
     with pytest.raises(AssertionError):
         test_shift_equivariance("gelu")
+
+
+def test_stored_networks_load_without_pickles():
+    """The networks the benchmark loads (paper_2510_07672_amd/weights, made
+    by bench.py --save-weights): plain arrays and a JSON record, readable
+    with allow_pickle=False, shaped 1 -> C -> ... -> C -> 1 with 3 x 3
+    kernels, finite, and carrying the command that trained them."""
+    import glob
+    import json
+    import os
+    root = os.path.join(os.path.dirname(__file__), "..", "paper_2510_07672_amd", "weights")
+    files = sorted(glob.glob(os.path.join(root, "*.npz")))
+    assert files
+    for path in files:
+        with np.load(path, allow_pickle=False) as z:
+            meta = json.loads(str(z["meta"]))
+            L, C = meta["cnn"]
+            assert meta["command"].startswith("python bench.py ") and "--save-weights" in meta["command"]
+            assert meta["training"]["steps"] > 0
+            for l in range(L):
+                cin = 1 if l == 0 else C
+                cout = 1 if l == L - 1 else C
+                w, b = z[f"w{l}"], z[f"b{l}"]
+                assert w.shape == (cout, cin, 3, 3) and b.shape == (cout,)
+                assert w.dtype == np.float32 and np.isfinite(w).all() and np.isfinite(b).all()
