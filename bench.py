@@ -385,13 +385,21 @@ def calib_copy(nbytes=1 << 30, reps=3):
 
 
 def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32, loss="mse",
-                lr_final=None, lr_drop=None, train_prec="bf16"):
+                lr_final=None, lr_drop=None, train_prec="bf16", lr=1e-3, init=None):
     """The workload's network, trained with Adam on fine-solver trajectories
     from seeds 1000.. (bf16 forward, FP32 gradients, 8-step rollouts
-    checkpointed every 2), then evaluated in `prec`."""
+    checkpointed every 2), then evaluated in `prec`.  init: a stored network
+    (save_weights) to continue from instead of the seed-0 initialisation."""
     from paper_2510_07672_amd import train
     L, C = cfg["cnn"]
-    net = train.init_network(L, C, seed=0, prec=train_prec)
+    prior = None
+    if init:
+        g0, prior = load_weights(api, init, train_prec)
+        if (g0.n_layers, g0.channels) != (L, C):
+            raise SystemExit(f"{init} holds a {g0.n_layers} x {g0.channels} network, not {L} x {C}")
+        net = g0
+    else:
+        net = train.init_network(L, C, seed=0, prec=train_prec)
     info = None
     if steps > 0 and loss == "scheme":
         # Algorithm 1: subsets of `batch` random ICs evolved by G itself, 4
@@ -420,18 +428,24 @@ def trained_cnn(api, p, cfg, prec, steps, n_traj=512, n_slices=16, batch=32, los
         def progress(step, loss, ms):
             if step % 10 == 0 or step == steps:
                 note(f"train step {step}/{steps} loss {loss:.3e} ({ms:.0f} ms)")
-        log = train.train(net, p, data, steps=steps, batch=batch, rollout=8, ckpt=2, lr=1e-3,
+        log = train.train(net, p, data, steps=steps, batch=batch, rollout=8, ckpt=2, lr=lr,
                           progress=progress, lr_final=lr_final, lr_drop=lr_drop)
-        lr_txt = "1e-3"
+        lr_txt = f"{lr:g}"
         if lr_final is not None:
-            lr_txt = f"cosine 1e-3 -> {lr_final:g}"
+            lr_txt = f"cosine {lr:g} -> {lr_final:g}"
         elif lr_drop:
-            lr_txt = f"1e-3, then 1e-4 for the last {lr_drop:g} of the steps"
+            lr_txt = f"{lr:g}, then {lr / 10:g} for the last {lr_drop:g} of the steps"
         info = {"steps": steps, "lr": lr_txt, "forward_prec": train_prec,
                 "trajectories": n_traj, "slices_per_trajectory": n_slices,
                 "batch": batch,
                 "data_s": round(t_data, 2), "loss_first": log.loss[0], "loss_last": log.loss[-1],
                 "step_ms_median": round(sorted(log.step_ms)[len(log.step_ms) // 2], 2)}
+        if prior is not None:
+            # continued from a stored network: its record, and the total
+            info["continued_from"] = {k: prior.get(k) for k in ("stored", "command", "steps", "lr",
+                                                                "loss_last")}
+            info["steps"] = steps + int(prior.get("steps", 0))
+            info["steps_this_run"] = steps
         del data
     lay = net.layers()
     ws = [w.detach().float().cpu() for w, _ in lay]
@@ -707,7 +721,8 @@ def run_config(args, cname, api, torch, synth, full=True):
                                         n_traj=n_traj, batch=args.train_batch,
                                         loss=args.train_loss, lr_final=args.train_lr_final,
                                         lr_drop=cfg.get("train_lr_drop") if args.train_lr_drop is None
-                                        else args.train_lr_drop, train_prec=args.train_prec)
+                                        else args.train_lr_drop, train_prec=args.train_prec,
+                                        lr=args.train_lr, init=args.init_weights if full else None)
             if full and args.save_weights:
                 save_weights(args.save_weights, g, train_info, cname, cfg)
     else:
@@ -888,6 +903,10 @@ def main():
                          "default 2000 for c2 and 60 for c3")
     ap.add_argument("--save-weights", default=None,
                     help="store the network trained in this run (.npz) for later runs")
+    ap.add_argument("--init-weights", default=None,
+                    help="continue training from this stored network (.npz) instead of the "
+                         "seed-0 initialisation")
+    ap.add_argument("--train-lr", type=float, default=1e-3, help="Adam learning rate (start)")
     ap.add_argument("--no-stored-weights", action="store_true",
                     help="train at run time even where paper_2510_07672_amd/weights holds "
                          "the workload's network")
