@@ -224,6 +224,12 @@ template <int C, bool SPLIT, int TH_ = 8, int TW_ = 32> struct HidTile {
   // read, then the first layer's C x 9 weights and C biases (FP32).
   static constexpr int UH = HC::TH + 4, UW = HC::TW + 4;
   static constexpr size_t FIRST_BYTES = BYTES + (size_t)(UH * UW + 10 * C) * 4;
+  // At C = 48 the layer's biases (FP32) and, with TAIL, the last layer's
+  // packed weight fragments (2 LKB bf16x8 per lane) follow, staged once
+  // per work-group and read from LDS per 16-pixel block.
+  static constexpr int LKB = (C + 31) / 32;
+  static constexpr size_t STAGE_BYTES = C == 48 ? (size_t)C * 4 + (size_t)2 * LKB * 64 * 16 : 0;
+  static_assert(BYTES % 16 == 0 && FIRST_BYTES % 16 == 0, "staged block alignment");
 };
 
 // Tuning knobs (compile time): whether the last layer folds into the last
@@ -381,6 +387,9 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
   float* su = (float*)(smem + HT::BYTES);                     // FIRST: [UH][UW]
   float* sw0 = su + HT::UH * HT::UW;                          // FIRST: [C][9]
   float* sb0 = sw0 + 9 * C;                                   // FIRST: [C]
+  // C = 48: biases [C], then (TAIL) the last layer's fragments [2 LKB][64]
+  float* sbias = (float*)(smem + (FIRST ? HT::FIRST_BYTES : HT::BYTES));
+  bf16x8* swl = (bf16x8*)(sbias + C);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = lane & 15, g = lane >> 4;
@@ -398,6 +407,12 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
   // the whole kernel, or at C = 48 read per 16-pixel block (16-byte loads),
   // which leaves the registers the folded last layer needs at 2 waves per SIMD
   constexpr bool kBiasRegs = C != 48;
+  if constexpr (!kBiasRegs) {
+    // read after the tile loop's first barrier
+    for (int i = tid; i < C; i += H::NT) sbias[i] = b[i];
+    if constexpr (TAIL)
+      for (int i = tid; i < 2 * HT::LKB * 64; i += H::NT) swl[i] = WLp[i];
+  }
   float bias[NBL][4];
 #pragma unroll
   for (int j = 0; j < NBL; ++j) {
@@ -532,7 +547,7 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
 #pragma unroll
           for (int i = 0; i < 4; ++i) z[i] = acc[j][i] + bias[j][i];
         } else {
-          const float4 bv = *(const float4*)&b[och(nb, 4 * g)];
+          const float4 bv = *(const float4*)&sbias[och(nb, 4 * g)];
           z[0] = acc[j][0] + bv.x;
           z[1] = acc[j][1] + bv.y;
           z[2] = acc[j][2] + bv.z;
@@ -559,8 +574,8 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
               wh = lwhi[kb];
               wl = lwlo[kb];
             } else {
-              wh = WLp[(2 * kb) * 64 + lane];
-              wl = WLp[(2 * kb + 1) * 64 + lane];
+              wh = swl[(2 * kb) * 64 + lane];
+              wl = swl[(2 * kb + 1) * 64 + lane];
             }
             y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, wh, y, 0, 0, 0);
             y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, wl, y, 0, 0, 0);
@@ -2054,7 +2069,8 @@ template <int C, int SHAPE>
 static size_t hid_lds(bool split, bool first) {
   using S = HidTile<C, true, tile_h<SHAPE>(), tile_w<SHAPE>()>;
   using U = HidTile<C, false, tile_h<SHAPE>(), tile_w<SHAPE>()>;
-  return split ? (first ? S::FIRST_BYTES : S::BYTES) : (first ? U::FIRST_BYTES : U::BYTES);
+  return split ? (first ? S::FIRST_BYTES : S::BYTES) + S::STAGE_BYTES
+               : (first ? U::FIRST_BYTES : U::BYTES) + U::STAGE_BYTES;
 }
 
 size_t cnn_lds_bytes(int C, bool split, bool first, int shape) {
