@@ -604,17 +604,49 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
       for (int q = 0; q < NBLK; ++q) epilogue(m + q, acc[q]);
     }
   };
+  // FIRST: the state patch su[sy][sx] = u[y0 + sy - 2][x0 + sx - 2]
+  // (periodic) of tile tt, this thread's entries tid, tid + NT, .. into
+  // registers; the next tile's patch is fetched before the current tile's
+  // products, so that its loads are in flight during them (not where the
+  // registers would cost a wave per SIMD: 32 channels with TAIL)
+  constexpr bool kPrefetch = FIRST && !(C == 32 && TAIL);
+  constexpr int kUp = FIRST ? (HT::UH * HT::UW + H::NT - 1) / H::NT : 1;
+  double upatch[kUp];
+  auto fetch_patch = [&](int64_t tt) {
+    int64_t f_;
+    int y0_, x0_;
+    tile_at(tt, f_, y0_, x0_);
+    const double* u = fi.u_base + (fi.u_offs ? fi.u_offs[f_] : f_ * (int64_t)n * n);
+#pragma unroll
+    for (int k = 0; k < kUp; ++k) {
+      const int i = tid + k * H::NT;
+      if (i < HT::UH * HT::UW) {
+        const int sy = i / HT::UW, sx = i % HT::UW;
+        upatch[k] = u[(int64_t)((y0_ + sy - 2) & (n - 1)) * n + ((x0_ + sx - 2) & (n - 1))];
+      }
+    }
+  };
+  if constexpr (kPrefetch) {
+    if (blockIdx.x < tiles) fetch_patch(blockIdx.x);
+  }
   for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     int64_t f;
     int y0, x0;
     tile_at(t, f, y0, x0);
     __syncthreads();  // the previous tile is no longer read
     if constexpr (FIRST) {
-      // state patch: su[sy][sx] = u[y0 + sy - 2][x0 + sx - 2], periodic
-      const double* u = fi.u_base + (fi.u_offs ? fi.u_offs[f] : f * (int64_t)n * n);
-      for (int i = tid; i < HT::UH * HT::UW; i += H::NT) {
-        const int sy = i / HT::UW, sx = i % HT::UW;
-        su[i] = (float)u[(int64_t)((y0 + sy - 2) & (n - 1)) * n + ((x0 + sx - 2) & (n - 1))];
+      if constexpr (kPrefetch) {
+#pragma unroll
+        for (int k = 0; k < kUp; ++k) {
+          const int i = tid + k * H::NT;
+          if (i < HT::UH * HT::UW) su[i] = (float)upatch[k];
+        }
+      } else {
+        const double* u = fi.u_base + (fi.u_offs ? fi.u_offs[f] : f * (int64_t)n * n);
+        for (int i = tid; i < HT::UH * HT::UW; i += H::NT) {
+          const int sy = i / HT::UW, sx = i % HT::UW;
+          su[i] = (float)u[(int64_t)((y0 + sy - 2) & (n - 1)) * n + ((x0 + sx - 2) & (n - 1))];
+        }
       }
       __syncthreads();
       // tile pixel (ty, tx) is state point (y0 + ty - 1, x0 + tx - 1); its
@@ -650,6 +682,9 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
       __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed in LDS
     }
     __syncthreads();
+    if constexpr (kPrefetch) {
+      if (t + gridDim.x < tiles) fetch_patch(t + gridDim.x);
+    }
     compute_tile(t, tile);
   }
 }
