@@ -696,6 +696,93 @@ def network_only(args, api, torch, synth):
     return ck
 
 
+def _event_ms(torch, fn, reps, trials=3):
+    """Best of `trials` mean durations of fn() over `reps` calls (events on
+    torch's current stream, which the library launches on)."""
+    fn()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(trials):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        best = ms if best is None else min(best, ms)
+    return best
+
+
+def tile_sweep(args, api, torch, synth):
+    """The network's inference plans under each hidden-layer tile, per call,
+    on the workloads' shapes and a few others (seed-0 weights), and what
+    pr_autotune_coarse picks; the settings are restored to 'auto'."""
+    import ctypes
+    from paper_2510_07672_amd import _lib as Lb
+    from paper_2510_07672_amd import train
+    shapes = [(512, 6, 48, "bf16x2", 16), (512, 6, 48, "bf16", 16), (1024, 6, 48, "bf16x2", 4),
+              (64, 6, 48, "bf16x2", 16), (256, 4, 32, "bf16x2", 8), (256, 4, 32, "bf16x2", 64),
+              (128, 4, 32, "bf16x2", 32)]
+    rows = []
+    for n, L, C, prec, nf in shapes:
+        g = train.init_network(L, C, seed=1, prec=prec)
+        p = api.Problem(n=n, length=1.0, eps=0.01, conservative=True, stab=2.0, dt=1e-5, steps=10)
+        u = torch.from_numpy(synth.random_ic(n, range(nf))).to("cuda")
+        out = torch.empty_like(u)
+        wsb = api.workspace(Lb.lib().pr_coarse_workspace_bytes(ctypes.byref(p.c()),
+                                                                ctypes.byref(g.c()), nf), "cuda")
+        ms = {}
+        try:
+            for plan in ("layered", "folded"):
+                for tile in ("8x32", "16x16"):
+                    api.pr_set_coarse_plan(plan)
+                    api.pr_set_coarse_tile(tile)
+                    ms[f"{plan}/{tile}"] = round(_event_ms(
+                        torch, lambda: api.pr_coarse_apply(p, g, u, out=out, ws=wsb), 40), 4)
+        finally:
+            api.pr_set_coarse_plan("auto")
+            api.pr_set_coarse_tile("auto")
+        chosen = api.pr_autotune_coarse(p, g, u)
+        rows.append({"n": n, "layers": L, "channels": C, "prec": prec, "fields": nf,
+                     "ms_per_call": ms, "autotune": f"{chosen}/{api.pr_get_coarse_tile(g, n)}"})
+        note(f"tile sweep {n}^2 {L}x{C} {prec} x{nf}: {ms} -> {rows[-1]['autotune']}")
+    return {"sweep": "network plan x hidden-layer tile", "rows": rows}
+
+
+def split_sweep(args, api, torch, synth):
+    """The streaming semi-implicit fine step under both FFT radix splits
+    where they differ (N = 128, 1024), per step, with its algorithmic HBM
+    rate; the settings are restored to 'auto'."""
+    import ctypes
+    from paper_2510_07672_amd import _lib as Lb
+    cases = [(1024, "f64", 32, 20), (1024, "f64", 256, 10), (1024, "f32", 32, 20),
+             (1024, "f32", 256, 10), (128, "f64", 512, 50), (128, "f64", 4096, 20),
+             (128, "f32", 1024, 50)]
+    rows = []
+    for n, prec, nf, steps in cases:
+        p = api.Problem(n=n, length=1.0, eps=0.01, conservative=True, stab=2.0, dt=2e-5,
+                        steps=steps, fine_prec=prec)
+        u = torch.from_numpy(synth.random_ic(n, range(nf))).to("cuda")
+        wsb = api.workspace(Lb.lib().pr_fine_workspace_bytes(ctypes.byref(p.c()), nf), "cuda")
+        out = torch.empty_like(u)
+        bpp = 32 if prec == "f64" else 16
+        us, gbs = {}, {}
+        try:
+            api.pr_set_fine_plan(n, prec, "stream")
+            for split in ("r8", "r4_tail"):
+                api.pr_set_fft_split(n, prec, split)
+                t = _event_ms(torch, lambda: api.pr_fine_propagate(p, u, out=out, ws=wsb), 3)
+                us[split] = round(t * 1e3 / steps, 2)
+                gbs[split] = round(bpp * nf * n * n / (t * 1e-3 / steps) / 1e9, 1)
+        finally:
+            api.pr_set_fft_split(n, prec, "auto")
+            api.pr_set_fine_plan(n, prec, "auto")
+        rows.append({"n": n, "prec": prec, "fields": nf, "us_per_step": us, "GB_per_s": gbs})
+        note(f"split sweep {n}^2 {prec} x{nf}: {us}")
+    return {"sweep": "FFT radix split of the streaming semi-implicit step", "rows": rows}
+
+
 def run_config(args, cname, api, torch, synth, full=True):
     """The timed step and its sections for workload `cname` (c1, c2, c3)."""
     cfg = CONFIGS[cname]
@@ -932,6 +1019,12 @@ def main():
                          "(0 = one chunk, every field through each step in turn)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--tile-sweep", action="store_true",
+                    help="time the network's plans under each hidden-layer tile on several "
+                         "shapes, and the autotuner's choice (one JSON line)")
+    ap.add_argument("--split-sweep", action="store_true",
+                    help="time the fine step under both FFT radix splits where they differ "
+                         "(one JSON line)")
     ap.add_argument("--network-only", action="store_true",
                     help="time only the network G of the workload (seed-0 weights, --steps x 10 "
                          "calls) and print its per-call figures")
@@ -963,6 +1056,12 @@ def main():
         return
     if args.network_only:
         print(json.dumps(network_only(args, api, torch, synth)), flush=True)
+        return
+    if args.tile_sweep:
+        print(json.dumps(tile_sweep(args, api, torch, synth)), flush=True)
+        return
+    if args.split_sweep:
+        print(json.dumps(split_sweep(args, api, torch, synth)), flush=True)
         return
     if args.config == "c5":
         print(json.dumps(uneven_bench(args)), flush=True)
