@@ -783,6 +783,31 @@ def split_sweep(args, api, torch, synth):
     return {"sweep": "FFT radix split of the streaming semi-implicit step", "rows": rows}
 
 
+def size_sweep(args, api, torch, synth):
+    """The fine step (semi-implicit, streaming plan, default working-set
+    chunking and radix split) per step at the workloads' grid sizes and
+    batches, FP64 and FP32, with its algorithmic HBM rate."""
+    import ctypes
+    from paper_2510_07672_amd import _lib as Lb
+    cases = [(256, 512, 200), (512, 2048, 100), (1024, 256, 20)]
+    rows = []
+    for n, nf, steps in cases:
+        for prec in ("f64", "f32"):
+            p = api.Problem(n=n, length=1.0, eps=0.01, conservative=True, stab=2.0, dt=2e-5,
+                            steps=steps, fine_prec=prec)
+            u = torch.from_numpy(synth.random_ic(n, range(nf))).to("cuda")
+            wsb = api.workspace(Lb.lib().pr_fine_workspace_bytes(ctypes.byref(p.c()), nf), "cuda")
+            out = torch.empty_like(u)
+            t = _event_ms(torch, lambda: api.pr_fine_propagate(p, u, out=out, ws=wsb), 3)
+            bpp = 32 if prec == "f64" else 16
+            gbs = bpp * nf * n * n / (t * 1e-3 / steps) / 1e9
+            rows.append({"n": n, "fields": nf, "prec": prec, "us_per_step": round(t * 1e3 / steps, 1),
+                         "GB_per_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+            note(f"size sweep {n}^2 x{nf} {prec}: {rows[-1]['us_per_step']} us/step, {gbs:.0f} GB/s")
+            del u, out, wsb
+    return {"sweep": "fine step by grid size", "rows": rows}
+
+
 def run_config(args, cname, api, torch, synth, full=True):
     """The timed step and its sections for workload `cname` (c1, c2, c3)."""
     cfg = CONFIGS[cname]
@@ -1025,6 +1050,8 @@ def main():
     ap.add_argument("--split-sweep", action="store_true",
                     help="time the fine step under both FFT radix splits where they differ "
                          "(one JSON line)")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="time the fine step at 256^2, 512^2 and 1024^2, FP64 and FP32 (one JSON line)")
     ap.add_argument("--network-only", action="store_true",
                     help="time only the network G of the workload (seed-0 weights, --steps x 10 "
                          "calls) and print its per-call figures")
@@ -1062,6 +1089,9 @@ def main():
         return
     if args.split_sweep:
         print(json.dumps(split_sweep(args, api, torch, synth)), flush=True)
+        return
+    if args.size_sweep:
+        print(json.dumps(size_sweep(args, api, torch, synth)), flush=True)
         return
     if args.config == "c5":
         print(json.dumps(uneven_bench(args)), flush=True)
