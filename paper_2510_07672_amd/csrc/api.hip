@@ -1419,7 +1419,10 @@ pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nf
   // every (plan, hidden-layer tile) pair that exists for the shape; the
   // tile matters only to the plans with hidden-layer launches of 32 or 48
   // channels (LAYERED, FOLDED)
-  int best = PR_CNN_PLAN_LAYERED, best_tile = 0;
+  // best_tile: the fastest tile among the plans that have tiles (a FUSED
+  // win records no tile)
+  int best = PR_CNN_PLAN_LAYERED, best_tile = -1;
+  float best_tile_ms = -1.f;
   const bool bf16 = g->prec == PR_BF16 || g->prec == PR_BF16X2;
   const bool fused = cnn_fused_available(g->channels, g->n_layers, g->prec) && g->n_layers <= 10;
   const bool folded = cnn_folded_available(g->channels, g->n_layers, g->prec);
@@ -1452,6 +1455,9 @@ pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nf
         if (best_ms < 0.f || ms < best_ms) {
           best_ms = ms;
           best = plan;
+        }
+        if (ntiles > 1 && (best_tile_ms < 0.f || ms < best_tile_ms)) {
+          best_tile_ms = ms;
           best_tile = tile;
         }
       }
@@ -1460,7 +1466,7 @@ pr_status pr_autotune_coarse(const pr_problem* p, const pr_coarse* g, int64_t nf
     cnn_set_tile(saved_tile);
   }
   cnn_record_tuned(g->channels, g->n_layers, g->prec, best);
-  if (tiles) cnn_record_tile(g->channels, g->prec, p->n, best_tile);
+  if (tiles && best_tile >= 0) cnn_record_tile(g->channels, g->prec, p->n, best_tile);
   if (chosen) *chosen = best;
   return PR_OK;
 }
