@@ -11,12 +11,13 @@
 //                 channels (16 per block of a 16x16x32 bf16 MFMA), N = output
 //                 pixels (16 per block), K = 9 C ordered (tap, channel)
 //                 and padded to a multiple of 32; FP32 accumulation.  A
-//                 work-group stages a (TH+2) x (TW+2) input tile in LDS;
+//                 work-group stages a (TH+2) x (TW+2) input tile in LDS
+//                 (8 x 32 or, at 32 and 48 channels, 16 x 16 outputs);
 //                 the weights stay in registers.  With SPLIT the activation
 //                 is carried as hi + lo bfloat16 and every product is done
 //                 twice (hi W + lo W), which keeps ~16 mantissa bits.
-//   k_cnn_hidden_f32  the same layer on the vector ALU in FP32 (reference
-//                 precision).
+//   k_cnn_first_ref, k_cnn_hidden_ref, k_cnn_last_ref  the layers on the
+//                 vector ALU in FP32 or FP64 (the reference precisions).
 //   k_cnn_last_mma  C -> 1 on the matrix cores with the nine taps as the N
 //                 dimension, then a 3x3 gather of the per-tap products;
 //                 plus the residual, written in FP64, with per-tile FP64
@@ -24,7 +25,11 @@
 //   Folded inference plan: k_cnn_hidden computes the first layer on its own
 //                 input tile (FIRST) and, at C = 32 or 48, the last layer's
 //                 per-tap products in its epilogue (TAIL);
-//                 k_cnn_last_gather then sums the products over the taps.
+//                 k_cnn_last_gather / k_cnn_last_gather_lin then sum the
+//                 products over the taps (k_cnn_gather_correct also applies
+//                 the Parareal correction).
+//   k_cnn_fused   all layers of a call in one launch (16 x 16 output tiles,
+//                 halos recomputed, activations in LDS).
 //   k_cnn_fix     the uniform mass fix and the limiter.
 #include <hip/hip_runtime.h>
 
@@ -42,30 +47,36 @@ typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
 // GELU(x) = x/2 (1 + erf(x / sqrt 2)) in FP32 without branches.  With
-// z = |x| / sqrt 2 and E = erfc(z), 1 + erf(x / sqrt 2) is 2 - E for x >= 0
-// and E for x < 0.  E comes from the Chebyshev-fitted form
+// z = |x| / sqrt 2, erfc(z) comes from the Chebyshev-fitted form
 // erfc(z) = t exp(-z^2 + P(t)), t = 1 / (1 + z / 2), P of degree 9, whose
 // fractional error is below 1.2e-7 for every z >= 0 (Press et al.,
-// Numerical Recipes, 2nd ed., Section 6.2): one reciprocal, one exp2 and
-// eleven FMAs, where the library's erff evaluates two branches across a
-// wave.  Relative error of the result: a few FP32 ulps where the factor
-// 1 + erf is not small, and ~1e-6 of a value that is already below 1e-5
-// of x where it is (x < -5).
+// Numerical Recipes, 2nd ed., Section 6.2).  With h = x erfc(z) / 2 the
+// result is x - h for x >= 0 and h for x < 0; h has the sign of x, so both
+// cases are max(x, 0) - |x t| 2^(log2(e) (P(t) - z^2) - 1), one FMA.  The
+// factor log2(e) and the -1 sit in P's coefficients (each rounded once from
+// its double-precision product): one reciprocal, one exp2 and 15 other
+// instructions, where the library's erff evaluates two branches across a
+// wave.  Relative error of the result in FP32 with a correctly rounded
+// reciprocal and exp2: below 5e-7 for x > -2, 1.3e-6 down to x = -5 and
+// 3.2e-6 of a value that is already below 1e-5 of x beyond.
 __device__ __forceinline__ float gelu_f32(float x) {
-  const float z = fabsf(x) * 0.70710678118654752440f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.0f));
-  float p = 0.17087277f;
-  p = fmaf(p, t, -0.82215223f);
-  p = fmaf(p, t, 1.48851587f);
-  p = fmaf(p, t, -1.13520398f);
-  p = fmaf(p, t, 0.27886807f);
-  p = fmaf(p, t, -0.18628806f);
-  p = fmaf(p, t, 0.09678418f);
-  p = fmaf(p, t, 0.37409196f);
-  p = fmaf(p, t, 1.00002368f);
-  p = fmaf(p, t, -1.26551223f);
-  const float e = t * __builtin_amdgcn_exp2f(fmaf(-z, z, p) * 1.44269504088896340736f);
-  return 0.5f * x * (x >= 0.f ? 2.f - e : e);
+  constexpr double L = 1.44269504088896340736;  // log2(e)
+  const float t = __builtin_amdgcn_rcpf(fmaf(fabsf(x), 0.35355339059327376220f, 1.0f));
+  float p = (float)(0.17087277 * L);
+  p = fmaf(p, t, (float)(-0.82215223 * L));
+  p = fmaf(p, t, (float)(1.48851587 * L));
+  p = fmaf(p, t, (float)(-1.13520398 * L));
+  p = fmaf(p, t, (float)(0.27886807 * L));
+  p = fmaf(p, t, (float)(-0.18628806 * L));
+  p = fmaf(p, t, (float)(0.09678418 * L));
+  p = fmaf(p, t, (float)(0.37409196 * L));
+  p = fmaf(p, t, (float)(1.00002368 * L));
+  p = fmaf(p, t, (float)(-1.26551223 * L - 1.0));
+  const float e = __builtin_amdgcn_exp2f(fmaf(x * (float)(-0.5 * L), x, p));
+  // max(x, 0) as a signed-integer max of the bit pattern (one instruction:
+  // negative values, -0 included, have the sign bit set)
+  const float relu = __int_as_float(max(__float_as_int(x), 0));
+  return fmaf(-fabsf(x * t), e, relu);
 }
 
 __device__ __forceinline__ float act_fn(float x, int act) {
@@ -360,8 +371,19 @@ template <int C> constexpr bool both_tile_shapes() { return C == 32 || C == 48; 
 template <int C, bool TAIL> constexpr bool hidden_nbw() { return PR_HID48_NBW && C == 48 && !TAIL; }
 template <int C, bool TAIL> constexpr int hidden_waves() { return hidden_nbw<C, TAIL>() ? 6 : 4; }
 
+// Waves per SIMD the register allocator must leave room for: at 48
+// channels 2 (3 with the channel blocks split over waves); at 32 channels 3,
+// which the compiler would otherwise give up for a few registers in some
+// variants, except the bf16 kernel with both the first and the last layer
+// folded in, which would then spill.
+template <int C, bool SPLIT, bool FIRST, bool TAIL> constexpr int hidden_min_waves() {
+  if constexpr (C == 48) return hidden_nbw<C, TAIL>() ? 3 : PR_HID48_WAVES;
+  if constexpr (C == 32) return (FIRST && TAIL && !SPLIT) ? 1 : 3;
+  return 1;
+}
+
 template <int C, bool SPLIT, bool FIRST = false, bool TAIL = false, int SHAPE = 0>
-__global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribute__((amdgpu_waves_per_eu(C == 48 ? (hidden_nbw<C, TAIL>() ? 3 : PR_HID48_WAVES) : 1))) void k_cnn_hidden(
+__global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribute__((amdgpu_waves_per_eu(hidden_min_waves<C, SPLIT, FIRST, TAIL>()))) void k_cnn_hidden(
     const __bf16* __restrict__ in, const __bf16* __restrict__ in_lo, int n, int64_t nfields,
     const __bf16* __restrict__ Wp, const float* __restrict__ b, int act,
     __bf16* __restrict__ out, __bf16* __restrict__ out_lo, float* __restrict__ zout,
