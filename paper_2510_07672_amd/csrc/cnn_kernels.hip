@@ -206,6 +206,24 @@ __global__ __launch_bounds__(256) void k_cnn_first(const double* __restrict__ u_
 
 // ----------------------------------------------------------- hidden layers
 
+// x / D for 0 <= x < LIMIT as (x M) >> S with one 24-bit multiply (full
+// rate on the vector ALU, where a 32-bit division by a constant takes
+// quarter-rate high-half multiplies).  M and S are fixed at compile time and
+// the quotient is checked against x / D for every x below LIMIT.
+constexpr bool div24_exact(int d, int limit, unsigned m, int s) {
+  for (int x = 0; x < limit; ++x)
+    if ((unsigned long long)x * m >= (1ull << 32) || (int)(((unsigned long long)x * m) >> s) != x / d)
+      return false;
+  return true;
+}
+template <int D, int LIMIT> struct Div24 {
+  static constexpr int S = 20;
+  static constexpr unsigned M = ((1u << S) + D - 1) / D;
+  static_assert(LIMIT < (1 << 24) && M < (1u << 24) && div24_exact(D, LIMIT, M, S),
+                "24-bit reciprocal division is not exact on this range");
+  __device__ static int div(int x) { return (int)(__umul24((unsigned)x, M) >> S); }
+};
+
 template <int C, int NWAVES = 4, int TH_ = 8, int TW_ = 32> struct HidCfg {
   static constexpr int TH = TH_, TW = TW_;           // output tile (rows, columns)
   static constexpr int NW = NWAVES, NT = 64 * NW;    // waves, threads
@@ -476,22 +494,36 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
   // the 16-byte chunk s % SP of tile pixel s / SP (SP = PS / 8 chunks per
   // pixel: C / 8 hi chunks, with SPLIT C / 8 lo chunks, then the pad, which
   // no lane loads).  Offsets within a field are 32-bit.
+  // The slot's pixel and chunk, and the pixel's row and column, come from
+  // 24-bit reciprocal multiplies, the byte offset within the field is 32-bit
+  // (n a power of two up to 4096), and the slot base is scalar (it sets the
+  // LDS address of the wave's load).
   auto load_tile = [&](int64_t tt, __bf16* dst) {
     int64_t f_;
     int y0_, x0_;
     tile_at(tt, f_, y0_, x0_);
     constexpr int SP = HT::PS / 8, NSLOT = H::TPIX * SP, DATA = (SPLIT ? 2 : 1) * (C / 8);
-    const __bf16* hb = in + f_ * (int64_t)n * n * C;
-    const __bf16* lb = SPLIT ? in_lo + f_ * (int64_t)n * n * C : hb;
-    for (int s0 = wave * 64; s0 < NSLOT; s0 += H::NT) {
+    constexpr int RW = H::TW + 2;
+    using DivS = Div24<SP, NSLOT>;
+    using DivR = Div24<RW, H::TPIX>;
+    const char* hb = (const char*)(in + f_ * (int64_t)n * n * C);
+    // byte distance from a hi chunk to the same chunk's lo values
+    const int64_t dlo = SPLIT ? (const char*)(in_lo + f_ * (int64_t)n * n * C) - hb : 0;
+    const int ym = y0_ - 1, xm = x0_ - 1, msk = n - 1, ln = __builtin_ctz(n);
+    const int w0 = __builtin_amdgcn_readfirstlane(wave) * 64;
+    for (int s0 = w0; s0 < NSLOT; s0 += H::NT) {
       const int sl = s0 + lane;
-      const int pp = sl / SP, j = sl - pp * SP;
+      const int pp = DivS::div(sl), j = sl - __mul24(pp, SP);
       if (sl < NSLOT && j < DATA) {
         const bool lo = SPLIT && j >= C / 8;
         const int c8 = lo ? j - C / 8 : j;
-        const int ty = pp / (H::TW + 2), tx = pp - ty * (H::TW + 2);
-        const int gy = (y0_ + ty - 1) & (n - 1), gx = (x0_ + tx - 1) & (n - 1);
-        const __bf16* src = (lo ? lb : hb) + ((gy * n + gx) * C + c8 * 8);
+        const int ty = DivR::div(pp);
+        int tx = pp - __mul24(ty, RW);
+        asm volatile("" : "+v"(tx));  // keeps tx a 24-bit multiply-add of its own
+        const int gy = (ym + ty) & msk, gx = (xm + tx) & msk;
+        // byte offset of the chunk within the field's hi plane (< 2^31)
+        const unsigned off = __umul24((unsigned)((gy << ln) | gx), (unsigned)(2 * C)) + (unsigned)(c8 * 16);
+        const char* src = hb + (lo ? dlo : (int64_t)0) + off;
         __builtin_amdgcn_global_load_lds((const void*)src,
                                          (__attribute__((address_space(3))) void*)(dst + s0 * 8),
                                          16, 0, 0);
