@@ -474,9 +474,6 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
   if constexpr (TAIL && kTailRegs) last_weights<C>(WL, lane, lwhi, lwlo);
   const int64_t yplane = nfields * (int64_t)n * n;
 
-  // LDS element of 16-byte chunk i of the tile (pixel i / (C/8) of the
-  // (TH+2) x (TW+2) region, channels 8 (i % (C/8)) ..)
-  auto lidx = [&](int i) { return (i / (C / 8)) * HT::PS + (i % (C / 8)) * 8; };
   if constexpr (FIRST) {
     for (int i = tid; i < 9 * C; i += H::NT) sw0[i] = fi.W[i];
     for (int i = tid; i < C; i += H::NT) sb0[i] = fi.b[i];
@@ -708,12 +705,17 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
       // one pixel, as in k_cnn_first.
       auto first_tile = [&](auto tanh_tag) {
         constexpr bool kTanh = decltype(tanh_tag)::value;
+        // item -> (pixel, channel group) and pixel -> (row, column) by
+        // 24-bit reciprocal multiplies, as in load_tile
+        using DivG = Div24<C / 8, H::TCH>;
+        using DivR = Div24<H::TW + 2, H::TPIX>;
         for (int item = tid; item < H::TCH; item += H::NT) {
-          const int c8 = item % (C / 8), px = item / (C / 8);
-          const int ty = px / (H::TW + 2), tx = px % (H::TW + 2);
+          const int px = DivG::div(item), c8 = item - __mul24(px, C / 8);
+          const int ty = DivR::div(px), tx = px - __mul24(ty, H::TW + 2);
+          const int ub = __mul24(ty, HT::UW) + tx;
           float v[9];
 #pragma unroll
-          for (int tp = 0; tp < 9; ++tp) v[tp] = su[(ty + tp / 3) * HT::UW + tx + tp % 3];
+          for (int tp = 0; tp < 9; ++tp) v[tp] = su[ub + (tp / 3) * HT::UW + tp % 3];
           bf16x8 h, l;
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
@@ -725,8 +727,10 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
             h[j] = (__bf16)r;
             l[j] = (__bf16)(r - (float)h[j]);
           }
-          *(bf16x8*)&tile[lidx(item)] = h;
-          if constexpr (SPLIT) *(bf16x8*)&tile_lo[lidx(item)] = l;
+          // LDS element of the item's 16-byte chunk: pixel px, channels 8 c8 ..
+          const int li = __mul24(px, HT::PS) + c8 * 8;
+          *(bf16x8*)&tile[li] = h;
+          if constexpr (SPLIT) *(bf16x8*)&tile_lo[li] = l;
         }
       };
       if (act == kActTanh) first_tile(std::true_type{});
