@@ -88,7 +88,7 @@ def network_traffic(cfg_name):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("src_hash") != kernel_src_hash(("cnn_kernels.hip", "internal.h")):
+    if d.get("src_hash") != kernel_src_hash(("cnn_kernels.hip", "gelu_coef.h", "internal.h")):
         return None
     return d["bytes_per_call"]
 

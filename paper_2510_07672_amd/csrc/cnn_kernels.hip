@@ -39,6 +39,7 @@
 #include <utility>
 
 #include "internal.h"
+#include "gelu_coef.h"
 
 namespace pr {
 
@@ -47,31 +48,24 @@ typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
 // GELU(x) = x/2 (1 + erf(x / sqrt 2)) in FP32 without branches.  With
-// z = |x| / sqrt 2, erfc(z) comes from the Chebyshev-fitted form
-// erfc(z) = t exp(-z^2 + P(t)), t = 1 / (1 + z / 2), P of degree 9, whose
-// fractional error is below 1.2e-7 for every z >= 0 (Press et al.,
-// Numerical Recipes, 2nd ed., Section 6.2).  With h = x erfc(z) / 2 the
-// result is x - h for x >= 0 and h for x < 0; h has the sign of x, so both
-// cases are max(x, 0) - |x t| 2^(log2(e) (P(t) - z^2) - 1), one FMA.  The
-// factor log2(e) and the -1 sit in P's coefficients (each rounded once from
-// its double-precision product): one reciprocal, one exp2 and 15 other
-// instructions, where the library's erff evaluates two branches across a
-// wave.  Relative error of the result in FP32 with a correctly rounded
-// reciprocal and exp2: below 5e-7 for x > -2, 1.3e-6 down to x = -5 and
-// 3.2e-6 of a value that is already below 1e-5 of x beyond.
+// z = |x| / sqrt 2, erfc(z) takes the form t exp(-z^2 + Q(t)),
+// t = 1 / (1 + 0.3 z); with h = x erfc(z) / 2 the result is x - h for x >= 0
+// and h for x < 0, and h has the sign of x, so both cases are
+// max(x, 0) - |x t| 2^(P(t) - z^2 log2(e)), one FMA, where P = log2(e) Q - 1
+// is a degree-7 polynomial fitted to that exponent on z in [0, 6.5]
+// (gelu_coef.h, written by gelu_fit.py; its error there is below 2.5e-7,
+// a relative error of erfc below 1.7e-7).
+// One reciprocal, one exp2 and 13 other instructions, where the library's
+// erff evaluates two branches across a wave.  Relative error of the result
+// in FP32 with a correctly rounded reciprocal and exp2: below 6e-7 for
+// |x| < 2, 1.5e-6 down to x = -5 and a few 1e-6 of a value that is already
+// below 1e-5 of x beyond.
 __device__ __forceinline__ float gelu_f32(float x) {
   constexpr double L = 1.44269504088896340736;  // log2(e)
-  const float t = __builtin_amdgcn_rcpf(fmaf(fabsf(x), 0.35355339059327376220f, 1.0f));
-  float p = (float)(0.17087277 * L);
-  p = fmaf(p, t, (float)(-0.82215223 * L));
-  p = fmaf(p, t, (float)(1.48851587 * L));
-  p = fmaf(p, t, (float)(-1.13520398 * L));
-  p = fmaf(p, t, (float)(0.27886807 * L));
-  p = fmaf(p, t, (float)(-0.18628806 * L));
-  p = fmaf(p, t, (float)(0.09678418 * L));
-  p = fmaf(p, t, (float)(0.37409196 * L));
-  p = fmaf(p, t, (float)(1.00002368 * L));
-  p = fmaf(p, t, (float)(-1.26551223 * L - 1.0));
+  const float t = __builtin_amdgcn_rcpf(fmaf(fabsf(x), kGeluT, 1.0f));
+  float p = kGeluP[0];
+#pragma unroll
+  for (int i = 1; i <= kGeluDeg; ++i) p = fmaf(p, t, kGeluP[i]);
   const float e = __builtin_amdgcn_exp2f(fmaf(x * (float)(-0.5 * L), x, p));
   // max(x, 0) as a signed-integer max of the bit pattern (one instruction:
   // negative values, -0 included, have the sign bit set)
