@@ -485,39 +485,45 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
   // the 16-byte chunk s % SP of tile pixel s / SP (SP = PS / 8 chunks per
   // pixel: C / 8 hi chunks, with SPLIT C / 8 lo chunks, then the pad, which
   // no lane loads).  Offsets within a field are 32-bit.
-  // The slot's pixel and chunk, and the pixel's row and column, come from
-  // 24-bit reciprocal multiplies, the byte offset within the field is 32-bit
-  // (n a power of two up to 4096), and the slot base is scalar (it sets the
-  // LDS address of the wave's load).
+  // Each step covers DP whole pixels (STEP = DP SP slots, at most NT): a
+  // lane keeps its chunk j, so its plane (hi or lo) and source base, and
+  // its pixel advances by DP, i.e. DP / RW rows and DP % RW columns with at
+  // most one more wrap.  The lane's first pixel and chunk come from 24-bit
+  // reciprocal multiplies once per tile, the byte offset within the field is
+  // 32-bit (n a power of two up to 4096), and the slot base is scalar (it
+  // sets the LDS address of the wave's load).  Lanes past STEP and pad
+  // chunks load nothing.
   auto load_tile = [&](int64_t tt, __bf16* dst) {
     int64_t f_;
     int y0_, x0_;
     tile_at(tt, f_, y0_, x0_);
     constexpr int SP = HT::PS / 8, NSLOT = H::TPIX * SP, DATA = (SPLIT ? 2 : 1) * (C / 8);
-    constexpr int RW = H::TW + 2;
-    using DivS = Div24<SP, NSLOT>;
-    using DivR = Div24<RW, H::TPIX>;
-    const char* hb = (const char*)(in + f_ * (int64_t)n * n * C);
-    // byte distance from a hi chunk to the same chunk's lo values
-    const int64_t dlo = SPLIT ? (const char*)(in_lo + f_ * (int64_t)n * n * C) - hb : 0;
-    const int ym = y0_ - 1, xm = x0_ - 1, msk = n - 1, ln = __builtin_ctz(n);
+    constexpr int RW = H::TW + 2, DP = H::NT / SP, STEP = DP * SP;
+    using DivS = Div24<SP, H::NT>;
+    using DivR = Div24<RW, H::NT / SP + 1>;
     const int w0 = __builtin_amdgcn_readfirstlane(wave) * 64;
-    for (int s0 = w0; s0 < NSLOT; s0 += H::NT) {
-      const int sl = s0 + lane;
-      const int pp = DivS::div(sl), j = sl - __mul24(pp, SP);
-      if (sl < NSLOT && j < DATA) {
-        const bool lo = SPLIT && j >= C / 8;
-        const int c8 = lo ? j - C / 8 : j;
-        const int ty = DivR::div(pp);
-        int tx = pp - __mul24(ty, RW);
-        asm volatile("" : "+v"(tx));  // keeps tx a 24-bit multiply-add of its own
+    const int q = w0 + lane;  // the lane's slot within a step
+    const int pp = DivS::div(q), j = q - __mul24(pp, SP);
+    int ty = DivR::div(pp), tx = pp - __mul24(ty, RW);
+    const bool lo = SPLIT && j >= C / 8;
+    const unsigned c16 = (unsigned)((lo ? j - C / 8 : j) * 16);
+    const char* base = (const char*)((lo ? in_lo : in) + f_ * (int64_t)n * n * C);
+    const bool live = q < STEP && j < DATA;
+    const int ym = y0_ - 1, xm = x0_ - 1, msk = n - 1, ln = __builtin_ctz(n);
+    for (int s0 = 0; s0 < NSLOT; s0 += STEP) {
+      if (live && q < NSLOT - s0) {
         const int gy = (ym + ty) & msk, gx = (xm + tx) & msk;
-        // byte offset of the chunk within the field's hi plane (< 2^31)
-        const unsigned off = __umul24((unsigned)((gy << ln) | gx), (unsigned)(2 * C)) + (unsigned)(c8 * 16);
-        const char* src = hb + (lo ? dlo : (int64_t)0) + off;
-        __builtin_amdgcn_global_load_lds((const void*)src,
-                                         (__attribute__((address_space(3))) void*)(dst + s0 * 8),
+        // byte offset of the chunk within its field's plane (< 2^31)
+        const unsigned off = __umul24((unsigned)((gy << ln) | gx), (unsigned)(2 * C)) + c16;
+        __builtin_amdgcn_global_load_lds((const void*)(base + off),
+                                         (__attribute__((address_space(3))) void*)(dst + (s0 + w0) * 8),
                                          16, 0, 0);
+      }
+      tx += DP % RW;
+      ty += DP / RW;
+      if (tx >= RW) {
+        tx -= RW;
+        ++ty;
       }
     }
   };
