@@ -143,7 +143,7 @@ typedef struct {
   int32_t channels;     /* CNN: hidden width C                           */
   const void* weights;  /* CNN: device, concatenated Conv2d weights      */
   const void* biases;   /* CNN: device, concatenated biases              */
-  int32_t act;          /* CNN: PR_ACT_GELU (exact erf) or PR_ACT_TANH   */
+  int32_t act;          /* CNN: PR_ACT_GELU (erf form) or PR_ACT_TANH    */
   int32_t residual;     /* CNN: 1: G(u) = u + net(u)                     */
   int32_t mass_fix;     /* CNN: 1: restore the input's mean              */
   int32_t limiter;      /* CNN: 1: clamp to [lim_lo, lim_hi]             */
