@@ -57,9 +57,9 @@ typedef __attribute__((ext_vector_type(4))) float f32x4;
 // a relative error of erfc below 1.7e-7).
 // One reciprocal, one exp2 and 13 other instructions, where the library's
 // erff evaluates two branches across a wave.  Relative error of the result
-// in FP32 with a correctly rounded reciprocal and exp2: below 6e-7 for
-// |x| < 2, 1.5e-6 down to x = -5 and a few 1e-6 of a value that is already
-// below 1e-5 of x beyond.
+// in FP32 with a correctly rounded reciprocal and exp2: below 8e-7 for
+// |x| < 2 (5.9e-7 on a dense grid), 1.5e-6 down to x = -5 and a few 1e-6 of
+// a value that is already below 1e-5 of x beyond.
 __device__ __forceinline__ float gelu_f32(float x) {
   constexpr double L = 1.44269504088896340736;  // log2(e)
   const float t = __builtin_amdgcn_rcpf(fmaf(fabsf(x), kGeluT, 1.0f));
@@ -484,7 +484,7 @@ __global__ __launch_bounds__((HidCfg<C, hidden_waves<C, TAIL>()>::NT)) __attribu
   // lane l of a wave's load at slot base s0 fills slot s0 + l, slot s being
   // the 16-byte chunk s % SP of tile pixel s / SP (SP = PS / 8 chunks per
   // pixel: C / 8 hi chunks, with SPLIT C / 8 lo chunks, then the pad, which
-  // no lane loads).  Offsets within a field are 32-bit.
+  // no lane loads).
   // Each step covers DP whole pixels (STEP = DP SP slots, at most NT): a
   // lane keeps its chunk j, so its plane (hi or lo) and source base, and
   // its pixel advances by DP, i.e. DP / RW rows and DP % RW columns with at
